@@ -1,0 +1,107 @@
+"""Seeded synthetic workloads shared by the tests, the benchmark and the oracle.
+
+This module holds shapes, seeds and sampling only -- none of the method's
+arithmetic.  Every surface is a radial perturbation of the unit sphere,
+    R(t, theta) = 1 + sum_{l,m} a[l-1, m] sin(l t) cos(m theta),
+with t in [0, pi] split into ``n_panels`` equal panels of 16 Gauss-Legendre
+nodes (Sec. 3.1) and 2M equispaced target azimuths theta_j = pi j / M
+(eq. (3.8)).  The paper measures on analytic surfaces only; these seeded
+stand-ins have the same structure (panel/node layout, azimuth grid, near and
+far pair mix).
+"""
+import math
+
+import numpy as np
+
+GL_ORDER = 16
+
+
+def gl_nodes(n=GL_ORDER):
+    """Gauss-Legendre nodes and weights on [-1, 1] (numpy's rule)."""
+    return np.polynomial.legendre.leggauss(n)
+
+
+def panel_edges(n_panels, length=math.pi):
+    return length * np.arange(n_panels + 1) / n_panels
+
+
+def curve_nodes(n_panels, length=math.pi):
+    """t_i^l for all panels, shape (n_panels, 16), and the GL weights w_i^l."""
+    x, w = gl_nodes()
+    e = panel_edges(n_panels, length)
+    half = 0.5 * (e[1:] - e[:-1])
+    mid = 0.5 * (e[1:] + e[:-1])
+    return mid[:, None] + half[:, None] * x[None, :], half[:, None] * w[None, :]
+
+
+def star_amplitudes(lmax, mmax, scale, rng):
+    """Amplitude table a[l-1, m] ~ U(-scale, scale), drawn l-major."""
+    return rng.uniform(-scale, scale, size=(lmax, mmax + 1))
+
+
+def random_direction(rng):
+    d = rng.standard_normal(3)
+    return d / np.linalg.norm(d)
+
+
+def config(i):
+    """The five benchmark configurations (shapes, seeds, amplitudes)."""
+    if i == 1:
+        return dict(name="sphere-k1-Np8-M32", amp=np.zeros((0, 1)), k=1.0, n_panels=8, M=32,
+                    d=np.array([0.0, 0.0, 1.0]), seed=1)
+    if i == 2:
+        amp = np.zeros((3, 3))
+        amp[2, 2] = 0.2                      # 0.2 sin(3t) cos(2 theta)
+        rng = np.random.default_rng(2)
+        return dict(name="star-k5-Np16-M64", amp=amp, k=5.0, n_panels=16, M=64,
+                    d=random_direction(rng), seed=2)
+    if i == 3:
+        rng = np.random.default_rng(3)
+        amp = star_amplitudes(4, 4, 0.1, rng)
+        return dict(name="star20-k20-Np32-M128", amp=amp, k=20.0, n_panels=32, M=128,
+                    d=random_direction(rng), seed=3)
+    raise ValueError(i)
+
+
+def all_pairs(n_panels, M, length=math.pi):
+    """Every (target node, target azimuth, source curve node) with t_s != t.
+
+    Order: target node i (outer), source node s, target azimuth j (inner).
+    Returns float64 t, int32 j, float64 ts.
+    """
+    t_nodes = curve_nodes(n_panels, length)[0].ravel()
+    n = t_nodes.size
+    ii, ss = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    keep = ii != ss
+    ii, ss = ii[keep], ss[keep]
+    nj = 2 * M
+    t = np.repeat(t_nodes[ii], nj)
+    ts = np.repeat(t_nodes[ss], nj)
+    j = np.tile(np.arange(nj, dtype=np.int32), ii.size)
+    return t, j, ts
+
+
+def sample_pairs(n_panels, M, n, seed, near_fraction=0.3, length=math.pi):
+    """Seeded sample of pairs: curve-node pairs plus near pairs.
+
+    A fraction ``near_fraction`` of the pairs put the source a log-uniform
+    distance 10^-7 .. 10^-1 (times the panel length) from the target node, as
+    the near-panel quadrature nodes do; the rest pair two distinct curve nodes.
+    """
+    rng = np.random.default_rng(seed)
+    t_nodes = curve_nodes(n_panels, length)[0].ravel()
+    nt = t_nodes.size
+    n_near = int(round(near_fraction * n))
+    n_far = n - n_near
+    i = rng.integers(0, nt, size=n_far)
+    s = (i + rng.integers(1, nt, size=n_far)) % nt
+    t_far, ts_far = t_nodes[i], t_nodes[s]
+    i2 = rng.integers(0, nt, size=n_near)
+    h = length / n_panels
+    off = h * 10.0 ** rng.uniform(-7, -1, size=n_near) * rng.choice([-1.0, 1.0], size=n_near)
+    t_near = t_nodes[i2]
+    ts_near = np.clip(t_near + off, 1e-3, length - 1e-3)
+    t = np.concatenate([t_far, t_near])
+    ts = np.concatenate([ts_far, ts_near])
+    j = rng.integers(0, 2 * M, size=n).astype(np.int32)
+    return t, j, ts
