@@ -1,0 +1,151 @@
+/*
+ * ffbie.h -- C ABI of the MI355X (gfx950) library for the azimuthal Fourier
+ * coefficients of the singular 3-D Helmholtz kernels on smooth surfaces.
+ *
+ * Method: W. Hua, J. Lai, H. Li, W. Lu, "An FFT-accelerated boundary integral
+ * equation method for wave scattering by smooth surfaces in three
+ * dimensions".  Section and equation numbers below refer to that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every d_* argument is a caller-owned DEVICE pointer (for example the
+ *    data_ptr() of a torch tensor on the context's device).  The library never
+ *    frees or reallocates it.  Host pointers are copied before the call returns.
+ *  - Work is enqueued on the context's HIP stream; calls return before the
+ *    device work completes.  The caller synchronises the stream.
+ *  - Complex values are interleaved (re, im) float64 pairs, the layout of
+ *    torch.complex128.
+ *  - Return value: FFBIE_OK (0), an error (< 0) or a warning (> 0).  On an
+ *    error nothing is enqueued; ffbie_last_error() describes it.  Per-pair
+ *    conditions found on the device are reported through the optional
+ *    per-pair status array, never through the return value.
+ *  - One context per host thread; a context is not thread safe.
+ */
+#ifndef FFBIE_H
+#define FFBIE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FFBIE_OK = 0,
+  FFBIE_EINVAL = -1,         /* invalid argument, shape or unsupported size        */
+  FFBIE_ENOMEM = -4,         /* device allocation of a workspace failed             */
+  FFBIE_EDEVICE = -5,        /* a HIP runtime call failed                           */
+  FFBIE_ENOPROBLEM = -7      /* ffbie_set_problem has not been called               */
+} ffbie_status;
+
+/* Per-pair status bits written to d_pair_status by ffbie_kernel_coeffs. */
+enum {
+  FFBIE_PAIR_OK = 0,
+  FFBIE_PAIR_SINGULAR = 1,        /* t == t_s: the coefficients diverge (b = 0); row is NaN */
+  FFBIE_PAIR_ROOT_FALLBACK = 2,   /* complex Newton did not converge; the quadratic-model
+                                     root estimate was used (accuracy is then governed by
+                                     the smooth-factor truncation test)                    */
+  FFBIE_PAIR_REFINED = 4,         /* smooth factor not resolved by 2M samples; recomputed
+                                     with 4M samples                                        */
+  FFBIE_PAIR_UNRESOLVED = 8,      /* smooth factor not resolved even by 4M samples          */
+  FFBIE_PAIR_FAR = 16             /* b0 >= 3: the quadratic-model estimate (a0, b0), not a
+                                     Newton-refined root, parametrises the swap             */
+};
+
+/* How the kernel coefficients <e^{ik rho}/rho>_n are formed from the swap. */
+enum {
+  FFBIE_KAPPA_SWAP = 0,        /* default: the singularity swap of Sec. 3.3 applied to the
+                                  whole singular part, cos(k rho)/rho = [F cos(k rho)] s_{a,b}^{-1/2}
+                                  (cos(k rho) is analytic in rho^2), one convolution with A_m(b);
+                                  the construction the paper uses for tau_3 in eqs. (4.5)-(4.6) */
+  FFBIE_KAPPA_PAPER_CONV = 1   /* eq. (3.10): <cos(k rho)>_n (|n| < M0) convolved with the
+                                  swapped <rho^-1>_l of eq. (3.25) */
+};
+
+typedef struct ffbie_ctx ffbie_ctx;
+
+/* Surface of the star family, a radial perturbation of the unit sphere in the
+ * parametrisation of Sec. 2, eq. (2.1), with t in [0, pi] (polar angle) and
+ * theta the azimuth:
+ *   r(t, theta) = R(t, theta) (sin t cos theta, sin t sin theta, cos t),
+ *   R(t, theta) = 1 + sum_{l=1..lmax} sum_{m=0..mmax} a[(l-1)(mmax+1) + m] sin(l t) cos(m theta).
+ * lmax = 0 gives the unit sphere.  `a` is a HOST pointer, row-major
+ * [lmax][mmax+1], copied by ffbie_set_problem.  Limits: lmax <= 8, mmax <= 8. */
+typedef struct {
+  int lmax;
+  int mmax;
+  const double *a;
+} ffbie_geometry;
+
+/* Discretisation (Sec. 3.1-3.2): n_panels Gauss-Legendre panels of 16 nodes
+ * in t, 2M equispaced azimuths theta_j = pi j / M (eq. (3.8)), M0 modes of
+ * cos(k rho) in eq. (3.10) (0 < M0 <= M; the paper uses M0 = M), eps0 the
+ * truncation threshold of eq. (3.13) applied to the smooth factor of eq. (3.24)
+ * (0 selects 1e-15), kappa_variant one of FFBIE_KAPPA_*.  Supported M: 16, 32,
+ * 64, 128. */
+typedef struct {
+  int n_panels;
+  int M;
+  int M0;
+  double eps0;
+  int kappa_variant;   /* FFBIE_KAPPA_SWAP (default) or FFBIE_KAPPA_PAPER_CONV */
+} ffbie_discretization;
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL selects the default stream).  *out receives the
+ * context or NULL on failure. */
+ffbie_status ffbie_create(ffbie_ctx **out, int device, void *hip_stream);
+
+/* Release the context and its device workspaces.  Accepts NULL. */
+ffbie_status ffbie_destroy(ffbie_ctx *ctx);
+
+/* Text of the last error on this context (valid until the next call); a
+ * static string when ctx is NULL. */
+const char *ffbie_last_error(const ffbie_ctx *ctx);
+
+/* Set the surface, discretisation and wavenumber k >= 0 (eq. (2.2)).  Uploads
+ * the geometry and the angle tables to the device.  Must precede every
+ * compute call; may be called again to change the problem. */
+ffbie_status ffbie_set_problem(ffbie_ctx *ctx, const ffbie_geometry *g,
+                               const ffbie_discretization *d, double k);
+
+/* Azimuthal Fourier coefficients of the single-layer kernel for n_pairs
+ * (target, source-curve) pairs by singularity swapping (Sec. 3.2-3.3).
+ *
+ * A pair is a target point r(t, theta_j) and a source curve t_s (t_s != t):
+ *   d_tgt_t[i]   target curve parameter t (float64),
+ *   d_tgt_az[i]  target azimuth index j in [0, 2M) (int32), theta_j = pi j / M,
+ *   d_src_t[i]   source curve parameter t_s (float64).
+ * Outputs (row-major, one row per pair):
+ *   d_kappa      [n_pairs][2M] complex128: <e^{ik rho}/rho>_n for n = -M+1..M at
+ *                column n + M - 1 -- the coefficients of eq. (3.9), formed as
+ *                selected by kappa_variant.  Required.
+ *   d_rhoinv     [n_pairs][M+M0+1] complex128: <rho^-1>_l for l = 0..M+M0
+ *                (eq. (3.25)).  Optional (NULL).
+ *   d_root       [n_pairs][2] float64: (a - theta_j, b) of the complex root
+ *                theta_+ = a + i b of rho^2 used for the swap (Lemma 3.6).
+ *                Optional (NULL).
+ *   d_pair_status[n_pairs] int32: FFBIE_PAIR_* bits.  Optional (NULL).
+ * Every row is written.  A pair with t == t_s gets a NaN row and
+ * FFBIE_PAIR_SINGULAR.  Returns FFBIE_EINVAL for n_pairs < 0, a NULL d_kappa
+ * or inputs, or no problem set.  n_pairs == 0 is a no-op. */
+ffbie_status ffbie_kernel_coeffs(ffbie_ctx *ctx, int64_t n_pairs,
+                                 const double *d_tgt_t, const int32_t *d_tgt_az,
+                                 const double *d_src_t,
+                                 void *d_kappa, void *d_rhoinv, double *d_root,
+                                 int32_t *d_pair_status);
+
+/* Singular-factor coefficients A_m(b) = <s_{0,b}^{-1/2}>_m of eq. (3.26) for
+ * m = 0..m_max and n values of b > 0 (d_b, float64 [n]), written to
+ * d_A [n][m_max+1] float64.  Uses the same device routine as
+ * ffbie_kernel_coeffs (Miller's backward recurrence normalised by
+ * A_0 = (2/pi) K(e^{-2b}), or for small b the difference recurrence of
+ * eq. (3.28)).  b <= 0 gives a NaN row.  1 <= m_max <= 1023. */
+ffbie_status ffbie_singular_factor(ffbie_ctx *ctx, int64_t n, const double *d_b,
+                                   int m_max, double *d_A);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFBIE_H */

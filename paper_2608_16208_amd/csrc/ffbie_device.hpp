@@ -1,0 +1,271 @@
+// Device-side building blocks for the singularity-swapping coefficient kernels
+// (gfx950, wave64, FP64).
+//
+// Geometry: star family r(t,theta) = R(t,theta) (sin t cos theta, sin t sin theta,
+// cos t), R = 1 + sum a_lm sin(l t) cos(m theta)  (paper Sec. 2, eq. (2.1)).
+//
+// The point difference r(t_s, theta_j + d) - r(t, theta_j) is evaluated with
+// product-to-sum identities (sin x - sin y = 2 cos((x+y)/2) sin((x-y)/2), ...),
+// which are exact algebraic rewrites with no subtraction of nearly equal
+// quantities; this plays the role of the cancellation-free difference of the
+// paper's Remark 4.2 at a fraction of the cost of its 16-node line integral.
+// On the azimuth grid every angle is a multiple of pi/(4M), so its sine comes
+// from an exactly rounded table.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ffbie.h"
+
+#define FFBIE_HD __host__ __device__
+
+namespace ffbie {
+
+constexpr int kMaxL = 8;       // highest l in the amplitude table
+constexpr int kMaxM = 8;       // highest m in the amplitude table
+constexpr int kWave = 64;
+
+// Surface description passed by value as a kernel argument.
+struct Geom {
+  int lmax, mmax;
+  double a[kMaxL][kMaxM + 1];
+};
+
+// Problem-wide constants for the coefficient kernels.
+struct Prob {
+  Geom g;
+  double k;        // wavenumber
+  double eps0;     // smooth-factor truncation threshold (eq. (3.13) rule)
+  int M, M0, L;    // L = M + M0
+  int tab_n;       // 8M: period of the angle table (entries sin(pi i / (4M)))
+};
+
+// ----------------------------------------------------------------------------
+// complex double
+// ----------------------------------------------------------------------------
+struct cplx {
+  double re, im;
+};
+FFBIE_HD __forceinline__ cplx mk(double r, double i) { return cplx{r, i}; }
+FFBIE_HD __forceinline__ cplx operator+(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+FFBIE_HD __forceinline__ cplx operator-(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
+FFBIE_HD __forceinline__ cplx operator*(cplx a, cplx b) {
+  return {fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
+}
+FFBIE_HD __forceinline__ cplx operator*(double s, cplx a) { return {s * a.re, s * a.im}; }
+FFBIE_HD __forceinline__ cplx operator*(cplx a, double s) { return {s * a.re, s * a.im}; }
+FFBIE_HD __forceinline__ cplx conj(cplx a) { return {a.re, -a.im}; }
+FFBIE_HD __forceinline__ double abs2(cplx a) { return fma(a.re, a.re, a.im * a.im); }
+FFBIE_HD __forceinline__ cplx cdiv(cplx a, cplx b) {
+  // Smith's algorithm
+  if (fabs(b.re) >= fabs(b.im)) {
+    double r = b.im / b.re, d = b.re + b.im * r;
+    return {(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+  }
+  double r = b.re / b.im, d = b.re * r + b.im;
+  return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+}
+// sin and cos of a complex argument x + iy
+FFBIE_HD __forceinline__ void csincos(cplx z, cplx* s, cplx* c) {
+  double sx, cx;
+  sincos(z.re, &sx, &cx);
+  // sinh via expm1 keeps full relative accuracy for small |Im z|
+  const double em = expm1(z.im), emm = expm1(-z.im);
+  const double sh = 0.5 * (em - emm);
+  const double ch = 1.0 + 0.5 * (em + emm);
+  *s = {sx * ch, cx * sh};
+  *c = {cx * ch, -sx * sh};
+}
+
+// ----------------------------------------------------------------------------
+// Angle table: tab[i] = sin(pi i / (4M)), i in [0, 8M).  cos via +2M.
+// ----------------------------------------------------------------------------
+FFBIE_HD __forceinline__ double tsin(const double* tab, int i, int mask) { return tab[i & mask]; }
+FFBIE_HD __forceinline__ double tcos(const double* tab, int i, int mask, int quarter) {
+  return tab[(i + quarter) & mask];
+}
+
+// ----------------------------------------------------------------------------
+// Per-pair geometry.  Written as trigonometric polynomials in the source
+// azimuth, with coefficients that depend on (t, t_s) only:
+//   R(t_s, th)            = 1 + sum_m al_m cos(m th),   al_m = sum_l a_lm sin(l t_s)
+//   R(t_s, th) - R(t, tj) = sum_m be_m cos(m th) + ga_m (cos(m th) - cos(m tj)),
+//                           be_m = sum_l a_lm (sin(l t_s) - sin(l t)),  ga_m = sum_l a_lm sin(l t)
+// with sin(l t_s) - sin(l t) = 2 cos(l (t_s+t)/2) sin(l (t_s-t)/2) (no cancellation).
+// MM is a compile-time bound on the highest azimuthal order m of the surface.
+// ----------------------------------------------------------------------------
+template <int MM>
+struct PairGeo {
+  double st, sts, cts;        // sin t, sin t_s, cos t_s
+  double S1, C1;              // sin t_s - sin t, cos t_s - cos t (product forms)
+  double R;                   // R(t, theta_j)
+  double al[MM + 1], be[MM + 1], ga[MM + 1];
+};
+
+template <int MM>
+FFBIE_HD __forceinline__ void pair_geo(const Geom& g, double t, double ts, const double* tab,
+                                         int J, int mask, int quarter, PairGeo<MM>* p) {
+  double st, ct, sts, cts, shd, chd, shs, chs;
+  sincos(t, &st, &ct);
+  sincos(ts, &sts, &cts);
+  sincos(0.5 * (ts - t), &shd, &chd);
+  sincos(0.5 * (ts + t), &shs, &chs);
+  p->st = st; p->sts = sts; p->cts = cts;
+  p->S1 = 2.0 * chs * shd;
+  p->C1 = -2.0 * shs * shd;
+#pragma unroll
+  for (int m = 0; m <= MM; ++m) { p->al[m] = 0.0; p->be[m] = 0.0; p->ga[m] = 0.0; }
+  // multiple angles by the Chebyshev recurrences (accurate for small arguments)
+  double s_t0 = 0.0, s_t1 = st, s_s0 = 0.0, s_s1 = sts;
+  double sd0 = 0.0, sd1 = shd, cs0 = 1.0, cs1 = chs;
+  for (int l = 1; l <= g.lmax; ++l) {
+    const double Sl = 2.0 * cs1 * sd1;
+#pragma unroll
+    for (int m = 0; m <= MM; ++m) {
+      const double a = (m <= g.mmax) ? g.a[l - 1][m] : 0.0;
+      p->al[m] = fma(a, s_s1, p->al[m]);
+      p->be[m] = fma(a, Sl, p->be[m]);
+      p->ga[m] = fma(a, s_t1, p->ga[m]);
+    }
+    double nt = 2.0 * ct * s_t1 - s_t0;  s_t0 = s_t1; s_t1 = nt;
+    double ns = 2.0 * cts * s_s1 - s_s0; s_s0 = s_s1; s_s1 = ns;
+    double nd = 2.0 * chd * sd1 - sd0;   sd0 = sd1;   sd1 = nd;
+    double nc = 2.0 * chs * cs1 - cs0;   cs0 = cs1;   cs1 = nc;
+  }
+  double R = 1.0;
+#pragma unroll
+  for (int m = 0; m <= MM; ++m) R = fma(p->ga[m], tab[(m * J + quarter) & mask], R);
+  p->R = R;
+}
+
+// Delta r = r(t_s, theta_q) - r(t, theta_j) for a source azimuth on the table
+// grid: Kq = table index of theta_q, J = table index of theta_j (both even).
+template <int MM>
+FFBIE_HD __forceinline__ void dr_grid(const PairGeo<MM>& p, const double* tab, int Kq, int J,
+                                        int mask, int quarter, double* dx, double* dy, double* dz) {
+  const int hd = (Kq - J) >> 1;      // (theta_q - theta_j)/2
+  const int hs = (Kq + J) >> 1;      // (theta_q + theta_j)/2
+  const double cq = tcos(tab, Kq, mask, quarter), sq = tsin(tab, Kq, mask);
+  const double dh = tsin(tab, hd, mask);
+  const double dcos = -2.0 * tsin(tab, hs, mask) * dh;         // cos theta_q - cos theta_j
+  const double dsin = 2.0 * tcos(tab, hs, mask, quarter) * dh;  // sin theta_q - sin theta_j
+  double Rs = 1.0, dR = 0.0;
+#pragma unroll
+  for (int m = 0; m <= MM; ++m) {
+    const double cm = tcos(tab, m * Kq, mask, quarter);
+    // cos(m theta_q) - cos(m theta_j) = -2 sin(m hs) sin(m hd)
+    const double dc = -2.0 * tsin(tab, m * hs, mask) * tsin(tab, m * hd, mask);
+    Rs = fma(p.al[m], cm, Rs);
+    dR = fma(p.be[m], cm, fma(p.ga[m], dc, dR));
+  }
+  const double wx = p.sts * cq, wy = p.sts * sq, wz = p.cts;
+  const double ox = fma(p.S1, cq, p.st * dcos);
+  const double oy = fma(p.S1, sq, p.st * dsin);
+  const double oz = p.C1;
+  *dx = fma(dR, wx, p.R * ox);
+  *dy = fma(dR, wy, p.R * oy);
+  *dz = fma(dR, wz, p.R * oz);
+}
+
+// rho^2 and its first two derivatives in the source azimuth at a complex
+// offset d (source azimuth theta_j + d).  sj, cj = sin/cos(theta_j);
+// smj[m], cmj[m] = sin/cos(m theta_j).  Used by the root finder.
+struct Rho2 {
+  cplx f, f1, f2;
+};
+
+template <int MM>
+FFBIE_HD __forceinline__ Rho2 rho2_complex(const PairGeo<MM>& p, double sj, double cj,
+                                             const double* smj, const double* cmj, cplx d,
+                                             bool want2) {
+  cplx h = 0.5 * d, sh, ch;
+  csincos(h, &sh, &ch);
+  // source azimuth theta' = theta_j + 2h
+  const cplx cd = ch * ch - sh * sh, sd = 2.0 * (sh * ch);
+  const cplx cq = cj * cd - sj * sd, sq = sj * cd + cj * sd;
+  // mid angle theta_j + h
+  const cplx smid = sj * ch + cj * sh, cmid = cj * ch - sj * sh;
+  const cplx dcos = -2.0 * (smid * sh), dsin = 2.0 * (cmid * sh);
+  cplx Rs = mk(1, 0), dR = mk(0, 0), Rth = mk(0, 0), Rthth = mk(0, 0);
+  // sin(m h), cos(m h) by the Chebyshev recurrences
+  cplx s_prev = mk(0, 0), c_prev = mk(1, 0), s_cur = sh, c_cur = ch;
+#pragma unroll
+  for (int m = 0; m <= MM; ++m) {
+    cplx smh, cmh;
+    if (m == 0) { smh = mk(0, 0); cmh = mk(1, 0); }
+    else if (m == 1) { smh = sh; cmh = ch; }
+    else {
+      const cplx sn = 2.0 * (ch * s_cur) - s_prev, cn = 2.0 * (ch * c_cur) - c_prev;
+      s_prev = s_cur; c_prev = c_cur; s_cur = sn; c_cur = cn;
+      smh = sn; cmh = cn;
+    }
+    // m theta' = m theta_j + 2 m h
+    const cplx c2 = cmh * cmh - smh * smh, s2 = 2.0 * (smh * cmh);
+    const cplx cmq = cmj[m] * c2 - smj[m] * s2;
+    const cplx smq = smj[m] * c2 + cmj[m] * s2;
+    const cplx smm = smj[m] * cmh + cmj[m] * smh;   // sin(m (theta_j + h))
+    const cplx dcm = -2.0 * (smm * smh);            // cos(m theta') - cos(m theta_j)
+    Rs = Rs + p.al[m] * cmq;
+    dR = dR + p.be[m] * cmq + p.ga[m] * dcm;
+    Rth = Rth + (-p.al[m] * m) * smq;
+    Rthth = Rthth + (-p.al[m] * m * m) * cmq;
+  }
+  const cplx wx = p.sts * cq, wy = p.sts * sq, wz = mk(p.cts, 0);
+  const cplx ox = p.S1 * cq + p.st * dcos, oy = p.S1 * sq + p.st * dsin, oz = mk(p.C1, 0);
+  const cplx Dx = dR * wx + p.R * ox, Dy = dR * wy + p.R * oy, Dz = dR * wz + p.R * oz;
+  // r_theta(t_s, theta') = R_theta w + Rs w_theta,  w_theta = (-sts sin, sts cos, 0)
+  const cplx tx = Rth * wx - Rs * (p.sts * sq), ty = Rth * wy + Rs * (p.sts * cq), tz = Rth * wz;
+  Rho2 out;
+  out.f = Dx * Dx + Dy * Dy + Dz * Dz;
+  out.f1 = 2.0 * (Dx * tx + Dy * ty + Dz * tz);
+  if (want2) {
+    // r_thth = R_thth w + 2 R_th w_th + Rs w_thth,  w_thth = (-sts cos, -sts sin, 0)
+    const cplx ux = Rthth * wx - 2.0 * (Rth * (p.sts * sq)) - Rs * (p.sts * cq);
+    const cplx uy = Rthth * wy + 2.0 * (Rth * (p.sts * cq)) - Rs * (p.sts * sq);
+    const cplx uz = Rthth * wz;
+    out.f2 = 2.0 * (tx * tx + ty * ty + tz * tz + Dx * ux + Dy * uy + Dz * uz);
+  } else {
+    out.f2 = mk(0, 0);
+  }
+  return out;
+}
+
+// ----------------------------------------------------------------------------
+// Complete elliptic integrals K(m), E(m) (parameter convention, m = e^{-2b})
+// by the arithmetic-geometric mean, with sqrt(1 - m) supplied directly so that
+// m -> 1 (b -> 0) keeps full relative accuracy.
+// ----------------------------------------------------------------------------
+FFBIE_HD inline void ellip_KE(double m, double sqrt_1m, double* K, double* E) {
+  double a = 1.0, gm = sqrt_1m, c = sqrt(m);
+  double sum = 0.5 * c * c, pw = 0.5;
+  for (int it = 0; it < 40; ++it) {
+    double an = 0.5 * (a + gm);
+    c = 0.5 * (a - gm);
+    gm = sqrt(a * gm);
+    a = an;
+    pw *= 2.0;
+    sum = fma(pw, c * c, sum);
+    if (c <= 1e-17 * a) break;
+  }
+  *K = M_PI / (2.0 * a);
+  *E = *K * (1.0 - sum);
+}
+
+// ----------------------------------------------------------------------------
+// Wave-level helpers
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d));
+  return v;
+}
+
+}  // namespace ffbie

@@ -1,0 +1,573 @@
+// Singularity-swapping coefficient kernels for gfx950.
+//
+// For a target r(t, theta_j) and a source curve t_s the path evaluates the
+// azimuthal Fourier coefficients of the single-layer kernel e^{ik rho}/rho
+// (paper Sec. 3.2-3.3).  With theta_+ = a + ib the root of rho^2 nearest to
+// the real axis (Lemma 3.6), s_{a,b} of eq. (3.22) and the smooth factor
+// F = (s_{a,b}/rho^2)^{1/2} of eq. (3.23):
+//   <rho^-1>_l = sum_j <F>_j e^{-i(l-j)a} A_{|l-j|}(b)                     eq. (3.25)
+// and, since cos(k rho) is analytic in rho^2, the same swap applied to the
+// whole singular part cos(k rho)/rho = [F cos(k rho)] s_{a,b}^{-1/2} gives
+//   <cos(k rho)/rho>_n = sum_j <F cos(k rho)>_j e^{-i(n-j)a} A_{|n-j|}(b),
+// the construction the paper uses for tau_3 in eqs. (4.5)-(4.6).  This is the
+// default path for the kernel coefficients; the double convolution of
+// eq. (3.10) (<cos(k rho)>_n convolved with <rho^-1>_l) is kept as a variant.
+// The smooth part <sin(k rho)/rho>_n comes from the same FFT.
+//
+// Kernel 1 (ffbie_root_kernel), one lane per pair: grid minimiser of rho^2,
+//   Newton on d rho^2 for the real minimiser a0, b0 = sqrt(2 rho^2 / rho^2'')
+//   (Sec. 3.3), damped complex Newton for theta_+, then K and E of parameter
+//   e^{-2b} for A_0 and A_1.
+// Kernel 2 (ffbie_coeff_kernel), one wavefront per pair: samples on the
+//   azimuth grid, radix-2 Stockham FFT in LDS, truncation index p of
+//   eq. (3.24), A_m(b) by a wave-parallel scan of the 2x2 transfer matrices of
+//   Miller's backward recurrence (or of the difference recurrence (3.28) for
+//   small b), the convolutions, and a coalesced row write.
+#include "ffbie_kernels.hpp"
+#include "ffbie_root.hpp"
+
+namespace ffbie {
+
+constexpr double kTauFwd = 9.0;      // forward difference recurrence while m_max * b <= this
+constexpr double kMillerStart = 1e-280;
+
+__device__ __forceinline__ void load_table(double* tab, const double* __restrict__ tab_g, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tab[i] = tab_g[i];
+  __syncthreads();
+}
+
+__device__ __forceinline__ double rcp_int(double x) {
+  // 1/x for a small positive integer x: hardware estimate + two Newton steps
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// ===========================================================================
+// Kernel 1: roots (lane per pair)
+// ===========================================================================
+template <int MM>
+__global__ __launch_bounds__(256) void ffbie_root_kernel_t(
+    Prob P, const double* __restrict__ tab_g, int64_t n, const double* __restrict__ t_in,
+    const int32_t* __restrict__ az_in, const double* __restrict__ ts_in, RootRec* __restrict__ out,
+    int32_t* __restrict__ status, double* __restrict__ root_out) {
+  extern __shared__ double tab[];
+  load_table(tab, tab_g, P.tab_n);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double t = t_in[i], ts = ts_in[i];
+  const int j = az_in[i] & (2 * P.M - 1);
+  const double nan = __builtin_nan("");
+  if (t == ts || !(t == t) || !(ts == ts)) {
+    out[i] = RootRec{nan, nan, nan, nan};
+    status[i] = FFBIE_PAIR_SINGULAR;
+    if (root_out) { root_out[2 * i] = nan; root_out[2 * i + 1] = nan; }
+    return;
+  }
+  int st;
+  const RootRec r = find_root<MM>(P, tab, t, j, ts, &st);
+  out[i] = r;
+  status[i] = st;
+  if (root_out) { root_out[2 * i] = r.u; root_out[2 * i + 1] = r.b; }
+}
+
+// ===========================================================================
+// A_m(b), m = 0..mtop, into LDS `A`, cooperatively by one wavefront.
+//
+// For m_max b <= kTauFwd the difference recurrence of eq. (3.28) runs forward
+// from A_0 and D_1; otherwise Miller's backward recurrence
+//   (2m - 1) y_{m-1} = 4 m cosh(b) y_m - (2m + 1) y_{m+1}
+// (the three-term recurrence of the half-integer Legendre functions of
+// eq. (3.27)) starts at N >= (m_max + 37/b)/2 and is normalised by A_0.
+// Either recurrence is a product of 2x2 transfer matrices: each lane forms the
+// product over its own segment of indices, a Hillis-Steele scan across the 64
+// lanes composes the segments, and each lane then replays its segment from
+// the state entering it.
+// ===========================================================================
+__device__ __forceinline__ void mat_mul(double a00, double a01, double a10, double a11, double b00,
+                                        double b01, double b10, double b11, double* c00,
+                                        double* c01, double* c10, double* c11) {
+  *c00 = fma(a00, b00, a01 * b10);
+  *c01 = fma(a00, b01, a01 * b11);
+  *c10 = fma(a10, b00, a11 * b10);
+  *c11 = fma(a10, b01, a11 * b11);
+}
+
+__device__ __forceinline__ void singular_factor_wave(double b, double A0, double D1, int mtop,
+                                                     double* A) {
+  const int lane = threadIdx.x & 63;
+  if (!(b > 0) || !(A0 == A0)) {
+    for (int m = lane; m <= mtop; m += 64) A[m] = __builtin_nan("");
+    wave_sync();
+    return;
+  }
+  if (mtop == 0) {
+    if (lane == 0) A[0] = A0;
+    wave_sync();
+    return;
+  }
+  if ((double)mtop * b <= kTauFwd) {
+    // ---- forward: w_{m+1} = F_m w_m, w = (D, A),
+    //      F_m = [[alpha, beta], [alpha, 1 + beta]], alpha = (2m-1)/(2m+1),
+    //      beta = 8 m sinh^2(b/2)/(2m+1), for m = 1 .. mtop-1
+    const double sh = sinh(0.5 * b), s2 = 8.0 * sh * sh;
+    const int cnt = mtop - 1;
+    const int S = cnt > 0 ? (cnt + 63) / 64 : 1;
+    const int m_first = 1 + lane * S;
+    double e00 = 1, e01 = 0, e10 = 0, e11 = 1;
+    for (int s = 0; s < S; ++s) {
+      const int m = m_first + s;
+      if (m > mtop - 1) break;
+      const double r = rcp_int(2.0 * m + 1.0);
+      const double al = (2.0 * m - 1.0) * r, be = s2 * m * r;
+      double n00, n01, n10, n11;
+      mat_mul(al, be, al, 1.0 + be, e00, e01, e10, e11, &n00, &n01, &n10, &n11);
+      e00 = n00; e01 = n01; e10 = n10; e11 = n11;
+    }
+    // inclusive prefix scan: E_l = Phi_l ... Phi_0
+    for (int d = 1; d < 64; d <<= 1) {
+      const double o00 = __shfl_up(e00, d), o01 = __shfl_up(e01, d);
+      const double o10 = __shfl_up(e10, d), o11 = __shfl_up(e11, d);
+      if (lane >= d) {
+        double n00, n01, n10, n11;
+        mat_mul(e00, e01, e10, e11, o00, o01, o10, o11, &n00, &n01, &n10, &n11);
+        e00 = n00; e01 = n01; e10 = n10; e11 = n11;
+      }
+    }
+    double x00 = __shfl_up(e00, 1), x01 = __shfl_up(e01, 1);
+    double x10 = __shfl_up(e10, 1), x11 = __shfl_up(e11, 1);
+    if (lane == 0) { x00 = 1; x01 = 0; x10 = 0; x11 = 1; }
+    const double w1D = D1, w1A = A0 + D1;
+    double wD = fma(x00, w1D, x01 * w1A), wA = fma(x10, w1D, x11 * w1A);
+    for (int s = 0; s < S; ++s) {
+      const int m = m_first + s;
+      if (m > mtop - 1) break;
+      const double r = rcp_int(2.0 * m + 1.0);
+      const double al = (2.0 * m - 1.0) * r, be = s2 * m * r;
+      const double nD = fma(al, wD, be * wA);
+      wA = wA + nD;
+      wD = nD;
+      A[m + 1] = wA;
+    }
+    if (lane == 0) { A[0] = A0; A[1] = A0 + D1; }
+    wave_sync();
+    return;
+  }
+  // ---- Miller, backward: v_{m-1} = T_m v_m, v_m = (y_m, y_{m+1}),
+  //      T_m = [[4 m cosh b/(2m-1), -(2m+1)/(2m-1)], [1, 0]], m = N .. 1
+  int meff = mtop;
+  int N = max(mtop + 10, (int)ceil(0.5 * (mtop + 37.0 / b)) + 10);
+  if (b * N > 640.0) {
+    // the recurrence would leave the double range; A_m < e^{-630} A_0 is set to 0
+    N = (int)floor(640.0 / b);
+    meff = min(mtop, max(0, N - 10));
+    if (N < 1) {   // b > 640: A_m / A_0 < 1e-270 for every m >= 1
+      for (int m = lane; m <= mtop; m += 64) A[m] = (m == 0) ? A0 : 0.0;
+      wave_sync();
+      return;
+    }
+  }
+  const double ch4 = 4.0 * cosh(b);
+  const int S = (N + 63) / 64;
+  const int top = lane * S + S;     // segment: transitions m = top .. lane*S + 1
+  double p00 = 1, p01 = 0, p10 = 0, p11 = 1;
+  for (int m = top; m > lane * S; --m) {
+    if (m > N) continue;
+    const double r = rcp_int(2.0 * m - 1.0);
+    const double al = ch4 * m * r, be = -(2.0 * m + 1.0) * r;
+    double n00, n01, n10, n11;
+    mat_mul(al, be, 1.0, 0.0, p00, p01, p10, p11, &n00, &n01, &n10, &n11);
+    p00 = n00; p01 = n01; p10 = n10; p11 = n11;
+  }
+  // inclusive suffix scan: Q_l = P_l P_{l+1} ... P_63
+  for (int d = 1; d < 64; d <<= 1) {
+    const double o00 = __shfl_down(p00, d), o01 = __shfl_down(p01, d);
+    const double o10 = __shfl_down(p10, d), o11 = __shfl_down(p11, d);
+    if (lane + d < 64) {
+      double n00, n01, n10, n11;
+      mat_mul(p00, p01, p10, p11, o00, o01, o10, o11, &n00, &n01, &n10, &n11);
+      p00 = n00; p01 = n01; p10 = n10; p11 = n11;
+    }
+  }
+  double q00 = __shfl_down(p00, 1), q10 = __shfl_down(p10, 1);
+  if (lane == 63) { q00 = 1; q10 = 0; }
+  // state entering the segment: Q_{l+1} (y_s, 0)
+  double y0 = q00 * kMillerStart, y1 = q10 * kMillerStart;   // (y_top, y_top+1)
+  for (int m = top; m > lane * S; --m) {
+    if (m > N) continue;
+    const double r = rcp_int(2.0 * m - 1.0);
+    const double yn = (ch4 * m * y0 - (2.0 * m + 1.0) * y1) * r;
+    y1 = y0;
+    y0 = yn;                         // y_{m-1}
+    if (m - 1 <= mtop) A[m - 1] = yn;
+  }
+  wave_sync();
+  const double scale = A0 / A[0];
+  wave_sync();
+  for (int m = lane; m <= mtop; m += 64) A[m] = (m <= meff) ? A[m] * scale : 0.0;
+  wave_sync();
+}
+
+// ===========================================================================
+// Forward DFT X_n = sum_q x_q e^{-2 pi i q n / NF} of one or two sequences,
+// radix-2 Stockham autosort in LDS.  On return ia/ib hold the transforms and
+// oa/ob are free.
+// ===========================================================================
+__device__ __forceinline__ void fft_stockham(cplx*& ia, cplx*& oa, cplx*& ib, cplx*& ob, bool two,
+                                             int NF, int M, const double* tab, int mask,
+                                             int quarter) {
+  const int lane = threadIdx.x & 63;
+  const int half = NF >> 1;
+  for (int Ns = 1; Ns < NF; Ns <<= 1) {
+    for (int jj = lane; jj < half; jj += 64) {
+      const int r = jj & (Ns - 1);
+      const int tk = r * ((4 * M) / Ns);            // angle pi r / Ns
+      const cplx wt = mk(tcos(tab, tk, mask, quarter), -tsin(tab, tk, mask));
+      const int idxD = ((jj - r) << 1) + r;
+      const cplx v0 = ia[jj], v1 = ia[jj + half] * wt;
+      oa[idxD] = v0 + v1;
+      oa[idxD + Ns] = v0 - v1;
+      if (two) {
+        const cplx u0 = ib[jj], u1 = ib[jj + half] * wt;
+        ob[idxD] = u0 + u1;
+        ob[idxD + Ns] = u0 - u1;
+      }
+    }
+    wave_sync();
+    cplx* tmp = ia; ia = oa; oa = tmp;
+    tmp = ib; ib = ob; ob = tmp;
+  }
+}
+
+// Coefficient j of the real sequence packed in the real part of the
+// transform X: (X_j + conj(X_{NF-j})) / (2 NF).
+__device__ __forceinline__ cplx real_part_coeff(const cplx* X, int jj, int NF, double invNF) {
+  return (0.5 * invNF) * (X[jj & (NF - 1)] + conj(X[(NF - jj) & (NF - 1)]));
+}
+// Coefficient j of the real sequence packed in the imaginary part:
+// (X_j - conj(X_{NF-j})) / (2i NF).
+__device__ __forceinline__ cplx imag_part_coeff(const cplx* X, int jj, int NF, double invNF) {
+  const cplx d = (0.5 * invNF) * (X[jj & (NF - 1)] - conj(X[(NF - jj) & (NF - 1)]));
+  return mk(d.im, -d.re);
+}
+
+// Truncation index of a real sequence's coefficients (the rule of eq. (3.13)
+// applied as for eq. (3.24)): the highest j < NF/2 with |c_j| > eps * scale,
+// where scale = max(max_j |c_j|, ref).  `ref` lets the coefficients of
+// F cos(k rho) be measured against the size of F itself: |cos(k rho)| <= 1, and
+// where cos(k rho) averages out its coefficients are small while the rounding
+// floor still follows F.
+__device__ __forceinline__ int trunc_index_real(const cplx* X, int NF, double invNF, double eps,
+                                                double ref) {
+  const int lane = threadIdx.x & 63;
+  double maxv = 0.0;
+  for (int jj = lane; jj < NF / 2; jj += 64) maxv = fmax(maxv, abs2(real_part_coeff(X, jj, NF, invNF)));
+  maxv = fmax(wave_max(maxv), ref * ref);
+  const double thr = eps * eps * maxv;
+  int p = 0;
+  for (int jj = lane; jj < NF / 2; jj += 64) {
+    const uint64_t bal = __ballot(abs2(real_part_coeff(X, jj, NF, invNF)) > thr);
+    if (bal) p = max(p, (jj - lane) + 63 - __clzll(bal));
+  }
+  return __builtin_amdgcn_readfirstlane(p);
+}
+
+// out_n = e^{-i n a} sum_{|j| <= p} G_j A_{|n-j|} for n = 0..nmax, with
+// e^{-i n a} = e^{-i n (theta_j + qu gstep)} e^{-i n ur}.
+__device__ __forceinline__ void swap_convolution(const cplx* G, int p, const double* A, int nmax,
+                                                 double ur, int Jq, const double* tab, int mask,
+                                                 int quarter, cplx* out, cplx* mirror,
+                                                 cplx* global_row) {
+  const int lane = threadIdx.x & 63;
+  for (int n = lane; n <= nmax; n += 64) {
+    double accr = 0.0, acci = 0.0;
+    for (int jj = -p; jj <= p; ++jj) {
+      const cplx g = G[p + jj];
+      const double Av = A[abs(n - jj)];
+      accr = fma(g.re, Av, accr);
+      acci = fma(g.im, Av, acci);
+    }
+    double s1, c1;
+    sincos(n * ur, &s1, &c1);
+    const cplx ph = mk(tcos(tab, n * Jq, mask, quarter), -tsin(tab, n * Jq, mask)) * mk(c1, -s1);
+    const cplx c = ph * mk(accr, acci);
+    out[n] = c;
+    if (mirror) mirror[-n] = conj(c);
+    if (global_row) global_row[n] = c;
+  }
+}
+
+// ===========================================================================
+// Kernel 2: coefficients (one wavefront per pair)
+//
+// LDS per wave: four NF-complex buffers (FFT ping-pong) and cb (2L+1 complex).
+// After the FFT, Z1 (and Z2) hold transforms and free1/free2 are free:
+//   default path:   Z1 = FFT(F cos(k rho) + i sin(k rho)/rho), Z2 = FFT(F) if <rho^-1> wanted
+//                   GH -> free1, GF -> free2, A -> free2 (no <rho^-1>) or Z2,
+//                   <rho^-1> -> cb, kc -> cb (no <rho^-1>) or free2
+//   eq. (3.10):     Z1 = FFT(F + i cos(k rho)), Z2 = FFT(sin(k rho)/rho)
+//                   C -> free1, GF -> free2, A -> Z1, <rho^-1> -> cb, kc -> free2
+// ===========================================================================
+template <int MM>
+__global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
+  extern __shared__ double smem[];
+  const Prob& P = a.P;
+  double* tab = smem;
+  load_table(tab, a.tab_g, P.tab_n);
+  const int M = P.M, M0 = P.M0, L = P.L, NF = a.NF, mask = P.tab_n - 1, quarter = 2 * M;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int waves_per_block = blockDim.x >> 6;
+  const int per_wave = 2 * (4 * NF + 2 * L + 1);
+  cplx* base = reinterpret_cast<cplx*>(smem + P.tab_n + (size_t)wave * per_wave);
+  cplx* z1a = base;
+  cplx* z1b = z1a + NF;
+  cplx* z2a = z1b + NF;
+  cplx* z2b = z2a + NF;
+  cplx* cb = z2b + NF;
+
+  int64_t count = a.n;
+  if (a.list) count = *a.list_count;
+  const int64_t total_waves = (int64_t)gridDim.x * waves_per_block;
+  const int64_t gw = (int64_t)blockIdx.x * waves_per_block + wave;
+  const int64_t chunk = (count + total_waves - 1) / total_waves;
+  const int64_t beg = gw * chunk, end = min(count, beg + chunk);
+
+  const int tstride = (8 * M) / NF;        // table index step of the sample grid
+  const int hstep = (4 * M) / NF;          // table index step of half a grid step
+  const double nan = __builtin_nan("");
+  const bool paper = a.variant == FFBIE_KAPPA_PAPER_CONV;
+  const bool want_c = paper || a.rhoinv != nullptr;
+  const double k = P.k;
+  const double invNF = 1.0 / NF;
+  // sin(k rho)/rho <= k is packed beside F cos(k rho) = O(1) in one transform;
+  // it is scaled by an exact power of two near 1/k so that its size does not
+  // raise the rounding floor of the other sequence's coefficients
+  const int kexp = (k > 1.0) ? (int)ceil(log2(k)) : 0;
+  const double s_down = ldexp(1.0, -kexp), s_up = ldexp(1.0, kexp);
+
+  double t_prev = nan, ts_prev = nan;
+  int j_prev = -1;
+  PairGeo<MM> pg;
+
+  for (int64_t w = beg; w < end; ++w) {
+    const int64_t pi = a.list ? a.list[w] : w;
+    const double t = a.t_in[pi], ts = a.ts_in[pi];
+    const int j = a.az_in[pi] & (2 * M - 1);
+    const RootRec rr = a.roots[pi];
+    int st = a.status[pi];
+    cplx* krow = a.kappa + pi * (int64_t)(2 * M);
+    cplx* crow = a.rhoinv ? a.rhoinv + pi * (int64_t)(L + 1) : nullptr;
+    if (st & FFBIE_PAIR_SINGULAR) {
+      for (int c = lane; c < 2 * M; c += 64) krow[c] = mk(nan, nan);
+      if (crow)
+        for (int c = lane; c <= L; c += 64) crow[c] = mk(nan, nan);
+      continue;
+    }
+    const int J = 4 * j;
+    if (!(t == t_prev && ts == ts_prev && j == j_prev)) {
+      pair_geo<MM>(P.g, t, ts, tab, J, mask, quarter, &pg);
+      t_prev = t; ts_prev = ts; j_prev = j;
+    }
+    const double u = rr.u, b = rr.b;
+    // a = theta_j + qu * (2 pi / NF) + ur,  |ur| <= pi / NF
+    const double gstep = 2.0 * M_PI / NF;
+    const double qu_d = rint(u / gstep);
+    const int qu = (int)qu_d;
+    const double ur = fma(-qu_d, gstep, u);
+    double sur, cur;
+    sincos(0.5 * ur, &sur, &cur);
+    const double eb = exp(-b), omq = -expm1(-b);
+    const int qj = j * (NF / (2 * M));
+
+    // ---- samples on the NF-point grid
+    double sumF = 0.0;
+    for (int q = lane; q < NF; q += 64) {
+      double dx, dy, dz;
+      dr_grid<MM>(pg, tab, q * tstride, J, mask, quarter, &dx, &dy, &dz);
+      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+      const double rho = sqrt(r2);
+      double skr, ckr;
+      sincos(k * rho, &skr, &ckr);
+      const int hidx = (q - qj - qu) * hstep;   // (theta_q - a)/2 = hidx pi/(4M) - ur/2
+      const double sh = fma(tsin(tab, hidx, mask), cur, -tcos(tab, hidx, mask, quarter) * sur);
+      const double s = fma(omq, omq, 4.0 * eb * sh * sh);
+      const double F = sqrt(s / r2);
+      const double S = (k == 0.0) ? 0.0 : skr / rho;
+      sumF += F;
+      if (paper) {
+        z1a[q] = mk(F, ckr);
+        z2a[q] = mk(S, 0.0);
+      } else {
+        z1a[q] = mk(F * ckr, S * s_down);
+        if (want_c) z2a[q] = mk(F, 0.0);
+      }
+    }
+    wave_sync();
+    cplx *Z1 = z1a, *free1 = z1b, *Z2 = z2a, *free2 = z2b;
+    fft_stockham(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter);
+
+    // truncation indices of the smooth factors
+    const cplx* Fsrc = paper ? Z1 : Z2;
+    const double F0 = wave_sum(sumF) * invNF;   // <F>_0 = max_j |<F>_j| since F > 0
+    const int pF = want_c ? trunc_index_real(Fsrc, NF, invNF, P.eps0, 0.0) : 0;
+    const int pH = paper ? 0 : trunc_index_real(Z1, NF, invNF, P.eps0, F0);
+    if (max(pF, pH) >= NF / 2 - 2) {
+      if (a.flag_list) {
+        // not resolved on this grid: queue for the 4M-sample pass
+        if (lane == 0) {
+          const int32_t slot = atomicAdd(a.flag_count, 1);
+          a.flag_list[slot] = pi;
+          a.status[pi] = st | FFBIE_PAIR_REFINED;
+        }
+        continue;
+      }
+      st |= FFBIE_PAIR_UNRESOLVED;
+    }
+    const int Jq = J + qu * tstride;          // table index of theta_j + qu * gstep
+
+    // ---- weighted coefficient vectors G_j = <f>_j e^{i j a}, |j| <= p
+    cplx* GF = free2;
+    cplx* GH = free1;
+    cplx* Cn = free1 + (M0 - 1);
+    const int pmax = max(pF, pH);
+    for (int jj = lane; jj <= pmax; jj += 64) {
+      double s1, c1;
+      sincos(jj * ur, &s1, &c1);
+      const cplx ph = mk(tcos(tab, jj * Jq, mask, quarter), tsin(tab, jj * Jq, mask)) * mk(c1, s1);
+      if (want_c && jj <= pF) {
+        const cplx G = real_part_coeff(Fsrc, jj, NF, invNF) * ph;
+        GF[pF + jj] = G;
+        GF[pF - jj] = conj(G);
+      }
+      if (!paper && jj <= pH) {
+        const cplx G = real_part_coeff(Z1, jj, NF, invNF) * ph;
+        GH[pH + jj] = G;
+        GH[pH - jj] = conj(G);
+      }
+    }
+    if (paper) {
+      // <cos(k rho)>_n, |n| <= M0 - 1, from the imaginary part of Z1
+      for (int n = lane; n < M0; n += 64) {
+        const cplx C = imag_part_coeff(Z1, n, NF, invNF);
+        Cn[n] = C;
+        Cn[-n] = conj(C);
+      }
+    }
+    wave_sync();
+    // ---- A_m(b)
+    double* A = reinterpret_cast<double*>(paper ? Z1 : (want_c ? Z2 : free2));
+    const int mtop = paper ? L + pF : (want_c ? max(L + pF, M + pH) : M + pH);
+    singular_factor_wave(b, rr.A0, rr.D1, mtop, A);
+
+    // ---- <rho^-1>_l, l = 0..L (eq. (3.25)) into cb[L + l] (and cb[L - l] = conj)
+    if (want_c) {
+      swap_convolution(GF, pF, A, L, ur, Jq, tab, mask, quarter, cb + L, cb + L, crow);
+      wave_sync();
+    }
+    // ---- kc_n = <cos(k rho)/rho>_n, n = 0..M
+    cplx* kc = want_c ? free2 : cb;
+    if (paper) {
+      // eq. (3.10): kc_n = sum_{|n'| < M0} C_{n'} c_{n-n'}
+      for (int n = lane; n < M; n += 64) {
+        double accr = 0.0, acci = 0.0;
+        for (int np = -(M0 - 1); np <= M0 - 1; ++np) {
+          const cplx C = Cn[np];
+          const cplx c = cb[L + n - np];
+          accr = fma(C.re, c.re, fma(-C.im, c.im, accr));
+          acci = fma(C.re, c.im, fma(C.im, c.re, acci));
+        }
+        kc[n] = mk(accr, acci);
+      }
+      double accr = 0.0, acci = 0.0;
+      for (int np = -(M0 - 1) + lane; np <= M0 - 1; np += 64) {
+        const cplx C = Cn[np];
+        const cplx c = cb[L + M - np];
+        accr = fma(C.re, c.re, fma(-C.im, c.im, accr));
+        acci = fma(C.re, c.im, fma(C.im, c.re, acci));
+      }
+      accr = wave_sum(accr);
+      acci = wave_sum(acci);
+      if (lane == 0) kc[M] = mk(accr, acci);
+    } else {
+      // swap applied to cos(k rho)/rho
+      swap_convolution(GH, pH, A, M, ur, Jq, tab, mask, quarter, kc, nullptr, nullptr);
+    }
+    wave_sync();
+    // ---- kappa_n = kc_n + i <sin(k rho)/rho>_n, n = -M+1..M at column n + M - 1
+    for (int c = lane; c < 2 * M; c += 64) {
+      const int n = c - M + 1;
+      const cplx kcn = n >= 0 ? kc[n] : conj(kc[-n]);
+      const cplx S = paper ? invNF * Z2[n & (NF - 1)] : s_up * imag_part_coeff(Z1, n, NF, invNF);
+      krow[c] = mk(kcn.re - S.im, kcn.im + S.re);
+    }
+    if (lane == 0) a.status[pi] = st;
+    wave_sync();
+  }
+}
+
+// ===========================================================================
+// Diagnostic kernel: A_m(b) for a batch of b (one wavefront per b)
+// ===========================================================================
+__global__ __launch_bounds__(256) void ffbie_singular_factor_kernel(int64_t n,
+                                                                    const double* __restrict__ b_in,
+                                                                    int mtop, double* __restrict__ out) {
+  extern __shared__ double smem[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  double* A = smem + (size_t)wave * (mtop + 1);
+  const int64_t idx = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (idx >= n) return;
+  const double b = b_in[idx];
+  double K = 0, E = 0, A0 = __builtin_nan(""), D1 = __builtin_nan("");
+  if (b > 0) {
+    ellip_KE(exp(-2.0 * b), sqrt(-expm1(-2.0 * b)), &K, &E);
+    A0 = M_2_PI * K;
+    D1 = M_2_PI * (expm1(b) * K - exp(b) * E);
+  }
+  singular_factor_wave(b, A0, D1, mtop, A);
+  for (int m = lane; m <= mtop; m += 64) out[idx * (mtop + 1) + m] = A[m];
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers (one instantiation per bound on the surface's azimuthal order)
+// ---------------------------------------------------------------------------
+#define FFBIE_FOR_MM(X) X(0) X(1) X(2) X(4) X(8)
+
+int mm_bucket(int mmax) { return mmax <= 0 ? 0 : mmax <= 1 ? 1 : mmax <= 2 ? 2 : mmax <= 4 ? 4 : 8; }
+
+hipError_t launch_root(const Prob& P, const double* tab, int64_t n, const double* t,
+                       const int32_t* az, const double* ts, RootRec* out, int32_t* status,
+                       double* root_out, hipStream_t stream) {
+  const int threads = 256;
+  const int64_t blocks = (n + threads - 1) / threads;
+  const size_t lds = P.tab_n * sizeof(double);
+  switch (mm_bucket(P.g.mmax)) {
+#define X(MMV)                                                                                   \
+  case MMV:                                                                                      \
+    hipLaunchKernelGGL(ffbie_root_kernel_t<MMV>, dim3((unsigned)blocks), dim3(threads), lds,    \
+                       stream, P, tab, n, t, az, ts, out, status, root_out);                     \
+    break;
+    FFBIE_FOR_MM(X)
+#undef X
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t lds,
+                        hipStream_t stream) {
+  switch (mm_bucket(a.P.g.mmax)) {
+#define X(MMV)                                                                                   \
+  case MMV:                                                                                      \
+    hipLaunchKernelGGL(ffbie_coeff_kernel_t<MMV>, dim3((unsigned)blocks), dim3(64 * waves), lds, \
+                       stream, a);                                                               \
+    break;
+    FFBIE_FOR_MM(X)
+#undef X
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ffbie

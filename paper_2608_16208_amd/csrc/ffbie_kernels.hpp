@@ -1,0 +1,40 @@
+// Records shared by the host launch code and the coefficient kernels.
+#pragma once
+#include "ffbie_device.hpp"
+
+namespace ffbie {
+
+// Per-pair output of the root kernel: offset u = a - theta_j of the complex
+// root theta_+ = a + ib of rho^2, its imaginary part b, A_0(b) and A_1 - A_0.
+struct RootRec {
+  double u, b, A0, D1;
+};
+
+struct CoeffArgs {
+  Prob P;
+  const double* tab_g;
+  int64_t n;                 // pairs (ignored when `list` is set)
+  const double* t_in;
+  const int32_t* az_in;
+  const double* ts_in;
+  const RootRec* roots;
+  int32_t* status;
+  cplx* kappa;               // [n][2M]
+  cplx* rhoinv;              // [n][L+1] or null
+  int NF;                    // azimuthal samples: 2M (main pass) or 4M (refine pass)
+  const int64_t* list;       // refine pass: pair indices
+  const int32_t* list_count; // refine pass: number of indices
+  int64_t* flag_list;        // main pass: pairs queued for the refine pass
+  int32_t* flag_count;
+  int variant;               // FFBIE_KAPPA_SWAP or FFBIE_KAPPA_PAPER_CONV
+};
+
+hipError_t launch_root(const Prob& P, const double* tab, int64_t n, const double* t,
+                       const int32_t* az, const double* ts, RootRec* out, int32_t* status,
+                       double* root_out, hipStream_t stream);
+hipError_t launch_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t lds,
+                        hipStream_t stream);
+__global__ void ffbie_singular_factor_kernel(int64_t n, const double* __restrict__ b_in, int mtop,
+                                             double* __restrict__ out);
+
+}  // namespace ffbie

@@ -1,0 +1,177 @@
+"""GPU parity of the singularity-swapping coefficient kernels against the oracle.
+
+Tolerance: per-pair relative 2-norm error <= 1e-10 for <e^{ik rho}/rho>_n and
+<rho^-1>_l (FP64 path).  The values observed are reported in the assertion
+messages.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import coeffs as ocoeffs
+from oracle import special as ospecial
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2608_16208_amd as ffbie
+    c = ffbie.Context(0)
+    yield c
+    c.close()
+
+
+def _run(ctx, cfg, t, j, ts, variant=0, **kw):
+    ctx.set_problem(cfg["amp"], cfg["n_panels"], cfg["M"], cfg["k"], variant=variant)
+    dev = ctx.device
+    out = ctx.kernel_coeffs(torch.tensor(t, device=dev), torch.tensor(j, device=dev),
+                            torch.tensor(ts, device=dev), rhoinv=True, root=True, **kw)
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+
+
+def _compare(cfg, t, j, ts, out, n_check=None, processes=8):
+    M = cfg["M"]
+    L = 2 * M
+    idx = np.arange(len(t)) if n_check is None else np.linspace(0, len(t) - 1, n_check).astype(int)
+    c_o, k_o, info = ocoeffs.pairs_coeffs(cfg["amp"], cfg["k"], M, L, t[idx], j[idx], ts[idx],
+                                          processes=processes)
+    ek = np.linalg.norm(out["kappa"][idx] - k_o, axis=1) / np.linalg.norm(k_o, axis=1)
+    ec = np.linalg.norm(out["rhoinv"][idx] - c_o, axis=1) / np.linalg.norm(c_o, axis=1)
+    assert all(i["converged"] for i in info)
+    return ek, ec, idx
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("cfgi", [1, 2, 3])
+def test_coeffs_match_oracle_sampled_pairs(ctx, cfgi, variant):
+    cfg = workloads.config(cfgi)
+    t, j, ts = workloads.sample_pairs(cfg["n_panels"], cfg["M"], 160, seed=100 + cfgi)
+    out = _run(ctx, cfg, t, j, ts, variant=variant)
+    ek, ec, _ = _compare(cfg, t, j, ts, out)
+    bad = out["status"] & 8
+    assert not bad.any(), "unresolved smooth factor"
+    assert ek.max() <= TOL and ec.max() <= TOL, (ek.max(), ec.max())
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_coeffs_config2_all_pairs_full_size_sampled(ctx, variant):
+    """The benchmarked launch: every (target node, azimuth, source node) pair of
+    config 2 (8,355,840 pairs, M = 64); rows sampled uniformly are checked."""
+    cfg = workloads.config(2)
+    t, j, ts = workloads.all_pairs(cfg["n_panels"], cfg["M"])
+    ctx.set_problem(cfg["amp"], cfg["n_panels"], cfg["M"], cfg["k"], variant=variant)
+    dev = ctx.device
+    tt, jj, tss = (torch.tensor(v, device=dev) for v in (t, j, ts))
+    out = ctx.kernel_coeffs(tt, jj, tss, rhoinv=False, root=False)
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    assert not (st & 1).any() and not (st & 8).any(), ((st & 8) > 0).sum()
+    rng = np.random.default_rng(5)
+    # uniform sample plus every pair that needed the 4M-sample pass or the root fallback
+    idx = np.sort(rng.choice(t.size, 40, replace=False))
+    special = np.where(st & 6)[0]
+    idx = np.unique(np.concatenate([idx, special[:: max(1, len(special) // 24)]]))
+    kap = out["kappa"][torch.tensor(idx, device=dev)].cpu().numpy()
+    _, k_o, _ = ocoeffs.pairs_coeffs(cfg["amp"], cfg["k"], cfg["M"], 2 * cfg["M"], t[idx], j[idx],
+                                     ts[idx], processes=8)
+    ek = np.linalg.norm(kap - k_o, axis=1) / np.linalg.norm(k_o, axis=1)
+    assert np.isfinite(out["kappa"].abs().sum().item())
+    assert ek.max() <= TOL, ek.max()
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_refine_pass_near_pole(ctx, variant):
+    """Pairs whose smooth factor needs more than 2M samples (next to the pole of
+    the config-2 surface) are recomputed with 4M samples and still match."""
+    cfg = workloads.config(2)
+    t = np.array([0.1723, 3.0527, 0.9, 0.1723])
+    ts = np.array([0.2204, 3.0341, 0.9 + 1e-5, 0.2204])
+    j = np.array([95, 32, 3, 94], dtype=np.int32)
+    out = _run(ctx, cfg, t, j, ts, variant=variant)
+    assert (out["status"][:2] & 4).all(), out["status"]
+    ek, ec, _ = _compare(cfg, t, j, ts, out)
+    assert ek.max() <= TOL and ec.max() <= TOL, (ek, ec)
+
+
+def test_far_pairs_opposite_poles(ctx):
+    """Targets and sources near opposite poles (b of order 10-160): the Miller
+    recurrence must stay in range and the rows must match."""
+    for cfgi in (1, 2):
+        cfg = workloads.config(cfgi)
+        t = np.array([0.07502982395917475, 0.0026, 3.139, 0.001, 0.0010405607739110423])
+        ts = np.array([3.1395115320419706, 3.139, 0.0026, 3.14, 0.6265635345276735])
+        j = np.array([20, 0, 7, 63, 32], dtype=np.int32)
+        out = _run(ctx, cfg, t, j, ts)
+        assert np.isfinite(out["kappa"]).all() and np.isfinite(out["rhoinv"]).all()
+        ek, ec, _ = _compare(cfg, t, j, ts, out, processes=1)
+        assert ek.max() <= TOL and ec.max() <= TOL, (cfgi, ek, ec)
+
+
+def test_root_is_a_zero_of_rho2(ctx):
+    """The complex root used for the swap satisfies rho^2(theta_j + u + ib) = 0
+    (evaluated independently in 30-digit complex arithmetic)."""
+    import mpmath as mp
+    mp.mp.dps = 30
+    cfg = workloads.config(2)
+    t, j, ts = workloads.sample_pairs(cfg["n_panels"], cfg["M"], 40, seed=9)
+    out = _run(ctx, cfg, t, j, ts)
+    a = cfg["amp"]
+    M = cfg["M"]
+
+    def r_mp(tt, th):
+        R = 1 + mp.mpf(a[2, 2]) * mp.sin(3 * tt) * mp.cos(2 * th)
+        return [R * mp.sin(tt) * mp.cos(th), R * mp.sin(tt) * mp.sin(th), R * mp.cos(tt)]
+
+    checked = 0
+    for i in range(len(t)):
+        if out["status"][i] & (2 | 16):     # root fallback / far-pair model: not a Newton root
+            continue
+        u, b = out["root"][i]
+        th = mp.pi * int(j[i]) / M
+        p0 = r_mp(mp.mpf(t[i]), th)
+        z = th + mp.mpf(u) + 1j * mp.mpf(b)
+        f = lambda zz: sum((x - y) ** 2 for x, y in zip(r_mp(mp.mpf(ts[i]), zz), p0))
+        fz, fp = f(z), mp.diff(f, z)
+        # Newton correction relative to b
+        assert abs(fz / fp) <= 1e-13 * b, (i, float(abs(fz / fp)), b)
+        assert b > 0
+        checked += 1
+    assert checked >= 25
+
+
+def test_singular_pair_and_empty(ctx):
+    cfg = workloads.config(2)
+    t = np.array([0.7, 0.7])
+    ts = np.array([0.7, 0.8])
+    j = np.array([3, 3], dtype=np.int32)
+    out = _run(ctx, cfg, t, j, ts)
+    assert out["status"][0] & 1 and np.isnan(out["kappa"][0]).all()
+    assert not (out["status"][1] & 1) and np.isfinite(out["kappa"][1]).all()
+    e = ctx.kernel_coeffs(torch.empty(0, dtype=torch.float64), torch.empty(0, dtype=torch.int32),
+                          torch.empty(0, dtype=torch.float64))
+    assert e["kappa"].shape == (0, 2 * cfg["M"])
+
+
+def test_deterministic(ctx):
+    cfg = workloads.config(3)
+    t, j, ts = workloads.sample_pairs(cfg["n_panels"], cfg["M"], 300, seed=3)
+    o1 = _run(ctx, cfg, t, j, ts)
+    o2 = _run(ctx, cfg, t, j, ts)
+    assert np.array_equal(o1["kappa"], o2["kappa"], equal_nan=True)
+
+
+def test_singular_factor_matches_oracle(ctx):
+    bs = np.array([1e-9, 1e-6, 1e-4, 3e-3, 0.02, 0.05, 0.1, 0.3, 1.0, 2.5, 7.0, 40.0])
+    m_max = 200
+    A = ctx.singular_factor(torch.tensor(bs, device=ctx.device), m_max).cpu().numpy()
+    for i, b in enumerate(bs):
+        ref = ospecial.singular_factor(b, m_max)
+        err = np.max(np.abs(A[i] - ref)) / ref[0]
+        assert err <= 1e-13, (b, err)
