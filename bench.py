@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark of the azimuthal kernel-coefficient path on one MI355X.
+
+One step = one ffbie_kernel_coeffs call over the whole workload: the root
+kernel, the main coefficient pass and the 4M-sample refine pass (geometry,
+pair sampling, root, smooth factor, singular factor A_m(b), convolutions and
+the coefficient-table write).  Workload: the star surface
+R = 1 + 0.2 sin(3t) cos(2 theta), k = 5, 16 panels x 16 Gauss-Legendre nodes
+(256 curve nodes), M = 64 (128 azimuths), every (target node, target
+azimuth, source node) pair with t_s != t: 8,355,840 pairs, 2M = 128
+coefficients each.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line (rank 0); see the design doc for the roofline accounting.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "kernel coeff pair-modes/s + time-to-1e-8 field error, mixed vs plain FP64 GPU"
+PEAK_FP64_VALU = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+COEFF_KERNEL = "ffbie_coeff_kernel"
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "coeff_kernel_config2_allpairs_hbm_traffic.md")
+
+
+def algorithmic_flops_per_pair(NF, M, M0, p, m0, newton_iters=6.0, miller_extra=100.0):
+    """Flops one pair needs by the method of Sec. 3.3 with eq. (3.10): sampling,
+    three real FFTs, Newton, Miller, both convolutions at the cheaper of direct
+    and zero-padded-FFT cost (FMA = 2 flops, complex multiply = 6, a complex
+    FFT of size N = 5 N log2 N, real = half)."""
+    L = M + M0
+    lg = math.log2(NF)
+    w = 8 * NF + 12 * NF + 3 * 2.5 * NF * lg
+    w += 16 * newton_iters * (2 * m0 + 1)
+    w += 6 * (L + p + miller_extra)
+    n1 = 2 ** math.ceil(math.log2(L + 1 + 2 * p))
+    w += min(4 * (2 * p + 1) * (L + 1), 15 * n1 * math.log2(n1) + 6 * n1) + 6 * (L + 1)
+    n2 = 2 ** math.ceil(math.log2(2 * M0 + 2 * L + 1))
+    w += min(8 * (2 * M0) * (2 * M), 15 * n2 * math.log2(n2) + 6 * n2)
+    w += 5 * NF
+    return w
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in ("ffbie_kernels.hip", "ffbie_device.hpp", "ffbie_kernels.hpp", "ffbie_root.hpp"):
+        with open(os.path.join(ROOT, "paper_2608_16208_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(variant):
+    """HBM bytes per launch of the main coefficient pass from the committed
+    rocprofv3 counter summary, if it was taken from the current kernel source."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    txt = open(TRAFFIC_SUMMARY).read()
+    m = re.search(r"source_digest:\s*(\w+)", txt)
+    if not m or m.group(1) != kernel_source_digest():
+        return None
+    m = re.search(rf"variant{variant}_hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    return float(m.group(1)) if m else None
+
+
+def cpu_baseline(cfg, n_sample, processes):
+    """The oracle (direct quadrature of the coefficients) on a seeded sample of
+    the same workload, timed on the host cores; pair-modes/s."""
+    import numpy as np
+    import workloads
+    from oracle import coeffs as ocoeffs
+    t, j, ts = workloads.all_pairs(cfg["n_panels"], cfg["M"])
+    rng = np.random.default_rng(12345)
+    sel = np.sort(rng.choice(t.size, n_sample, replace=False))
+    t0 = time.perf_counter()
+    ocoeffs.pairs_coeffs(cfg["amp"], cfg["k"], cfg["M"], 2 * cfg["M"], t[sel], j[sel], ts[sel],
+                         processes=processes)
+    dt = time.perf_counter() - t0
+    return dict(value=n_sample * 2 * cfg["M"] / dt, unit="pair-modes/s", cores=processes,
+                kind="oracle",
+                sample=f"{n_sample} seeded pairs of the same all-pairs workload, "
+                       f"{dt:.1f} s wall on {processes} processes")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--variant", type=int, default=0, help="0: swap of cos(k rho)/rho, 1: eq. (3.10)")
+    ap.add_argument("--cpu-sample", type=int, default=6144)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-second-variant", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 2 GiB device copy (reference dispatch for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads
+    import paper_2608_16208_amd as ffbie
+
+    if args.copy_calibration:
+        a = torch.ones(256 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
+
+    cfg = workloads.config(2)
+    M, M0 = cfg["M"], cfg["M"]
+    t, j, ts = workloads.all_pairs(cfg["n_panels"], M)
+    n = t.size
+    dev = torch.device("cuda", 0)
+    tt = torch.tensor(t, device=dev)
+    jj = torch.tensor(j, device=dev)
+    tss = torch.tensor(ts, device=dev)
+    kappa = torch.empty((n, 2 * M), dtype=torch.complex128, device=dev)
+    status = torch.empty((n,), dtype=torch.int32, device=dev)
+    ctx = ffbie.Context(0)
+
+    def run_variant(variant, steps, warmup):
+        ctx.set_problem(cfg["amp"], cfg["n_panels"], M, cfg["k"], M0=M0, variant=variant)
+        ctx.enable_timing(True)
+        for _ in range(warmup):
+            ctx.kernel_coeffs(tt, jj, tss, kappa=kappa, status=True)
+        torch.cuda.synchronize()
+        per = []
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            out = ctx.kernel_coeffs(tt, jj, tss, kappa=kappa, status=True)
+            per.append(ctx.timing())
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        ms = e0.elapsed_time(e1)
+        st = out["status"].cpu().numpy()
+        return ms, wall, np.array(per), st
+
+    ms, wall, per, st = run_variant(args.variant, args.steps, args.warmup)
+    ms_step = ms / args.steps
+    value = n * 2 * M * args.steps / (ms * 1e-3)
+    p = (st >> ffbie.P_SHIFT) & 0xFFF
+    ok = (st & (ffbie.PAIR_SINGULAR | ffbie.PAIR_UNRESOLVED)) == 0
+    p_mean = float(p[ok].mean())
+    NF = 2 * M
+    m0 = 2 * max(1, cfg["amp"].shape[1] - 1)      # highest Fourier mode of rho^2
+    w_pair = algorithmic_flops_per_pair(NF, M, M0, p_mean, m0)
+    main_ms = float(per[:, 1].mean())
+    achieved = w_pair * n / (main_ms * 1e-3)
+    traffic = measured_traffic(args.variant)
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair-modes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "star surface R=1+0.2 sin(3t) cos(2 theta), k=5, 16 panels x 16 GL nodes, "
+                        "M=64 (128 azimuths), all 8,355,840 (target node, azimuth, source node) "
+                        "pairs; kernel coefficients <e^{ik rho}/rho>_n, n=-63..64",
+            "pairs": int(n),
+            "pair_modes_per_step": int(n * 2 * M),
+            "kappa_variant": "swap of cos(k rho)/rho" if args.variant == 0 else "eq. (3.10)",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP64_VALU / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_VALU,
+            "traffic": traffic,
+            "kernel": COEFF_KERNEL + " (main pass)",
+            "flops_per_pair": w_pair,
+            "p_mean": p_mean,
+        },
+        "kernels_ms": {"root": float(per[:, 0].mean()), "coeff_main": main_ms,
+                       "coeff_refine": float(per[:, 2].mean())},
+        "pair_status": {"root_fallback": int(((st & ffbie.PAIR_ROOT_FALLBACK) > 0).sum()),
+                        "far_model": int(((st & ffbie.PAIR_FAR) > 0).sum()),
+                        "refined": int(((st & ffbie.PAIR_REFINED) > 0).sum()),
+                        "unresolved": int(((st & ffbie.PAIR_UNRESOLVED) > 0).sum())},
+        "time_to_1e-8_field_error": None,
+        "wall_s_timed": wall,
+    }
+    if not args.no_second_variant:
+        other = 1 - args.variant
+        ms2, _, per2, _ = run_variant(other, max(1, args.steps // 2), 1)
+        result["value_other_variant"] = {
+            "kappa_variant": "eq. (3.10)" if other == 1 else "swap of cos(k rho)/rho",
+            "value": n * 2 * M * max(1, args.steps // 2) / (ms2 * 1e-3),
+            "coeff_main_ms": float(per2[:, 1].mean())}
+    del kappa
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        procs = min(16, os.cpu_count() or 1)
+        result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample, procs)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -51,6 +51,9 @@ enum {
   FFBIE_PAIR_FAR = 16             /* b0 >= 3: the quadratic-model estimate (a0, b0), not a
                                      Newton-refined root, parametrises the swap             */
 };
+/* Bits 8..19 of a pair's status word hold the truncation index p (eq. (3.24))
+ * of the smooth factor used for its kernel coefficients: (status >> 8) & 0xfff. */
+#define FFBIE_PAIR_P_SHIFT 8
 
 /* How the kernel coefficients <e^{ik rho}/rho>_n are formed from the swap. */
 enum {
@@ -134,6 +137,16 @@ ffbie_status ffbie_kernel_coeffs(ffbie_ctx *ctx, int64_t n_pairs,
                                  const double *d_src_t,
                                  void *d_kappa, void *d_rhoinv, double *d_root,
                                  int32_t *d_pair_status);
+
+/* Device-side timing of the kernels ffbie_kernel_coeffs launches.  With
+ * timing enabled, HIP events are recorded on the context's stream around the
+ * root kernel, the main coefficient pass and the refine pass of every call;
+ * ffbie_get_timing waits for the last call's events and returns the three
+ * durations in milliseconds (any pointer may be NULL).  FFBIE_EINVAL if timing
+ * is disabled or no call has been timed. */
+ffbie_status ffbie_enable_timing(ffbie_ctx *ctx, int on);
+ffbie_status ffbie_get_timing(ffbie_ctx *ctx, double *ms_root, double *ms_main,
+                              double *ms_refine);
 
 /* Singular-factor coefficients A_m(b) = <s_{0,b}^{-1/2}>_m of eq. (3.26) for
  * m = 0..m_max and n values of b > 0 (d_b, float64 [n]), written to

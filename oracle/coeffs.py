@@ -129,6 +129,15 @@ def pair_coeffs(amp, k, M, L, t, j_az, ts, rtol=1e-14):
     return c, kap, dict(a=u, beta=beta, diff=float(diff), converged=bool(diff <= rtol))
 
 
+def _one_thread():
+    """Worker initializer: one BLAS thread per process (no oversubscription)."""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
 def pairs_coeffs(amp, k, M, L, t, j_az, ts, processes=None):
     """``pair_coeffs`` over arrays of pairs; optional multiprocessing pool.
 
@@ -141,7 +150,7 @@ def pairs_coeffs(amp, k, M, L, t, j_az, ts, processes=None):
     if processes and processes > 1 and len(args) > 1:
         import multiprocessing as mp
         ctx = mp.get_context("fork")
-        with ctx.Pool(processes) as pool:
+        with ctx.Pool(processes, initializer=_one_thread) as pool:
             out = pool.starmap(pair_coeffs, args, chunksize=max(1, len(args) // (4 * processes)))
     else:
         out = [pair_coeffs(*a) for a in args]

@@ -18,7 +18,8 @@ PAIR_SINGULAR, PAIR_ROOT_FALLBACK, PAIR_REFINED, PAIR_UNRESOLVED, PAIR_FAR = 1, 
 KAPPA_SWAP, KAPPA_PAPER_CONV = 0, 1
 
 EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_problem",
-           "ffbie_kernel_coeffs", "ffbie_singular_factor")
+           "ffbie_kernel_coeffs", "ffbie_singular_factor", "ffbie_enable_timing", "ffbie_get_timing")
+P_SHIFT = 8
 
 
 class FfbieError(RuntimeError):
@@ -53,6 +54,9 @@ def load_library(path=LIB_PATH):
     lib.ffbie_set_problem.argtypes = [vp, ctypes.POINTER(_Geometry), ctypes.POINTER(_Disc), ctypes.c_double]
     lib.ffbie_kernel_coeffs.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     lib.ffbie_singular_factor.argtypes = [vp, i64, vp, i32, vp]
+    lib.ffbie_enable_timing.argtypes = [vp, i32]
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.ffbie_get_timing.argtypes = [vp, dp, dp, dp]
     for name in EXPORTS:
         f = getattr(lib, name)
         if name != "ffbie_last_error":
@@ -129,6 +133,15 @@ class Context:
                                           _ptr(out["rhoinv"]), _ptr(out["root"]), _ptr(out["status"]))
         self._check(rc, self.h)
         return out
+
+    def enable_timing(self, on=True):
+        self._check(self.lib.ffbie_enable_timing(self.h, int(bool(on))), self.h)
+
+    def timing(self):
+        """(ms_root, ms_main, ms_refine) of the last kernel_coeffs call (HIP events)."""
+        v = [ctypes.c_double() for _ in range(3)]
+        self._check(self.lib.ffbie_get_timing(self.h, *(ctypes.byref(x) for x in v)), self.h)
+        return tuple(x.value for x in v)
 
     def singular_factor(self, b, m_max):
         torch = self._torch

@@ -30,6 +30,10 @@ struct ffbie_ctx {
   int64_t* d_list = nullptr;
   int32_t* d_count = nullptr;
   int64_t ws_pairs = 0;
+  // optional event timing of the three launches
+  bool timing = false;
+  bool timed = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -116,6 +120,8 @@ ffbie_status ffbie_create(ffbie_ctx** out, int device, void* hip_stream) {
 ffbie_status ffbie_destroy(ffbie_ctx* c) {
   if (!c) return FFBIE_OK;
   hipSetDevice(c->device);
+  for (auto& e : c->ev)
+    if (e) hipEventDestroy(e);
   if (c->d_tab) hipFree(c->d_tab);
   if (c->d_roots) hipFree(c->d_roots);
   if (c->d_status) hipFree(c->d_status);
@@ -184,6 +190,7 @@ ffbie_status ffbie_kernel_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, con
   const Prob& P = c->prob;
   int32_t* status = d_pair_status ? d_pair_status : c->d_status;
 
+  if (c->timing) FFBIE_HIP(c, hipEventRecord(c->ev[0], c->stream));
   // kernel 1: roots, one lane per pair
   FFBIE_HIP(c, launch_root(P, c->d_tab, n, d_t, d_az, d_ts, c->d_roots, status, d_root, c->stream));
   FFBIE_HIP(c, hipMemsetAsync(c->d_count, 0, sizeof(int32_t), c->stream));
@@ -209,7 +216,9 @@ ffbie_status ffbie_kernel_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, con
     const int64_t pairs_per_wave = 16;
     int64_t blocks = (n + w * pairs_per_wave - 1) / (w * pairs_per_wave);
     if (blocks < 1) blocks = 1;
+    if (c->timing) FFBIE_HIP(c, hipEventRecord(c->ev[1], c->stream));
     FFBIE_HIP(c, launch_coeff(a, blocks, w, lds, c->stream));
+    if (c->timing) FFBIE_HIP(c, hipEventRecord(c->ev[2], c->stream));
   }
   {
     a.NF = 4 * P.M;
@@ -220,7 +229,31 @@ ffbie_status ffbie_kernel_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, con
     size_t lds;
     const int w = coeff_waves(P, a.NF, &lds);
     FFBIE_HIP(c, launch_coeff(a, 512, w, lds, c->stream));
+    if (c->timing) FFBIE_HIP(c, hipEventRecord(c->ev[3], c->stream));
   }
+  if (c->timing) c->timed = true;
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_enable_timing(ffbie_ctx* c, int on) {
+  if (!c) return FFBIE_EINVAL;
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  if (on && !c->ev[0])
+    for (auto& e : c->ev) FFBIE_HIP(c, hipEventCreate(&e));
+  c->timing = on != 0;
+  c->timed = false;
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_get_timing(ffbie_ctx* c, double* ms_root, double* ms_main, double* ms_refine) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->timing || !c->timed) return fail(c, FFBIE_EINVAL, "ffbie_get_timing: no timed call");
+  FFBIE_HIP(c, hipEventSynchronize(c->ev[3]));
+  float t[3];
+  for (int i = 0; i < 3; ++i) FFBIE_HIP(c, hipEventElapsedTime(&t[i], c->ev[i], c->ev[i + 1]));
+  if (ms_root) *ms_root = t[0];
+  if (ms_main) *ms_main = t[1];
+  if (ms_refine) *ms_refine = t[2];
   return FFBIE_OK;
 }
 

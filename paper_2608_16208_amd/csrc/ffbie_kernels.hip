@@ -357,7 +357,7 @@ __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
     const double t = a.t_in[pi], ts = a.ts_in[pi];
     const int j = a.az_in[pi] & (2 * M - 1);
     const RootRec rr = a.roots[pi];
-    int st = a.status[pi];
+    int st = a.status[pi] & ((1 << FFBIE_PAIR_P_SHIFT) - 1);
     cplx* krow = a.kappa + pi * (int64_t)(2 * M);
     cplx* crow = a.rhoinv ? a.rhoinv + pi * (int64_t)(L + 1) : nullptr;
     if (st & FFBIE_PAIR_SINGULAR) {
@@ -503,7 +503,7 @@ __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
       const cplx S = paper ? invNF * Z2[n & (NF - 1)] : s_up * imag_part_coeff(Z1, n, NF, invNF);
       krow[c] = mk(kcn.re - S.im, kcn.im + S.re);
     }
-    if (lane == 0) a.status[pi] = st;
+    if (lane == 0) a.status[pi] = st | (min(paper ? pF : pH, 0xfff) << FFBIE_PAIR_P_SHIFT);
     wave_sync();
   }
 }
