@@ -90,8 +90,8 @@ ffbie_status ensure_ws(ffbie_ctx* c, int64_t n) {
 }
 
 // waves per workgroup so that the coefficient kernel fits 64 KiB of LDS
-int coeff_waves(const Prob& P, int NF, size_t* lds_bytes) {
-  const size_t per_wave = sizeof(double) * 2 * (4 * (size_t)NF + 2 * P.L + 1);
+int coeff_waves(const Prob& P, int NF, bool compact, size_t* lds_bytes) {
+  const size_t per_wave = sizeof(double) * coeff_lds_per_wave(NF, P.M, P.L, compact);
   const size_t tab = sizeof(double) * P.tab_n;
   int w = 4;
   while (w > 1 && tab + w * per_wave > 65536) --w;
@@ -207,17 +207,18 @@ ffbie_status ffbie_kernel_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, con
   a.kappa = static_cast<cplx*>(d_kappa);
   a.rhoinv = static_cast<cplx*>(d_rhoinv);
   a.variant = c->variant;
+  const bool compact = c->variant == FFBIE_KAPPA_SWAP && d_rhoinv == nullptr;
   {
     a.NF = 2 * P.M;
     a.flag_list = c->d_list;
     a.flag_count = c->d_count;
     size_t lds;
-    const int w = coeff_waves(P, a.NF, &lds);
+    const int w = coeff_waves(P, a.NF, compact, &lds);
     const int64_t pairs_per_wave = 16;
     int64_t blocks = (n + w * pairs_per_wave - 1) / (w * pairs_per_wave);
     if (blocks < 1) blocks = 1;
     if (c->timing) FFBIE_HIP(c, hipEventRecord(c->ev[1], c->stream));
-    FFBIE_HIP(c, launch_coeff(a, blocks, w, lds, c->stream));
+    FFBIE_HIP(c, launch_coeff(a, blocks, w, lds, c->stream, false));
     if (c->timing) FFBIE_HIP(c, hipEventRecord(c->ev[2], c->stream));
   }
   {
@@ -227,8 +228,8 @@ ffbie_status ffbie_kernel_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, con
     a.flag_list = nullptr;
     a.flag_count = nullptr;
     size_t lds;
-    const int w = coeff_waves(P, a.NF, &lds);
-    FFBIE_HIP(c, launch_coeff(a, 512, w, lds, c->stream));
+    const int w = coeff_waves(P, a.NF, compact, &lds);
+    FFBIE_HIP(c, launch_coeff(a, 512, w, lds, c->stream, true));
     if (c->timing) FFBIE_HIP(c, hipEventRecord(c->ev[3], c->stream));
   }
   if (c->timing) c->timed = true;

@@ -65,10 +65,48 @@ FFBIE_HD __forceinline__ cplx cdiv(cplx a, cplx b) {
   double r = b.re / b.im, d = b.re * r + b.im;
   return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
 }
+// sin and cos of a real argument with |x| <= 2^19 pi (all arguments on this
+// path are bounded: k rho, multiples of grid offsets, curve parameters).
+// Cody-Waite reduction x = q pi/2 + r, with pi/2 split into three parts of which
+// the first two have 33 significant bits (q * part is exact for |q| < 2^20),
+// then the Taylor series of sin (to r^17) and cos (to r^16) on |r| <= pi/4,
+// whose truncation errors are below 1e-19 and 3e-18.  The split and the
+// coefficients 1/n! were evaluated in 50-digit arithmetic.
+FFBIE_HD __forceinline__ void sincos_bounded(double x, double* s, double* c) {
+  const double qf = rint(x * 0.6366197723675814);           // x * 2/pi
+  double r = fma(-qf, 1.5707963267341256, x);
+  r = fma(-qf, 6.077100506303966e-11, r);
+  r = fma(-qf, 2.0222662487959506e-21, r);
+  const double r2 = r * r;
+  double ps = 2.8114572543455206e-15;                         // 1/17!
+  ps = fma(ps, r2, -7.647163731819816e-13);                  // -1/15!
+  ps = fma(ps, r2, 1.6059043836821613e-10);                  //  1/13!
+  ps = fma(ps, r2, -2.505210838544172e-08);                  // -1/11!
+  ps = fma(ps, r2, 2.7557319223985893e-06);                  //  1/9!
+  ps = fma(ps, r2, -0.0001984126984126984);                  // -1/7!
+  ps = fma(ps, r2, 0.008333333333333333);                    //  1/5!
+  ps = fma(ps, r2, -0.16666666666666666);                    // -1/3!
+  const double sr = fma(ps * r2, r, r);
+  double pc = 4.779477332387385e-14;                          // 1/16!
+  pc = fma(pc, r2, -1.1470745597729725e-11);                 // -1/14!
+  pc = fma(pc, r2, 2.08767569878681e-09);                    //  1/12!
+  pc = fma(pc, r2, -2.755731922398589e-07);                  // -1/10!
+  pc = fma(pc, r2, 2.48015873015873e-05);                    //  1/8!
+  pc = fma(pc, r2, -0.001388888888888889);                   // -1/6!
+  pc = fma(pc, r2, 0.041666666666666664);                    //  1/4!
+  pc = fma(pc, r2, -0.5);                                    // -1/2!
+  const double cr = fma(pc, r2, 1.0);
+  const int q = static_cast<int>(static_cast<long long>(qf) & 3);
+  const double ss = (q & 1) ? cr : sr;
+  const double cc = (q & 1) ? sr : cr;
+  *s = (q & 2) ? -ss : ss;
+  *c = ((q + 1) & 2) ? -cc : cc;
+}
+
 // sin and cos of a complex argument x + iy
 FFBIE_HD __forceinline__ void csincos(cplx z, cplx* s, cplx* c) {
   double sx, cx;
-  sincos(z.re, &sx, &cx);
+  sincos_bounded(z.re, &sx, &cx);
   // sinh via expm1 keeps full relative accuracy for small |Im z|
   const double em = expm1(z.im), emm = expm1(-z.im);
   const double sh = 0.5 * (em - emm);
@@ -102,14 +140,24 @@ struct PairGeo {
   double al[MM + 1], be[MM + 1], ga[MM + 1];
 };
 
+// R(t, theta_j) = 1 + sum_m ga_m cos(m theta_j), theta_j at table index J.
+template <int MM>
+FFBIE_HD __forceinline__ void pair_geo_R(const double* tab, int J, int mask, int quarter,
+                                         PairGeo<MM>* p) {
+  double R = 1.0;
+#pragma unroll
+  for (int m = 0; m <= MM; ++m) R = fma(p->ga[m], tab[(m * J + quarter) & mask], R);
+  p->R = R;
+}
+
 template <int MM>
 FFBIE_HD __forceinline__ void pair_geo(const Geom& g, double t, double ts, const double* tab,
                                          int J, int mask, int quarter, PairGeo<MM>* p) {
   double st, ct, sts, cts, shd, chd, shs, chs;
-  sincos(t, &st, &ct);
-  sincos(ts, &sts, &cts);
-  sincos(0.5 * (ts - t), &shd, &chd);
-  sincos(0.5 * (ts + t), &shs, &chs);
+  sincos_bounded(t, &st, &ct);
+  sincos_bounded(ts, &sts, &cts);
+  sincos_bounded(0.5 * (ts - t), &shd, &chd);
+  sincos_bounded(0.5 * (ts + t), &shs, &chs);
   p->st = st; p->sts = sts; p->cts = cts;
   p->S1 = 2.0 * chs * shd;
   p->C1 = -2.0 * shs * shd;
@@ -132,31 +180,42 @@ FFBIE_HD __forceinline__ void pair_geo(const Geom& g, double t, double ts, const
     double nd = 2.0 * chd * sd1 - sd0;   sd0 = sd1;   sd1 = nd;
     double nc = 2.0 * chs * cs1 - cs0;   cs0 = cs1;   cs1 = nc;
   }
-  double R = 1.0;
-#pragma unroll
-  for (int m = 0; m <= MM; ++m) R = fma(p->ga[m], tab[(m * J + quarter) & mask], R);
-  p->R = R;
+  pair_geo_R<MM>(tab, J, mask, quarter, p);
 }
 
 // Delta r = r(t_s, theta_q) - r(t, theta_j) for a source azimuth on the table
 // grid: Kq = table index of theta_q, J = table index of theta_j (both even).
 template <int MM>
 FFBIE_HD __forceinline__ void dr_grid(const PairGeo<MM>& p, const double* tab, int Kq, int J,
-                                        int mask, int quarter, double* dx, double* dy, double* dz) {
+                                      int mask, int quarter, double* dx, double* dy, double* dz) {
   const int hd = (Kq - J) >> 1;      // (theta_q - theta_j)/2
   const int hs = (Kq + J) >> 1;      // (theta_q + theta_j)/2
   const double cq = tcos(tab, Kq, mask, quarter), sq = tsin(tab, Kq, mask);
   const double dh = tsin(tab, hd, mask);
-  const double dcos = -2.0 * tsin(tab, hs, mask) * dh;         // cos theta_q - cos theta_j
-  const double dsin = 2.0 * tcos(tab, hs, mask, quarter) * dh;  // sin theta_q - sin theta_j
-  double Rs = 1.0, dR = 0.0;
+  const double sS = tsin(tab, hs, mask), cS = tcos(tab, hs, mask, quarter);
+  const double dcos = -2.0 * sS * dh;   // cos theta_q - cos theta_j
+  const double dsin = 2.0 * cS * dh;    // sin theta_q - sin theta_j
+  double dR = p.be[0];
+  if (MM >= 1) {
+    // cos(m theta_q), sin(m hs), sin(m hd) by the Chebyshev recurrences
+    const double cD = MM >= 2 ? tcos(tab, hd, mask, quarter) : 0.0;
+    double c_prev = 1.0, c_cur = cq;
+    double s_prev = 0.0, s_cur = sS;
+    double d_prev = 0.0, d_cur = dh;
 #pragma unroll
-  for (int m = 0; m <= MM; ++m) {
-    const double cm = tcos(tab, m * Kq, mask, quarter);
-    // cos(m theta_q) - cos(m theta_j) = -2 sin(m hs) sin(m hd)
-    const double dc = -2.0 * tsin(tab, m * hs, mask) * tsin(tab, m * hd, mask);
-    Rs = fma(p.al[m], cm, Rs);
-    dR = fma(p.be[m], cm, fma(p.ga[m], dc, dR));
+    for (int m = 1; m <= MM; ++m) {
+      if (m >= 2) {
+        const double cn = 2.0 * cq * c_cur - c_prev;
+        const double sn = 2.0 * cS * s_cur - s_prev;
+        const double dn = 2.0 * cD * d_cur - d_prev;
+        c_prev = c_cur; c_cur = cn;
+        s_prev = s_cur; s_cur = sn;
+        d_prev = d_cur; d_cur = dn;
+      }
+      // cos(m theta_q) - cos(m theta_j) = -2 sin(m hs) sin(m hd)
+      const double dc = -2.0 * s_cur * d_cur;
+      dR = fma(p.be[m], c_cur, fma(p.ga[m], dc, dR));
+    }
   }
   const double wx = p.sts * cq, wy = p.sts * sq, wz = p.cts;
   const double ox = fma(p.S1, cq, p.st * dcos);

@@ -275,27 +275,57 @@ __device__ __forceinline__ int trunc_index_real(const cplx* X, int NF, double in
 }
 
 // out_n = e^{-i n a} sum_{|j| <= p} G_j A_{|n-j|} for n = 0..nmax, with
-// e^{-i n a} = e^{-i n (theta_j + qu gstep)} e^{-i n ur}.
+// e^{-i n a} = e^{-i n (theta_j + qu gstep)} e^{-i n ur}.  Outputs are spread
+// over the lanes; when the count exceeds a multiple of 64 by a few, those last
+// outputs are summed cooperatively (terms over lanes, then a wave sum) instead
+// of costing the whole wave another pass.
+__device__ __forceinline__ cplx swap_phase(int n, double ur, int Jq, const double* tab, int mask,
+                                           int quarter) {
+  double s1, c1;
+  sincos_bounded(n * ur, &s1, &c1);
+  return mk(tcos(tab, n * Jq, mask, quarter), -tsin(tab, n * Jq, mask)) * mk(c1, -s1);
+}
+
+// A must be mirrored: A[-m] = A[m] for m <= p.
 __device__ __forceinline__ void swap_convolution(const cplx* G, int p, const double* A, int nmax,
                                                  double ur, int Jq, const double* tab, int mask,
                                                  int quarter, cplx* out, cplx* mirror,
                                                  cplx* global_row) {
   const int lane = threadIdx.x & 63;
-  for (int n = lane; n <= nmax; n += 64) {
+  const int cnt = nmax + 1;
+  const int rem = cnt & 63;
+  const int split = (cnt > 64 && rem <= 4) ? cnt - rem : cnt;
+  for (int n = lane; n < split; n += 64) {
     double accr = 0.0, acci = 0.0;
-    for (int jj = -p; jj <= p; ++jj) {
-      const cplx g = G[p + jj];
-      const double Av = A[abs(n - jj)];
+    const double* An = A + n + p;     // A is mirrored: An[-i] = A_{|n + p - i|}
+#pragma unroll 4
+    for (int i = 0; i <= 2 * p; ++i) {
+      const cplx g = G[i];
+      const double Av = An[-i];
       accr = fma(g.re, Av, accr);
       acci = fma(g.im, Av, acci);
     }
-    double s1, c1;
-    sincos(n * ur, &s1, &c1);
-    const cplx ph = mk(tcos(tab, n * Jq, mask, quarter), -tsin(tab, n * Jq, mask)) * mk(c1, -s1);
-    const cplx c = ph * mk(accr, acci);
+    const cplx c = swap_phase(n, ur, Jq, tab, mask, quarter) * mk(accr, acci);
     out[n] = c;
     if (mirror) mirror[-n] = conj(c);
     if (global_row) global_row[n] = c;
+  }
+  for (int n = split; n < cnt; ++n) {
+    double accr = 0.0, acci = 0.0;
+    for (int jj = -p + lane; jj <= p; jj += 64) {
+      const cplx g = G[p + jj];
+      const double Av = A[n - jj];
+      accr = fma(g.re, Av, accr);
+      acci = fma(g.im, Av, acci);
+    }
+    accr = wave_sum(accr);
+    acci = wave_sum(acci);
+    if (lane == 0) {
+      const cplx c = swap_phase(n, ur, Jq, tab, mask, quarter) * mk(accr, acci);
+      out[n] = c;
+      if (mirror) mirror[-n] = conj(c);
+      if (global_row) global_row[n] = c;
+    }
   }
 }
 
@@ -310,7 +340,7 @@ __device__ __forceinline__ void swap_convolution(const cplx* G, int p, const dou
 //   eq. (3.10):     Z1 = FFT(F + i cos(k rho)), Z2 = FFT(sin(k rho)/rho)
 //                   C -> free1, GF -> free2, A -> Z1, <rho^-1> -> cb, kc -> free2
 // ===========================================================================
-template <int MM>
+template <int MM, bool REFINE>
 __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
   extern __shared__ double smem[];
   const Prob& P = a.P;
@@ -320,13 +350,17 @@ __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int waves_per_block = blockDim.x >> 6;
-  const int per_wave = 2 * (4 * NF + 2 * L + 1);
+  const bool paper = a.variant == FFBIE_KAPPA_PAPER_CONV;
+  const bool want_c = paper || a.rhoinv != nullptr;
+  const int per_wave = coeff_lds_per_wave(NF, M, L, !want_c);
   cplx* base = reinterpret_cast<cplx*>(smem + P.tab_n + (size_t)wave * per_wave);
   cplx* z1a = base;
   cplx* z1b = z1a + NF;
+  // full layout: z2a, z2b, cb; compact layout: A_m buffer and kc
   cplx* z2a = z1b + NF;
   cplx* z2b = z2a + NF;
-  cplx* cb = z2b + NF;
+  cplx* cb = want_c ? z2b + NF : z1b + NF + (M + NF + 2) / 2;
+  double* Acompact = reinterpret_cast<double*>(z1b + NF);
 
   int64_t count = a.n;
   if (a.list) count = *a.list_count;
@@ -338,8 +372,6 @@ __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
   const int tstride = (8 * M) / NF;        // table index step of the sample grid
   const int hstep = (4 * M) / NF;          // table index step of half a grid step
   const double nan = __builtin_nan("");
-  const bool paper = a.variant == FFBIE_KAPPA_PAPER_CONV;
-  const bool want_c = paper || a.rhoinv != nullptr;
   const double k = P.k;
   const double invNF = 1.0 / NF;
   // sin(k rho)/rho <= k is packed beside F cos(k rho) = O(1) in one transform;
@@ -349,7 +381,6 @@ __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
   const double s_down = ldexp(1.0, -kexp), s_up = ldexp(1.0, kexp);
 
   double t_prev = nan, ts_prev = nan;
-  int j_prev = -1;
   PairGeo<MM> pg;
 
   for (int64_t w = beg; w < end; ++w) {
@@ -367,9 +398,11 @@ __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
       continue;
     }
     const int J = 4 * j;
-    if (!(t == t_prev && ts == ts_prev && j == j_prev)) {
+    if (!(t == t_prev && ts == ts_prev)) {
       pair_geo<MM>(P.g, t, ts, tab, J, mask, quarter, &pg);
-      t_prev = t; ts_prev = ts; j_prev = j;
+      t_prev = t; ts_prev = ts;
+    } else {
+      pair_geo_R<MM>(tab, J, mask, quarter, &pg);
     }
     const double u = rr.u, b = rr.b;
     // a = theta_j + qu * (2 pi / NF) + ur,  |ur| <= pi / NF
@@ -378,7 +411,7 @@ __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
     const int qu = (int)qu_d;
     const double ur = fma(-qu_d, gstep, u);
     double sur, cur;
-    sincos(0.5 * ur, &sur, &cur);
+    sincos_bounded(0.5 * ur, &sur, &cur);
     const double eb = exp(-b), omq = -expm1(-b);
     const int qj = j * (NF / (2 * M));
 
@@ -390,7 +423,7 @@ __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
       const double rho = sqrt(r2);
       double skr, ckr;
-      sincos(k * rho, &skr, &ckr);
+      sincos_bounded(k * rho, &skr, &ckr);
       const int hidx = (q - qj - qu) * hstep;   // (theta_q - a)/2 = hidx pi/(4M) - ur/2
       const double sh = fma(tsin(tab, hidx, mask), cur, -tcos(tab, hidx, mask, quarter) * sur);
       const double s = fma(omq, omq, 4.0 * eb * sh * sh);
@@ -435,7 +468,7 @@ __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
     const int pmax = max(pF, pH);
     for (int jj = lane; jj <= pmax; jj += 64) {
       double s1, c1;
-      sincos(jj * ur, &s1, &c1);
+      sincos_bounded(jj * ur, &s1, &c1);
       const cplx ph = mk(tcos(tab, jj * Jq, mask, quarter), tsin(tab, jj * Jq, mask)) * mk(c1, s1);
       if (want_c && jj <= pF) {
         const cplx G = real_part_coeff(Fsrc, jj, NF, invNF) * ph;
@@ -458,9 +491,12 @@ __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
     }
     wave_sync();
     // ---- A_m(b)
-    double* A = reinterpret_cast<double*>(paper ? Z1 : (want_c ? Z2 : free2));
+    double* A = (paper ? reinterpret_cast<double*>(Z1)
+                       : (want_c ? reinterpret_cast<double*>(Z2) : Acompact)) + NF / 2;
     const int mtop = paper ? L + pF : (want_c ? max(L + pF, M + pH) : M + pH);
     singular_factor_wave(b, rr.A0, rr.D1, mtop, A);
+    for (int m = 1 + lane; m <= max(pF, pH); m += 64) A[-m] = A[m];
+    wave_sync();
 
     // ---- <rho^-1>_l, l = 0..L (eq. (3.25)) into cb[L + l] (and cb[L - l] = conj)
     if (want_c) {
@@ -557,12 +593,16 @@ hipError_t launch_root(const Prob& P, const double* tab, int64_t n, const double
 }
 
 hipError_t launch_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t lds,
-                        hipStream_t stream) {
+                        hipStream_t stream, bool refine) {
   switch (mm_bucket(a.P.g.mmax)) {
 #define X(MMV)                                                                                   \
   case MMV:                                                                                      \
-    hipLaunchKernelGGL(ffbie_coeff_kernel_t<MMV>, dim3((unsigned)blocks), dim3(64 * waves), lds, \
-                       stream, a);                                                               \
+    if (refine)                                                                                  \
+      hipLaunchKernelGGL((ffbie_coeff_kernel_t<MMV, true>), dim3((unsigned)blocks),             \
+                         dim3(64 * waves), lds, stream, a);                                      \
+    else                                                                                         \
+      hipLaunchKernelGGL((ffbie_coeff_kernel_t<MMV, false>), dim3((unsigned)blocks),            \
+                         dim3(64 * waves), lds, stream, a);                                      \
     break;
     FFBIE_FOR_MM(X)
 #undef X

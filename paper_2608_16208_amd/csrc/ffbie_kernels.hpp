@@ -29,11 +29,22 @@ struct CoeffArgs {
   int variant;               // FFBIE_KAPPA_SWAP or FFBIE_KAPPA_PAPER_CONV
 };
 
+// Per-wavefront LDS of the coefficient kernel, in doubles.
+//   compact (default variant without <rho^-1> output):
+//     two NF-complex FFT buffers, A_m (m <= M + NF/2), kc (M + 1 complex)
+//   full: four NF-complex buffers and the <rho^-1> buffer (2L + 1 complex)
+//     A_m is stored mirrored, A[-m] = A[m] for m <= NF/2, so it needs M + NF + 2 doubles
+//     (compact) or fits an NF-complex buffer (full, since L <= NF).
+FFBIE_HD inline int coeff_lds_per_wave(int NF, int M, int L, bool compact) {
+  if (compact) return 2 * (2 * NF) + 2 * ((M + NF + 2) / 2) + 2 * (M + 1);
+  return 2 * (4 * NF + 2 * L + 1);
+}
+
 hipError_t launch_root(const Prob& P, const double* tab, int64_t n, const double* t,
                        const int32_t* az, const double* ts, RootRec* out, int32_t* status,
                        double* root_out, hipStream_t stream);
 hipError_t launch_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t lds,
-                        hipStream_t stream);
+                        hipStream_t stream, bool refine);
 __global__ void ffbie_singular_factor_kernel(int64_t n, const double* __restrict__ b_in, int mtop,
                                              double* __restrict__ out);
 

@@ -1,0 +1,63 @@
+// Host build of the device math of the coefficient path (the same headers the
+// kernels include), driven from tests/test_host_device_code.py.
+//   sincos <x...>            : prints sin, cos of each x with sincos_bounded
+//   roots  (stdin problem)   : prints u, b, status of find_root for each pair
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "ffbie_root.hpp"
+
+using namespace ffbie;
+
+static double table_sin(int i, int M) {
+  const int n = 8 * M;
+  i %= n;
+  if (i < 0) i += n;
+  int sign = 1;
+  if (i >= 4 * M) { i -= 4 * M; sign = -1; }
+  if (i > 2 * M) i = 4 * M - i;
+  long double v = (i <= M) ? sinl((long double)M_PI * i / (4.0L * M))
+                           : cosl((long double)M_PI * (2 * M - i) / (4.0L * M));
+  return sign * (double)v;
+}
+
+int main(int argc, char** argv) {
+  if (argc > 1 && !strcmp(argv[1], "sincos")) {
+    double x;
+    while (scanf("%lf", &x) == 1) {
+      double s, c;
+      sincos_bounded(x, &s, &c);
+      printf("%.17g %.17g\n", s, c);
+    }
+    return 0;
+  }
+  int M, lmax, mmax;
+  double k;
+  if (scanf("%d %lf %d %d", &M, &k, &lmax, &mmax) != 4) return 1;
+  Prob P{};
+  P.M = M; P.M0 = M; P.L = 2 * M; P.tab_n = 8 * M; P.k = k; P.eps0 = 1e-15;
+  P.g.lmax = lmax; P.g.mmax = mmax;
+  for (int l = 0; l < lmax; ++l)
+    for (int m = 0; m <= mmax; ++m)
+      if (scanf("%lf", &P.g.a[l][m]) != 1) return 1;
+  std::vector<double> tab(P.tab_n);
+  for (int i = 0; i < P.tab_n; ++i) tab[i] = table_sin(i, M);
+  int n;
+  if (scanf("%d", &n) != 1) return 1;
+  for (int i = 0; i < n; ++i) {
+    double t, ts;
+    int j;
+    if (scanf("%lf %d %lf", &t, &j, &ts) != 3) return 1;
+    int st = 0;
+    RootRec r;
+    if (mmax <= 0) r = find_root<0>(P, tab.data(), t, j, ts, &st);
+    else if (mmax <= 2) r = find_root<2>(P, tab.data(), t, j, ts, &st);
+    else if (mmax <= 4) r = find_root<4>(P, tab.data(), t, j, ts, &st);
+    else r = find_root<8>(P, tab.data(), t, j, ts, &st);
+    printf("%.17g %.17g %d\n", r.u, r.b, st);
+  }
+  return 0;
+}

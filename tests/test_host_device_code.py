@@ -1,0 +1,78 @@
+"""Device math of the coefficient path, compiled for the host and checked on
+the CPU: the bounded-argument sin/cos and the root finder (the exact code the
+root kernel runs), against 30-50 digit arithmetic."""
+import math
+import os
+import shutil
+import subprocess
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("host") / "device_math_harness")
+    cmd = [HIPCC, "-O2", "-std=c++17", "-x", "hip", "--offload-arch=gfx950",
+           "-I" + os.path.join(ROOT, "include"),
+           "-I" + os.path.join(ROOT, "paper_2608_16208_amd", "csrc"),
+           "-o", exe, os.path.join(ROOT, "tests", "host", "device_math_harness.cpp")]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr[-2000:]
+    return exe
+
+
+def test_sincos_bounded_accuracy(harness):
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([rng.uniform(-100, 100, 400), rng.uniform(-1e-3, 1e-3, 50),
+                         np.array([0.0, math.pi / 4, math.pi / 2, math.pi, 3 * math.pi / 2,
+                                   1e-300, -2.5, 1000.0, 12345.678])])
+    out = subprocess.run([harness, "sincos"], input="\n".join(repr(float(x)) for x in xs),
+                         capture_output=True, text=True).stdout.split()
+    got = np.array(out, dtype=float).reshape(-1, 2)
+    mp.mp.dps = 50
+    for x, (s, c) in zip(xs, got):
+        rs, rc = mp.sin(mp.mpf(float(x))), mp.cos(mp.mpf(float(x)))
+        assert abs(s - float(rs)) <= 3e-16 * max(1e-300, abs(float(rs))) + 2.3e-16 * (abs(x) > 1e-3)
+        assert abs(c - float(rc)) <= 3.3e-16
+
+
+@pytest.mark.parametrize("cfgi", [2, 3])
+def test_root_finder_on_host(harness, cfgi):
+    """Roots from the root kernel's code zero rho^2 to 1e-13 b (30-digit check)."""
+    cfg = workloads.config(cfgi)
+    M, a = cfg["M"], cfg["amp"]
+    t, j, ts = workloads.sample_pairs(cfg["n_panels"], M, 60, seed=700 + cfgi)
+    inp = (f"{M} {cfg['k']} {a.shape[0]} {a.shape[1] - 1}\n"
+           + " ".join(repr(float(v)) for v in a.ravel()) + f"\n{len(t)}\n"
+           + "\n".join(f"{float(t[i])!r} {int(j[i])} {float(ts[i])!r}" for i in range(len(t))))
+    out = subprocess.run([harness], input=inp, capture_output=True, text=True).stdout.split()
+    res = np.array(out, dtype=float).reshape(-1, 3)
+    mp.mp.dps = 30
+
+    def r_mp(tt, th):
+        R = 1 + sum(mp.mpf(float(a[l - 1, m])) * mp.sin(l * tt) * mp.cos(m * th)
+                    for l in range(1, a.shape[0] + 1) for m in range(a.shape[1]) if a[l - 1, m])
+        return [R * mp.sin(tt) * mp.cos(th), R * mp.sin(tt) * mp.sin(th), R * mp.cos(tt)]
+
+    checked = 0
+    for i in range(len(t)):
+        u, b, st = res[i]
+        if int(st) & (2 | 16):
+            continue
+        th = mp.pi * int(j[i]) / M
+        p0 = r_mp(mp.mpf(float(t[i])), th)
+        f = lambda zz: sum((x - y) ** 2 for x, y in zip(r_mp(mp.mpf(float(ts[i])), zz), p0))
+        z = th + mp.mpf(u) + 1j * mp.mpf(b)
+        assert b > 0
+        assert abs(f(z) / mp.diff(f, z)) <= 1e-13 * b, (i, b)
+        checked += 1
+    assert checked >= 40
