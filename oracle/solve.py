@@ -1,0 +1,51 @@
+"""Dense solve and analytic references for the single-layer equation.  TEST
+INFRASTRUCTURE ONLY.
+
+* ``lu_solve``: LAPACK LU with partial pivoting (scipy), FP64.
+* ``mie_scattered``: field scattered by the sound-soft unit sphere for the
+  incident plane wave e^{ik d.x} (separation of variables),
+      u_s(x) = -sum_n (2n+1) i^n [j_n(k)/h_n(k)] h_n(k|x|) P_n(d.x/|x|).
+* ``sphere_single_layer_eigenvalue``: on the unit sphere the operator of
+  eq. (2.8), S[phi] = 2 int G phi dsigma, maps the spherical harmonic Y_n^m to
+  2ik j_n(k) h_n(k) Y_n^m.
+* ``point_source``: G(x; p) = e^{ik|x-p|}/(4 pi |x-p|), the exact interior
+  solution of the Dirichlet test of Sec. 5.
+"""
+import numpy as np
+from scipy import linalg, special
+
+
+def lu_solve(S, g):
+    return linalg.lu_solve(linalg.lu_factor(S), g)
+
+
+def hankel1(n, z):
+    return special.spherical_jn(n, z) + 1j * special.spherical_yn(n, z)
+
+
+def mie_scattered(k, pts, d, nmax=40):
+    pts = np.atleast_2d(pts)
+    r = np.linalg.norm(pts, axis=1)
+    cosg = pts @ np.asarray(d) / r
+    u = np.zeros(len(pts), dtype=complex)
+    for n in range(nmax + 1):
+        a = (2 * n + 1) * (1j ** n) * special.spherical_jn(n, k) / hankel1(n, k)
+        u -= a * hankel1(n, k * r) * special.eval_legendre(n, cosg)
+    return u
+
+
+def sphere_single_layer_eigenvalue(n, k):
+    return 2j * k * special.spherical_jn(n, k) * hankel1(n, k)
+
+
+def spherical_harmonic(n, m, t, th):
+    """Y_n^m(t, th) with t the polar angle (scipy's sph_harm convention)."""
+    try:
+        return special.sph_harm_y(n, m, t, th)
+    except AttributeError:                       # older scipy
+        return special.sph_harm(m, n, th, t)
+
+
+def point_source(k, x, p):
+    rho = np.linalg.norm(np.atleast_2d(x) - np.asarray(p), axis=1)
+    return np.exp(1j * k * rho) / (4 * np.pi * rho)
