@@ -1,0 +1,146 @@
+"""Pins of the oracle's discrete single-layer system (Sec. 3.1, 3.4) and of the
+near-panel rules, on the CPU.
+
+* near rules: exactness on the 32 functions {P_k, P_k log} (k < 16), with
+  30-digit moments, for the oracle's rules (tests/golden) and for the library's
+  built-in table (read through the C ABI, no GPU needed);
+* operator: on the unit sphere the single-layer operator has the spherical
+  harmonics as eigenfunctions with eigenvalue 2ik j_n(k) h_n(k);
+* solve + field: the sound-soft sphere against the Mie series, and the
+  interior point-source test of Sec. 5 on a star surface.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import assembly as oasm
+from oracle import ggq as oggq
+from oracle import solve as osolve
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "ggq16_oracle.txt")
+
+
+def load_golden():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("mkggq", os.path.join(HERE, "golden", "make_ggq_golden.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.load(GOLDEN)
+
+
+@pytest.fixture(scope="module")
+def rule():
+    return load_golden()
+
+
+XG = np.polynomial.legendre.leggauss(16)[0]
+RULE_CASES = [(0, 0), (0, 5), (0, 9), (0, 15), (1, 0), (1, 6), (1, 10), (1, 12), (1, 15)]
+
+
+@pytest.mark.parametrize("rel,l", RULE_CASES)
+def test_oracle_near_rule_is_exact(rule, rel, l):
+    x = rule["self_x" if rel == 0 else "right_x"][l]
+    w = rule["self_w" if rel == 0 else "right_w"][l]
+    assert np.all(np.abs(x) < 1) and np.all(w > 0)
+    res = oggq.moment_residual(x, w, XG[l], rel, dps=25)
+    assert res <= 5e-13, res
+
+
+@pytest.mark.parametrize("rel,l", RULE_CASES)
+def test_library_near_rule_is_exact(rel, l):
+    import paper_2608_16208_amd as ffbie
+    try:
+        tab = ffbie.builtin_near_rule()
+    except ffbie.FfbieError as e:
+        pytest.skip(str(e))
+    x = tab["self_x" if rel == 0 else "right_x"][l]
+    w = tab["self_w" if rel == 0 else "right_w"][l]
+    assert np.all(np.abs(x) < 1) and np.all(w > 0)
+    assert np.all(np.diff(x) > 0)
+    res = oggq.moment_residual(x, w, XG[l], rel, dps=25)
+    assert res <= 5e-13, res
+
+
+def test_left_rule_is_mirror(rule):
+    y, w = oggq.relation_rule(rule, 3, -1)
+    yr, wr = oggq.relation_rule(rule, 12, 1)
+    assert np.array_equal(y, -yr[::-1]) and np.array_equal(w, wr[::-1])
+
+
+def test_lagrange_interpolates_polynomials():
+    xg = XG
+    y = 0.3137
+    p = np.polynomial.Polynomial(np.random.default_rng(0).standard_normal(16))
+    assert abs(oasm.lagrange(xg, y) @ p(xg) - p(y)) < 1e-12
+
+
+def test_parseval_weights_reproduce_trapezoid():
+    """With kappa_n the DFT coefficients of samples f(theta_l), the Parseval
+    weights are the samples themselves / 2M (discrete Parseval relation)."""
+    M = 8
+    rng = np.random.default_rng(1)
+    f = rng.standard_normal(2 * M) + 1j * rng.standard_normal(2 * M)
+    th = np.pi * np.arange(2 * M) / M
+    n = np.arange(-M + 1, M + 1)
+    kap = np.array([np.mean(f * np.exp(-1j * m * th)) for m in n])
+    w = oasm.parseval_weights(kap[None, :], M)[0]
+    # sum_j' w_j' phi_j' = sum_n kappa_n <phi>_{-n} for any phi: take phi = e^{-i m theta}
+    for m in (-3, 0, 5):
+        phi = np.exp(-1j * m * th)
+        lhs = np.sum(w * phi)
+        assert abs(lhs - kap[n == m][0]) < 1e-14
+
+
+@pytest.fixture(scope="module")
+def sphere_system(rule):
+    k, M, npan = 1.0, 8, 4
+    S = oasm.matrix(None, k, M, npan, rule, processes=8)
+    return k, M, npan, S
+
+
+@pytest.mark.parametrize("n,m", [(0, 0), (1, 0), (2, 1), (3, -2), (4, 3)])
+def test_oracle_operator_sphere_eigenfunctions(sphere_system, n, m):
+    k, M, npan, S = sphere_system
+    L = oasm.layout(npan, M)
+    Y = osolve.spherical_harmonic(n, m, L["t"], L["th"])
+    v = Y * np.sin(L["t"])                         # phi~ = phi J, J = sin t
+    lam = osolve.sphere_single_layer_eigenvalue(n, k)
+    err = np.max(np.abs(S @ v - lam * Y)) / np.max(np.abs(lam * Y))
+    # measured 1.6e-5 or less at (4 panels, 2M = 16); a dropped term or a wrong
+    # sign in any block gives an O(1) error
+    assert err <= 3e-5, err
+
+
+def test_oracle_solve_sphere_mie(sphere_system):
+    k, M, npan, S = sphere_system
+    d = np.array([0.0, 0.0, 1.0])
+    g = oasm.rhs_plane_wave(None, npan, M, k, d)
+    phi = osolve.lu_solve(S, g)
+    rng = np.random.default_rng(1)
+    dirs = rng.standard_normal((8, 3))
+    pts = dirs / np.linalg.norm(dirs, axis=1)[:, None] * rng.uniform(3, 5, 8)[:, None]
+    u = oasm.field(None, npan, M, k, phi, pts)
+    ref = osolve.mie_scattered(k, pts, d)
+    err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+    assert err <= 1e-8, err              # measured 1.1e-9
+
+
+@pytest.mark.slow
+def test_oracle_green_identity_star(rule):
+    """Interior Dirichlet problem with g = G(.; r*), r* = (3, 4, 10.5) outside:
+    the field inside equals G(.; r*) (Sec. 5)."""
+    amp = np.zeros((3, 3))
+    amp[2, 2] = 0.2
+    k, M, npan = 1.0, 8, 4
+    S = oasm.matrix(amp, k, M, npan, rule, processes=8)
+    rs = np.array([3.0, 4.0, 10.5])
+    g = oasm.rhs_point_source(amp, npan, M, k, rs)
+    phi = osolve.lu_solve(S, g)
+    rng = np.random.default_rng(2)
+    pts = np.array([0.0, -0.2, 0.1]) + 0.2 * rng.uniform(-1, 1, (8, 3)) / np.sqrt(3)
+    u = oasm.field(amp, npan, M, k, phi, pts)
+    ref = osolve.point_source(k, pts, rs)
+    err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+    assert err <= 1e-6, err
