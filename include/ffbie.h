@@ -33,9 +33,12 @@ extern "C" {
 typedef enum {
   FFBIE_OK = 0,
   FFBIE_EINVAL = -1,         /* invalid argument, shape or unsupported size        */
+  FFBIE_ESINGULAR = -2,      /* exactly zero pivot in an LU factorisation            */
   FFBIE_ENOMEM = -4,         /* device allocation of a workspace failed             */
   FFBIE_EDEVICE = -5,        /* a HIP runtime call failed                           */
-  FFBIE_ENOPROBLEM = -7      /* ffbie_set_problem has not been called               */
+  FFBIE_ENOPROBLEM = -7,     /* ffbie_set_problem has not been called               */
+  FFBIE_EBLAS = -8,          /* a rocBLAS GEMM call failed                          */
+  FFBIE_WNOTCONV = 2         /* warning: an iterative solve stopped at max_iter     */
 } ffbie_status;
 
 /* Per-pair status bits written to d_pair_status by ffbie_kernel_coeffs. */
@@ -156,6 +159,126 @@ ffbie_status ffbie_get_timing(ffbie_ctx *ctx, double *ms_root, double *ms_main,
  * eq. (3.28)).  b <= 0 gives a NaN row.  1 <= m_max <= 1023. */
 ffbie_status ffbie_singular_factor(ffbie_ctx *ctx, int64_t n, const double *d_b,
                                    int m_max, double *d_A);
+
+/* ------------------------------------------------------------------------
+ * The discrete single-layer system (Sec. 3.1 and 3.4)
+ * ------------------------------------------------------------------------
+ * Unknowns and collocation points share one ordering: index
+ *   r = (i * 16 + l) * 2M + j
+ * for panel i in [0, n_panels), Gauss-Legendre node l in [0, 16) and azimuth
+ * j in [0, 2M); the point is r(t_i^l, theta_j) with t_i^l the l-th node of the
+ * panel [i pi / n_panels, (i + 1) pi / n_panels] and theta_j = pi j / M.
+ * N = 32 M n_panels.  The unknown at index r is the density times the surface
+ * Jacobian, phi~ = phi J (eq. (3.1)).  Complex vectors are complex128 [N]. */
+
+/* Near-panel quadrature rules (Sec. 3.1): for a target at Gauss-Legendre
+ * position x_l of its panel (panel coordinate in (-1, 1)), the t_s integral
+ * over its own panel uses nodes self_x[l][q] and weights self_w[l][q]
+ * (q < 16) in that panel's coordinate, and over the right-hand neighbour the
+ * nodes right_x[l][q], weights right_w[l][q] in the neighbour's coordinate.
+ * The left-hand neighbour uses the mirror image of the right-hand rule of
+ * target 15 - l (nodes -right_x[15-l][q], same weights).  Weights are for
+ * the panel coordinate (they sum to 2 for an exact rule). */
+typedef struct {
+  double self_x[16][16];
+  double self_w[16][16];
+  double right_x[16][16];
+  double right_w[16][16];
+} ffbie_near_rule;
+
+/* Copy the library's built-in rules (16-node generalized Gaussian rules,
+ * exact for P_k and P_k log|t_s - t| with k < 16) into *out.  Host only; needs
+ * no context or device. */
+ffbie_status ffbie_builtin_near_rule(ffbie_near_rule *out);
+
+/* Select the near rules used by ffbie_near_pairs and ffbie_assemble: a HOST
+ * pointer, copied; NULL restores the built-in rules.  Nodes must lie in
+ * (-1, 1) and differ from the target position for the self panel, else
+ * FFBIE_EINVAL.  Persists across ffbie_set_problem. */
+ffbie_status ffbie_set_near_rule(ffbie_ctx *ctx, const ffbie_near_rule *rule);
+
+/* Sizes for the current problem: the number of unknowns N = 32 M n_panels,
+ * and the number of near pairs (target point, near-rule source node):
+ * 512 M (3 n_panels - 2) for n_panels >= 2.  Either pointer may be NULL. */
+ffbie_status ffbie_query(ffbie_ctx *ctx, int64_t *n_unknowns, int64_t *n_near_pairs);
+
+/* Write the near pair set as ffbie_kernel_coeffs inputs: d_t, d_az, d_ts
+ * [n_near_pairs] (float64, int32, float64).  Order: panel i, node l, azimuth
+ * j, relation (left neighbour, own panel, right neighbour; neighbours outside
+ * [0, n_panels) are absent), rule node q. */
+ffbie_status ffbie_near_pairs(ffbie_ctx *ctx, double *d_t, int32_t *d_az, double *d_ts);
+
+/* Collocation points x_r (d_xyz [N][3] float64), surface Jacobians
+ * J = |r_t x r_theta| (d_jac [N], optional NULL) and the quadrature weight of
+ * each unknown, w_i^l / (2M) with w_i^l the Gauss-Legendre weight on the panel
+ * (d_wq [N], optional NULL), so that a surface integral of phi is
+ * sum_r wq_r phi~_r * 2 pi (eq. (3.8) with the 16-point rule of eq. (3.7)). */
+ffbie_status ffbie_collocation(ffbie_ctx *ctx, double *d_xyz, double *d_jac, double *d_wq);
+
+/* Right-hand sides on the collocation points (d_g [N] complex128):
+ *   FFBIE_RHS_POINT_SOURCE: g = G(x; p) = e^{ik|x - p|} / (4 pi |x - p|) with
+ *     p = (params[0], params[1], params[2]), the interior Dirichlet test of
+ *     Sec. 5 (exact interior field G(.; p) when p is outside the surface);
+ *   FFBIE_RHS_PLANE_WAVE: g = -e^{ik d.x} with d = params[0..2] (unit), the
+ *     sound-soft exterior problem for the incident wave e^{ik d.x}.
+ * params is a HOST pointer to 3 doubles. */
+enum { FFBIE_RHS_POINT_SOURCE = 0, FFBIE_RHS_PLANE_WAVE = 1 };
+ffbie_status ffbie_rhs(ffbie_ctx *ctx, int kind, const double *params, void *d_g);
+
+/* Assemble the N x N matrix S of the discretised single-layer equation
+ * S phi~ = g (Sec. 3.4, eq. (3.29)) into d_S, ROW-major complex128: entry (r, c) at
+ * d_S[r * ld + c], ld >= N.  Row r is the collocation point, column c the
+ * unknown.
+ *  - far panels (|i - i'| >= 2): S = (h/2) w_{l'} (1/2M) e^{ik rho}/rho with
+ *    rho = |x_r - x_c| and h = pi / n_panels (eqs. (3.7)-(3.8));
+ *  - near panels (|i - i'| <= 1): S = sum_q (h/2) W_q L_{l'}(y_q) w_{j'} with
+ *    the near rule (W_q, y_q), L_{l'} the Lagrange basis of the panel's
+ *    Gauss-Legendre nodes (interpolation of phi~ in t_s), and
+ *    w_{j'} = (1/2M) sum_{n=-M+1}^{M} kappa_n e^{i n theta_{j'}} the inverse
+ *    DFT (discrete Parseval relation) of the kernel coefficients of
+ *    ffbie_kernel_coeffs at (x_r, t_s = node y_q) (eqs. (3.9)-(3.10)).
+ * Uses a device workspace for the near kernel coefficients (at most about
+ * 2 GB, allocated on first use).  FFBIE_EINVAL for a NULL matrix or ld < N. */
+ffbie_status ffbie_assemble(ffbie_ctx *ctx, void *d_S, int64_t ld);
+
+/* Field of the single-layer representation u(x) = 2 int G(x, y) phi(y) dsigma
+ * (eq. (2.6)) at n_pts points off the surface, by the same 16-point-by-2M
+ * product rule: u(x) = sum_c wq_c e^{ik|x - x_c|} / |x - x_c| phi~_c.
+ * d_pts [n_pts][3] float64, d_phi [N] complex128, d_u [n_pts] complex128. */
+ffbie_status ffbie_eval_field(ffbie_ctx *ctx, int64_t n_pts, const double *d_pts,
+                              const void *d_phi, void *d_u);
+
+/* Dense solve of S phi~ = g for the matrix of ffbie_assemble (row-major
+ * complex128, leading dimension ld >= N).  The paper leaves the solver open;
+ * three are provided:
+ *   FFBIE_SOLVE_LU64       LU with partial pivoting in complex128.  S is
+ *                          OVERWRITTEN by its factors.  tol, max_iter unused.
+ *   FFBIE_SOLVE_LU32_IR64  LU of a complex64 copy of S (workspace N*N*8 bytes),
+ *                          then iterative refinement phi += (LU32)^{-1} r with the
+ *                          residual r = g - S phi in complex128; S is read only.
+ *                          Stops when |r|_2 <= tol |g|_2 or after max_iter steps.
+ *   FFBIE_SOLVE_GMRES      restarted GMRES (restart 100) in complex128 with the
+ *                          matrix-vector product of S; S is read only (workspace
+ *                          101 N complex128).  Stops as above (max_iter counts
+ *                          Krylov iterations).
+ * d_g [N] and d_phi [N] complex128 (distinct buffers).  The call synchronises
+ * the context's stream (iterative methods read norms on the host) and returns
+ * after the solve has finished.  info (optional): iterations and the final
+ * relative residual |g - S phi| / |g| (NaN for LU64, whose S is destroyed).
+ * Returns FFBIE_ESINGULAR on an exactly zero pivot, FFBIE_WNOTCONV if an
+ * iterative method did not reach tol (phi holds the last iterate). */
+enum { FFBIE_SOLVE_LU64 = 0, FFBIE_SOLVE_LU32_IR64 = 1, FFBIE_SOLVE_GMRES = 2 };
+typedef struct {
+  int iterations;
+  int converged;
+  double rel_residual;
+} ffbie_solve_info;
+ffbie_status ffbie_solve(ffbie_ctx *ctx, int method, void *d_S, int64_t ld, const void *d_g,
+                         void *d_phi, double tol, int max_iter, ffbie_solve_info *info);
+
+/* r = g - S phi in complex128 (row-major S, leading dimension ld); d_r [N]. */
+ffbie_status ffbie_residual(ffbie_ctx *ctx, const void *d_S, int64_t ld, const void *d_phi,
+                            const void *d_g, void *d_r);
 
 #ifdef __cplusplus
 }

@@ -18,7 +18,13 @@ PAIR_SINGULAR, PAIR_ROOT_FALLBACK, PAIR_REFINED, PAIR_UNRESOLVED, PAIR_FAR = 1, 
 KAPPA_SWAP, KAPPA_PAPER_CONV = 0, 1
 
 EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_problem",
-           "ffbie_kernel_coeffs", "ffbie_singular_factor", "ffbie_enable_timing", "ffbie_get_timing")
+           "ffbie_kernel_coeffs", "ffbie_singular_factor", "ffbie_enable_timing", "ffbie_get_timing",
+           "ffbie_builtin_near_rule", "ffbie_set_near_rule", "ffbie_query", "ffbie_near_pairs",
+           "ffbie_collocation", "ffbie_rhs", "ffbie_assemble", "ffbie_eval_field", "ffbie_solve",
+           "ffbie_residual")
+SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES = 0, 1, 2
+WNOTCONV = 2
+RHS_POINT_SOURCE, RHS_PLANE_WAVE = 0, 1
 P_SHIFT = 8
 
 
@@ -33,6 +39,14 @@ class _Geometry(ctypes.Structure):
 class _Disc(ctypes.Structure):
     _fields_ = [("n_panels", ctypes.c_int), ("M", ctypes.c_int), ("M0", ctypes.c_int),
                 ("eps0", ctypes.c_double), ("kappa_variant", ctypes.c_int)]
+
+
+class _SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("rel_residual", ctypes.c_double)]
+
+
+class _NearRule(ctypes.Structure):
+    _fields_ = [(name, (ctypes.c_double * 16) * 16) for name in ("self_x", "self_w", "right_x", "right_w")]
 
 
 _lib = None
@@ -57,6 +71,16 @@ def load_library(path=LIB_PATH):
     lib.ffbie_enable_timing.argtypes = [vp, i32]
     dp = ctypes.POINTER(ctypes.c_double)
     lib.ffbie_get_timing.argtypes = [vp, dp, dp, dp]
+    lib.ffbie_builtin_near_rule.argtypes = [ctypes.POINTER(_NearRule)]
+    lib.ffbie_set_near_rule.argtypes = [vp, ctypes.POINTER(_NearRule)]
+    lib.ffbie_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.ffbie_near_pairs.argtypes = [vp, vp, vp, vp]
+    lib.ffbie_collocation.argtypes = [vp, vp, vp, vp]
+    lib.ffbie_rhs.argtypes = [vp, i32, dp, vp]
+    lib.ffbie_assemble.argtypes = [vp, vp, i64]
+    lib.ffbie_eval_field.argtypes = [vp, i64, vp, vp, vp]
+    lib.ffbie_solve.argtypes = [vp, i32, vp, i64, vp, vp, ctypes.c_double, i32, ctypes.POINTER(_SolveInfo)]
+    lib.ffbie_residual.argtypes = [vp, vp, i64, vp, vp, vp]
     for name in EXPORTS:
         f = getattr(lib, name)
         if name != "ffbie_last_error":
@@ -67,6 +91,17 @@ def load_library(path=LIB_PATH):
 
 def _ptr(x):
     return None if x is None else ctypes.c_void_p(x.data_ptr())
+
+
+def builtin_near_rule():
+    """The library's built-in 16-node near-panel rules (host call, no GPU):
+    dict of float64 arrays self_x, self_w, right_x, right_w, each [16][16]."""
+    lib = load_library()
+    r = _NearRule()
+    rc = lib.ffbie_builtin_near_rule(ctypes.byref(r))
+    if rc != FFBIE_OK:
+        raise FfbieError(f"ffbie_builtin_near_rule failed ({rc})")
+    return {name: np.ctypeslib.as_array(getattr(r, name)).copy() for name, _ in _NearRule._fields_}
 
 
 class Context:
@@ -142,6 +177,91 @@ class Context:
         v = [ctypes.c_double() for _ in range(3)]
         self._check(self.lib.ffbie_get_timing(self.h, *(ctypes.byref(x) for x in v)), self.h)
         return tuple(x.value for x in v)
+
+    # ---- discrete single-layer system -------------------------------------
+    def set_near_rule(self, rule=None):
+        """Near-panel rules: dict as returned by builtin_near_rule(), or None
+        for the built-in rules."""
+        if rule is None:
+            self._check(self.lib.ffbie_set_near_rule(self.h, None), self.h)
+            return
+        r = _NearRule()
+        for name, _ in _NearRule._fields_:
+            np.ctypeslib.as_array(getattr(r, name))[:] = np.asarray(rule[name], dtype=np.float64)
+        self._check(self.lib.ffbie_set_near_rule(self.h, ctypes.byref(r)), self.h)
+
+    def query(self):
+        """(N unknowns, number of near pairs)."""
+        n, p = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.ffbie_query(self.h, ctypes.byref(n), ctypes.byref(p)), self.h)
+        return n.value, p.value
+
+    def near_pairs(self):
+        torch = self._torch
+        _, n = self.query()
+        t = torch.empty(n, dtype=torch.float64, device=self.device)
+        az = torch.empty(n, dtype=torch.int32, device=self.device)
+        ts = torch.empty(n, dtype=torch.float64, device=self.device)
+        self._check(self.lib.ffbie_near_pairs(self.h, _ptr(t), _ptr(az), _ptr(ts)), self.h)
+        return t, az, ts
+
+    def collocation(self):
+        """(xyz [N, 3], J [N], wq [N]) on the device."""
+        torch = self._torch
+        N, _ = self.query()
+        xyz = torch.empty((N, 3), dtype=torch.float64, device=self.device)
+        jac = torch.empty(N, dtype=torch.float64, device=self.device)
+        wq = torch.empty(N, dtype=torch.float64, device=self.device)
+        self._check(self.lib.ffbie_collocation(self.h, _ptr(xyz), _ptr(jac), _ptr(wq)), self.h)
+        return xyz, jac, wq
+
+    def rhs(self, kind, params):
+        torch = self._torch
+        N, _ = self.query()
+        g = torch.empty(N, dtype=torch.complex128, device=self.device)
+        p = (ctypes.c_double * 3)(*[float(v) for v in params])
+        self._check(self.lib.ffbie_rhs(self.h, int(kind), p, _ptr(g)), self.h)
+        return g
+
+    def assemble(self, S=None):
+        """Row-major N x N complex128 single-layer matrix (allocated if S is None)."""
+        torch = self._torch
+        N, _ = self.query()
+        if S is None:
+            S = torch.empty((N, N), dtype=torch.complex128, device=self.device)
+        if S.dim() != 2 or S.shape[0] != N or S.stride(1) != 1 or S.stride(0) < N or S.dtype != torch.complex128:
+            raise FfbieError("S must be a row-major complex128 [N, >=N] device tensor")
+        self._check(self.lib.ffbie_assemble(self.h, _ptr(S), S.stride(0)), self.h)
+        return S
+
+    def eval_field(self, pts, phi):
+        torch = self._torch
+        pts = pts.to(self.device, torch.float64).contiguous()
+        phi = phi.to(self.device, torch.complex128).contiguous()
+        u = torch.empty(pts.shape[0], dtype=torch.complex128, device=self.device)
+        self._check(self.lib.ffbie_eval_field(self.h, pts.shape[0], _ptr(pts), _ptr(phi), _ptr(u)), self.h)
+        return u
+
+    def solve(self, S, g, method=SOLVE_LU64, tol=1e-12, max_iter=50, phi=None):
+        """phi with S phi = g.  LU64 overwrites S with its factors.  Returns
+        (phi, info dict)."""
+        torch = self._torch
+        g = g.to(self.device, torch.complex128).contiguous()
+        if phi is None:
+            phi = torch.empty_like(g)
+        info = _SolveInfo()
+        rc = self.lib.ffbie_solve(self.h, int(method), _ptr(S), S.stride(0), _ptr(g), _ptr(phi),
+                                  float(tol), int(max_iter), ctypes.byref(info))
+        self._check(rc, self.h)
+        return phi, dict(iterations=info.iterations, converged=bool(info.converged),
+                         rel_residual=info.rel_residual, status=rc)
+
+    def residual(self, S, phi, g):
+        torch = self._torch
+        r = torch.empty_like(g)
+        self._check(self.lib.ffbie_residual(self.h, _ptr(S), S.stride(0), _ptr(phi), _ptr(g), _ptr(r)),
+                    self.h)
+        return r
 
     def singular_factor(self, b, m_max):
         torch = self._torch

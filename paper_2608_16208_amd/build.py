@@ -5,7 +5,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/ffbie_api.hip", "csrc/ffbie_kernels.hip"]
+SOURCES = ["csrc/ffbie_api.hip", "csrc/ffbie_kernels.hip", "csrc/ffbie_assembly.hip",
+           "csrc/ffbie_solve.hip"]
 LIB = os.path.join(HERE, "libffbie.so")
 
 FLAGS = [
@@ -19,7 +20,7 @@ FLAGS = [
 def build(verbose=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc] + FLAGS + ["-o", tmp] + [os.path.join(HERE, s) for s in SOURCES]
+    cmd = [hipcc] + FLAGS + ["-o", tmp] + [os.path.join(HERE, s) for s in SOURCES] + ["-lrocblas"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

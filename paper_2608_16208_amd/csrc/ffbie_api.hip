@@ -11,9 +11,15 @@
 #include "ffbie.h"
 #include "ffbie_device.hpp"
 
+#include "ffbie_assembly.hpp"
 #include "ffbie_kernels.hpp"
+#include "ffbie_solve.hpp"
 
 using namespace ffbie;
+
+namespace {
+#include "ggq16_table.inc"
+}
 
 struct ffbie_ctx {
   int device = 0;
@@ -34,6 +40,34 @@ struct ffbie_ctx {
   bool timing = false;
   bool timed = false;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // discrete system (assembly, right-hand sides, field)
+  ffbie_near_rule rule{};
+  double gl_x[kNodes] = {0}, gl_w[kNodes] = {0};
+  bool sys_ready = false;            // rule tables and collocation data of the current problem
+  double* d_rule_y = nullptr;        // [16 l][3 rel][16 q]
+  double* d_wl = nullptr;            // [16 l][3 rel][16 q][16 l']
+  double* d_colloc = nullptr;        // 5 N doubles: x, y, z, wq, jac
+  int64_t colloc_n = 0;
+  double* d_near_t = nullptr;        // near-pair workspace of one chunk
+  int32_t* d_near_az = nullptr;
+  double* d_near_ts = nullptr;
+  cplx* d_near_kappa = nullptr;
+  int64_t near_cap = 0;              // pairs
+  int near_cap_M = 0;
+  cplx* d_partial = nullptr;         // field partial sums
+  int64_t partial_cap = 0;
+  // dense solvers
+  rocblas_handle blas = nullptr;
+  int64_t solve_n = 0;               // size the vector workspaces were made for
+  int64_t* d_ipiv = nullptr;
+  int64_t* d_perm = nullptr;
+  int* d_info = nullptr;
+  cplx* d_vecs = nullptr;            // 3 N complex128
+  cplx* d_small = nullptr;           // reduction partials and Hessenberg column
+  void* d_s32 = nullptr;
+  int64_t s32_n = 0;
+  cplx* d_krylov = nullptr;
+  int64_t krylov_n = 0;
 };
 
 namespace {
@@ -74,6 +108,97 @@ double table_sin(int i, int M) {
 
 bool valid_M(int M) { return M == 16 || M == 32 || M == 64 || M == 128; }
 
+// Gauss-Legendre nodes (ascending) and weights on [-1, 1]: Newton on P_16 in
+// long double from the asymptotic initial guesses.
+void gauss_legendre16(double* x, double* w) {
+  const int n = kNodes;
+  for (int i = 0; i < n; ++i) {
+    long double z = cosl((long double)M_PI * (i + 0.75L) / (n + 0.5L));
+    long double dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1);
+      const long double dz = p1 / dp;
+      z -= dz;
+      if (fabsl(dz) < 1e-19L) break;
+    }
+    long double p0 = 1, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1);
+    x[n - 1 - i] = (double)z;
+    w[n - 1 - i] = (double)(2 / ((1 - z * z) * dp * dp));
+  }
+}
+
+void builtin_rule(ffbie_near_rule* r) {
+  std::memcpy(r->self_x, kGgqSelfNode, sizeof(r->self_x));
+  std::memcpy(r->self_w, kGgqSelfWeight, sizeof(r->self_w));
+  std::memcpy(r->right_x, kGgqRightNode, sizeof(r->right_x));
+  std::memcpy(r->right_w, kGgqRightWeight, sizeof(r->right_w));
+}
+
+// Rule nodes and weights of target l, relation rel (-1, 0, +1), in the source
+// panel's coordinate; the left rule mirrors the right rule of target 15 - l.
+void relation_rule(const ffbie_near_rule& R, int l, int rel, double* y, double* w) {
+  for (int q = 0; q < kNodes; ++q) {
+    if (rel == 0) {
+      y[q] = R.self_x[l][q];
+      w[q] = R.self_w[l][q];
+    } else if (rel == 1) {
+      y[q] = R.right_x[l][q];
+      w[q] = R.right_w[l][q];
+    } else {
+      y[q] = -R.right_x[kNodes - 1 - l][kNodes - 1 - q];
+      w[q] = R.right_w[kNodes - 1 - l][kNodes - 1 - q];
+    }
+  }
+}
+
+// Lagrange basis of the Gauss-Legendre nodes at y (barycentric form).
+void lagrange_row(const double* xg, double y, double* out) {
+  long double lam[kNodes], s = 0;
+  for (int a = 0; a < kNodes; ++a) {
+    long double p = 1;
+    for (int b = 0; b < kNodes; ++b)
+      if (b != a) p *= (long double)xg[a] - xg[b];
+    lam[a] = 1 / p;
+  }
+  for (int a = 0; a < kNodes; ++a) {
+    if (y == xg[a]) {
+      for (int b = 0; b < kNodes; ++b) out[b] = (a == b) ? 1.0 : 0.0;
+      return;
+    }
+    s += lam[a] / ((long double)y - xg[a]);
+  }
+  for (int a = 0; a < kNodes; ++a) out[a] = (double)(lam[a] / ((long double)y - xg[a]) / s);
+}
+
+int64_t n_unknowns(const ffbie_ctx* c) { return (int64_t)32 * c->prob.M * c->n_panels; }
+
+SysDims sys_dims(const ffbie_ctx* c) {
+  SysDims d;
+  d.n_panels = c->n_panels;
+  d.M = c->prob.M;
+  d.N = n_unknowns(c);
+  d.h = M_PI / c->n_panels;
+  return d;
+}
+
+Colloc colloc_view(const ffbie_ctx* c) {
+  const int64_t N = c->colloc_n;
+  double* b = c->d_colloc;
+  return Colloc{b, b + N, b + 2 * N, b + 3 * N, b + 4 * N};
+}
+
 ffbie_status ensure_ws(ffbie_ctx* c, int64_t n) {
   if (n <= c->ws_pairs) return FFBIE_OK;
   if (c->d_roots) hipFree(c->d_roots);
@@ -109,6 +234,8 @@ ffbie_status ffbie_create(ffbie_ctx** out, int device, void* hip_stream) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return FFBIE_EINVAL;
   ffbie_ctx* c = new ffbie_ctx();
+  builtin_rule(&c->rule);
+  gauss_legendre16(c->gl_x, c->gl_w);
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
   if (hipSetDevice(device) != hipSuccess) { delete c; return FFBIE_EDEVICE; }
@@ -127,6 +254,12 @@ ffbie_status ffbie_destroy(ffbie_ctx* c) {
   if (c->d_status) hipFree(c->d_status);
   if (c->d_list) hipFree(c->d_list);
   if (c->d_count) hipFree(c->d_count);
+  for (void* p : {(void*)c->d_rule_y, (void*)c->d_wl, (void*)c->d_colloc, (void*)c->d_near_t,
+                  (void*)c->d_near_az, (void*)c->d_near_ts, (void*)c->d_near_kappa,
+                  (void*)c->d_partial, (void*)c->d_ipiv, (void*)c->d_perm, (void*)c->d_info,
+                  (void*)c->d_vecs, (void*)c->d_small, c->d_s32, (void*)c->d_krylov})
+    if (p) hipFree(p);
+  if (c->blas) rocblas_destroy_handle(c->blas);
   delete c;
   return FFBIE_OK;
 }
@@ -171,20 +304,19 @@ ffbie_status ffbie_set_problem(ffbie_ctx* c, const ffbie_geometry* g, const ffbi
   c->variant = d->kappa_variant;
   c->n_panels = d->n_panels;
   c->has_problem = true;
+  c->sys_ready = false;
   return FFBIE_OK;
 }
 
-ffbie_status ffbie_kernel_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_t* d_az,
-                                 const double* d_ts, void* d_kappa, void* d_rhoinv, double* d_root,
-                                 int32_t* d_pair_status) {
-  if (!c) return FFBIE_EINVAL;
-  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_kernel_coeffs: no problem set");
-  if (n < 0) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs: n_pairs < 0");
-  if (n == 0) return FFBIE_OK;
-  if (!d_t || !d_az || !d_ts || !d_kappa)
-    return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs: NULL input or kappa pointer");
-  if (n > (int64_t)1 << 31) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs: n_pairs > 2^31");
-  FFBIE_HIP(c, hipSetDevice(c->device));
+}  // extern "C"
+
+namespace {
+
+// The coefficient path on n pairs: root kernel, main pass (2M samples), refine
+// pass (4M samples).  Inputs validated by the caller.
+ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_t* d_az,
+                        const double* d_ts, void* d_kappa, void* d_rhoinv, double* d_root,
+                        int32_t* d_pair_status) {
   ffbie_status s = ensure_ws(c, n);
   if (s != FFBIE_OK) return s;
   const Prob& P = c->prob;
@@ -236,6 +368,234 @@ ffbie_status ffbie_kernel_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, con
   return FFBIE_OK;
 }
 
+// Rule tables (node positions per relation and the weighted Lagrange matrices)
+// and collocation data of the current problem.
+ffbie_status prepare_system(ffbie_ctx* c) {
+  if (c->sys_ready) return FFBIE_OK;
+  const SysDims d = sys_dims(c);
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  std::vector<double> ry(kNodes * 3 * kNodes), wl(kNodes * 3 * kNodes * kNodes);
+  for (int l = 0; l < kNodes; ++l)
+    for (int rel = -1; rel <= 1; ++rel) {
+      double y[kNodes], w[kNodes];
+      relation_rule(c->rule, l, rel, y, w);
+      for (int q = 0; q < kNodes; ++q) {
+        ry[(l * 3 + rel + 1) * kNodes + q] = y[q];
+        double L[kNodes];
+        lagrange_row(c->gl_x, y[q], L);
+        // (h/2) W_q L_{l'}(y_q) and the 1/(2M) of the inverse DFT
+        const double f = 0.5 * d.h * w[q] / (2.0 * d.M);
+        for (int lp = 0; lp < kNodes; ++lp)
+          wl[((l * 3 + rel + 1) * kNodes + q) * kNodes + lp] = f * L[lp];
+      }
+    }
+  if (!c->d_rule_y) FFBIE_HIP(c, hipMalloc(&c->d_rule_y, ry.size() * sizeof(double)));
+  if (!c->d_wl) FFBIE_HIP(c, hipMalloc(&c->d_wl, wl.size() * sizeof(double)));
+  FFBIE_HIP(c, hipMemcpy(c->d_rule_y, ry.data(), ry.size() * sizeof(double), hipMemcpyHostToDevice));
+  FFBIE_HIP(c, hipMemcpy(c->d_wl, wl.data(), wl.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (c->colloc_n != d.N) {
+    if (c->d_colloc) hipFree(c->d_colloc);
+    c->d_colloc = nullptr;
+    c->colloc_n = 0;
+    if (hipMalloc(&c->d_colloc, 5 * d.N * sizeof(double)) != hipSuccess)
+      return fail(c, FFBIE_ENOMEM, "ffbie: collocation workspace allocation failed");
+    c->colloc_n = d.N;
+  }
+  FFBIE_HIP(c, launch_collocation(c->prob.g, d, c->gl_x, c->gl_w, colloc_view(c), nullptr, nullptr,
+                                  nullptr, c->stream));
+  c->sys_ready = true;
+  return FFBIE_OK;
+}
+
+constexpr int64_t kNearKappaBytes = (int64_t)2 << 30;    // near-coefficient workspace bound
+
+ffbie_status ensure_near_ws(ffbie_ctx* c, int64_t pairs) {
+  if (pairs <= c->near_cap && c->near_cap_M == c->prob.M) return FFBIE_OK;
+  for (void* p : {(void*)c->d_near_t, (void*)c->d_near_az, (void*)c->d_near_ts,
+                  (void*)c->d_near_kappa})
+    if (p) hipFree(p);
+  c->d_near_t = nullptr; c->d_near_az = nullptr; c->d_near_ts = nullptr; c->d_near_kappa = nullptr;
+  c->near_cap = 0;
+  if (hipMalloc(&c->d_near_t, pairs * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_near_az, pairs * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&c->d_near_ts, pairs * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_near_kappa, pairs * 2 * c->prob.M * sizeof(cplx)) != hipSuccess)
+    return fail(c, FFBIE_ENOMEM, "ffbie: near-pair workspace allocation failed");
+  c->near_cap = pairs;
+  c->near_cap_M = c->prob.M;
+  return FFBIE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ffbie_status ffbie_kernel_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_t* d_az,
+                                 const double* d_ts, void* d_kappa, void* d_rhoinv, double* d_root,
+                                 int32_t* d_pair_status) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_kernel_coeffs: no problem set");
+  if (n < 0) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs: n_pairs < 0");
+  if (n == 0) return FFBIE_OK;
+  if (!d_t || !d_az || !d_ts || !d_kappa)
+    return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs: NULL input or kappa pointer");
+  if (n > (int64_t)1 << 31) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs: n_pairs > 2^31");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  return run_coeffs(c, n, d_t, d_az, d_ts, d_kappa, d_rhoinv, d_root, d_pair_status);
+}
+
+ffbie_status ffbie_builtin_near_rule(ffbie_near_rule* out) {
+  if (!out) return FFBIE_EINVAL;
+  builtin_rule(out);
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_set_near_rule(ffbie_ctx* c, const ffbie_near_rule* rule) {
+  if (!c) return FFBIE_EINVAL;
+  ffbie_near_rule r;
+  if (rule) {
+    r = *rule;
+  } else {
+    builtin_rule(&r);
+  }
+  for (int l = 0; l < kNodes; ++l)
+    for (int q = 0; q < kNodes; ++q) {
+      const double sx = r.self_x[l][q], rx = r.right_x[l][q];
+      if (!(std::fabs(sx) < 1.0) || !(std::fabs(rx) < 1.0) || !std::isfinite(r.self_w[l][q]) ||
+          !std::isfinite(r.right_w[l][q]))
+        return fail(c, FFBIE_EINVAL, "ffbie_set_near_rule: nodes must lie in (-1, 1), weights finite");
+      if (std::fabs(sx - c->gl_x[l]) < 1e-13)
+        return fail(c, FFBIE_EINVAL, "ffbie_set_near_rule: a self-panel node coincides with its target");
+    }
+  c->rule = r;
+  c->sys_ready = false;
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_query(ffbie_ctx* c, int64_t* n_unknowns_out, int64_t* n_near_pairs) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_query: no problem set");
+  const SysDims d = sys_dims(c);
+  if (n_unknowns_out) *n_unknowns_out = d.N;
+  if (n_near_pairs) *n_near_pairs = near_pairs_before(c->n_panels, d);
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_near_pairs(ffbie_ctx* c, double* d_t, int32_t* d_az, double* d_ts) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_near_pairs: no problem set");
+  if (!d_t || !d_az || !d_ts) return fail(c, FFBIE_EINVAL, "ffbie_near_pairs: NULL output");
+  ffbie_status s = prepare_system(c);
+  if (s != FFBIE_OK) return s;
+  const SysDims d = sys_dims(c);
+  NearChunk ch{0, c->n_panels, 0, near_pairs_before(c->n_panels, d)};
+  FFBIE_HIP(c, launch_near_pairs(d, ch, c->gl_x, c->d_rule_y, d_t, d_az, d_ts, c->stream));
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_collocation(ffbie_ctx* c, double* d_xyz, double* d_jac, double* d_wq) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_collocation: no problem set");
+  if (!d_xyz) return fail(c, FFBIE_EINVAL, "ffbie_collocation: NULL d_xyz");
+  ffbie_status s = prepare_system(c);
+  if (s != FFBIE_OK) return s;
+  FFBIE_HIP(c, launch_collocation(c->prob.g, sys_dims(c), c->gl_x, c->gl_w, colloc_view(c), d_xyz,
+                                  d_jac, d_wq, c->stream));
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_rhs(ffbie_ctx* c, int kind, const double* params, void* d_g) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_rhs: no problem set");
+  if (!params || !d_g) return fail(c, FFBIE_EINVAL, "ffbie_rhs: NULL pointer");
+  if (kind != FFBIE_RHS_POINT_SOURCE && kind != FFBIE_RHS_PLANE_WAVE)
+    return fail(c, FFBIE_EINVAL, "ffbie_rhs: unknown kind");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(params[i])) return fail(c, FFBIE_EINVAL, "ffbie_rhs: non-finite parameter");
+  ffbie_status s = prepare_system(c);
+  if (s != FFBIE_OK) return s;
+  FFBIE_HIP(c, launch_rhs(sys_dims(c), c->prob.k, kind, params, colloc_view(c),
+                          static_cast<cplx*>(d_g), c->stream));
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_assemble(ffbie_ctx* c, void* d_S, int64_t ld) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_assemble: no problem set");
+  const SysDims d = sys_dims(c);
+  if (!d_S || ld < d.N) return fail(c, FFBIE_EINVAL, "ffbie_assemble: NULL matrix or ld < N");
+  ffbie_status s = prepare_system(c);
+  if (s != FFBIE_OK) return s;
+  cplx* S = static_cast<cplx*>(d_S);
+  FFBIE_HIP(c, launch_far_assembly(d, c->prob.k, colloc_view(c), S, ld, c->stream));
+  // near blocks, a chunk of target panels at a time
+  const int64_t per_rel = (int64_t)kNodes * 2 * d.M * kNodes;      // pairs of one relation
+  const int64_t cap_pairs = kNearKappaBytes / (int64_t)(2 * d.M * sizeof(cplx));
+  int64_t max_chunk = 0;
+  for (int p0 = 0; p0 < c->n_panels;) {
+    int p1 = p0 + 1;
+    while (p1 < c->n_panels &&
+           (near_relations_before(p1 + 1, d.n_panels) - near_relations_before(p0, d.n_panels)) *
+                   per_rel <= cap_pairs)
+      ++p1;
+    const int64_t np = (near_relations_before(p1, d.n_panels) - near_relations_before(p0, d.n_panels)) *
+                       per_rel;
+    if (np > max_chunk) max_chunk = np;
+    p0 = p1;
+  }
+  s = ensure_near_ws(c, max_chunk);
+  if (s != FFBIE_OK) return s;
+  for (int p0 = 0; p0 < c->n_panels;) {
+    int p1 = p0 + 1;
+    while (p1 < c->n_panels &&
+           (near_relations_before(p1 + 1, d.n_panels) - near_relations_before(p0, d.n_panels)) *
+                   per_rel <= cap_pairs)
+      ++p1;
+    NearChunk ch;
+    ch.p0 = p0;
+    ch.p1 = p1;
+    ch.pair_base = near_pairs_before(p0, d);
+    ch.n_pairs = near_pairs_before(p1, d) - ch.pair_base;
+    FFBIE_HIP(c, launch_near_pairs(d, ch, c->gl_x, c->d_rule_y, c->d_near_t, c->d_near_az,
+                                   c->d_near_ts, c->stream));
+    s = run_coeffs(c, ch.n_pairs, c->d_near_t, c->d_near_az, c->d_near_ts, c->d_near_kappa, nullptr,
+                   nullptr, nullptr);
+    if (s != FFBIE_OK) return s;
+    FFBIE_HIP(c, launch_near_assembly(d, ch, c->d_near_kappa, c->d_wl, c->d_tab, S, ld, c->stream));
+    p0 = p1;
+  }
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_eval_field(ffbie_ctx* c, int64_t n_pts, const double* d_pts, const void* d_phi,
+                              void* d_u) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_eval_field: no problem set");
+  if (n_pts < 0 || n_pts > 65535) return fail(c, FFBIE_EINVAL, "ffbie_eval_field: need 0 <= n_pts <= 65535");
+  if (n_pts == 0) return FFBIE_OK;
+  if (!d_pts || !d_phi || !d_u) return fail(c, FFBIE_EINVAL, "ffbie_eval_field: NULL pointer");
+  ffbie_status s = prepare_system(c);
+  if (s != FFBIE_OK) return s;
+  const SysDims d = sys_dims(c);
+  int n_chunks = (int)((2048 + n_pts - 1) / n_pts);
+  const int max_chunks = (int)((d.N + 255) / 256);
+  if (n_chunks > max_chunks) n_chunks = max_chunks;
+  if (n_chunks < 1) n_chunks = 1;
+  const int64_t need = n_pts * n_chunks;
+  if (need > c->partial_cap) {
+    if (c->d_partial) hipFree(c->d_partial);
+    c->d_partial = nullptr;
+    c->partial_cap = 0;
+    if (hipMalloc(&c->d_partial, need * sizeof(cplx)) != hipSuccess)
+      return fail(c, FFBIE_ENOMEM, "ffbie_eval_field: workspace allocation failed");
+    c->partial_cap = need;
+  }
+  FFBIE_HIP(c, launch_field(d, c->prob.k, colloc_view(c), n_pts, d_pts,
+                            static_cast<const cplx*>(d_phi), c->d_partial, n_chunks,
+                            static_cast<cplx*>(d_u), c->stream));
+  return FFBIE_OK;
+}
+
 ffbie_status ffbie_enable_timing(ffbie_ctx* c, int on) {
   if (!c) return FFBIE_EINVAL;
   FFBIE_HIP(c, hipSetDevice(c->device));
@@ -272,6 +632,131 @@ ffbie_status ffbie_singular_factor(ffbie_ctx* c, int64_t n, const double* d_b, i
   hipLaunchKernelGGL(ffbie_singular_factor_kernel, dim3((unsigned)blocks), dim3(64 * w), lds,
                      c->stream, n, d_b, m_max, d_A);
   FFBIE_HIP(c, hipGetLastError());
+  return FFBIE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kRestart = 100;
+
+ffbie_status ensure_solve_ws(ffbie_ctx* c, int64_t N, int method) {
+  if (!c->blas) {
+    if (rocblas_create_handle(&c->blas) != rocblas_status_success)
+      return fail(c, FFBIE_EBLAS, "ffbie_solve: rocblas_create_handle failed");
+  }
+  if (rocblas_set_stream(c->blas, c->stream) != rocblas_status_success)
+    return fail(c, FFBIE_EBLAS, "ffbie_solve: rocblas_set_stream failed");
+  if (c->solve_n != N) {
+    for (void* p : {(void*)c->d_ipiv, (void*)c->d_perm, (void*)c->d_info, (void*)c->d_vecs,
+                    (void*)c->d_small})
+      if (p) hipFree(p);
+    c->d_ipiv = nullptr; c->d_perm = nullptr; c->d_info = nullptr; c->d_vecs = nullptr;
+    c->d_small = nullptr; c->solve_n = 0;
+    if (hipMalloc(&c->d_ipiv, N * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&c->d_perm, N * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&c->d_info, sizeof(int)) != hipSuccess ||
+        hipMalloc(&c->d_vecs, 3 * N * sizeof(cplx)) != hipSuccess ||
+        hipMalloc(&c->d_small, (256 * (kRestart + 1) + kRestart + 1) * sizeof(cplx)) != hipSuccess)
+      return fail(c, FFBIE_ENOMEM, "ffbie_solve: workspace allocation failed");
+    c->solve_n = N;
+  }
+  if (method == FFBIE_SOLVE_LU32_IR64 && c->s32_n != N) {
+    if (c->d_s32) hipFree(c->d_s32);
+    c->d_s32 = nullptr;
+    c->s32_n = 0;
+    if (hipMalloc(&c->d_s32, (size_t)N * N * 8) != hipSuccess)
+      return fail(c, FFBIE_ENOMEM, "ffbie_solve: complex64 factor allocation failed");
+    c->s32_n = N;
+  }
+  if (method == FFBIE_SOLVE_GMRES && c->krylov_n != N) {
+    if (c->d_krylov) hipFree(c->d_krylov);
+    c->d_krylov = nullptr;
+    c->krylov_n = 0;
+    if (hipMalloc(&c->d_krylov, (size_t)(kRestart + 1) * N * sizeof(cplx)) != hipSuccess)
+      return fail(c, FFBIE_ENOMEM, "ffbie_solve: Krylov basis allocation failed");
+    c->krylov_n = N;
+  }
+  return FFBIE_OK;
+}
+
+SolveCtx solve_ctx(ffbie_ctx* c) {
+  SolveCtx sc;
+  sc.stream = c->stream;
+  sc.blas = c->blas;
+  sc.ipiv = c->d_ipiv;
+  sc.perm = c->d_perm;
+  sc.info = c->d_info;
+  sc.vec_tmp = c->d_vecs;
+  sc.vec_r = c->d_vecs + c->solve_n;
+  sc.vec_d = c->d_vecs + 2 * c->solve_n;
+  sc.partial = c->d_small;
+  sc.hvec = c->d_small + 256 * (kRestart + 1);
+  sc.s32 = c->d_s32;
+  sc.krylov = c->d_krylov;
+  return sc;
+}
+
+}  // namespace
+
+extern "C" {
+
+ffbie_status ffbie_solve(ffbie_ctx* c, int method, void* d_S, int64_t ld, const void* d_g,
+                         void* d_phi, double tol, int max_iter, ffbie_solve_info* info) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_solve: no problem set");
+  const int64_t N = n_unknowns(c);
+  if (!d_S || !d_g || !d_phi || ld < N || d_g == d_phi)
+    return fail(c, FFBIE_EINVAL, "ffbie_solve: NULL or aliased buffer, or ld < N");
+  if (method != FFBIE_SOLVE_LU64 && method != FFBIE_SOLVE_LU32_IR64 && method != FFBIE_SOLVE_GMRES)
+    return fail(c, FFBIE_EINVAL, "ffbie_solve: unknown method");
+  if (method != FFBIE_SOLVE_LU64 && (!(tol > 0) || max_iter < 1))
+    return fail(c, FFBIE_EINVAL, "ffbie_solve: need tol > 0 and max_iter >= 1");
+  if (N > 2147483647 / 2) return fail(c, FFBIE_EINVAL, "ffbie_solve: N too large");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  ffbie_status s = ensure_solve_ws(c, N, method);
+  if (s != FFBIE_OK) return s;
+  SolveCtx sc = solve_ctx(c);
+  cplx* S = static_cast<cplx*>(d_S);
+  const cplx* g = static_cast<const cplx*>(d_g);
+  cplx* phi = static_cast<cplx*>(d_phi);
+  SolveResult r;
+  int iters = 0;
+  double rel = std::nan("");
+  if (method == FFBIE_SOLVE_LU64) {
+    FFBIE_HIP(c, hipMemcpyAsync(phi, g, N * sizeof(cplx), hipMemcpyDeviceToDevice, c->stream));
+    r = lu64_factor_solve(sc, S, ld, N, phi);
+  } else if (method == FFBIE_SOLVE_LU32_IR64) {
+    r = lu32_ir64(sc, S, ld, N, g, phi, tol, max_iter, &iters, &rel);
+  } else {
+    r = gmres64(sc, S, ld, N, g, phi, tol, max_iter, kRestart, &iters, &rel);
+  }
+  if (r.hip != hipSuccess) return hip_fail(c, r.hip, "ffbie_solve");
+  if (r.blas != 0) return fail(c, FFBIE_EBLAS, "ffbie_solve: rocBLAS GEMM failed");
+  FFBIE_HIP(c, hipStreamSynchronize(c->stream));
+  if (info) {
+    info->iterations = iters;
+    info->converged = r.converged ? 1 : 0;
+    info->rel_residual = rel;
+  }
+  if (r.singular_col != 0) return fail(c, FFBIE_ESINGULAR, "ffbie_solve: exactly zero pivot");
+  if (!r.converged) return FFBIE_WNOTCONV;
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_residual(ffbie_ctx* c, const void* d_S, int64_t ld, const void* d_phi,
+                            const void* d_g, void* d_r) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_residual: no problem set");
+  const int64_t N = n_unknowns(c);
+  if (!d_S || !d_g || !d_phi || !d_r || ld < N)
+    return fail(c, FFBIE_EINVAL, "ffbie_residual: NULL buffer or ld < N");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  SolveCtx sc{};
+  sc.stream = c->stream;
+  FFBIE_HIP(c, residual64(sc, static_cast<const cplx*>(d_S), ld, N, static_cast<const cplx*>(d_phi),
+                          static_cast<const cplx*>(d_g), static_cast<cplx*>(d_r)));
   return FFBIE_OK;
 }
 

@@ -1,0 +1,368 @@
+// Assembly of the discrete single-layer system, right-hand sides and field
+// evaluation (paper Sec. 3.1 and 3.4) for gfx950.
+//
+// Layout: unknowns and collocation points share the index r = (i*16 + l)*2M + j
+// (panel i, Gauss-Legendre node l, azimuth j).  S is row-major: a row is one
+// collocation point, so every kernel below writes whole row segments and its
+// stores are coalesced.
+//
+//   collocation   one thread per point: x, y, z, Jacobian and the product
+//                 quadrature weight (h/2) w_l / (2M)            (eqs. (3.7)-(3.8))
+//   far blocks    |i - i'| >= 2: (h/2) w_l' (1/2M) e^{ik rho}/rho; a block of 256
+//                 threads owns 256 columns and walks 8 rows, so each thread keeps
+//                 its source point in registers; near columns are skipped
+//   near pairs    the (target, near-rule node) pairs fed to the coefficient kernels
+//   near blocks   one workgroup per (target point, near panel): contracts the 16
+//                 coefficient rows with the Lagrange-times-weight matrix of the
+//                 near rule, then inverse-DFTs the 16 contracted rows (discrete
+//                 Parseval, eq. (3.9)) with a radix-2 Stockham FFT in LDS and
+//                 writes 16 x 2M contiguous entries
+//   field, rhs    one workgroup per (point, source chunk) with a fixed-order
+//                 reduction; one thread per collocation point
+#include "ffbie_assembly.hpp"
+
+namespace ffbie {
+
+namespace {
+
+struct GL16 {
+  double x[kNodes], w[kNodes];
+};
+
+// Point of the star surface and the Jacobian |r_t x r_theta| (eq. (2.1)).
+__device__ void surface_point(const Geom& g, double t, double th, double* px, double* py,
+                              double* pz, double* jac) {
+  double st, ct, sth, cth;
+  sincos_bounded(t, &st, &ct);
+  sincos_bounded(th, &sth, &cth);
+  double R = 1.0, Rt = 0.0, Rth = 0.0;
+  for (int l = 1; l <= g.lmax; ++l) {
+    double sl, cl;
+    sincos_bounded(l * t, &sl, &cl);
+    for (int m = 0; m <= g.mmax; ++m) {
+      const double a = g.a[l - 1][m];
+      if (a == 0.0) continue;
+      double sm, cm;
+      sincos_bounded(m * th, &sm, &cm);
+      R = fma(a * sl, cm, R);
+      Rt = fma(a * l * cl, cm, Rt);
+      Rth = fma(-a * m * sl, sm, Rth);
+    }
+  }
+  const double ox = st * cth, oy = st * sth, oz = ct;          // omega
+  const double tx = ct * cth, ty = ct * sth, tz = -st;         // d omega / dt
+  const double hx = -st * sth, hy = st * cth, hz = 0.0;        // d omega / dtheta
+  const double rtx = Rt * ox + R * tx, rty = Rt * oy + R * ty, rtz = Rt * oz + R * tz;
+  const double rhx = Rth * ox + R * hx, rhy = Rth * oy + R * hy, rhz = Rth * oz + R * hz;
+  const double cx = rty * rhz - rtz * rhy;
+  const double cy = rtz * rhx - rtx * rhz;
+  const double cz = rtx * rhy - rty * rhx;
+  *px = R * ox;
+  *py = R * oy;
+  *pz = R * oz;
+  *jac = sqrt(cx * cx + cy * cy + cz * cz);
+}
+
+__global__ __launch_bounds__(256) void collocation_kernel(Geom g, SysDims d, GL16 gl, Colloc c,
+                                                          double* xyz, double* jac_out,
+                                                          double* wq_out) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= d.N) return;
+  const int nj = 2 * d.M;
+  const int j = (int)(r % nj);
+  const int l = (int)((r / nj) % kNodes);
+  const int i = (int)(r / (nj * kNodes));
+  const double t = i * d.h + 0.5 * d.h * (gl.x[l] + 1.0);
+  const double th = M_PI * j / d.M;
+  double x, y, z, J;
+  surface_point(g, t, th, &x, &y, &z, &J);
+  const double wq = 0.5 * d.h * gl.w[l] / nj;
+  c.x[r] = x;
+  c.y[r] = y;
+  c.z[r] = z;
+  c.wq[r] = wq;
+  c.jac[r] = J;
+  if (xyz) {
+    xyz[3 * r] = x;
+    xyz[3 * r + 1] = y;
+    xyz[3 * r + 2] = z;
+  }
+  if (jac_out) jac_out[r] = J;
+  if (wq_out) wq_out[r] = wq;
+}
+
+// One thread per (target point, relation slot, rule node) of the chunk.
+__global__ __launch_bounds__(256) void near_pairs_kernel(SysDims d, NearChunk ch, GL16 gl,
+                                                         const double* __restrict__ rule_y,
+                                                         double* t_out, int32_t* az_out,
+                                                         double* ts_out) {
+  const int nj = 2 * d.M;
+  const int64_t n_tgt = (int64_t)(ch.p1 - ch.p0) * kNodes * nj;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= n_tgt * 3 * kNodes) return;
+  const int q = (int)(idx % kNodes);
+  const int slot = (int)((idx / kNodes) % 3);
+  const int64_t tgt = idx / (3 * kNodes);
+  const int j = (int)(tgt % nj);
+  const int l = (int)((tgt / nj) % kNodes);
+  const int i = ch.p0 + (int)(tgt / ((int64_t)nj * kNodes));
+  const int nrel = near_relations(i, d.n_panels);
+  if (slot >= nrel) return;
+  const int rel = (i > 0) ? slot - 1 : slot;               // -1, 0, +1
+  const int64_t p = near_pairs_before(i, d) - ch.pair_base +
+                    (((int64_t)l * nj + j) * nrel + slot) * kNodes + q;
+  const double y = rule_y[(l * 3 + rel + 1) * kNodes + q];
+  t_out[p] = i * d.h + 0.5 * d.h * (gl.x[l] + 1.0);
+  az_out[p] = j;
+  ts_out[p] = (i + rel) * d.h + 0.5 * d.h * (y + 1.0);
+}
+
+constexpr int kFarRows = 8;
+
+__global__ __launch_bounds__(256) void far_kernel(SysDims d, double k, Colloc c,
+                                                  cplx* __restrict__ S, int64_t ld) {
+  const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (col >= d.N) return;
+  const int64_t per_panel = (int64_t)kNodes * 2 * d.M;
+  const int pc = (int)(col / per_panel);
+  const double xc = c.x[col], yc = c.y[col], zc = c.z[col], wc = c.wq[col];
+  const int64_t r0 = blockIdx.y * (int64_t)kFarRows;
+  for (int rr = 0; rr < kFarRows; ++rr) {
+    const int64_t r = r0 + rr;
+    if (r >= d.N) break;
+    const int pr = (int)(r / per_panel);
+    if (abs(pr - pc) <= 1) continue;
+    const double dx = xc - c.x[r], dy = yc - c.y[r], dz = zc - c.z[r];
+    const double rho = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
+    const double f = wc / rho;
+    double s, co;
+    sincos_bounded(k * rho, &s, &co);
+    S[r * ld + col] = mk(f * co, f * s);
+  }
+}
+
+// Inverse DFT size NF = 2M of G sequences held in LDS (positive exponent,
+// radix-2 Stockham); on return `src` holds the transforms.
+__device__ void block_ifft(cplx*& src, cplx*& dst, int G, int NF, int M, const double* tab) {
+  const int half = NF >> 1;
+  const int mask = 8 * M - 1, quarter = 2 * M;
+  for (int Ns = 1; Ns < NF; Ns <<= 1) {
+    for (int b = threadIdx.x; b < G * half; b += blockDim.x) {
+      const int s = b / half;
+      const int jj = b - s * half;
+      const int r = jj & (Ns - 1);
+      const int tk = r * ((4 * M) / Ns);                 // angle pi r / Ns
+      const cplx wt = mk(tab[(tk + quarter) & mask], tab[tk & mask]);
+      const int idxD = ((jj - r) << 1) + r;
+      const cplx* in = src + s * NF;
+      cplx* out = dst + s * NF;
+      const cplx v0 = in[jj], v1 = in[jj + half] * wt;
+      out[idxD] = v0 + v1;
+      out[idxD + Ns] = v0 - v1;
+    }
+    __syncthreads();
+    cplx* tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+}
+
+__global__ __launch_bounds__(256) void near_kernel(SysDims d, NearChunk ch,
+                                                   const cplx* __restrict__ kappa,
+                                                   const double* __restrict__ wl,
+                                                   const double* __restrict__ tab_g,
+                                                   cplx* __restrict__ S, int64_t ld, int G) {
+  extern __shared__ double lds[];
+  const int M = d.M, NF = 2 * M;
+  const int64_t tgt = blockIdx.x / 3;
+  const int slot = blockIdx.x % 3;
+  const int j = (int)(tgt % NF);
+  const int l = (int)((tgt / NF) % kNodes);
+  const int i = ch.p0 + (int)(tgt / ((int64_t)NF * kNodes));
+  const int nrel = near_relations(i, d.n_panels);
+  if (slot >= nrel) return;                          // uniform over the block
+  const int rel = (i > 0) ? slot - 1 : slot;
+  const int64_t p0 = near_pairs_before(i, d) - ch.pair_base +
+                     (((int64_t)l * NF + j) * nrel + slot) * kNodes;
+  const cplx* krow = kappa + p0 * NF;                // 16 rows of NF coefficients
+  const double* W = wl + (size_t)(l * 3 + rel + 1) * kNodes * kNodes;   // [q][l']
+
+  double* tab = lds;                                 // 8M doubles
+  double* w_s = tab + 8 * M;                         // 256 doubles
+  cplx* bufA = reinterpret_cast<cplx*>(w_s + kNodes * kNodes);
+  cplx* bufB = bufA + G * NF;
+  for (int x = threadIdx.x; x < 8 * M; x += blockDim.x) tab[x] = tab_g[x];
+  for (int x = threadIdx.x; x < kNodes * kNodes; x += blockDim.x) w_s[x] = W[x];
+  __syncthreads();
+
+  const int64_t row = ((int64_t)i * kNodes + l) * NF + j;
+  cplx* srow = S + row * ld + (int64_t)(i + rel) * kNodes * NF;
+  for (int g0 = 0; g0 < kNodes; g0 += G) {
+    // contract over the rule nodes, store in natural frequency order
+    for (int x = threadIdx.x; x < G * NF; x += blockDim.x) {
+      const int s = x / NF;
+      const int col = x - s * NF;                    // n = col - M + 1
+      const int lp = g0 + s;
+      cplx acc = mk(0.0, 0.0);
+#pragma unroll 4
+      for (int q = 0; q < kNodes; ++q) {
+        const cplx kv = krow[q * NF + col];
+        const double wv = w_s[q * kNodes + lp];
+        acc.re = fma(wv, kv.re, acc.re);
+        acc.im = fma(wv, kv.im, acc.im);
+      }
+      bufA[s * NF + ((col - M + 1 + NF) & (NF - 1))] = acc;
+    }
+    __syncthreads();
+    cplx* src = bufA;
+    cplx* dst = bufB;
+    block_ifft(src, dst, G, NF, M, tab);
+    for (int x = threadIdx.x; x < G * NF; x += blockDim.x) {
+      const int s = x / NF;
+      const int jp = x - s * NF;
+      srow[(int64_t)(g0 + s) * NF + jp] = src[s * NF + jp];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void rhs_kernel(SysDims d, double k, int kind, double p0,
+                                                  double p1, double p2, Colloc c, cplx* g) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= d.N) return;
+  if (kind == FFBIE_RHS_POINT_SOURCE) {
+    const double dx = c.x[r] - p0, dy = c.y[r] - p1, dz = c.z[r] - p2;
+    const double rho = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
+    double s, co;
+    sincos_bounded(k * rho, &s, &co);
+    const double f = 1.0 / (4.0 * M_PI * rho);
+    g[r] = mk(f * co, f * s);
+  } else {
+    const double ph = k * (p0 * c.x[r] + p1 * c.y[r] + p2 * c.z[r]);
+    double s, co;
+    sincos_bounded(ph, &s, &co);
+    g[r] = mk(-co, -s);
+  }
+}
+
+__global__ __launch_bounds__(256) void field_partial_kernel(SysDims d, double k, Colloc c,
+                                                            const double* __restrict__ pts,
+                                                            const cplx* __restrict__ phi,
+                                                            cplx* partial, int n_chunks) {
+  __shared__ double red[2][256];
+  const int64_t p = blockIdx.y;
+  const int chunk = blockIdx.x;
+  const int64_t per = (d.N + n_chunks - 1) / n_chunks;
+  const int64_t c0 = chunk * per;
+  const int64_t c1 = min(d.N, c0 + per);
+  const double px = pts[3 * p], py = pts[3 * p + 1], pz = pts[3 * p + 2];
+  double ar = 0.0, ai = 0.0;
+  for (int64_t s = c0 + threadIdx.x; s < c1; s += blockDim.x) {
+    const double dx = c.x[s] - px, dy = c.y[s] - py, dz = c.z[s] - pz;
+    const double rho = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
+    double sn, cs;
+    sincos_bounded(k * rho, &sn, &cs);
+    const double f = c.wq[s] / rho;
+    const cplx v = mk(f * cs, f * sn) * phi[s];
+    ar += v.re;
+    ai += v.im;
+  }
+  red[0][threadIdx.x] = ar;
+  red[1][threadIdx.x] = ai;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[p * n_chunks + chunk] = mk(red[0][0], red[1][0]);
+}
+
+__global__ void field_sum_kernel(int64_t n_pts, int n_chunks, const cplx* partial, cplx* u) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n_pts) return;
+  cplx acc = mk(0.0, 0.0);
+  for (int c = 0; c < n_chunks; ++c) acc = acc + partial[p * n_chunks + c];
+  u[p] = acc;
+}
+
+GL16 pack_gl(const double* x, const double* w) {
+  GL16 g;
+  for (int i = 0; i < kNodes; ++i) {
+    g.x[i] = x[i];
+    g.w[i] = w[i];
+  }
+  return g;
+}
+
+}  // namespace
+
+hipError_t launch_collocation(const Geom& g, const SysDims& d, const double* gl_x,
+                              const double* gl_w, Colloc c, double* xyz, double* jac,
+                              double* wq, hipStream_t s) {
+  const int64_t blocks = (d.N + 255) / 256;
+  hipLaunchKernelGGL(collocation_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g, d,
+                     pack_gl(gl_x, gl_w), c, xyz, jac, wq);
+  return hipGetLastError();
+}
+
+hipError_t launch_near_pairs(const SysDims& d, const NearChunk& ch, const double* gl_x,
+                             const double* rule_y, double* t, int32_t* az, double* ts,
+                             hipStream_t s) {
+  const int64_t n = (int64_t)(ch.p1 - ch.p0) * kNodes * 2 * d.M * 3 * kNodes;
+  const int64_t blocks = (n + 255) / 256;
+  double zero[kNodes] = {0};
+  hipLaunchKernelGGL(near_pairs_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d, ch,
+                     pack_gl(gl_x, zero), rule_y, t, az, ts);
+  return hipGetLastError();
+}
+
+hipError_t launch_far_assembly(const SysDims& d, double k, Colloc c, cplx* S, int64_t ld,
+                               hipStream_t s) {
+  const dim3 grid((unsigned)((d.N + 255) / 256), (unsigned)((d.N + kFarRows - 1) / kFarRows));
+  hipLaunchKernelGGL(far_kernel, grid, dim3(256), 0, s, d, k, c, S, ld);
+  return hipGetLastError();
+}
+
+int near_group(int M) {
+  const int NF = 2 * M;
+  int G = 1024 / NF;                                 // 2 G NF complex = 32 KiB
+  if (G > kNodes) G = kNodes;
+  if (G < 1) G = 1;
+  return G;
+}
+
+hipError_t launch_near_assembly(const SysDims& d, const NearChunk& ch, const cplx* kappa,
+                                const double* wl, const double* tab, cplx* S, int64_t ld,
+                                hipStream_t s) {
+  const int G = near_group(d.M);
+  const int NF = 2 * d.M;
+  const size_t lds = sizeof(double) * (8 * d.M + kNodes * kNodes) + sizeof(cplx) * 2 * G * NF;
+  const int64_t blocks = (int64_t)(ch.p1 - ch.p0) * kNodes * NF * 3;
+  hipLaunchKernelGGL(near_kernel, dim3((unsigned)blocks), dim3(256), lds, s, d, ch, kappa, wl, tab,
+                     S, ld, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs(const SysDims& d, double k, int kind, const double* p, Colloc c, cplx* g,
+                      hipStream_t s) {
+  const int64_t blocks = (d.N + 255) / 256;
+  hipLaunchKernelGGL(rhs_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d, k, kind, p[0], p[1],
+                     p[2], c, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_field(const SysDims& d, double k, Colloc c, int64_t n_pts, const double* pts,
+                        const cplx* phi, cplx* partial, int n_chunks, cplx* u, hipStream_t s) {
+  hipLaunchKernelGGL(field_partial_kernel, dim3(n_chunks, (unsigned)n_pts), dim3(256), 0, s, d, k,
+                     c, pts, phi, partial, n_chunks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(field_sum_kernel, dim3((unsigned)((n_pts + 255) / 256)), dim3(256), 0, s,
+                     n_pts, n_chunks, partial, u);
+  return hipGetLastError();
+}
+
+}  // namespace ffbie

@@ -1,0 +1,650 @@
+// Dense solvers for the single-layer system S phi~ = g (paper Sec. 3.4; the
+// paper does not name a solver).
+//
+// S is row-major (one row per collocation point).  LU with partial (row)
+// pivoting, S = P L U, works on that layout directly, so a row interchange
+// swaps two contiguous rows.  The factorisation is recursive (split the columns
+// in halves: factor the left half, apply its interchanges to the right half,
+// triangular solve with the unit-lower block, trailing update, factor the
+// trailing part, apply its interchanges back to the left half).  The trailing
+// updates are plain GEMMs (rocBLAS, matrix cores); the column pivot search,
+// interchanges, small triangular solves, substitutions, residuals and
+// precision conversion are the kernels below.  The same code runs in complex128
+// (LU64) and complex64 (the LU32 factor of mixed-precision refinement).
+//
+// Methods:
+//   LU64       factor S in place (S is overwritten), solve;
+//   LU32+IR64  factor a complex64 copy, then iterative refinement with the
+//              residual g - S phi evaluated in complex128 against the untouched S;
+//   GMRES      restarted GMRES in complex128 with the row-major matrix-vector
+//              product (classical Gram-Schmidt with one re-orthogonalisation).
+#include <rocblas/rocblas.h>
+
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "ffbie_solve.hpp"
+
+namespace ffbie {
+
+namespace {
+
+template <typename R>
+struct C2 {
+  R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ C2<R> cmul(C2<R> a, C2<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ C2<R> csub(C2<R> a, C2<R> b) {
+  return {a.re - b.re, a.im - b.im};
+}
+
+// ---------------------------------------------------------------------------
+// pivot search, interchange and scaling of one column (one workgroup)
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(1024) void pivot_kernel(C2<R>* S, int64_t ld, int64_t r0, int64_t m,
+                                                     int64_t c, int64_t* ipiv, int* info) {
+  __shared__ R best[1024];
+  __shared__ int64_t where[1024];
+  R b = -1;
+  int64_t w = r0;
+  for (int64_t r = r0 + threadIdx.x; r < r0 + m; r += blockDim.x) {
+    const C2<R> v = S[r * ld + c];
+    const R a = fabs(v.re) + fabs(v.im);
+    if (a > b) {
+      b = a;
+      w = r;
+    }
+  }
+  best[threadIdx.x] = b;
+  where[threadIdx.x] = w;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      const R o = best[threadIdx.x + s];
+      const int64_t ow = where[threadIdx.x + s];
+      if (o > best[threadIdx.x] || (o == best[threadIdx.x] && ow < where[threadIdx.x])) {
+        best[threadIdx.x] = o;
+        where[threadIdx.x] = ow;
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t p = where[0];
+  const bool zero = !(best[0] > 0);
+  if (threadIdx.x == 0) {
+    ipiv[c] = p;
+    if (zero && *info == 0) *info = (int)(c + 1);
+    if (p != r0) {
+      const C2<R> t = S[r0 * ld + c];
+      S[r0 * ld + c] = S[p * ld + c];
+      S[p * ld + c] = t;
+    }
+  }
+  __syncthreads();
+  if (zero) return;
+  const C2<R> piv = S[r0 * ld + c];
+  const R den = piv.re * piv.re + piv.im * piv.im;
+  const C2<R> inv = {piv.re / den, -piv.im / den};
+  for (int64_t r = r0 + 1 + threadIdx.x; r < r0 + m; r += blockDim.x)
+    S[r * ld + c] = cmul(S[r * ld + c], inv);
+}
+
+// Row interchanges k0..k1-1 (in order) on columns [c0, c1): one thread per column.
+template <typename R>
+__global__ __launch_bounds__(256) void laswp_kernel(C2<R>* S, int64_t ld, int64_t k0, int64_t k1,
+                                                    const int64_t* __restrict__ ipiv, int64_t c0,
+                                                    int64_t c1) {
+  const int64_t c = c0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= c1) return;
+  for (int64_t k = k0; k < k1; ++k) {
+    const int64_t p = ipiv[k];
+    if (p != k) {
+      const C2<R> t = S[k * ld + c];
+      S[k * ld + c] = S[p * ld + c];
+      S[p * ld + c] = t;
+    }
+  }
+}
+
+// X = L^{-1} X for a unit-lower n x n block L (n <= kTrsmBase) at rows
+// [r0, r0+n), columns [cl, cl+n), and X at rows [r0, r0+n), columns [cx, cx+nx).
+constexpr int kTrsmBase = 16;
+
+template <typename R>
+__global__ __launch_bounds__(256) void trsm_base_kernel(C2<R>* S, int64_t ld, int64_t r0, int n,
+                                                        int64_t cl, int64_t cx, int64_t nx) {
+  __shared__ C2<R> L[kTrsmBase][kTrsmBase];
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) L[e / n][e % n] = S[(r0 + e / n) * ld + cl + e % n];
+  __syncthreads();
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= nx) return;
+  C2<R> x[kTrsmBase];
+#pragma unroll
+  for (int i = 0; i < kTrsmBase; ++i) {
+    if (i < n) {
+      C2<R> v = S[(r0 + i) * ld + cx + j];
+      for (int k = 0; k < i; ++k) v = csub(v, cmul(L[i][k], x[k]));
+      x[i] = v;
+      S[(r0 + i) * ld + cx + j] = v;
+    }
+  }
+}
+
+template <typename R>
+__global__ void convert_kernel(const C2<double>* __restrict__ src, int64_t lds, C2<R>* dst,
+                               int64_t ldd, int64_t N) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  for (int64_t r = blockIdx.y; r < N; r += gridDim.y) {
+    const C2<double> v = src[r * lds + c];
+    dst[r * ldd + c] = C2<R>{(R)v.re, (R)v.im};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// triangular solves with the row-major factors, blocks of kSolveBlock rows
+// ---------------------------------------------------------------------------
+constexpr int kSolveBlock = 64;
+
+// Solve the diagonal block in place: lower unit (forward) or upper (backward).
+template <typename R, bool LOWER>
+__global__ __launch_bounds__(64) void tri_diag_kernel(const C2<R>* S, int64_t ld, int64_t k0,
+                                                      int nb, C2<R>* y) {
+  __shared__ C2<R> ys[kSolveBlock];
+  const int lane = threadIdx.x;
+  if (lane < nb) ys[lane] = y[k0 + lane];
+  __syncthreads();
+  if (lane == 0) {
+    if (LOWER) {
+      for (int i = 0; i < nb; ++i) {
+        C2<R> v = ys[i];
+        for (int k = 0; k < i; ++k) v = csub(v, cmul(S[(k0 + i) * ld + k0 + k], ys[k]));
+        ys[i] = v;
+      }
+    } else {
+      for (int i = nb - 1; i >= 0; --i) {
+        C2<R> v = ys[i];
+        for (int k = i + 1; k < nb; ++k) v = csub(v, cmul(S[(k0 + i) * ld + k0 + k], ys[k]));
+        const C2<R> d = S[(k0 + i) * ld + k0 + i];
+        const R den = d.re * d.re + d.im * d.im;
+        ys[i] = C2<R>{(v.re * d.re + v.im * d.im) / den, (v.im * d.re - v.re * d.im) / den};
+      }
+    }
+  }
+  __syncthreads();
+  if (lane < nb) y[k0 + lane] = ys[lane];
+}
+
+// y[r] -= sum_{c in block} S[r][c] y[c] for rows r in [r_begin, r_end): one wave per row.
+template <typename R>
+__global__ __launch_bounds__(256) void tri_update_kernel(const C2<R>* S, int64_t ld, int64_t k0,
+                                                         int nb, int64_t r_begin, int64_t r_end,
+                                                         C2<R>* y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = r_begin + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= r_end) return;
+  R sr = 0, si = 0;
+  if (lane < nb) {
+    const C2<R> a = S[r * ld + k0 + lane];
+    const C2<R> b = y[k0 + lane];
+    sr = a.re * b.re - a.im * b.im;
+    si = a.re * b.im + a.im * b.re;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    sr += __shfl_xor(sr, o);
+    si += __shfl_xor(si, o);
+  }
+  if (lane == 0) {
+    C2<R> v = y[r];
+    y[r] = C2<R>{v.re - sr, v.im - si};
+  }
+}
+
+// out[r] = b[r] - sum_c S[r][c] x[c] (complex128), one wave per row.
+__global__ __launch_bounds__(256) void residual_kernel(const C2<double>* __restrict__ S, int64_t ld,
+                                                       int64_t N, const C2<double>* __restrict__ x,
+                                                       const C2<double>* __restrict__ b,
+                                                       C2<double>* out, double alpha) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= N) return;
+  double sr = 0, si = 0;
+  const C2<double>* row = S + r * ld;
+  for (int64_t c = lane; c < N; c += 64) {
+    const C2<double> a = row[c], v = x[c];
+    sr = fma(a.re, v.re, fma(-a.im, v.im, sr));
+    si = fma(a.re, v.im, fma(a.im, v.re, si));
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    sr += __shfl_xor(sr, o);
+    si += __shfl_xor(si, o);
+  }
+  if (lane == 0) {
+    const C2<double> bb = b ? b[r] : C2<double>{0, 0};
+    out[r] = C2<double>{bb.re - alpha * sr, bb.im - alpha * si};
+  }
+}
+
+template <typename R>
+__global__ void gather_kernel(const C2<R>* src, const int64_t* perm, C2<R>* dst, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[perm[i]];
+}
+
+template <typename R>
+__global__ void to_prec_kernel(const C2<double>* src, C2<R>* dst, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = C2<R>{(R)src[i].re, (R)src[i].im};
+}
+
+__global__ void add_kernel(C2<double>* x, const C2<float>* d, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] = C2<double>{x[i].re + (double)d[i].re, x[i].im + (double)d[i].im};
+}
+
+// partial sums of conj(a_k) . w for k < nv (columns of V, stride N), and of |w|^2
+__global__ __launch_bounds__(256) void multidot_kernel(const C2<double>* V, int64_t N, int nv,
+                                                       const C2<double>* w, C2<double>* partial,
+                                                       int nblk) {
+  __shared__ double red[2][256];
+  const int k = blockIdx.y;
+  const C2<double>* a = (k < nv) ? V + (int64_t)k * N : w;
+  double sr = 0, si = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const C2<double> p = a[i], q = w[i];
+    sr = fma(p.re, q.re, fma(p.im, q.im, sr));
+    si = fma(p.re, q.im, fma(-p.im, q.re, si));
+  }
+  red[0][threadIdx.x] = sr;
+  red[1][threadIdx.x] = si;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[k * nblk + blockIdx.x] = C2<double>{red[0][0], red[1][0]};
+}
+
+// w -= sum_k h_k V_k ; then optionally scale w into V_out: V_out = w / nrm
+__global__ void orth_update_kernel(const C2<double>* V, int64_t N, int nv, const C2<double>* h,
+                                   C2<double>* w) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  C2<double> v = w[i];
+  for (int k = 0; k < nv; ++k) {
+    const C2<double> a = V[(int64_t)k * N + i], c = h[k];
+    v.re -= c.re * a.re - c.im * a.im;
+    v.im -= c.re * a.im + c.im * a.re;
+  }
+  w[i] = v;
+}
+
+__global__ void scale_copy_kernel(const C2<double>* w, double s, C2<double>* out, int64_t N) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N) out[i] = C2<double>{w[i].re * s, w[i].im * s};
+}
+
+// x += sum_k y_k V_k
+__global__ void combine_kernel(const C2<double>* V, int64_t N, int nv, const C2<double>* y,
+                               C2<double>* x) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  C2<double> v = x[i];
+  for (int k = 0; k < nv; ++k) {
+    const C2<double> a = V[(int64_t)k * N + i], c = y[k];
+    v.re += c.re * a.re - c.im * a.im;
+    v.im += c.re * a.im + c.im * a.re;
+  }
+  x[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// host-side recursion
+// ---------------------------------------------------------------------------
+inline dim3 grid1(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
+
+rocblas_status gemm_sub(rocblas_handle h, C2<double>* S, int64_t ld, int64_t r_a, int64_t c_a,
+                        int64_t r_b, int64_t c_b, int64_t r_c, int64_t c_c, int64_t m, int64_t n,
+                        int64_t k) {
+  // row-major C(m x n) -= A(m x k) B(k x n)  <=>  col-major C^T -= B^T A^T
+  const rocblas_double_complex alpha(-1.0, 0.0), beta(1.0, 0.0);
+  auto p = [&](int64_t r, int64_t c) {
+    return reinterpret_cast<rocblas_double_complex*>(S + r * ld + c);
+  };
+  return rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)n,
+                       (rocblas_int)m, (rocblas_int)k, &alpha, p(r_b, c_b), (rocblas_int)ld,
+                       p(r_a, c_a), (rocblas_int)ld, &beta, p(r_c, c_c), (rocblas_int)ld);
+}
+rocblas_status gemm_sub(rocblas_handle h, C2<float>* S, int64_t ld, int64_t r_a, int64_t c_a,
+                        int64_t r_b, int64_t c_b, int64_t r_c, int64_t c_c, int64_t m, int64_t n,
+                        int64_t k) {
+  const rocblas_float_complex alpha(-1.0f, 0.0f), beta(1.0f, 0.0f);
+  auto p = [&](int64_t r, int64_t c) {
+    return reinterpret_cast<rocblas_float_complex*>(S + r * ld + c);
+  };
+  return rocblas_cgemm(h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)n,
+                       (rocblas_int)m, (rocblas_int)k, &alpha, p(r_b, c_b), (rocblas_int)ld,
+                       p(r_a, c_a), (rocblas_int)ld, &beta, p(r_c, c_c), (rocblas_int)ld);
+}
+
+struct Err {
+  hipError_t hip = hipSuccess;
+  rocblas_status blas = rocblas_status_success;
+  bool ok() const { return hip == hipSuccess && blas == rocblas_status_success; }
+};
+
+// X (rows [r0, r0+n), cols [cx, cx+nx)) = L^{-1} X, L unit lower at cols [cl, cl+n).
+template <typename R>
+void trsm_rec(SolveCtx& sc, C2<R>* S, int64_t ld, int64_t r0, int64_t n, int64_t cl, int64_t cx,
+              int64_t nx, Err& e) {
+  if (!e.ok() || n <= 1 || nx <= 0) return;
+  if (n <= kTrsmBase) {
+    hipLaunchKernelGGL(trsm_base_kernel<R>, grid1(nx), dim3(256), 0, sc.stream, S, ld, r0, (int)n,
+                       cl, cx, nx);
+    e.hip = hipGetLastError();
+    return;
+  }
+  const int64_t n1 = n / 2, n2 = n - n1;
+  trsm_rec(sc, S, ld, r0, n1, cl, cx, nx, e);
+  if (!e.ok()) return;
+  e.blas = gemm_sub(sc.blas, S, ld, r0 + n1, cl, r0, cx, r0 + n1, cx, n2, nx, n1);
+  trsm_rec(sc, S, ld, r0 + n1, n2, cl + n1, cx, nx, e);
+}
+
+// Factor rows [r0, r0+m) x cols [c0, c0+n) (m >= n), row interchanges recorded
+// in ipiv[c0 .. c0+n) as absolute row indices, applied inside these columns.
+template <typename R>
+void getrf_rec(SolveCtx& sc, C2<R>* S, int64_t ld, int64_t r0, int64_t m, int64_t c0, int64_t n,
+               int64_t* ipiv, int* info, Err& e) {
+  if (!e.ok()) return;
+  if (n == 1) {
+    hipLaunchKernelGGL(pivot_kernel<R>, dim3(1), dim3(1024), 0, sc.stream, S, ld, r0, m, c0, ipiv,
+                       info);
+    e.hip = hipGetLastError();
+    return;
+  }
+  const int64_t n1 = n / 2, n2 = n - n1;
+  getrf_rec(sc, S, ld, r0, m, c0, n1, ipiv, info, e);
+  if (!e.ok()) return;
+  hipLaunchKernelGGL(laswp_kernel<R>, grid1(n2), dim3(256), 0, sc.stream, S, ld, c0, c0 + n1,
+                     ipiv, c0 + n1, c0 + n);
+  e.hip = hipGetLastError();
+  trsm_rec(sc, S, ld, r0, n1, c0, c0 + n1, n2, e);
+  if (!e.ok()) return;
+  e.blas = gemm_sub(sc.blas, S, ld, r0 + n1, c0, r0, c0 + n1, r0 + n1, c0 + n1, m - n1, n2, n1);
+  if (!e.ok()) return;
+  getrf_rec(sc, S, ld, r0 + n1, m - n1, c0 + n1, n2, ipiv, info, e);
+  if (!e.ok()) return;
+  hipLaunchKernelGGL(laswp_kernel<R>, grid1(n1), dim3(256), 0, sc.stream, S, ld, c0 + n1, c0 + n,
+                     ipiv, c0, c0 + n1);
+  e.hip = hipGetLastError();
+}
+
+// y := U^{-1} L^{-1} y (after the row permutation has been applied to y).
+template <typename R>
+hipError_t lu_substitute(SolveCtx& sc, const C2<R>* S, int64_t ld, int64_t N, C2<R>* y) {
+  for (int64_t k0 = 0; k0 < N; k0 += kSolveBlock) {
+    const int nb = (int)std::min<int64_t>(kSolveBlock, N - k0);
+    hipLaunchKernelGGL((tri_diag_kernel<R, true>), dim3(1), dim3(64), 0, sc.stream, S, ld, k0, nb, y);
+    if (k0 + nb < N)
+      hipLaunchKernelGGL(tri_update_kernel<R>, grid1(N - k0 - nb, 4), dim3(256), 0, sc.stream, S,
+                         ld, k0, nb, k0 + nb, N, y);
+  }
+  for (int64_t k1 = N; k1 > 0; k1 -= kSolveBlock) {
+    const int64_t k0 = std::max<int64_t>(0, k1 - kSolveBlock);
+    const int nb = (int)(k1 - k0);
+    hipLaunchKernelGGL((tri_diag_kernel<R, false>), dim3(1), dim3(64), 0, sc.stream, S, ld, k0, nb,
+                       y);
+    if (k0 > 0)
+      hipLaunchKernelGGL(tri_update_kernel<R>, grid1(k0, 4), dim3(256), 0, sc.stream, S, ld, k0, nb,
+                         (int64_t)0, k0, y);
+  }
+  return hipGetLastError();
+}
+
+// Permutation of the right-hand side implied by the interchanges: perm[i] is the
+// original index of the entry that ends at position i.
+std::vector<int64_t> compose_perm(const std::vector<int64_t>& ipiv) {
+  const int64_t N = (int64_t)ipiv.size();
+  std::vector<int64_t> p(N);
+  for (int64_t i = 0; i < N; ++i) p[i] = i;
+  for (int64_t k = 0; k < N; ++k) std::swap(p[k], p[ipiv[k]]);
+  return p;
+}
+
+double norm2(SolveCtx& sc, const C2<double>* v, int64_t N, hipError_t* err) {
+  const int nblk = 256;
+  hipLaunchKernelGGL(multidot_kernel, dim3(nblk, 1), dim3(256), 0, sc.stream, v, N, 0, v,
+                     reinterpret_cast<C2<double>*>(sc.partial), nblk);
+  std::vector<C2<double>> h(nblk);
+  *err = hipMemcpyAsync(h.data(), sc.partial, nblk * sizeof(C2<double>), hipMemcpyDeviceToHost,
+                        sc.stream);
+  if (*err == hipSuccess) *err = hipStreamSynchronize(sc.stream);
+  double s = 0;
+  for (auto& x : h) s += x.re;
+  return std::sqrt(s);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// entry points used by the C ABI
+// ---------------------------------------------------------------------------
+template <typename R>
+static SolveResult lu_factor_solve_t(SolveCtx& sc, C2<R>* S, int64_t ld, int64_t N, C2<R>* y,
+                                     bool factor) {
+  SolveResult res;
+  if (factor) {
+    Err e;
+    hipError_t he = hipMemsetAsync(sc.info, 0, sizeof(int), sc.stream);
+    if (he != hipSuccess) { res.hip = he; return res; }
+    getrf_rec(sc, S, ld, 0, N, 0, N, sc.ipiv, sc.info, e);
+    if (!e.ok()) { res.hip = e.hip; res.blas = (int)e.blas; return res; }
+    int info = 0;
+    std::vector<int64_t> ipiv(N);
+    res.hip = hipMemcpyAsync(&info, sc.info, sizeof(int), hipMemcpyDeviceToHost, sc.stream);
+    if (res.hip == hipSuccess)
+      res.hip = hipMemcpyAsync(ipiv.data(), sc.ipiv, N * sizeof(int64_t), hipMemcpyDeviceToHost, sc.stream);
+    if (res.hip == hipSuccess) res.hip = hipStreamSynchronize(sc.stream);
+    if (res.hip != hipSuccess) return res;
+    res.singular_col = info;
+    const std::vector<int64_t> perm = compose_perm(ipiv);
+    res.hip = hipMemcpyAsync(sc.perm, perm.data(), N * sizeof(int64_t), hipMemcpyHostToDevice, sc.stream);
+    if (res.hip != hipSuccess) return res;
+    res.hip = hipStreamSynchronize(sc.stream);
+    if (res.hip != hipSuccess || info != 0) return res;
+  }
+  C2<R>* tmp = reinterpret_cast<C2<R>*>(sc.vec_tmp);
+  hipLaunchKernelGGL(gather_kernel<R>, grid1(N), dim3(256), 0, sc.stream, y, sc.perm, tmp, N);
+  res.hip = hipMemcpyAsync(y, tmp, N * sizeof(C2<R>), hipMemcpyDeviceToDevice, sc.stream);
+  if (res.hip != hipSuccess) return res;
+  res.hip = lu_substitute(sc, S, ld, N, y);
+  return res;
+}
+
+SolveResult lu64_factor_solve(SolveCtx& sc, cplx* S, int64_t ld, int64_t N, cplx* y) {
+  return lu_factor_solve_t(sc, reinterpret_cast<C2<double>*>(S), ld, N,
+                           reinterpret_cast<C2<double>*>(y), true);
+}
+
+SolveResult lu32_ir64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cplx* g, cplx* x,
+                      double tol, int max_iter, int* iters, double* rel_res) {
+  SolveResult res;
+  auto* S64 = reinterpret_cast<const C2<double>*>(S);
+  auto* g64 = reinterpret_cast<const C2<double>*>(g);
+  auto* x64 = reinterpret_cast<C2<double>*>(x);
+  auto* S32 = reinterpret_cast<C2<float>*>(sc.s32);
+  auto* r64 = reinterpret_cast<C2<double>*>(sc.vec_r);
+  auto* d32 = reinterpret_cast<C2<float>*>(sc.vec_d);
+  hipLaunchKernelGGL(convert_kernel<float>, dim3((unsigned)((N + 255) / 256), (unsigned)std::min<int64_t>(N, 8192)), dim3(256),
+                     0, sc.stream, S64, ld, S32, N, N);
+  res.hip = hipGetLastError();
+  if (res.hip != hipSuccess) return res;
+  // x = 0, r = g
+  res.hip = hipMemsetAsync(x64, 0, N * sizeof(C2<double>), sc.stream);
+  if (res.hip != hipSuccess) return res;
+  res.hip = hipMemcpyAsync(r64, g64, N * sizeof(C2<double>), hipMemcpyDeviceToDevice, sc.stream);
+  if (res.hip != hipSuccess) return res;
+  hipError_t he;
+  const double gn = norm2(sc, g64, N, &he);
+  if (he != hipSuccess) { res.hip = he; return res; }
+  double rn = gn;
+  int it = 0;
+  bool factored = false;
+  while (true) {
+    if (gn == 0 || rn <= tol * gn || it >= max_iter) break;
+    hipLaunchKernelGGL(to_prec_kernel<float>, grid1(N), dim3(256), 0, sc.stream, r64, d32, N);
+    SolveResult s = lu_factor_solve_t(sc, S32, N, N, d32, !factored);
+    factored = true;
+    if (s.hip != hipSuccess || s.blas != 0 || s.singular_col != 0) return s;
+    hipLaunchKernelGGL(add_kernel, grid1(N), dim3(256), 0, sc.stream, x64, d32, N);
+    hipLaunchKernelGGL(residual_kernel, grid1(N, 4), dim3(256), 0, sc.stream, S64, ld, N, x64, g64,
+                       r64, 1.0);
+    rn = norm2(sc, r64, N, &he);
+    if (he != hipSuccess) { res.hip = he; return res; }
+    ++it;
+  }
+  *iters = it;
+  *rel_res = gn > 0 ? rn / gn : 0.0;
+  res.converged = gn == 0 || rn <= tol * gn;
+  return res;
+}
+
+SolveResult gmres64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cplx* g, cplx* x,
+                    double tol, int max_iter, int restart, int* iters, double* rel_res) {
+  SolveResult res;
+  auto* S64 = reinterpret_cast<const C2<double>*>(S);
+  auto* g64 = reinterpret_cast<const C2<double>*>(g);
+  auto* x64 = reinterpret_cast<C2<double>*>(x);
+  auto* V = reinterpret_cast<C2<double>*>(sc.krylov);        // [restart+1][N]
+  auto* w = reinterpret_cast<C2<double>*>(sc.vec_r);
+  auto* hdev = reinterpret_cast<C2<double>*>(sc.hvec);
+  const int nblk = 256;
+  hipError_t he;
+  res.hip = hipMemsetAsync(x64, 0, N * sizeof(C2<double>), sc.stream);
+  if (res.hip != hipSuccess) return res;
+  const double gn = norm2(sc, g64, N, &he);
+  if (he != hipSuccess) { res.hip = he; return res; }
+  if (gn == 0) { *iters = 0; *rel_res = 0; res.converged = true; return res; }
+  int total = 0;
+  double rn = gn;
+  using cd = std::complex<double>;
+  while (total < max_iter && rn > tol * gn) {
+    // r = g - S x -> V_0
+    hipLaunchKernelGGL(residual_kernel, grid1(N, 4), dim3(256), 0, sc.stream, S64, ld, N, x64, g64, w, 1.0);
+    const double beta = norm2(sc, w, N, &he);
+    if (he != hipSuccess) { res.hip = he; return res; }
+    rn = beta;
+    if (rn <= tol * gn) break;
+    hipLaunchKernelGGL(scale_copy_kernel, grid1(N), dim3(256), 0, sc.stream, w, 1.0 / beta, V, N);
+    std::vector<cd> Hc((restart + 1) * restart, 0.0), cs(restart), sn(restart), e1(restart + 1, 0.0);
+    e1[0] = beta;
+    int j = 0;
+    for (; j < restart && total < max_iter; ++j, ++total) {
+      // w = S V_j
+      hipLaunchKernelGGL(residual_kernel, grid1(N, 4), dim3(256), 0, sc.stream, S64, ld, N,
+                         V + (int64_t)j * N, (const C2<double>*)nullptr, w, -1.0);
+      std::vector<cd> hcol(j + 2, 0.0);
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(multidot_kernel, dim3(nblk, j + 1), dim3(256), 0, sc.stream, V, N, j + 1,
+                           w, reinterpret_cast<C2<double>*>(sc.partial), nblk);
+        std::vector<C2<double>> part((j + 1) * nblk);
+        he = hipMemcpyAsync(part.data(), sc.partial, part.size() * sizeof(C2<double>),
+                            hipMemcpyDeviceToHost, sc.stream);
+        if (he == hipSuccess) he = hipStreamSynchronize(sc.stream);
+        if (he != hipSuccess) { res.hip = he; return res; }
+        std::vector<C2<double>> hk(j + 1);
+        for (int k = 0; k <= j; ++k) {
+          double a = 0, b = 0;
+          for (int q = 0; q < nblk; ++q) { a += part[k * nblk + q].re; b += part[k * nblk + q].im; }
+          hk[k] = C2<double>{a, b};
+          hcol[k] += cd(a, b);
+        }
+        he = hipMemcpyAsync(hdev, hk.data(), (j + 1) * sizeof(C2<double>), hipMemcpyHostToDevice, sc.stream);
+        if (he != hipSuccess) { res.hip = he; return res; }
+        hipLaunchKernelGGL(orth_update_kernel, grid1(N), dim3(256), 0, sc.stream, V, N, j + 1, hdev, w);
+      }
+      const double hn = norm2(sc, w, N, &he);
+      if (he != hipSuccess) { res.hip = he; return res; }
+      hcol[j + 1] = hn;
+      if (hn > 0)
+        hipLaunchKernelGGL(scale_copy_kernel, grid1(N), dim3(256), 0, sc.stream, w, 1.0 / hn,
+                           V + (int64_t)(j + 1) * N, N);
+      // Givens rotations
+      for (int k = 0; k < j; ++k) {
+        const cd t = cs[k] * hcol[k] + sn[k] * hcol[k + 1];
+        hcol[k + 1] = -std::conj(sn[k]) * hcol[k] + cs[k] * hcol[k + 1];
+        hcol[k] = t;
+      }
+      // complex Givens rotation with real cosine zeroing hcol[j+1]
+      const double den = std::sqrt(std::norm(hcol[j]) + std::norm(hcol[j + 1]));
+      {
+        const double a = std::abs(hcol[j]);
+        if (a == 0) {
+          cs[j] = 0.0;
+          sn[j] = 1.0;
+        } else {
+          const cd ph = hcol[j] / a;
+          cs[j] = a / den;
+          sn[j] = ph * std::conj(hcol[j + 1]) / den;
+        }
+      }
+      const cd hj = cs[j] * hcol[j] + sn[j] * hcol[j + 1];
+      hcol[j] = hj;
+      hcol[j + 1] = 0.0;
+      e1[j + 1] = -std::conj(sn[j]) * e1[j];
+      e1[j] = cs[j] * e1[j];
+      for (int k = 0; k <= j; ++k) Hc[k * restart + j] = hcol[k];
+      rn = std::abs(e1[j + 1]);
+      if (rn <= tol * gn || hn == 0) { ++j; ++total; break; }
+    }
+    // back substitution y = H^{-1} e1 (j x j upper), x += V y
+    std::vector<cd> y(j);
+    for (int i = j - 1; i >= 0; --i) {
+      cd v = e1[i];
+      for (int k = i + 1; k < j; ++k) v -= Hc[i * restart + k] * y[k];
+      y[i] = v / Hc[i * restart + i];
+    }
+    std::vector<C2<double>> yd(j);
+    for (int i = 0; i < j; ++i) yd[i] = C2<double>{y[i].real(), y[i].imag()};
+    he = hipMemcpyAsync(hdev, yd.data(), j * sizeof(C2<double>), hipMemcpyHostToDevice, sc.stream);
+    if (he != hipSuccess) { res.hip = he; return res; }
+    hipLaunchKernelGGL(combine_kernel, grid1(N), dim3(256), 0, sc.stream, V, N, j, hdev, x64);
+    he = hipStreamSynchronize(sc.stream);
+    if (he != hipSuccess) { res.hip = he; return res; }
+  }
+  // true residual
+  hipLaunchKernelGGL(residual_kernel, grid1(N, 4), dim3(256), 0, sc.stream, S64, ld, N, x64, g64, w, 1.0);
+  rn = norm2(sc, w, N, &he);
+  if (he != hipSuccess) { res.hip = he; return res; }
+  *iters = total;
+  *rel_res = rn / gn;
+  res.converged = rn <= tol * gn;
+  return res;
+}
+
+hipError_t residual64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cplx* x,
+                      const cplx* g, cplx* r) {
+  hipLaunchKernelGGL(residual_kernel, grid1(N, 4), dim3(256), 0, sc.stream,
+                     reinterpret_cast<const C2<double>*>(S), ld, N,
+                     reinterpret_cast<const C2<double>*>(x), reinterpret_cast<const C2<double>*>(g),
+                     reinterpret_cast<C2<double>*>(r), 1.0);
+  return hipGetLastError();
+}
+
+double device_norm2(SolveCtx& sc, const cplx* v, int64_t N, hipError_t* err) {
+  return norm2(sc, reinterpret_cast<const C2<double>*>(v), N, err);
+}
+
+}  // namespace ffbie

@@ -1,0 +1,41 @@
+// Interface of the dense solvers (row-major complex matrices).
+#pragma once
+#include <rocblas/rocblas.h>
+
+#include "ffbie_device.hpp"
+
+namespace ffbie {
+
+// Device workspaces and handles the solvers use; owned by the context.
+struct SolveCtx {
+  hipStream_t stream;
+  rocblas_handle blas;
+  int64_t* ipiv;       // [N] pivot rows
+  int64_t* perm;       // [N] permutation of the right-hand side
+  int* info;           // first zero pivot (1-based), 0 if none
+  void* vec_tmp;       // [N] complex128
+  void* vec_r;         // [N] complex128
+  void* vec_d;         // [N] complex128 (holds a complex64 vector)
+  void* partial;       // reduction partials: 256 x (restart + 1) complex128
+  void* hvec;          // [restart + 1] complex128
+  void* s32;           // [N][N] complex64 (mixed-precision factor), or null
+  void* krylov;        // [restart + 1][N] complex128 (GMRES), or null
+};
+
+struct SolveResult {
+  hipError_t hip = hipSuccess;
+  int blas = 0;              // rocblas_status of a failed GEMM
+  int singular_col = 0;      // 1-based column of an exactly zero pivot
+  bool converged = true;
+};
+
+SolveResult lu64_factor_solve(SolveCtx& sc, cplx* S, int64_t ld, int64_t N, cplx* y);
+SolveResult lu32_ir64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cplx* g, cplx* x,
+                      double tol, int max_iter, int* iters, double* rel_res);
+SolveResult gmres64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cplx* g, cplx* x,
+                    double tol, int max_iter, int restart, int* iters, double* rel_res);
+hipError_t residual64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cplx* x,
+                      const cplx* g, cplx* r);
+double device_norm2(SolveCtx& sc, const cplx* v, int64_t N, hipError_t* err);
+
+}  // namespace ffbie

@@ -1,0 +1,117 @@
+"""GPU parity of the discrete single-layer system (Sec. 3.1, 3.4) against the
+oracle: collocation data, near pairs, right-hand sides, sampled rows of the
+assembled matrix, and the field evaluation.  The oracle's own near-panel rules
+(tests/golden) are loaded into the library so that both sides use the same rule;
+near rules are not unique, and each side's table is pinned separately by its
+exactness.
+
+Tolerances: 1e-13 for geometry, right-hand sides and field sums (plain sums of
+O(N) well-conditioned terms); 1e-10 relative to the row's largest entry for
+matrix rows, the bound of the kernel coefficients they are built from.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import assembly as oasm
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _rule():
+    from test_oracle_system import load_golden
+    return load_golden()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2608_16208_amd as ffbie
+    c = ffbie.Context(0)
+    c.set_near_rule(_rule())
+    yield c
+    c.close()
+
+
+def _problem(ctx, cfgi):
+    cfg = workloads.config(cfgi)
+    ctx.set_problem(cfg["amp"], cfg["n_panels"], cfg["M"], cfg["k"])
+    return cfg
+
+
+@pytest.mark.parametrize("cfgi", [1, 2])
+def test_collocation_matches_oracle(ctx, cfgi):
+    cfg = _problem(ctx, cfgi)
+    xyz, jac, wq = (v.cpu().numpy() for v in ctx.collocation())
+    x_o, j_o, w_o = oasm.collocation(cfg["amp"], cfg["n_panels"], cfg["M"])
+    assert np.max(np.abs(xyz - x_o)) <= 1e-13
+    assert np.max(np.abs(jac - j_o)) / np.max(j_o) <= 1e-13
+    assert np.max(np.abs(wq - w_o) / w_o) <= 1e-13
+
+
+def test_near_pairs_match_oracle(ctx):
+    cfg = _problem(ctx, 1)
+    t, az, ts = (v.cpu().numpy() for v in ctx.near_pairs())
+    N, n_near = ctx.query()
+    assert N == 32 * cfg["M"] * cfg["n_panels"]
+    assert n_near == 512 * cfg["M"] * (3 * cfg["n_panels"] - 2) == t.size
+    t_o, az_o, ts_o = oasm.near_pairs(cfg["n_panels"], cfg["M"], _rule())
+    assert np.array_equal(az, az_o)
+    assert np.max(np.abs(t - t_o)) <= 4e-16 and np.max(np.abs(ts - ts_o)) <= 4e-16
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_rhs_matches_oracle(ctx, kind):
+    cfg = _problem(ctx, 2)
+    p = [3.0, 4.0, 10.5] if kind == 0 else list(cfg["d"])
+    g = ctx.rhs(kind, p).cpu().numpy()
+    if kind == 0:
+        ref = oasm.rhs_point_source(cfg["amp"], cfg["n_panels"], cfg["M"], cfg["k"], p)
+    else:
+        ref = oasm.rhs_plane_wave(cfg["amp"], cfg["n_panels"], cfg["M"], cfg["k"], p)
+    assert np.max(np.abs(g - ref)) / np.max(np.abs(ref)) <= 1e-13
+
+
+def _sample_rows(cfg, n, seed):
+    rng = np.random.default_rng(seed)
+    npan, M = cfg["n_panels"], cfg["M"]
+    N = 32 * M * npan
+    per_panel = 32 * M
+    # first and last panel (two near relations) plus uniform rows
+    rows = [int(rng.integers(0, per_panel)), int(N - 1 - rng.integers(0, per_panel))]
+    rows += list(rng.choice(N, n - 2, replace=False))
+    return np.array(sorted(set(rows)))
+
+
+@pytest.mark.parametrize("cfgi", [1, 2])
+def test_assembled_rows_match_oracle(ctx, cfgi):
+    """Full-size assembly (config 1: N = 8192; config 2: N = 32768, 17 GB);
+    sampled rows checked entry by entry."""
+    cfg = _problem(ctx, cfgi)
+    N, _ = ctx.query()
+    S = ctx.assemble()
+    torch.cuda.synchronize()
+    rows = _sample_rows(cfg, 6, seed=10 + cfgi)
+    got = S[torch.tensor(rows, device=ctx.device)].cpu().numpy()
+    del S
+    torch.cuda.empty_cache()
+    ref = oasm.rows(cfg["amp"], cfg["k"], cfg["M"], cfg["n_panels"], rows, _rule(), processes=8)
+    for a, r in enumerate(rows):
+        scale = np.max(np.abs(ref[a]))
+        err = np.max(np.abs(got[a] - ref[a])) / scale
+        assert np.isfinite(got[a]).all()
+        assert err <= 1e-10, (int(r), err)
+
+
+def test_field_matches_oracle(ctx):
+    cfg = _problem(ctx, 2)
+    N, _ = ctx.query()
+    rng = np.random.default_rng(3)
+    phi = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    dirs = rng.standard_normal((64, 3))
+    pts = dirs / np.linalg.norm(dirs, axis=1)[:, None] * rng.uniform(3, 5, 64)[:, None]
+    u = ctx.eval_field(torch.tensor(pts), torch.tensor(phi)).cpu().numpy()
+    ref = oasm.field(cfg["amp"], cfg["n_panels"], cfg["M"], cfg["k"], phi, pts)
+    assert np.max(np.abs(u - ref)) / np.max(np.abs(ref)) <= 1e-12
