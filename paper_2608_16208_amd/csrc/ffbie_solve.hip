@@ -1,16 +1,19 @@
 // Dense solvers for the single-layer system S phi~ = g (paper Sec. 3.4; the
 // paper does not name a solver).
 //
-// S is row-major (one row per collocation point).  LU with partial (row)
-// pivoting, S = P L U, works on that layout directly, so a row interchange
-// swaps two contiguous rows.  The factorisation is recursive (split the columns
-// in halves: factor the left half, apply its interchanges to the right half,
-// triangular solve with the unit-lower block, trailing update, factor the
-// trailing part, apply its interchanges back to the left half).  The trailing
-// updates are plain GEMMs (rocBLAS, matrix cores); the column pivot search,
-// interchanges, small triangular solves, substitutions, residuals and
-// precision conversion are the kernels below.  The same code runs in complex128
-// (LU64) and complex64 (the LU32 factor of mixed-precision refinement).
+// S is row-major (one row per collocation point).  Read as a column-major
+// array the same memory is A = S^T, and A is factored with partial (row)
+// pivoting, A = P L U, so the pivot search scans a contiguous column of A;
+// then S = U^T L^T P^T and S phi = g is solved by a forward substitution with
+// U^T, a backward one with L^T (rows of both are contiguous rows of S) and the
+// permutation P.  The factorisation is recursive (split the columns in halves:
+// factor the left half, apply its interchanges to the right half, triangular
+// solve with the unit-lower block, trailing update, factor the trailing part,
+// apply its interchanges back to the left half).  The trailing updates are
+// plain GEMMs (rocBLAS, matrix cores); the pivot search, interchanges, small
+// triangular solves, substitutions, residuals and precision conversion are the
+// kernels below.  The same code runs in complex128 (LU64) and complex64 (the
+// LU32 factor of mixed-precision refinement).
 //
 // Methods:
 //   LU64       factor S in place (S is overwritten), solve;
@@ -45,7 +48,7 @@ __device__ __forceinline__ C2<R> csub(C2<R> a, C2<R> b) {
 }
 
 // ---------------------------------------------------------------------------
-// pivot search, interchange and scaling of one column (one workgroup)
+// pivot search, interchange and scaling of one column of A (one workgroup)
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ __launch_bounds__(1024) void pivot_kernel(C2<R>* S, int64_t ld, int64_t r0, int64_t m,
@@ -54,8 +57,9 @@ __global__ __launch_bounds__(1024) void pivot_kernel(C2<R>* S, int64_t ld, int64
   __shared__ int64_t where[1024];
   R b = -1;
   int64_t w = r0;
+  const C2<R>* col = S + c * ld;                      // column c of A = S^T
   for (int64_t r = r0 + threadIdx.x; r < r0 + m; r += blockDim.x) {
-    const C2<R> v = S[r * ld + c];
+    const C2<R> v = col[r];
     const R a = fabs(v.re) + fabs(v.im);
     if (a > b) {
       b = a;
@@ -82,21 +86,22 @@ __global__ __launch_bounds__(1024) void pivot_kernel(C2<R>* S, int64_t ld, int64
     ipiv[c] = p;
     if (zero && *info == 0) *info = (int)(c + 1);
     if (p != r0) {
-      const C2<R> t = S[r0 * ld + c];
-      S[r0 * ld + c] = S[p * ld + c];
-      S[p * ld + c] = t;
+      const C2<R> t = S[c * ld + r0];
+      S[c * ld + r0] = S[c * ld + p];
+      S[c * ld + p] = t;
     }
   }
   __syncthreads();
   if (zero) return;
-  const C2<R> piv = S[r0 * ld + c];
+  C2<R>* colw = S + c * ld;
+  const C2<R> piv = colw[r0];
   const R den = piv.re * piv.re + piv.im * piv.im;
   const C2<R> inv = {piv.re / den, -piv.im / den};
-  for (int64_t r = r0 + 1 + threadIdx.x; r < r0 + m; r += blockDim.x)
-    S[r * ld + c] = cmul(S[r * ld + c], inv);
+  for (int64_t r = r0 + 1 + threadIdx.x; r < r0 + m; r += blockDim.x) colw[r] = cmul(colw[r], inv);
 }
 
-// Row interchanges k0..k1-1 (in order) on columns [c0, c1): one thread per column.
+// Row interchanges k0..k1-1 (in order) of A on its columns [c0, c1): one
+// thread per column (a contiguous row segment of S).
 template <typename R>
 __global__ __launch_bounds__(256) void laswp_kernel(C2<R>* S, int64_t ld, int64_t k0, int64_t k1,
                                                     const int64_t* __restrict__ ipiv, int64_t c0,
@@ -106,33 +111,35 @@ __global__ __launch_bounds__(256) void laswp_kernel(C2<R>* S, int64_t ld, int64_
   for (int64_t k = k0; k < k1; ++k) {
     const int64_t p = ipiv[k];
     if (p != k) {
-      const C2<R> t = S[k * ld + c];
-      S[k * ld + c] = S[p * ld + c];
-      S[p * ld + c] = t;
+      C2<R>* colw = S + c * ld;
+      const C2<R> t = colw[k];
+      colw[k] = colw[p];
+      colw[p] = t;
     }
   }
 }
 
-// X = L^{-1} X for a unit-lower n x n block L (n <= kTrsmBase) at rows
+// X = L^{-1} X for a unit-lower n x n block L of A (n <= kTrsmBase) at rows
 // [r0, r0+n), columns [cl, cl+n), and X at rows [r0, r0+n), columns [cx, cx+nx).
 constexpr int kTrsmBase = 16;
 
 template <typename R>
 __global__ __launch_bounds__(256) void trsm_base_kernel(C2<R>* S, int64_t ld, int64_t r0, int n,
                                                         int64_t cl, int64_t cx, int64_t nx) {
-  __shared__ C2<R> L[kTrsmBase][kTrsmBase];
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) L[e / n][e % n] = S[(r0 + e / n) * ld + cl + e % n];
+  __shared__ C2<R> L[kTrsmBase][kTrsmBase];                  // L[i][k] = A(r0 + i, cl + k)
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) L[e % n][e / n] = S[(cl + e / n) * ld + r0 + e % n];
   __syncthreads();
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= nx) return;
+  C2<R>* xcol = S + (cx + j) * ld + r0;                      // column cx + j of A
   C2<R> x[kTrsmBase];
 #pragma unroll
   for (int i = 0; i < kTrsmBase; ++i) {
     if (i < n) {
-      C2<R> v = S[(r0 + i) * ld + cx + j];
+      C2<R> v = xcol[i];
       for (int k = 0; k < i; ++k) v = csub(v, cmul(L[i][k], x[k]));
       x[i] = v;
-      S[(r0 + i) * ld + cx + j] = v;
+      xcol[i] = v;
     }
   }
 }
@@ -151,35 +158,37 @@ __global__ void convert_kernel(const C2<double>* __restrict__ src, int64_t lds, 
 // ---------------------------------------------------------------------------
 // triangular solves with the row-major factors, blocks of kSolveBlock rows
 // ---------------------------------------------------------------------------
-constexpr int kSolveBlock = 64;
+constexpr int kSolveBlock = 32;
 
-// Solve the diagonal block in place: lower unit (forward) or upper (backward).
+// Solve the diagonal block [k0, k0+nb) of a triangular matrix T with
+// T(i, j) = S[i*ld + j] in place: LOWER (forward, T = U^T, non-unit) or upper
+// (backward, T = L^T, unit diagonal).  The block is staged in LDS; lane j holds
+// y_j and the solved value is broadcast across the wavefront step by step.
 template <typename R, bool LOWER>
 __global__ __launch_bounds__(64) void tri_diag_kernel(const C2<R>* S, int64_t ld, int64_t k0,
                                                       int nb, C2<R>* y) {
-  __shared__ C2<R> ys[kSolveBlock];
+  __shared__ C2<R> T[kSolveBlock][kSolveBlock];
   const int lane = threadIdx.x;
-  if (lane < nb) ys[lane] = y[k0 + lane];
+  for (int e = lane; e < nb * nb; e += 64) T[e / nb][e % nb] = S[(k0 + e / nb) * ld + k0 + e % nb];
   __syncthreads();
-  if (lane == 0) {
-    if (LOWER) {
-      for (int i = 0; i < nb; ++i) {
-        C2<R> v = ys[i];
-        for (int k = 0; k < i; ++k) v = csub(v, cmul(S[(k0 + i) * ld + k0 + k], ys[k]));
-        ys[i] = v;
-      }
-    } else {
-      for (int i = nb - 1; i >= 0; --i) {
-        C2<R> v = ys[i];
-        for (int k = i + 1; k < nb; ++k) v = csub(v, cmul(S[(k0 + i) * ld + k0 + k], ys[k]));
-        const C2<R> d = S[(k0 + i) * ld + k0 + i];
+  C2<R> v = (lane < nb) ? y[k0 + lane] : C2<R>{0, 0};
+  if (LOWER) {
+    for (int i = 0; i < nb; ++i) {
+      if (lane == i) {
+        const C2<R> d = T[i][i];
         const R den = d.re * d.re + d.im * d.im;
-        ys[i] = C2<R>{(v.re * d.re + v.im * d.im) / den, (v.im * d.re - v.re * d.im) / den};
+        v = C2<R>{(v.re * d.re + v.im * d.im) / den, (v.im * d.re - v.re * d.im) / den};
       }
+      const C2<R> yi = {__shfl(v.re, i), __shfl(v.im, i)};
+      if (lane > i && lane < nb) v = csub(v, cmul(T[lane][i], yi));
+    }
+  } else {
+    for (int i = nb - 1; i >= 0; --i) {
+      const C2<R> yi = {__shfl(v.re, i), __shfl(v.im, i)};
+      if (lane < i) v = csub(v, cmul(T[lane][i], yi));
     }
   }
-  __syncthreads();
-  if (lane < nb) y[k0 + lane] = ys[lane];
+  if (lane < nb) y[k0 + lane] = v;
 }
 
 // y[r] -= sum_{c in block} S[r][c] y[c] for rows r in [r_begin, r_end): one wave per row.
@@ -314,28 +323,29 @@ __global__ void combine_kernel(const C2<double>* V, int64_t N, int nv, const C2<
 // ---------------------------------------------------------------------------
 inline dim3 grid1(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
 
+// A(rC.., cC..) (m x n) -= A(rA.., cA..) (m x k) * A(rB.., cB..) (k x n), with
+// A(r, c) = S[c*ld + r] the column-major view.
 rocblas_status gemm_sub(rocblas_handle h, C2<double>* S, int64_t ld, int64_t r_a, int64_t c_a,
                         int64_t r_b, int64_t c_b, int64_t r_c, int64_t c_c, int64_t m, int64_t n,
                         int64_t k) {
-  // row-major C(m x n) -= A(m x k) B(k x n)  <=>  col-major C^T -= B^T A^T
   const rocblas_double_complex alpha(-1.0, 0.0), beta(1.0, 0.0);
   auto p = [&](int64_t r, int64_t c) {
-    return reinterpret_cast<rocblas_double_complex*>(S + r * ld + c);
+    return reinterpret_cast<rocblas_double_complex*>(S + c * ld + r);
   };
-  return rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)n,
-                       (rocblas_int)m, (rocblas_int)k, &alpha, p(r_b, c_b), (rocblas_int)ld,
-                       p(r_a, c_a), (rocblas_int)ld, &beta, p(r_c, c_c), (rocblas_int)ld);
+  return rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)m,
+                       (rocblas_int)n, (rocblas_int)k, &alpha, p(r_a, c_a), (rocblas_int)ld,
+                       p(r_b, c_b), (rocblas_int)ld, &beta, p(r_c, c_c), (rocblas_int)ld);
 }
 rocblas_status gemm_sub(rocblas_handle h, C2<float>* S, int64_t ld, int64_t r_a, int64_t c_a,
                         int64_t r_b, int64_t c_b, int64_t r_c, int64_t c_c, int64_t m, int64_t n,
                         int64_t k) {
   const rocblas_float_complex alpha(-1.0f, 0.0f), beta(1.0f, 0.0f);
   auto p = [&](int64_t r, int64_t c) {
-    return reinterpret_cast<rocblas_float_complex*>(S + r * ld + c);
+    return reinterpret_cast<rocblas_float_complex*>(S + c * ld + r);
   };
-  return rocblas_cgemm(h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)n,
-                       (rocblas_int)m, (rocblas_int)k, &alpha, p(r_b, c_b), (rocblas_int)ld,
-                       p(r_a, c_a), (rocblas_int)ld, &beta, p(r_c, c_c), (rocblas_int)ld);
+  return rocblas_cgemm(h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)m,
+                       (rocblas_int)n, (rocblas_int)k, &alpha, p(r_a, c_a), (rocblas_int)ld,
+                       p(r_b, c_b), (rocblas_int)ld, &beta, p(r_c, c_c), (rocblas_int)ld);
 }
 
 struct Err {
@@ -391,7 +401,7 @@ void getrf_rec(SolveCtx& sc, C2<R>* S, int64_t ld, int64_t r0, int64_t m, int64_
   e.hip = hipGetLastError();
 }
 
-// y := U^{-1} L^{-1} y (after the row permutation has been applied to y).
+// y := L^{-T} U^{-T} y: forward substitution with U^T, backward with L^T.
 template <typename R>
 hipError_t lu_substitute(SolveCtx& sc, const C2<R>* S, int64_t ld, int64_t N, C2<R>* y) {
   for (int64_t k0 = 0; k0 < N; k0 += kSolveBlock) {
@@ -413,14 +423,14 @@ hipError_t lu_substitute(SolveCtx& sc, const C2<R>* S, int64_t ld, int64_t N, C2
   return hipGetLastError();
 }
 
-// Permutation of the right-hand side implied by the interchanges: perm[i] is the
-// original index of the entry that ends at position i.
+// x = P z for A = P L U: the interchanges applied in reverse order; q[i] is the
+// index of z that lands at position i.
 std::vector<int64_t> compose_perm(const std::vector<int64_t>& ipiv) {
   const int64_t N = (int64_t)ipiv.size();
-  std::vector<int64_t> p(N);
-  for (int64_t i = 0; i < N; ++i) p[i] = i;
-  for (int64_t k = 0; k < N; ++k) std::swap(p[k], p[ipiv[k]]);
-  return p;
+  std::vector<int64_t> q(N);
+  for (int64_t i = 0; i < N; ++i) q[i] = i;
+  for (int64_t k = N - 1; k >= 0; --k) std::swap(q[k], q[ipiv[k]]);
+  return q;
 }
 
 double norm2(SolveCtx& sc, const C2<double>* v, int64_t N, hipError_t* err) {
@@ -465,11 +475,11 @@ static SolveResult lu_factor_solve_t(SolveCtx& sc, C2<R>* S, int64_t ld, int64_t
     res.hip = hipStreamSynchronize(sc.stream);
     if (res.hip != hipSuccess || info != 0) return res;
   }
+  res.hip = lu_substitute(sc, S, ld, N, y);
+  if (res.hip != hipSuccess) return res;
   C2<R>* tmp = reinterpret_cast<C2<R>*>(sc.vec_tmp);
   hipLaunchKernelGGL(gather_kernel<R>, grid1(N), dim3(256), 0, sc.stream, y, sc.perm, tmp, N);
   res.hip = hipMemcpyAsync(y, tmp, N * sizeof(C2<R>), hipMemcpyDeviceToDevice, sc.stream);
-  if (res.hip != hipSuccess) return res;
-  res.hip = lu_substitute(sc, S, ld, N, y);
   return res;
 }
 
