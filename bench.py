@@ -88,6 +88,79 @@ def cpu_baseline(cfg, n_sample, processes):
                        f"{dt:.1f} s wall on {processes} processes")
 
 
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def time_to_field_error(ctx, cfg, torch, np, ffbie, target=1e-8):
+    """Time to a field within `target` (relative l2 over 64 far points) of the
+    plain FP64 LU field of the same discretised system: assembly + solve +
+    field evaluation, for LU64 (the reference itself), LU32 + FP64 iterative
+    refinement and GMRES.  Sound-soft exterior problem, incident plane wave
+    along the workload's direction d, points at radius 3..5."""
+    ctx.set_near_rule(None)
+    ctx.set_problem(cfg["amp"], cfg["n_panels"], cfg["M"], cfg["k"])
+    S = ctx.assemble()                                  # warm-up (allocations, code objects)
+    S, t_asm = _timed(torch, lambda: ctx.assemble(S))
+    g = ctx.rhs(ffbie.RHS_PLANE_WAVE, cfg["d"])
+    rng = np.random.default_rng(1)
+    d = rng.standard_normal((64, 3))
+    pts = torch.tensor(d / np.linalg.norm(d, axis=1)[:, None] * rng.uniform(3, 5, 64)[:, None])
+    W = S.clone()
+    (phi, _), t_lu = _timed(torch, lambda: ctx.solve(W, g, method=ffbie.SOLVE_LU64))
+    del W
+    torch.cuda.empty_cache()
+    u_ref, t_f = _timed(torch, lambda: ctx.eval_field(pts, phi))
+    out = {"reference": "plain FP64 LU field of the same system, 64 points at |x| in [3, 5]",
+           "assembly_s": t_asm, "field_eval_s": t_f, "n_unknowns": int(S.shape[0]),
+           "lu64": {"s": t_asm + t_lu + t_f, "solve_s": t_lu}}
+
+    def err(phi_):
+        u = ctx.eval_field(pts, phi_)
+        return float(((u - u_ref).abs().norm() / u_ref.abs().norm()).item())
+
+    for it in range(1, 9):
+        (phi, info), t = _timed(torch, lambda: ctx.solve(S, g, method=ffbie.SOLVE_LU32_IR64,
+                                                        tol=1e-15, max_iter=it))
+        e = err(phi)
+        if e <= target or it == 8:
+            out["lu32_ir64"] = {"s": t_asm + t + t_f, "solve_s": t, "refinement_steps": it,
+                                "field_error": e, "rel_residual": info["rel_residual"]}
+            break
+    for tol in (1e-7, 3e-8, 1e-8, 3e-9, 1e-9, 1e-10):
+        (phi, info), t = _timed(torch, lambda: ctx.solve(S, g, method=ffbie.SOLVE_GMRES,
+                                                        tol=tol, max_iter=3000))
+        e = err(phi)
+        if e <= target or tol == 1e-10:
+            out["gmres"] = {"s": t_asm + t + t_f, "solve_s": t, "iterations": info["iterations"],
+                            "residual_tol": tol, "field_error": e}
+            break
+    del S
+    torch.cuda.empty_cache()
+    return out
+
+
+def near_set_rate(ctx, cfg, torch):
+    """Kernel coefficients of the near set (target x near-rule node pairs, the
+    method's own workload inside the assembly): pair-modes/s."""
+    ctx.set_problem(cfg["amp"], cfg["n_panels"], cfg["M"], cfg["k"])
+    t, az, ts = ctx.near_pairs()
+    n = t.numel()
+    kap = torch.empty((n, 2 * cfg["M"]), dtype=torch.complex128, device=ctx.device)
+    ctx.kernel_coeffs(t, az, ts, kappa=kap, status=False)
+    reps = 3
+    _, dt = _timed(torch, lambda: [ctx.kernel_coeffs(t, az, ts, kappa=kap, status=False)
+                                   for _ in range(reps)])
+    del kap
+    torch.cuda.empty_cache()
+    return {"pairs": n, "ms": 1e3 * dt / reps, "value": n * 2 * cfg["M"] * reps / dt,
+            "unit": "pair-modes/s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +170,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=6144)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-second-variant", action="store_true")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the assembly + solve + field measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 2 GiB device copy (reference dispatch for HBM counters)")
     args = ap.parse_args()
@@ -215,6 +290,9 @@ def main():
             "coeff_main_ms": float(per2[:, 1].mean())}
     del kappa
     torch.cuda.empty_cache()
+    if not args.no_solve:
+        result["time_to_1e-8_field_error"] = time_to_field_error(ctx, cfg, torch, np, ffbie)
+        result["near_set"] = near_set_rate(ctx, cfg, torch)
     if not args.no_cpu_baseline:
         procs = min(16, os.cpu_count() or 1)
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample, procs)
