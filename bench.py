@@ -161,6 +161,51 @@ def near_set_rate(ctx, cfg, torch):
             "unit": "pair-modes/s"}
 
 
+def batch_rate(ctx, torch, n_surfaces=64, arena_bytes=32 << 30):
+    """Batched coefficient path: the near sets of a batch of star surfaces with
+    their own M, k and panel counts, in persistent launches.  The outputs
+    (complex128, ~370 GB for 64 surfaces) go through one reusable arena of
+    `arena_bytes`, a chunk of whole surfaces per batched call."""
+    import workloads
+    surfs = []
+    for s in range(n_surfaces):
+        c = workloads.batch_surface(s)
+        ctx.set_problem(c["amp"], c["n_panels"], c["M"], c["k"])
+        t, az, ts = ctx.near_pairs()
+        surfs.append(dict(amp=c["amp"], M=c["M"], k=c["k"], t=t, az=az, ts=ts))
+    chunks, cur, used = [], [], 0
+    for sf in surfs:
+        b = sf["t"].numel() * 2 * sf["M"] * 16
+        if cur and used + b > arena_bytes:
+            chunks.append(cur)
+            cur, used = [], 0
+        cur.append(sf)
+        used += b
+    chunks.append(cur)
+    arena = torch.empty(arena_bytes // 16, dtype=torch.complex128, device=ctx.device)
+    max_pairs = max(sum(sf["t"].numel() for sf in ch) for ch in chunks)
+    status = torch.empty(max_pairs, dtype=torch.int32, device=ctx.device)
+
+    def run(ch):
+        items, off, soff = [], 0, 0
+        for sf in ch:
+            n = sf["t"].numel()
+            kap = arena[off:off + n * 2 * sf["M"]].view(n, 2 * sf["M"])
+            items.append(dict(sf, kappa=kap, status=status[soff:soff + n]))
+            off += n * 2 * sf["M"]
+            soff += n
+        ctx.kernel_coeffs_batched(items)
+
+    run(chunks[0])                                   # warm-up
+    _, dt = _timed(torch, lambda: [run(ch) for ch in chunks])
+    modes = sum(sf["t"].numel() * 2 * sf["M"] for sf in surfs)
+    del arena, status
+    torch.cuda.empty_cache()
+    return {"surfaces": n_surfaces, "pair_modes": int(modes), "pairs": int(sum(sf["t"].numel() for sf in surfs)),
+            "chunks": len(chunks), "arena_GB": arena_bytes / 2 ** 30, "s": dt,
+            "value": modes / dt, "unit": "pair-modes/s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +215,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=6144)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-second-variant", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched many-surface measurement")
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the assembly + solve + field measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -293,6 +340,8 @@ def main():
     if not args.no_solve:
         result["time_to_1e-8_field_error"] = time_to_field_error(ctx, cfg, torch, np, ffbie)
         result["near_set"] = near_set_rate(ctx, cfg, torch)
+    if not args.no_batch:
+        result["batch_64_surfaces"] = batch_rate(ctx, torch)
     if not args.no_cpu_baseline:
         procs = min(16, os.cpu_count() or 1)
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample, procs)

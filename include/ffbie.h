@@ -160,6 +160,33 @@ ffbie_status ffbie_get_timing(ffbie_ctx *ctx, double *ms_root, double *ms_main,
 ffbie_status ffbie_singular_factor(ffbie_ctx *ctx, int64_t n, const double *d_b,
                                    int m_max, double *d_A);
 
+/* Batched coefficients: the coefficient path of ffbie_kernel_coeffs for many
+ * independent problems (surfaces, wavenumbers, M) in one persistent launch
+ * per phase.  Each item is a problem and its pair list:
+ *   g, d, k        as for ffbie_set_problem (d.n_panels is not used;
+ *                  d.kappa_variant must be FFBIE_KAPPA_SWAP),
+ *   n_pairs, d_t, d_az, d_ts   the pairs, as for ffbie_kernel_coeffs,
+ *   d_kappa        [n_pairs][2M] complex128 output (required if n_pairs > 0),
+ *   d_pair_status  [n_pairs] int32 output (optional NULL).
+ * items is a HOST array of n_items entries.  Results are those of one
+ * ffbie_kernel_coeffs call per item.  The problem of ffbie_set_problem is
+ * left unchanged.  Work items of 64 pairs are taken from a device-side queue
+ * ordered by decreasing M, so problems of different cost share the GPU.
+ * The call waits for the small descriptor upload to finish (stream sync) before
+ * enqueuing the kernels. */
+typedef struct {
+  ffbie_geometry g;
+  ffbie_discretization d;
+  double k;
+  int64_t n_pairs;
+  const double *d_t;
+  const int32_t *d_az;
+  const double *d_ts;
+  void *d_kappa;
+  int32_t *d_pair_status;
+} ffbie_batch_item;
+ffbie_status ffbie_kernel_coeffs_batched(ffbie_ctx *ctx, int n_items, const ffbie_batch_item *items);
+
 /* ------------------------------------------------------------------------
  * The discrete single-layer system (Sec. 3.1 and 3.4)
  * ------------------------------------------------------------------------

@@ -21,7 +21,7 @@ EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_probl
            "ffbie_kernel_coeffs", "ffbie_singular_factor", "ffbie_enable_timing", "ffbie_get_timing",
            "ffbie_builtin_near_rule", "ffbie_set_near_rule", "ffbie_query", "ffbie_near_pairs",
            "ffbie_collocation", "ffbie_rhs", "ffbie_assemble", "ffbie_eval_field", "ffbie_solve",
-           "ffbie_residual")
+           "ffbie_residual", "ffbie_kernel_coeffs_batched")
 SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES = 0, 1, 2
 WNOTCONV = 2
 RHS_POINT_SOURCE, RHS_PLANE_WAVE = 0, 1
@@ -39,6 +39,12 @@ class _Geometry(ctypes.Structure):
 class _Disc(ctypes.Structure):
     _fields_ = [("n_panels", ctypes.c_int), ("M", ctypes.c_int), ("M0", ctypes.c_int),
                 ("eps0", ctypes.c_double), ("kappa_variant", ctypes.c_int)]
+
+
+class _BatchItem(ctypes.Structure):
+    _fields_ = [("g", _Geometry), ("d", _Disc), ("k", ctypes.c_double), ("n_pairs", ctypes.c_int64),
+                ("d_t", ctypes.c_void_p), ("d_az", ctypes.c_void_p), ("d_ts", ctypes.c_void_p),
+                ("d_kappa", ctypes.c_void_p), ("d_pair_status", ctypes.c_void_p)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -81,6 +87,7 @@ def load_library(path=LIB_PATH):
     lib.ffbie_eval_field.argtypes = [vp, i64, vp, vp, vp]
     lib.ffbie_solve.argtypes = [vp, i32, vp, i64, vp, vp, ctypes.c_double, i32, ctypes.POINTER(_SolveInfo)]
     lib.ffbie_residual.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.ffbie_kernel_coeffs_batched.argtypes = [vp, i32, ctypes.POINTER(_BatchItem)]
     for name in EXPORTS:
         f = getattr(lib, name)
         if name != "ffbie_last_error":
@@ -168,6 +175,44 @@ class Context:
                                           _ptr(out["rhoinv"]), _ptr(out["root"]), _ptr(out["status"]))
         self._check(rc, self.h)
         return out
+
+    def kernel_coeffs_batched(self, problems):
+        """Coefficient path for several problems in one launch per phase.
+        problems: list of dicts with amp, M, k, t, az, ts (and optional M0, eps0,
+        kappa [n, 2M] and status [n] output tensors).  Returns a list of dicts
+        with kappa and status."""
+        torch = self._torch
+        dev = self.device
+        keep, outs = [], []
+        arr = (_BatchItem * max(1, len(problems)))()
+        for i, pr in enumerate(problems):
+            a = np.ascontiguousarray(np.zeros((0, 1)) if pr.get("amp") is None else pr["amp"], dtype=np.float64)
+            M = int(pr["M"])
+            t = pr["t"].to(dev, torch.float64).contiguous()
+            ts = pr["ts"].to(dev, torch.float64).contiguous()
+            az = pr["az"].to(dev, torch.int32).contiguous()
+            n = t.numel()
+            if az.numel() != n or ts.numel() != n:
+                raise FfbieError("t, az and ts must have the same length")
+            kap = pr.get("kappa")
+            if kap is None:
+                kap = torch.empty((n, 2 * M), dtype=torch.complex128, device=dev)
+            st = pr.get("status")
+            if st is None:
+                st = torch.empty((n,), dtype=torch.int32, device=dev)
+            keep += [a, t, ts, az]
+            it = arr[i]
+            it.g = _Geometry(a.shape[0], a.shape[1] - 1, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+            it.d = _Disc(1, M, int(pr.get("M0", M)), float(pr.get("eps0", 0.0)), KAPPA_SWAP)
+            it.k = float(pr["k"])
+            it.n_pairs = n
+            it.d_t, it.d_az, it.d_ts = t.data_ptr(), az.data_ptr(), ts.data_ptr()
+            it.d_kappa, it.d_pair_status = kap.data_ptr(), st.data_ptr()
+            outs.append({"kappa": kap, "status": st})
+        rc = self.lib.ffbie_kernel_coeffs_batched(self.h, len(problems), arr)
+        self._check(rc, self.h)
+        self._batch_keep = keep        # inputs stay alive until the stream has used them
+        return outs
 
     def enable_timing(self, on=True):
         self._check(self.lib.ffbie_enable_timing(self.h, int(bool(on))), self.h)

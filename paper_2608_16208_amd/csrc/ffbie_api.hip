@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -68,6 +69,10 @@ struct ffbie_ctx {
   int64_t s32_n = 0;
   cplx* d_krylov = nullptr;
   int64_t krylov_n = 0;
+  // batched coefficients
+  double* d_tabs[4] = {nullptr, nullptr, nullptr, nullptr};   // angle tables for M = 16 .. 128
+  void* d_batch = nullptr;           // descriptors and prefix arrays
+  size_t batch_bytes = 0;
 };
 
 namespace {
@@ -199,6 +204,42 @@ Colloc colloc_view(const ffbie_ctx* c) {
   return Colloc{b, b + N, b + 2 * N, b + 3 * N, b + 4 * N};
 }
 
+// Validated problem constants from the C-ABI description.
+bool make_prob(const ffbie_geometry* g, const ffbie_discretization* d, double k, Prob* out,
+               std::string* why) {
+  if (!g || !d) { *why = "NULL geometry or discretisation"; return false; }
+  if (g->lmax < 0 || g->lmax > kMaxL || g->mmax < 0 || g->mmax > kMaxM || (g->lmax > 0 && !g->a)) {
+    *why = "amplitude table must have lmax <= 8, mmax <= 8";
+    return false;
+  }
+  if (!valid_M(d->M)) { *why = "M must be 16, 32, 64 or 128"; return false; }
+  if (d->M0 < 1 || d->M0 > d->M) { *why = "need 1 <= M0 <= M"; return false; }
+  if (d->n_panels < 1) { *why = "n_panels must be >= 1"; return false; }
+  if (!(k >= 0) || !std::isfinite(k)) { *why = "need k >= 0"; return false; }
+  if (!(d->eps0 >= 0) || d->eps0 >= 1) { *why = "need 0 <= eps0 < 1"; return false; }
+  if (d->kappa_variant != FFBIE_KAPPA_SWAP && d->kappa_variant != FFBIE_KAPPA_PAPER_CONV) {
+    *why = "unknown kappa_variant";
+    return false;
+  }
+  Prob P{};
+  P.g.lmax = g->lmax;
+  P.g.mmax = g->mmax;
+  for (int l = 0; l < g->lmax; ++l)
+    for (int m = 0; m <= g->mmax; ++m) {
+      const double v = g->a[l * (g->mmax + 1) + m];
+      if (!std::isfinite(v)) { *why = "non-finite amplitude"; return false; }
+      P.g.a[l][m] = v;
+    }
+  P.k = k;
+  P.eps0 = d->eps0 > 0 ? d->eps0 : 1e-15;
+  P.M = d->M;
+  P.M0 = d->M0;
+  P.L = d->M + d->M0;
+  P.tab_n = 8 * d->M;
+  *out = P;
+  return true;
+}
+
 ffbie_status ensure_ws(ffbie_ctx* c, int64_t n) {
   if (n <= c->ws_pairs) return FFBIE_OK;
   if (c->d_roots) hipFree(c->d_roots);
@@ -257,7 +298,9 @@ ffbie_status ffbie_destroy(ffbie_ctx* c) {
   for (void* p : {(void*)c->d_rule_y, (void*)c->d_wl, (void*)c->d_colloc, (void*)c->d_near_t,
                   (void*)c->d_near_az, (void*)c->d_near_ts, (void*)c->d_near_kappa,
                   (void*)c->d_partial, (void*)c->d_ipiv, (void*)c->d_perm, (void*)c->d_info,
-                  (void*)c->d_vecs, (void*)c->d_small, c->d_s32, (void*)c->d_krylov})
+                  (void*)c->d_vecs, (void*)c->d_small, c->d_s32, (void*)c->d_krylov,
+                  c->d_batch, (void*)c->d_tabs[0], (void*)c->d_tabs[1], (void*)c->d_tabs[2],
+                  (void*)c->d_tabs[3]})
     if (p) hipFree(p);
   if (c->blas) rocblas_destroy_handle(c->blas);
   delete c;
@@ -269,31 +312,9 @@ const char* ffbie_last_error(const ffbie_ctx* c) { return c ? c->err.c_str() : k
 ffbie_status ffbie_set_problem(ffbie_ctx* c, const ffbie_geometry* g, const ffbie_discretization* d,
                                double k) {
   if (!c) return FFBIE_EINVAL;
-  if (!g || !d) return fail(c, FFBIE_EINVAL, "ffbie_set_problem: NULL geometry or discretisation");
-  if (g->lmax < 0 || g->lmax > kMaxL || g->mmax < 0 || g->mmax > kMaxM || (g->lmax > 0 && !g->a))
-    return fail(c, FFBIE_EINVAL, "ffbie_set_problem: amplitude table must have lmax <= 8, mmax <= 8");
-  if (!valid_M(d->M)) return fail(c, FFBIE_EINVAL, "ffbie_set_problem: M must be 16, 32, 64 or 128");
-  if (d->M0 < 1 || d->M0 > d->M) return fail(c, FFBIE_EINVAL, "ffbie_set_problem: need 1 <= M0 <= M");
-  if (d->n_panels < 1) return fail(c, FFBIE_EINVAL, "ffbie_set_problem: n_panels must be >= 1");
-  if (!(k >= 0) || !std::isfinite(k)) return fail(c, FFBIE_EINVAL, "ffbie_set_problem: need k >= 0");
-  if (!(d->eps0 >= 0) || d->eps0 >= 1) return fail(c, FFBIE_EINVAL, "ffbie_set_problem: need 0 <= eps0 < 1");
-  if (d->kappa_variant != FFBIE_KAPPA_SWAP && d->kappa_variant != FFBIE_KAPPA_PAPER_CONV)
-    return fail(c, FFBIE_EINVAL, "ffbie_set_problem: unknown kappa_variant");
   Prob P{};
-  P.g.lmax = g->lmax;
-  P.g.mmax = g->mmax;
-  for (int l = 0; l < g->lmax; ++l)
-    for (int m = 0; m <= g->mmax; ++m) {
-      const double v = g->a[l * (g->mmax + 1) + m];
-      if (!std::isfinite(v)) return fail(c, FFBIE_EINVAL, "ffbie_set_problem: non-finite amplitude");
-      P.g.a[l][m] = v;
-    }
-  P.k = k;
-  P.eps0 = d->eps0 > 0 ? d->eps0 : 1e-15;
-  P.M = d->M;
-  P.M0 = d->M0;
-  P.L = d->M + d->M0;
-  P.tab_n = 8 * d->M;
+  std::string why;
+  if (!make_prob(g, d, k, &P, &why)) return fail(c, FFBIE_EINVAL, "ffbie_set_problem: " + why);
   FFBIE_HIP(c, hipSetDevice(c->device));
   if (c->d_tab) { hipFree(c->d_tab); c->d_tab = nullptr; }
   std::vector<double> tab(P.tab_n);
@@ -632,6 +653,126 @@ ffbie_status ffbie_singular_factor(ffbie_ctx* c, int64_t n, const double* d_b, i
   hipLaunchKernelGGL(ffbie_singular_factor_kernel, dim3((unsigned)blocks), dim3(64 * w), lds,
                      c->stream, n, d_b, m_max, d_A);
   FFBIE_HIP(c, hipGetLastError());
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_kernel_coeffs_batched(ffbie_ctx* c, int n_items, const ffbie_batch_item* items) {
+  if (!c) return FFBIE_EINVAL;
+  if (n_items < 0 || (n_items > 0 && !items))
+    return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_batched: invalid item array");
+  if (n_items >= (1 << 22)) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_batched: too many items");
+  // validate, and order the non-empty problems by decreasing M (cost per pair)
+  std::vector<Prob> probs(n_items);
+  std::vector<int> order;
+  int64_t total = 0;
+  int mm = 0, Mmax = 16;
+  for (int i = 0; i < n_items; ++i) {
+    const ffbie_batch_item& it = items[i];
+    std::string why;
+    if (!make_prob(&it.g, &it.d, it.k, &probs[i], &why))
+      return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_batched: item " + std::to_string(i) + ": " + why);
+    if (it.d.kappa_variant != FFBIE_KAPPA_SWAP)
+      return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_batched: only FFBIE_KAPPA_SWAP is batched");
+    if (it.n_pairs < 0 || it.n_pairs > ((int64_t)1 << 31))
+      return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_batched: n_pairs out of range");
+    if (it.n_pairs == 0) continue;
+    if (!it.d_t || !it.d_az || !it.d_ts || !it.d_kappa)
+      return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_batched: NULL pair or kappa pointer");
+    order.push_back(i);
+    total += it.n_pairs;
+    mm = std::max(mm, it.g.mmax);
+    Mmax = std::max(Mmax, it.d.M);
+  }
+  if (order.empty()) return FFBIE_OK;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return items[a].d.M > items[b].d.M; });
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  ffbie_status s = ensure_ws(c, total);
+  if (s != FFBIE_OK) return s;
+  for (int q = 0; q < 4; ++q) {
+    const int M = 16 << q;
+    if (c->d_tabs[q]) continue;
+    std::vector<double> tab(8 * M);
+    for (int i = 0; i < 8 * M; ++i) tab[i] = table_sin(i, M);
+    FFBIE_HIP(c, hipMalloc(&c->d_tabs[q], tab.size() * sizeof(double)));
+    FFBIE_HIP(c, hipMemcpy(c->d_tabs[q], tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  // launch shape: LDS for the largest problem
+  const int tab_max = 8 * Mmax;
+  const size_t per_wave = sizeof(double) * coeff_lds_per_wave(2 * Mmax, Mmax, 2 * Mmax, true);
+  int waves = 4;
+  while (waves > 1 && tab_max * sizeof(double) + waves * per_wave > 65536) --waves;
+  const size_t lds = tab_max * sizeof(double) + waves * per_wave;
+  const size_t refine_lds =
+      tab_max * sizeof(double) + sizeof(double) * coeff_lds_per_wave(4 * Mmax, Mmax, 2 * Mmax, true);
+  const int64_t tile = (int64_t)waves * kBatchTile;
+  // descriptors
+  const int np = (int)order.size();
+  std::vector<CoeffArgs> args(np);
+  std::vector<int64_t> item_prefix(np), root_prefix(np);
+  int64_t off = 0, n_tiles = 0, n_root = 0;
+  for (int q = 0; q < np; ++q) {
+    const ffbie_batch_item& it = items[order[q]];
+    CoeffArgs& a = args[q];
+    a = CoeffArgs{};
+    a.P = probs[order[q]];
+    int qi = 0;
+    while ((16 << qi) != it.d.M) ++qi;
+    a.tab_g = c->d_tabs[qi];
+    a.n = it.n_pairs;
+    a.t_in = it.d_t;
+    a.az_in = it.d_az;
+    a.ts_in = it.d_ts;
+    a.roots = c->d_roots + off;
+    a.status = it.d_pair_status ? it.d_pair_status : c->d_status + off;
+    a.kappa = static_cast<cplx*>(it.d_kappa);
+    a.rhoinv = nullptr;
+    a.NF = 2 * it.d.M;
+    a.flag_list = c->d_list;
+    a.flag_count = c->d_count;
+    a.variant = FFBIE_KAPPA_SWAP;
+    a.flag_tag = (int64_t)q << 40;
+    item_prefix[q] = n_tiles;
+    root_prefix[q] = n_root;
+    n_tiles += (it.n_pairs + tile - 1) / tile;
+    n_root += (it.n_pairs + 255) / 256;
+    off += it.n_pairs;
+  }
+  const size_t bytes = np * sizeof(CoeffArgs) + 2 * np * sizeof(int64_t);
+  if (bytes > c->batch_bytes) {
+    if (c->d_batch) hipFree(c->d_batch);
+    c->d_batch = nullptr;
+    c->batch_bytes = 0;
+    if (hipMalloc(&c->d_batch, bytes) != hipSuccess)
+      return fail(c, FFBIE_ENOMEM, "ffbie_kernel_coeffs_batched: descriptor allocation failed");
+    c->batch_bytes = bytes;
+  }
+  char* base = static_cast<char*>(c->d_batch);
+  CoeffArgs* d_args = reinterpret_cast<CoeffArgs*>(base);
+  int64_t* d_item_prefix = reinterpret_cast<int64_t*>(base + np * sizeof(CoeffArgs));
+  int64_t* d_root_prefix = d_item_prefix + np;
+  FFBIE_HIP(c, hipMemcpyAsync(d_args, args.data(), np * sizeof(CoeffArgs), hipMemcpyHostToDevice, c->stream));
+  FFBIE_HIP(c, hipMemcpyAsync(d_item_prefix, item_prefix.data(), np * sizeof(int64_t),
+                              hipMemcpyHostToDevice, c->stream));
+  FFBIE_HIP(c, hipMemcpyAsync(d_root_prefix, root_prefix.data(), np * sizeof(int64_t),
+                              hipMemcpyHostToDevice, c->stream));
+  FFBIE_HIP(c, hipStreamSynchronize(c->stream));      // host vectors go out of scope
+  FFBIE_HIP(c, hipMemsetAsync(c->d_count, 0, 2 * sizeof(int32_t), c->stream));
+  BatchArgs b{};
+  b.probs = d_args;
+  b.n_probs = np;
+  b.item_prefix = d_item_prefix;
+  b.n_items = n_tiles;
+  b.root_prefix = d_root_prefix;
+  b.item_counter = c->d_count + 1;
+  b.flag_list = c->d_list;
+  b.flag_count = c->d_count;
+  b.tab_max = tab_max;
+  const size_t root_lds = tab_max * sizeof(double);
+  const int64_t blocks = std::min<int64_t>(n_tiles, 1024);
+  FFBIE_HIP(c, launch_batch(b, mm, n_root, root_lds, blocks, waves, lds, refine_lds, c->stream, 0));
+  FFBIE_HIP(c, launch_batch(b, mm, n_root, root_lds, blocks, waves, lds, refine_lds, c->stream, 1));
+  FFBIE_HIP(c, launch_batch(b, mm, n_root, root_lds, 512, waves, lds, refine_lds, c->stream, 2));
   return FFBIE_OK;
 }
 

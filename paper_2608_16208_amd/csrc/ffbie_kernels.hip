@@ -340,20 +340,18 @@ __device__ __forceinline__ void swap_convolution(const cplx* G, int p, const dou
 //   eq. (3.10):     Z1 = FFT(F + i cos(k rho)), Z2 = FFT(sin(k rho)/rho)
 //                   C -> free1, GF -> free2, A -> Z1, <rho^-1> -> cb, kc -> free2
 // ===========================================================================
+// The coefficient path for the pairs w in [beg, end) of one problem, by one
+// wavefront (indices into a.list when it is set).  `tab` is the problem's angle
+// table in LDS, `wbase` this wavefront's LDS workspace, NF the sample count.
 template <int MM, bool REFINE>
-__global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
-  extern __shared__ double smem[];
+__device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* tab, double* wbase,
+                                            int NF, int64_t beg, int64_t end) {
   const Prob& P = a.P;
-  double* tab = smem;
-  load_table(tab, a.tab_g, P.tab_n);
-  const int M = P.M, M0 = P.M0, L = P.L, NF = a.NF, mask = P.tab_n - 1, quarter = 2 * M;
+  const int M = P.M, M0 = P.M0, L = P.L, mask = P.tab_n - 1, quarter = 2 * M;
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int waves_per_block = blockDim.x >> 6;
   const bool paper = a.variant == FFBIE_KAPPA_PAPER_CONV;
   const bool want_c = paper || a.rhoinv != nullptr;
-  const int per_wave = coeff_lds_per_wave(NF, M, L, !want_c);
-  cplx* base = reinterpret_cast<cplx*>(smem + P.tab_n + (size_t)wave * per_wave);
+  cplx* base = reinterpret_cast<cplx*>(wbase);
   cplx* z1a = base;
   cplx* z1b = z1a + NF;
   // full layout: z2a, z2b, cb; compact layout: A_m buffer and kc
@@ -361,13 +359,6 @@ __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
   cplx* z2b = z2a + NF;
   cplx* cb = want_c ? z2b + NF : z1b + NF + (M + NF + 2) / 2;
   double* Acompact = reinterpret_cast<double*>(z1b + NF);
-
-  int64_t count = a.n;
-  if (a.list) count = *a.list_count;
-  const int64_t total_waves = (int64_t)gridDim.x * waves_per_block;
-  const int64_t gw = (int64_t)blockIdx.x * waves_per_block + wave;
-  const int64_t chunk = (count + total_waves - 1) / total_waves;
-  const int64_t beg = gw * chunk, end = min(count, beg + chunk);
 
   const int tstride = (8 * M) / NF;        // table index step of the sample grid
   const int hstep = (4 * M) / NF;          // table index step of half a grid step
@@ -448,11 +439,11 @@ __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
     const int pF = want_c ? trunc_index_real(Fsrc, NF, invNF, P.eps0, 0.0) : 0;
     const int pH = paper ? 0 : trunc_index_real(Z1, NF, invNF, P.eps0, F0);
     if (max(pF, pH) >= NF / 2 - 2) {
-      if (a.flag_list) {
+      if (!REFINE && a.flag_list) {
         // not resolved on this grid: queue for the 4M-sample pass
         if (lane == 0) {
           const int32_t slot = atomicAdd(a.flag_count, 1);
-          a.flag_list[slot] = pi;
+          a.flag_list[slot] = pi | a.flag_tag;
           a.status[pi] = st | FFBIE_PAIR_REFINED;
         }
         continue;
@@ -544,6 +535,113 @@ __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
   }
 }
 
+template <int MM, bool REFINE>
+__global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
+  extern __shared__ double smem[];
+  double* tab = smem;
+  load_table(tab, a.tab_g, a.P.tab_n);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int waves_per_block = blockDim.x >> 6;
+  const bool want_c = a.variant == FFBIE_KAPPA_PAPER_CONV || a.rhoinv != nullptr;
+  const int per_wave = coeff_lds_per_wave(a.NF, a.P.M, a.P.L, !want_c);
+  int64_t count = a.n;
+  if (a.list) count = *a.list_count;
+  const int64_t total_waves = (int64_t)gridDim.x * waves_per_block;
+  const int64_t gw = (int64_t)blockIdx.x * waves_per_block + wave;
+  const int64_t chunk = (count + total_waves - 1) / total_waves;
+  const int64_t beg = gw * chunk, end = min(count, beg + chunk);
+  coeff_range<MM, REFINE>(a, tab, smem + a.P.tab_n + (size_t)wave * per_wave, a.NF, beg, end);
+}
+
+// ===========================================================================
+// Batched coefficient path: many problems (surfaces) in one persistent launch.
+// Work items are tiles of (waves per block) x kBatchTile pairs of one problem,
+// numbered problem by problem; each workgroup takes the next item from a global
+// counter, stages the problem's angle table in LDS when the problem changes,
+// and each wavefront runs its share of the tile.  Every workgroup leaves the
+// loop once the counter passes the last item.
+// ===========================================================================
+__device__ __forceinline__ int batch_find(const int64_t* __restrict__ prefix, int n, int64_t x) {
+  int lo = 0, hi = n - 1;                     // last problem with prefix[s] <= x
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int MM>
+__global__ __launch_bounds__(256) void ffbie_coeff_batch_kernel_t(BatchArgs b) {
+  extern __shared__ double smem[];
+  __shared__ int64_t item_s;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int waves_per_block = blockDim.x >> 6;
+  const int64_t tile = (int64_t)waves_per_block * kBatchTile;
+  int cur = -1;
+  while (true) {
+    if (threadIdx.x == 0) item_s = atomicAdd(b.item_counter, 1);
+    __syncthreads();
+    const int64_t item = item_s;
+    if (item >= b.n_items) break;
+    const int s = batch_find(b.item_prefix, b.n_probs, item);
+    const CoeffArgs& a = b.probs[s];
+    if (s != cur) {
+      load_table(smem, a.tab_g, a.P.tab_n);    // ends with a barrier
+      cur = s;
+    }
+    const int NF = 2 * a.P.M;
+    const int per_wave = coeff_lds_per_wave(NF, a.P.M, a.P.L, true);
+    const int64_t t0 = (item - b.item_prefix[s]) * tile + (int64_t)wave * kBatchTile;
+    const int64_t beg = min(a.n, t0), end = min(a.n, t0 + kBatchTile);
+    coeff_range<MM, false>(a, smem, smem + b.tab_max + (size_t)wave * per_wave, NF, beg, end);
+    __syncthreads();                           // all waves done before item_s / the table change
+  }
+}
+
+// Refine pass of a batch: one wavefront per workgroup, entries (problem << 40 | pair).
+template <int MM>
+__global__ __launch_bounds__(64) void ffbie_coeff_batch_refine_t(BatchArgs b) {
+  extern __shared__ double smem[];
+  const int count = *b.flag_count;
+  int cur = -1;
+  for (int w = blockIdx.x; w < count; w += gridDim.x) {
+    const int64_t e = b.flag_list[w];
+    const int s = (int)(e >> 40);
+    const int64_t pi = e & ((int64_t(1) << 40) - 1);
+    const CoeffArgs& a = b.probs[s];
+    if (s != cur) {
+      load_table(smem, a.tab_g, a.P.tab_n);
+      cur = s;
+    }
+    coeff_range<MM, true>(a, smem, smem + b.tab_max, 4 * a.P.M, pi, pi + 1);
+    __syncthreads();
+  }
+}
+
+// Root kernel of a batch: one lane per pair, blocks of 256 pairs of one problem.
+template <int MM>
+__global__ __launch_bounds__(256) void ffbie_root_batch_kernel_t(BatchArgs b) {
+  extern __shared__ double tab[];
+  const int s = batch_find(b.root_prefix, b.n_probs, blockIdx.x);
+  const CoeffArgs& a = b.probs[s];
+  load_table(tab, a.tab_g, a.P.tab_n);
+  const int64_t i = (blockIdx.x - b.root_prefix[s]) * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const double t = a.t_in[i], ts = a.ts_in[i];
+  const int j = a.az_in[i] & (2 * a.P.M - 1);
+  const double nan = __builtin_nan("");
+  RootRec* out = const_cast<RootRec*>(a.roots);
+  if (t == ts || !(t == t) || !(ts == ts)) {
+    out[i] = RootRec{nan, nan, nan, nan};
+    a.status[i] = FFBIE_PAIR_SINGULAR;
+    return;
+  }
+  int st;
+  const RootRec r = find_root<MM>(a.P, tab, t, j, ts, &st);
+  out[i] = r;
+  a.status[i] = st;
+}
+
 // ===========================================================================
 // Diagnostic kernel: A_m(b) for a batch of b (one wavefront per b)
 // ===========================================================================
@@ -603,6 +701,28 @@ hipError_t launch_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t ld
     else                                                                                         \
       hipLaunchKernelGGL((ffbie_coeff_kernel_t<MMV, false>), dim3((unsigned)blocks),            \
                          dim3(64 * waves), lds, stream, a);                                      \
+    break;
+    FFBIE_FOR_MM(X)
+#undef X
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs& b, int mm, int64_t root_blocks, size_t root_lds,
+                        int64_t blocks, int waves, size_t lds, size_t refine_lds,
+                        hipStream_t stream, int phase) {
+  switch (mm_bucket(mm)) {
+#define X(MMV)                                                                                   \
+  case MMV:                                                                                      \
+    if (phase == 0)                                                                              \
+      hipLaunchKernelGGL(ffbie_root_batch_kernel_t<MMV>, dim3((unsigned)root_blocks), dim3(256), \
+                         root_lds, stream, b);                                                   \
+    else if (phase == 1)                                                                         \
+      hipLaunchKernelGGL(ffbie_coeff_batch_kernel_t<MMV>, dim3((unsigned)blocks),               \
+                         dim3(64 * waves), lds, stream, b);                                      \
+    else                                                                                         \
+      hipLaunchKernelGGL(ffbie_coeff_batch_refine_t<MMV>, dim3((unsigned)blocks), dim3(64),     \
+                         refine_lds, stream, b);                                                 \
     break;
     FFBIE_FOR_MM(X)
 #undef X

@@ -27,6 +27,24 @@ struct CoeffArgs {
   int64_t* flag_list;        // main pass: pairs queued for the refine pass
   int32_t* flag_count;
   int variant;               // FFBIE_KAPPA_SWAP or FFBIE_KAPPA_PAPER_CONV
+  int64_t flag_tag;          // or-ed into queued pair indices (problem index << 40 in a batch)
+};
+
+// Pairs per wavefront and work item of the batched launch.
+constexpr int kBatchTile = 16;
+
+// A batch of problems in one launch; probs[s] holds problem s's arguments
+// (its own P, angle table, pair arrays, outputs and workspace slices).
+struct BatchArgs {
+  const CoeffArgs* probs;    // [n_probs], device memory
+  int n_probs;
+  const int64_t* item_prefix;  // [n_probs] first work item (tile) of each problem
+  int64_t n_items;
+  const int64_t* root_prefix;  // [n_probs] first 256-pair root block of each problem
+  int* item_counter;         // work queue head (zeroed before the launch)
+  int64_t* flag_list;        // refine queue: (problem << 40) | pair
+  int32_t* flag_count;
+  int tab_max;               // doubles reserved for the angle table at the start of LDS
 };
 
 // Per-wavefront LDS of the coefficient kernel, in doubles.
@@ -45,6 +63,9 @@ hipError_t launch_root(const Prob& P, const double* tab, int64_t n, const double
                        double* root_out, hipStream_t stream);
 hipError_t launch_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t lds,
                         hipStream_t stream, bool refine);
+hipError_t launch_batch(const BatchArgs& b, int mm, int64_t root_blocks, size_t root_lds,
+                        int64_t blocks, int waves, size_t lds, size_t refine_lds,
+                        hipStream_t stream, int phase);
 __global__ void ffbie_singular_factor_kernel(int64_t n, const double* __restrict__ b_in, int mtop,
                                              double* __restrict__ out);
 

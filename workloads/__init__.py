@@ -63,6 +63,31 @@ def config(i):
     raise ValueError(i)
 
 
+def _min_radius(amp, n=256):
+    t = np.linspace(0, math.pi, n)
+    th = np.linspace(0, 2 * math.pi, n, endpoint=False)
+    R = np.ones((n, n))
+    for l in range(amp.shape[0]):
+        for m in range(amp.shape[1]):
+            R += amp[l, m] * np.outer(np.sin((l + 1) * t), np.cos(m * th))
+    return R.min()
+
+
+def batch_surface(s):
+    """Member s of the 64-surface batch: 20 amplitudes a_lm ~ U(-0.15, 0.15)
+    (l = 1..4, m = 0..4, l-major; redrawn while min R < 0.5 on a 256^2 grid),
+    then n_panels ~ U{4..32}, M from {16, 32, 64, 128} and k ~ U[2, 25], all
+    from rng(100 + s)."""
+    rng = np.random.default_rng(100 + s)
+    amp = star_amplitudes(4, 4, 0.15, rng)
+    while _min_radius(amp) < 0.5:
+        amp = star_amplitudes(4, 4, 0.15, rng)
+    n_panels = int(rng.integers(4, 33))
+    M = int(rng.choice([16, 32, 64, 128]))
+    k = float(rng.uniform(2.0, 25.0))
+    return dict(name=f"batch-star-{s}", amp=amp, k=k, n_panels=n_panels, M=M, seed=100 + s)
+
+
 def all_pairs(n_panels, M, length=math.pi):
     """Every (target node, target azimuth, source curve node) with t_s != t.
 
