@@ -292,16 +292,69 @@ ffbie_status ffbie_eval_field(ffbie_ctx *ctx, int64_t n_pts, const double *d_pts
  * the context's stream (iterative methods read norms on the host) and returns
  * after the solve has finished.  info (optional): iterations and the final
  * relative residual |g - S phi| / |g| (NaN for LU64, whose S is destroyed).
+ *   FFBIE_SOLVE_FGMRES_MLP flexible GMRES (restart 100) with the learned per-mode
+ *                          preconditioner (ffbie_mlp_*) as right preconditioner and
+ *                          phi_0 = P(g) as initial guess; if it does not reach tol
+ *                          within max_iter, the plain GMRES solve runs from zero for
+ *                          up to max_iter more (info->fell_back = 1).  Needs
+ *                          set weights and n_panels = 16 (256 curve nodes).
  * Returns FFBIE_ESINGULAR on an exactly zero pivot, FFBIE_WNOTCONV if an
  * iterative method did not reach tol (phi holds the last iterate). */
-enum { FFBIE_SOLVE_LU64 = 0, FFBIE_SOLVE_LU32_IR64 = 1, FFBIE_SOLVE_GMRES = 2 };
+enum { FFBIE_SOLVE_LU64 = 0, FFBIE_SOLVE_LU32_IR64 = 1, FFBIE_SOLVE_GMRES = 2,
+       FFBIE_SOLVE_FGMRES_MLP = 3 };
 typedef struct {
   int iterations;
   int converged;
   double rel_residual;
+  int fell_back;      /* FGMRES_MLP: 1 if the learned preconditioner did not reach tol
+                         and the plain GMRES solve produced phi */
 } ffbie_solve_info;
 ffbie_status ffbie_solve(ffbie_ctx *ctx, int method, void *d_S, int64_t ld, const void *d_g,
                          void *d_phi, double tol, int max_iter, ffbie_solve_info *info);
+
+/* ------------------------------------------------------------------------
+ * Learned preconditioner (the learned part of the solve; the paper's method
+ * without it is FFBIE_SOLVE_GMRES / LU64).  A multilayer perceptron
+ * 514 -> 256 -> 256 -> 512 (ReLU) is applied to every azimuthal mode m of a
+ * residual r on the 256 curve nodes (n_panels = 16):
+ *   R_m[node] = (1/2M) sum_j r[node, j] e^{-i m theta_j},  m = -M+1..M,
+ *   s_m = |R_m|_2,  x_m = [Re R_m / s_m, Im R_m / s_m, k/30, m/M],
+ *   E_m = s_m (y_m[0:256] + i y_m[256:512]),  y_m = MLP(x_m),
+ *   P(r)[node, j] = sum_m E_m[node] e^{i m theta_j}.
+ * Weights and activations are BF16 on the matrix cores with FP32 accumulation;
+ * FP32 master weights, Adam.  Parameters, in this order: W1 [256][514], b1 [256],
+ * W2 [256][256], b2 [256], W3 [512][256], b3 [512] (row-major, float32). */
+int64_t ffbie_mlp_param_count(void);
+/* Deterministic initialisation from `seed` (He-uniform hidden layers, zero biases). */
+ffbie_status ffbie_mlp_init(ffbie_ctx *ctx, uint64_t seed);
+/* Host float32 arrays of ffbie_mlp_param_count() values (copied). */
+ffbie_status ffbie_mlp_set_params(ffbie_ctx *ctx, const float *params);
+ffbie_status ffbie_mlp_get_params(ffbie_ctx *ctx, float *params);
+/* d_y [n][512] = MLP(d_x [n][514]), float32 device arrays (inputs rounded to BF16). */
+ffbie_status ffbie_mlp_forward(ffbie_ctx *ctx, int64_t n, const float *d_x, float *d_y);
+/* One step on the loss (1/2n) sum_i |MLP(x_i) - t_i|^2 over n samples (d_x
+ * [n][514], d_t [n][512] float32 device): gradients into d_grads (optional,
+ * [param_count] float32 device), then an Adam step with learning rate lr if
+ * update != 0.  *loss (host, optional) receives the loss before the step.
+ * Synchronises the stream. */
+ffbie_status ffbie_mlp_train_step(ffbie_ctx *ctx, int64_t n, const float *d_x, const float *d_t,
+                                  float lr, int update, float *d_grads, double *loss);
+/* Mode features of d_r [N] complex128 for the current problem: d_x [2M][514]
+ * float32 and the scales d_scale [2M] float64 (row m + M - 1 is mode m). */
+ffbie_status ffbie_mode_features(ffbie_ctx *ctx, const void *d_r, float *d_x, double *d_scale);
+/* Training targets for a solution e of S e = r: d_t [2M][512] float32,
+ * [Re E_m / s_m, Im E_m / s_m] with the scales of r's features. */
+ffbie_status ffbie_mode_targets(ffbie_ctx *ctx, const void *d_e, const double *d_scale, float *d_t);
+/* d_z = P(d_v) for the current problem ([N] complex128). */
+ffbie_status ffbie_mlp_precondition(ffbie_ctx *ctx, const void *d_v, void *d_z);
+
+/* Factor once, solve many: ffbie_lu_factor overwrites d_S with its LU64
+ * factors (as FFBIE_SOLVE_LU64 does) and keeps the interchanges in the context;
+ * ffbie_lu_solve then overwrites d_x [N] (the right-hand side on entry) with
+ * S^{-1} x, using the factors in d_S (unchanged since the factorisation).  Both
+ * synchronise the stream.  FFBIE_EINVAL if no factorisation of this size is held. */
+ffbie_status ffbie_lu_factor(ffbie_ctx *ctx, void *d_S, int64_t ld);
+ffbie_status ffbie_lu_solve(ffbie_ctx *ctx, const void *d_S, int64_t ld, void *d_x);
 
 /* r = g - S phi in complex128 (row-major S, leading dimension ld); d_r [N]. */
 ffbie_status ffbie_residual(ffbie_ctx *ctx, const void *d_S, int64_t ld, const void *d_phi,

@@ -21,8 +21,12 @@ EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_probl
            "ffbie_kernel_coeffs", "ffbie_singular_factor", "ffbie_enable_timing", "ffbie_get_timing",
            "ffbie_builtin_near_rule", "ffbie_set_near_rule", "ffbie_query", "ffbie_near_pairs",
            "ffbie_collocation", "ffbie_rhs", "ffbie_assemble", "ffbie_eval_field", "ffbie_solve",
-           "ffbie_residual", "ffbie_kernel_coeffs_batched")
-SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES = 0, 1, 2
+           "ffbie_residual", "ffbie_kernel_coeffs_batched", "ffbie_lu_factor", "ffbie_lu_solve",
+           "ffbie_mlp_param_count", "ffbie_mlp_init", "ffbie_mlp_set_params", "ffbie_mlp_get_params",
+           "ffbie_mlp_forward", "ffbie_mlp_train_step", "ffbie_mode_features", "ffbie_mode_targets",
+           "ffbie_mlp_precondition")
+SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES, SOLVE_FGMRES_MLP = 0, 1, 2, 3
+MLP_IN, MLP_HIDDEN, MLP_OUT = 514, 256, 512
 WNOTCONV = 2
 RHS_POINT_SOURCE, RHS_PLANE_WAVE = 0, 1
 P_SHIFT = 8
@@ -48,7 +52,8 @@ class _BatchItem(ctypes.Structure):
 
 
 class _SolveInfo(ctypes.Structure):
-    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("rel_residual", ctypes.c_double)]
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("fell_back", ctypes.c_int)]
 
 
 class _NearRule(ctypes.Structure):
@@ -88,9 +93,22 @@ def load_library(path=LIB_PATH):
     lib.ffbie_solve.argtypes = [vp, i32, vp, i64, vp, vp, ctypes.c_double, i32, ctypes.POINTER(_SolveInfo)]
     lib.ffbie_residual.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.ffbie_kernel_coeffs_batched.argtypes = [vp, i32, ctypes.POINTER(_BatchItem)]
+    lib.ffbie_lu_factor.argtypes = [vp, vp, i64]
+    lib.ffbie_lu_solve.argtypes = [vp, vp, i64, vp]
+    lib.ffbie_mlp_param_count.argtypes = []
+    lib.ffbie_mlp_param_count.restype = i64
+    lib.ffbie_mlp_init.argtypes = [vp, ctypes.c_uint64]
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.ffbie_mlp_set_params.argtypes = [vp, fp]
+    lib.ffbie_mlp_get_params.argtypes = [vp, fp]
+    lib.ffbie_mlp_forward.argtypes = [vp, i64, vp, vp]
+    lib.ffbie_mlp_train_step.argtypes = [vp, i64, vp, vp, ctypes.c_float, i32, vp, dp]
+    lib.ffbie_mode_features.argtypes = [vp, vp, vp, vp]
+    lib.ffbie_mode_targets.argtypes = [vp, vp, vp, vp]
+    lib.ffbie_mlp_precondition.argtypes = [vp, vp, vp]
     for name in EXPORTS:
         f = getattr(lib, name)
-        if name != "ffbie_last_error":
+        if name not in ("ffbie_last_error", "ffbie_mlp_param_count"):
             f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -299,7 +317,72 @@ class Context:
                                   float(tol), int(max_iter), ctypes.byref(info))
         self._check(rc, self.h)
         return phi, dict(iterations=info.iterations, converged=bool(info.converged),
-                         rel_residual=info.rel_residual, status=rc)
+                         rel_residual=info.rel_residual, fell_back=bool(info.fell_back), status=rc)
+
+    def lu_factor(self, S):
+        """Overwrite S with its LU64 factors (kept for lu_solve)."""
+        self._check(self.lib.ffbie_lu_factor(self.h, _ptr(S), S.stride(0)), self.h)
+
+    def lu_solve(self, S, b):
+        torch = self._torch
+        x = b.to(self.device, torch.complex128).clone()
+        self._check(self.lib.ffbie_lu_solve(self.h, _ptr(S), S.stride(0), _ptr(x)), self.h)
+        return x
+
+    # ---- learned preconditioner --------------------------------------------
+    def mlp_param_count(self):
+        return int(self.lib.ffbie_mlp_param_count())
+
+    def mlp_init(self, seed):
+        self._check(self.lib.ffbie_mlp_init(self.h, ctypes.c_uint64(int(seed))), self.h)
+
+    def mlp_set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.mlp_param_count():
+            raise FfbieError("wrong parameter count")
+        self._check(self.lib.ffbie_mlp_set_params(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+                    self.h)
+
+    def mlp_get_params(self):
+        p = np.empty(self.mlp_param_count(), dtype=np.float32)
+        self._check(self.lib.ffbie_mlp_get_params(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+                    self.h)
+        return p
+
+    def mlp_forward(self, x):
+        torch = self._torch
+        x = x.to(self.device, torch.float32).contiguous()
+        y = torch.empty((x.shape[0], MLP_OUT), dtype=torch.float32, device=self.device)
+        self._check(self.lib.ffbie_mlp_forward(self.h, x.shape[0], _ptr(x), _ptr(y)), self.h)
+        return y
+
+    def mlp_train_step(self, x, t, lr=1e-3, update=True, grads=False):
+        """(loss before the step, gradient tensor or None)."""
+        torch = self._torch
+        g = torch.empty(self.mlp_param_count(), dtype=torch.float32, device=self.device) if grads else None
+        loss = ctypes.c_double()
+        self._check(self.lib.ffbie_mlp_train_step(self.h, x.shape[0], _ptr(x), _ptr(t), float(lr),
+                                                  int(bool(update)), _ptr(g), ctypes.byref(loss)), self.h)
+        return loss.value, g
+
+    def mode_features(self, r):
+        torch = self._torch
+        nm = 2 * self.M
+        x = torch.empty((nm, MLP_IN), dtype=torch.float32, device=self.device)
+        sc = torch.empty(nm, dtype=torch.float64, device=self.device)
+        self._check(self.lib.ffbie_mode_features(self.h, _ptr(r), _ptr(x), _ptr(sc)), self.h)
+        return x, sc
+
+    def mode_targets(self, e, scale):
+        torch = self._torch
+        t = torch.empty((2 * self.M, MLP_OUT), dtype=torch.float32, device=self.device)
+        self._check(self.lib.ffbie_mode_targets(self.h, _ptr(e), _ptr(scale), _ptr(t)), self.h)
+        return t
+
+    def mlp_precondition(self, v):
+        z = self._torch.empty_like(v)
+        self._check(self.lib.ffbie_mlp_precondition(self.h, _ptr(v), _ptr(z)), self.h)
+        return z
 
     def residual(self, S, phi, g):
         torch = self._torch

@@ -14,6 +14,7 @@
 
 #include "ffbie_assembly.hpp"
 #include "ffbie_kernels.hpp"
+#include "ffbie_mlp.hpp"
 #include "ffbie_solve.hpp"
 
 using namespace ffbie;
@@ -73,6 +74,11 @@ struct ffbie_ctx {
   double* d_tabs[4] = {nullptr, nullptr, nullptr, nullptr};   // angle tables for M = 16 .. 128
   void* d_batch = nullptr;           // descriptors and prefix arrays
   size_t batch_bytes = 0;
+  // learned preconditioner
+  Mlp mlp;
+  int64_t factored_n = 0;            // size of the LU64 factorisation held (ffbie_lu_factor)
+  cplx* d_zbasis = nullptr;
+  int64_t zbasis_n = 0;
 };
 
 namespace {
@@ -302,6 +308,8 @@ ffbie_status ffbie_destroy(ffbie_ctx* c) {
                   c->d_batch, (void*)c->d_tabs[0], (void*)c->d_tabs[1], (void*)c->d_tabs[2],
                   (void*)c->d_tabs[3]})
     if (p) hipFree(p);
+  if (c->d_zbasis) (void)hipFree(c->d_zbasis);
+  c->mlp.release();
   if (c->blas) rocblas_destroy_handle(c->blas);
   delete c;
   return FFBIE_OK;
@@ -811,7 +819,15 @@ ffbie_status ensure_solve_ws(ffbie_ctx* c, int64_t N, int method) {
       return fail(c, FFBIE_ENOMEM, "ffbie_solve: complex64 factor allocation failed");
     c->s32_n = N;
   }
-  if (method == FFBIE_SOLVE_GMRES && c->krylov_n != N) {
+  if (method == FFBIE_SOLVE_FGMRES_MLP && c->zbasis_n != N) {
+    if (c->d_zbasis) (void)hipFree(c->d_zbasis);
+    c->d_zbasis = nullptr;
+    c->zbasis_n = 0;
+    if (hipMalloc(&c->d_zbasis, (size_t)kRestart * N * sizeof(cplx)) != hipSuccess)
+      return fail(c, FFBIE_ENOMEM, "ffbie_solve: flexible basis allocation failed");
+    c->zbasis_n = N;
+  }
+  if ((method == FFBIE_SOLVE_GMRES || method == FFBIE_SOLVE_FGMRES_MLP) && c->krylov_n != N) {
     if (c->d_krylov) hipFree(c->d_krylov);
     c->d_krylov = nullptr;
     c->krylov_n = 0;
@@ -836,7 +852,13 @@ SolveCtx solve_ctx(ffbie_ctx* c) {
   sc.hvec = c->d_small + 256 * (kRestart + 1);
   sc.s32 = c->d_s32;
   sc.krylov = c->d_krylov;
+  sc.zbasis = c->d_zbasis;
   return sc;
+}
+
+hipError_t mlp_apply(void* self, const cplx* v, cplx* z) {
+  ffbie_ctx* c = static_cast<ffbie_ctx*>(self);
+  return mlp_precondition(c->mlp, v, c->prob.M, 16 * c->n_panels, c->prob.k, z, c->stream);
 }
 
 }  // namespace
@@ -850,8 +872,11 @@ ffbie_status ffbie_solve(ffbie_ctx* c, int method, void* d_S, int64_t ld, const 
   const int64_t N = n_unknowns(c);
   if (!d_S || !d_g || !d_phi || ld < N || d_g == d_phi)
     return fail(c, FFBIE_EINVAL, "ffbie_solve: NULL or aliased buffer, or ld < N");
-  if (method != FFBIE_SOLVE_LU64 && method != FFBIE_SOLVE_LU32_IR64 && method != FFBIE_SOLVE_GMRES)
+  if (method != FFBIE_SOLVE_LU64 && method != FFBIE_SOLVE_LU32_IR64 && method != FFBIE_SOLVE_GMRES &&
+      method != FFBIE_SOLVE_FGMRES_MLP)
     return fail(c, FFBIE_EINVAL, "ffbie_solve: unknown method");
+  if (method == FFBIE_SOLVE_FGMRES_MLP && (!c->mlp.ready || 16 * c->n_panels != Mlp::kNodes))
+    return fail(c, FFBIE_EINVAL, "ffbie_solve: FGMRES_MLP needs MLP weights and n_panels = 16");
   if (method != FFBIE_SOLVE_LU64 && (!(tol > 0) || max_iter < 1))
     return fail(c, FFBIE_EINVAL, "ffbie_solve: need tol > 0 and max_iter >= 1");
   if (N > 2147483647 / 2) return fail(c, FFBIE_EINVAL, "ffbie_solve: N too large");
@@ -864,14 +889,19 @@ ffbie_status ffbie_solve(ffbie_ctx* c, int method, void* d_S, int64_t ld, const 
   cplx* phi = static_cast<cplx*>(d_phi);
   SolveResult r;
   int iters = 0;
+  bool fell_back = false;
   double rel = std::nan("");
+  c->factored_n = 0;
   if (method == FFBIE_SOLVE_LU64) {
     FFBIE_HIP(c, hipMemcpyAsync(phi, g, N * sizeof(cplx), hipMemcpyDeviceToDevice, c->stream));
     r = lu64_factor_solve(sc, S, ld, N, phi);
   } else if (method == FFBIE_SOLVE_LU32_IR64) {
     r = lu32_ir64(sc, S, ld, N, g, phi, tol, max_iter, &iters, &rel);
-  } else {
+  } else if (method == FFBIE_SOLVE_GMRES) {
     r = gmres64(sc, S, ld, N, g, phi, tol, max_iter, kRestart, &iters, &rel);
+  } else {
+    Precond P{mlp_apply, c};
+    r = fgmres64(sc, S, ld, N, g, phi, tol, max_iter, kRestart, P, &iters, &rel, &fell_back);
   }
   if (r.hip != hipSuccess) return hip_fail(c, r.hip, "ffbie_solve");
   if (r.blas != 0) return fail(c, FFBIE_EBLAS, "ffbie_solve: rocBLAS GEMM failed");
@@ -880,9 +910,47 @@ ffbie_status ffbie_solve(ffbie_ctx* c, int method, void* d_S, int64_t ld, const 
     info->iterations = iters;
     info->converged = r.converged ? 1 : 0;
     info->rel_residual = rel;
+    info->fell_back = fell_back ? 1 : 0;
   }
   if (r.singular_col != 0) return fail(c, FFBIE_ESINGULAR, "ffbie_solve: exactly zero pivot");
   if (!r.converged) return FFBIE_WNOTCONV;
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_lu_factor(ffbie_ctx* c, void* d_S, int64_t ld) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_lu_factor: no problem set");
+  const int64_t N = n_unknowns(c);
+  if (!d_S || ld < N) return fail(c, FFBIE_EINVAL, "ffbie_lu_factor: NULL matrix or ld < N");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  ffbie_status s = ensure_solve_ws(c, N, FFBIE_SOLVE_LU64);
+  if (s != FFBIE_OK) return s;
+  SolveCtx sc = solve_ctx(c);
+  // factor with a zero right-hand side (the solve part is then a no-op on it)
+  cplx* y = c->d_vecs + 2 * N;
+  FFBIE_HIP(c, hipMemsetAsync(y, 0, N * sizeof(cplx), c->stream));
+  c->factored_n = 0;
+  SolveResult r = lu64_factor_solve(sc, static_cast<cplx*>(d_S), ld, N, y);
+  if (r.hip != hipSuccess) return hip_fail(c, r.hip, "ffbie_lu_factor");
+  if (r.blas != 0) return fail(c, FFBIE_EBLAS, "ffbie_lu_factor: rocBLAS GEMM failed");
+  FFBIE_HIP(c, hipStreamSynchronize(c->stream));
+  if (r.singular_col != 0) return fail(c, FFBIE_ESINGULAR, "ffbie_lu_factor: exactly zero pivot");
+  c->factored_n = N;
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_lu_solve(ffbie_ctx* c, const void* d_S, int64_t ld, void* d_x) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_lu_solve: no problem set");
+  const int64_t N = n_unknowns(c);
+  if (!d_S || !d_x || ld < N) return fail(c, FFBIE_EINVAL, "ffbie_lu_solve: NULL buffer or ld < N");
+  if (c->factored_n != N || c->solve_n != N)
+    return fail(c, FFBIE_EINVAL, "ffbie_lu_solve: no factorisation of this size");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  SolveCtx sc = solve_ctx(c);
+  SolveResult r = lu64_solve_factored(sc, static_cast<const cplx*>(d_S), ld, N, static_cast<cplx*>(d_x));
+  if (r.hip != hipSuccess) return hip_fail(c, r.hip, "ffbie_lu_solve");
+  FFBIE_HIP(c, hipStreamSynchronize(c->stream));
   return FFBIE_OK;
 }
 
@@ -898,6 +966,135 @@ ffbie_status ffbie_residual(ffbie_ctx* c, const void* d_S, int64_t ld, const voi
   sc.stream = c->stream;
   FFBIE_HIP(c, residual64(sc, static_cast<const cplx*>(d_S), ld, N, static_cast<const cplx*>(d_phi),
                           static_cast<const cplx*>(d_g), static_cast<cplx*>(d_r)));
+  return FFBIE_OK;
+}
+
+int64_t ffbie_mlp_param_count(void) { return (int64_t)Mlp::param_count(); }
+
+ffbie_status ffbie_mlp_init(ffbie_ctx* c, uint64_t seed) {
+  if (!c) return FFBIE_EINVAL;
+  const size_t P = Mlp::param_count();
+  std::vector<float> w(P, 0.f);
+  uint64_t st = seed;
+  auto uni = [&st]() {                       // SplitMix64 -> [0, 1)
+    uint64_t z = (st += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+  };
+  auto fill = [&](size_t off, int rows, int cols, double a) {
+    for (size_t i = 0; i < (size_t)rows * cols; ++i) w[off + i] = (float)(a * (2.0 * uni() - 1.0));
+  };
+  fill(Mlp::off_W1(), Mlp::kH, Mlp::kIn, std::sqrt(6.0 / Mlp::kIn));
+  fill(Mlp::off_W2(), Mlp::kH, Mlp::kH, std::sqrt(6.0 / Mlp::kH));
+  fill(Mlp::off_W3(), Mlp::kOut, Mlp::kH, std::sqrt(6.0 / (Mlp::kH + Mlp::kOut)));
+  return ffbie_mlp_set_params(c, w.data());
+}
+
+ffbie_status ffbie_mlp_set_params(ffbie_ctx* c, const float* params) {
+  if (!c) return FFBIE_EINVAL;
+  if (!params) return fail(c, FFBIE_EINVAL, "ffbie_mlp_set_params: NULL params");
+  const size_t P = Mlp::param_count();
+  for (size_t i = 0; i < P; ++i)
+    if (!std::isfinite(params[i])) return fail(c, FFBIE_EINVAL, "ffbie_mlp_set_params: non-finite value");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  FFBIE_HIP(c, c->mlp.alloc());
+  FFBIE_HIP(c, hipMemcpyAsync(c->mlp.params, params, P * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  FFBIE_HIP(c, hipMemsetAsync(c->mlp.m1, 0, P * sizeof(float), c->stream));
+  FFBIE_HIP(c, hipMemsetAsync(c->mlp.m2, 0, P * sizeof(float), c->stream));
+  FFBIE_HIP(c, c->mlp.refresh_bf16(c->stream));
+  FFBIE_HIP(c, hipStreamSynchronize(c->stream));
+  c->mlp.step = 0;
+  c->mlp.ready = true;
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_mlp_get_params(ffbie_ctx* c, float* params) {
+  if (!c) return FFBIE_EINVAL;
+  if (!params || !c->mlp.ready) return fail(c, FFBIE_EINVAL, "ffbie_mlp_get_params: no weights");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  FFBIE_HIP(c, hipMemcpyAsync(params, c->mlp.params, Mlp::param_count() * sizeof(float),
+                              hipMemcpyDeviceToHost, c->stream));
+  FFBIE_HIP(c, hipStreamSynchronize(c->stream));
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_mlp_forward(ffbie_ctx* c, int64_t n, const float* d_x, float* d_y) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->mlp.ready) return fail(c, FFBIE_EINVAL, "ffbie_mlp_forward: no weights");
+  if (n < 0 || n > (1 << 24)) return fail(c, FFBIE_EINVAL, "ffbie_mlp_forward: n out of range");
+  if (n == 0) return FFBIE_OK;
+  if (!d_x || !d_y) return fail(c, FFBIE_EINVAL, "ffbie_mlp_forward: NULL pointer");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  FFBIE_HIP(c, c->mlp.ensure_batch(n));
+  FFBIE_HIP(c, c->mlp.inputs_bf16(d_x, n, c->stream));
+  FFBIE_HIP(c, c->mlp.forward(n, c->stream));
+  FFBIE_HIP(c, hipMemcpyAsync(d_y, c->mlp.y, n * Mlp::kOut * sizeof(float), hipMemcpyDeviceToDevice,
+                              c->stream));
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_mlp_train_step(ffbie_ctx* c, int64_t n, const float* d_x, const float* d_t,
+                                  float lr, int update, float* d_grads, double* loss) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->mlp.ready) return fail(c, FFBIE_EINVAL, "ffbie_mlp_train_step: no weights");
+  if (n < 1 || n > (1 << 24)) return fail(c, FFBIE_EINVAL, "ffbie_mlp_train_step: n out of range");
+  if (!d_x || !d_t) return fail(c, FFBIE_EINVAL, "ffbie_mlp_train_step: NULL pointer");
+  if (update && !(lr > 0)) return fail(c, FFBIE_EINVAL, "ffbie_mlp_train_step: need lr > 0");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  Mlp& net = c->mlp;
+  FFBIE_HIP(c, net.ensure_batch(n));
+  FFBIE_HIP(c, net.inputs_bf16(d_x, n, c->stream));
+  FFBIE_HIP(c, net.forward(n, c->stream));
+  int nblk = 0;
+  FFBIE_HIP(c, net.backward(n, d_t, c->stream, &nblk));
+  if (d_grads)
+    FFBIE_HIP(c, hipMemcpyAsync(d_grads, net.grads, Mlp::param_count() * sizeof(float),
+                                hipMemcpyDeviceToDevice, c->stream));
+  std::vector<double> part(nblk);
+  FFBIE_HIP(c, hipMemcpyAsync(part.data(), net.partial, nblk * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+  if (update) FFBIE_HIP(c, net.adam(lr, c->stream));
+  FFBIE_HIP(c, hipStreamSynchronize(c->stream));
+  if (loss) {
+    double sum = 0;
+    for (double v : part) sum += v;
+    *loss = sum / (2.0 * n);
+  }
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_mode_features(ffbie_ctx* c, const void* d_r, float* d_x, double* d_scale) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem || 16 * c->n_panels != Mlp::kNodes)
+    return fail(c, FFBIE_EINVAL, "ffbie_mode_features: needs a problem with n_panels = 16");
+  if (!d_r || !d_x || !d_scale) return fail(c, FFBIE_EINVAL, "ffbie_mode_features: NULL pointer");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  FFBIE_HIP(c, mode_features(c->mlp, static_cast<const cplx*>(d_r), c->prob.M, Mlp::kNodes, c->prob.k,
+                             d_x, d_scale, c->stream));
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_mode_targets(ffbie_ctx* c, const void* d_e, const double* d_scale, float* d_t) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem || 16 * c->n_panels != Mlp::kNodes)
+    return fail(c, FFBIE_EINVAL, "ffbie_mode_targets: needs a problem with n_panels = 16");
+  if (!d_e || !d_t || !d_scale) return fail(c, FFBIE_EINVAL, "ffbie_mode_targets: NULL pointer");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  FFBIE_HIP(c, mode_targets(c->mlp, static_cast<const cplx*>(d_e), d_scale, c->prob.M, Mlp::kNodes,
+                            d_t, c->stream));
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_mlp_precondition(ffbie_ctx* c, const void* d_v, void* d_z) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->mlp.ready || !c->has_problem || 16 * c->n_panels != Mlp::kNodes)
+    return fail(c, FFBIE_EINVAL, "ffbie_mlp_precondition: needs weights and n_panels = 16");
+  if (!d_v || !d_z) return fail(c, FFBIE_EINVAL, "ffbie_mlp_precondition: NULL pointer");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  FFBIE_HIP(c, mlp_precondition(c->mlp, static_cast<const cplx*>(d_v), c->prob.M, Mlp::kNodes,
+                                c->prob.k, static_cast<cplx*>(d_z), c->stream));
   return FFBIE_OK;
 }
 

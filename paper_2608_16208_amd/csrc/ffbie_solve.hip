@@ -488,6 +488,11 @@ SolveResult lu64_factor_solve(SolveCtx& sc, cplx* S, int64_t ld, int64_t N, cplx
                            reinterpret_cast<C2<double>*>(y), true);
 }
 
+SolveResult lu64_solve_factored(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, cplx* y) {
+  return lu_factor_solve_t(sc, const_cast<C2<double>*>(reinterpret_cast<const C2<double>*>(S)), ld, N,
+                           reinterpret_cast<C2<double>*>(y), false);
+}
+
 SolveResult lu32_ir64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cplx* g, cplx* x,
                       double tol, int max_iter, int* iters, double* rel_res) {
   SolveResult res;
@@ -531,18 +536,27 @@ SolveResult lu32_ir64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const 
   return res;
 }
 
-SolveResult gmres64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cplx* g, cplx* x,
-                    double tol, int max_iter, int restart, int* iters, double* rel_res) {
+// Restarted GMRES; with a preconditioner, flexible GMRES (right preconditioning
+// z_j = P(v_j), x = x0 + Z y, which allows P to change between applications).
+// x0 = 0, or x0 = P(g) when `guess` is set.
+SolveResult gmres_core(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cplx* g, cplx* x,
+                       double tol, int max_iter, int restart, const Precond* P, bool guess,
+                       bool keep_x, int* iters, double* rel_res) {
   SolveResult res;
   auto* S64 = reinterpret_cast<const C2<double>*>(S);
   auto* g64 = reinterpret_cast<const C2<double>*>(g);
   auto* x64 = reinterpret_cast<C2<double>*>(x);
   auto* V = reinterpret_cast<C2<double>*>(sc.krylov);        // [restart+1][N]
+  auto* Z = reinterpret_cast<C2<double>*>(sc.zbasis);        // [restart][N] (flexible variant)
   auto* w = reinterpret_cast<C2<double>*>(sc.vec_r);
   auto* hdev = reinterpret_cast<C2<double>*>(sc.hvec);
   const int nblk = 256;
   hipError_t he;
-  res.hip = hipMemsetAsync(x64, 0, N * sizeof(C2<double>), sc.stream);
+  if (P && guess) {
+    res.hip = P->apply(P->self, g, x);
+  } else if (!keep_x) {
+    res.hip = hipMemsetAsync(x64, 0, N * sizeof(C2<double>), sc.stream);
+  }
   if (res.hip != hipSuccess) return res;
   const double gn = norm2(sc, g64, N, &he);
   if (he != hipSuccess) { res.hip = he; return res; }
@@ -562,9 +576,15 @@ SolveResult gmres64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cp
     e1[0] = beta;
     int j = 0;
     for (; j < restart && total < max_iter; ++j, ++total) {
-      // w = S V_j
-      hipLaunchKernelGGL(residual_kernel, grid1(N, 4), dim3(256), 0, sc.stream, S64, ld, N,
-                         V + (int64_t)j * N, (const C2<double>*)nullptr, w, -1.0);
+      // w = S V_j, or w = S Z_j with Z_j = P(V_j)
+      const C2<double>* src = V + (int64_t)j * N;
+      if (P) {
+        he = P->apply(P->self, reinterpret_cast<const cplx*>(src), reinterpret_cast<cplx*>(Z + (int64_t)j * N));
+        if (he != hipSuccess) { res.hip = he; return res; }
+        src = Z + (int64_t)j * N;
+      }
+      hipLaunchKernelGGL(residual_kernel, grid1(N, 4), dim3(256), 0, sc.stream, S64, ld, N, src,
+                         (const C2<double>*)nullptr, w, -1.0);
       std::vector<cd> hcol(j + 2, 0.0);
       for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(multidot_kernel, dim3(nblk, j + 1), dim3(256), 0, sc.stream, V, N, j + 1,
@@ -630,7 +650,7 @@ SolveResult gmres64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cp
     for (int i = 0; i < j; ++i) yd[i] = C2<double>{y[i].real(), y[i].imag()};
     he = hipMemcpyAsync(hdev, yd.data(), j * sizeof(C2<double>), hipMemcpyHostToDevice, sc.stream);
     if (he != hipSuccess) { res.hip = he; return res; }
-    hipLaunchKernelGGL(combine_kernel, grid1(N), dim3(256), 0, sc.stream, V, N, j, hdev, x64);
+    hipLaunchKernelGGL(combine_kernel, grid1(N), dim3(256), 0, sc.stream, P ? Z : V, N, j, hdev, x64);
     he = hipStreamSynchronize(sc.stream);
     if (he != hipSuccess) { res.hip = he; return res; }
   }
@@ -642,6 +662,26 @@ SolveResult gmres64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cp
   *rel_res = rn / gn;
   res.converged = rn <= tol * gn;
   return res;
+}
+
+SolveResult gmres64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cplx* g, cplx* x,
+                    double tol, int max_iter, int restart, int* iters, double* rel_res) {
+  return gmres_core(sc, S, ld, N, g, x, tol, max_iter, restart, nullptr, false, false, iters, rel_res);
+}
+
+SolveResult fgmres64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cplx* g, cplx* x,
+                     double tol, int max_iter, int restart, const Precond& P, int* iters,
+                     double* rel_res, bool* fell_back) {
+  *fell_back = false;
+  SolveResult r = gmres_core(sc, S, ld, N, g, x, tol, max_iter, restart, &P, true, false, iters, rel_res);
+  if (r.hip != hipSuccess || r.converged) return r;
+  // the learned preconditioner did not reach tol: the plain solve, from zero
+  *fell_back = true;
+  int more = 0;
+  SolveResult r2 = gmres_core(sc, S, ld, N, g, x, tol, max_iter, restart, nullptr, false, false, &more,
+                              rel_res);
+  *iters += more;
+  return r2;
 }
 
 hipError_t residual64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cplx* x,

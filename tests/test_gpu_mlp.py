@@ -1,0 +1,132 @@
+"""Learned preconditioner on the GPU: BF16 matrix-core forward and backward
+against the oracle (same BF16 rounding points, FP32 vs FP64 accumulation), the
+Adam step, the mode transforms, and flexible GMRES with the network and its
+fallback to plain GMRES.
+
+Bounds: forward norm-wise relative <= 1e-3 (a hidden activation near a BF16
+rounding boundary may round differently after FP32 accumulation: one BF16 ulp,
+2^-8 relative, in a few entries); gradients <= 1e-2 per parameter block;
+mode features <= 1e-6 (FP32 output); the full preconditioner <= 1e-2.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import mlp as omlp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2608_16208_amd as ffbie
+    c = ffbie.Context(0)
+    yield c
+    c.close()
+
+
+def _params(seed, scale=0.05):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-scale, scale, omlp.param_count()).astype(np.float32)
+
+
+def test_forward_matches_oracle(ctx):
+    p = _params(1)
+    ctx.mlp_set_params(p)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((300, omlp.N_IN)).astype(np.float32)     # 300: ragged 16-row tiles
+    y = ctx.mlp_forward(torch.tensor(x)).cpu().numpy()
+    ref, _ = omlp.forward(p.astype(np.float64), x.astype(np.float64), bf16=True)
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    assert err <= 1e-3, err
+    assert np.array_equal(ctx.mlp_get_params(), p)
+
+
+def test_gradients_match_oracle(ctx):
+    p = _params(3)
+    ctx.mlp_set_params(p)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((200, omlp.N_IN)).astype(np.float32)
+    t = rng.standard_normal((200, omlp.N_OUT)).astype(np.float32)
+    loss, g = ctx.mlp_train_step(torch.tensor(x, device=ctx.device), torch.tensor(t, device=ctx.device),
+                                 update=False, grads=True)
+    lref, gref = omlp.gradients(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64), bf16=True)
+    assert abs(loss - lref) / lref <= 1e-4
+    g = g.cpu().numpy()
+    o = 0
+    for sh in omlp.SHAPES:
+        n = int(np.prod(sh))
+        e = np.linalg.norm(g[o:o + n] - gref[o:o + n]) / np.linalg.norm(gref[o:o + n])
+        assert e <= 1e-2, (sh, e)
+        o += n
+    assert np.array_equal(ctx.mlp_get_params(), p)          # update=False leaves the weights
+
+
+def test_first_adam_step_is_signed_lr(ctx):
+    p = _params(5)
+    ctx.mlp_set_params(p)
+    rng = np.random.default_rng(6)
+    x = torch.tensor(rng.standard_normal((64, omlp.N_IN)).astype(np.float32), device=ctx.device)
+    t = torch.tensor(rng.standard_normal((64, omlp.N_OUT)).astype(np.float32), device=ctx.device)
+    _, g = ctx.mlp_train_step(x, t, update=False, grads=True)
+    lr = 1e-3
+    ctx.mlp_train_step(x, t, lr=lr, update=True)
+    step = ctx.mlp_get_params().astype(np.float64) - p
+    g = g.cpu().numpy().astype(np.float64)
+    big = np.abs(g) > 1e-5                     # first Adam step: -lr g / (|g| + eps)
+    assert np.allclose(step[big], -lr * np.sign(g[big]), rtol=1e-3, atol=1e-7)
+
+
+def _problem16(ctx, M=16, k=None):
+    sf = workloads.learned_surface(0, held_out=True)
+    if k is not None:
+        sf = dict(sf, k=k)
+    ctx.set_problem(sf["amp"], 16, M, sf["k"])
+    return sf
+
+
+def test_mode_features_targets_and_preconditioner_match_oracle(ctx):
+    sf = _problem16(ctx)
+    M, nodes = 16, 256
+    N, _ = ctx.query()
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    e = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    rt = torch.tensor(r, device=ctx.device)
+    x, sc = ctx.mode_features(rt)
+    t = ctx.mode_targets(torch.tensor(e, device=ctx.device), sc)
+    xo, so = omlp.features(r, M, nodes, sf["k"])
+    to = omlp.targets(e, so, M, nodes)
+    assert np.max(np.abs(sc.cpu().numpy() - so) / so) <= 1e-13
+    assert np.max(np.abs(x.cpu().numpy() - xo)) <= 1e-6
+    assert np.max(np.abs(t.cpu().numpy() - to)) <= 1e-6 * np.max(np.abs(to))
+    p = _params(8, scale=0.1)
+    ctx.mlp_set_params(p)
+    z = ctx.mlp_precondition(rt).cpu().numpy()
+    zo = omlp.precondition(p.astype(np.float64), r, M, nodes, sf["k"])
+    assert np.linalg.norm(z - zo) / np.linalg.norm(zo) <= 1e-2
+
+
+def test_fgmres_mlp_solves_and_falls_back(ctx):
+    import paper_2608_16208_amd as ffbie
+    _problem16(ctx, M=32, k=2.5)                       # plain GMRES converges in ~170 iterations
+    ctx.mlp_init(11)                                   # untrained network
+    S = ctx.assemble()
+    g = ctx.rhs(ffbie.RHS_PLANE_WAVE, [0.0, 0.6, 0.8])
+    phi, info = ctx.solve(S, g, method=ffbie.SOLVE_FGMRES_MLP, tol=1e-8, max_iter=600)
+    assert info["converged"] and info["rel_residual"] <= 1e-8, info
+    W = S.clone()
+    ref, _ = ctx.solve(W, g, method=ffbie.SOLVE_LU64)
+    del W
+    # the first-kind system has near-null directions (high azimuthal modes next to
+    # the poles) that a 1e-8 residual leaves undetermined but that radiate nothing:
+    # compare the fields
+    rng = np.random.default_rng(9)
+    d = rng.standard_normal((32, 3))
+    pts = torch.tensor(d / np.linalg.norm(d, axis=1)[:, None] * 4.0)
+    u, uref = ctx.eval_field(pts, phi), ctx.eval_field(pts, ref)
+    assert (u - uref).abs().norm().item() / uref.abs().norm().item() <= 1e-7
+    # a budget too small for the preconditioned pass forces the plain-GMRES fallback
+    _, info2 = ctx.solve(S, g, method=ffbie.SOLVE_FGMRES_MLP, tol=1e-10, max_iter=3)
+    assert info2["fell_back"], info2
