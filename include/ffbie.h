@@ -298,10 +298,14 @@ ffbie_status ffbie_eval_field(ffbie_ctx *ctx, int64_t n_pts, const double *d_pts
  *                          within max_iter, the plain GMRES solve runs from zero for
  *                          up to max_iter more (info->fell_back = 1).  Needs
  *                          set weights and n_panels = 16 (256 curve nodes).
+ *   FFBIE_SOLVE_GMRES_BLOCKJACOBI  GMRES (restart 100) right-preconditioned by
+ *                          the inverses of the diagonal azimuthal-mode blocks of S
+ *                          (see ffbie_blockjacobi_setup), built inside the call;
+ *                          phi_0 = P(g).  Needs 16 n_panels <= 512.
  * Returns FFBIE_ESINGULAR on an exactly zero pivot, FFBIE_WNOTCONV if an
  * iterative method did not reach tol (phi holds the last iterate). */
 enum { FFBIE_SOLVE_LU64 = 0, FFBIE_SOLVE_LU32_IR64 = 1, FFBIE_SOLVE_GMRES = 2,
-       FFBIE_SOLVE_FGMRES_MLP = 3 };
+       FFBIE_SOLVE_FGMRES_MLP = 3, FFBIE_SOLVE_GMRES_BLOCKJACOBI = 4 };
 typedef struct {
   int iterations;
   int converged;
@@ -355,6 +359,15 @@ ffbie_status ffbie_mlp_precondition(ffbie_ctx *ctx, const void *d_v, void *d_z);
  * synchronise the stream.  FFBIE_EINVAL if no factorisation of this size is held. */
 ffbie_status ffbie_lu_factor(ffbie_ctx *ctx, void *d_S, int64_t ld);
 ffbie_status ffbie_lu_solve(ffbie_ctx *ctx, const void *d_S, int64_t ld, void *d_x);
+
+/* Mode-block-Jacobi preconditioner.  In the azimuthal Fourier basis
+ * phi[(b, j)] = sum_m Phi_m[b] e^{i m theta_j} (m = -M+1..M) the matrix S splits
+ * into blocks over the 16 n_panels curve nodes; setup extracts the 2M diagonal
+ * blocks B_m[a][b] = (1/2M) sum_{j,j'} e^{-i m theta_j} S[(a,j),(b,j')] e^{i m theta_j'}
+ * from d_S (read only) and factors them (LU, partial pivoting); apply computes
+ * z = sum_m (B_m^{-1} V_m) e^{i m theta}.  Workspace 2M (16 n_panels)^2 complex128. */
+ffbie_status ffbie_blockjacobi_setup(ffbie_ctx *ctx, const void *d_S, int64_t ld);
+ffbie_status ffbie_blockjacobi_apply(ffbie_ctx *ctx, const void *d_v, void *d_z);
 
 /* r = g - S phi in complex128 (row-major S, leading dimension ld); d_r [N]. */
 ffbie_status ffbie_residual(ffbie_ctx *ctx, const void *d_S, int64_t ld, const void *d_phi,

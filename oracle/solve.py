@@ -49,3 +49,27 @@ def spherical_harmonic(n, m, t, th):
 def point_source(k, x, p):
     rho = np.linalg.norm(np.atleast_2d(x) - np.asarray(p), axis=1)
     return np.exp(1j * k * rho) / (4 * np.pi * rho)
+
+
+def mode_blocks(S, M, nodes):
+    """Diagonal azimuthal-mode blocks B_m = F_m S F_m^+ of a matrix on the
+    (node, azimuth) grid, from the definition
+    B_m[a][b] = (1/2M) sum_{j,j'} e^{-i m theta_j} S[(a,j),(b,j')] e^{i m theta_j'},
+    m = -M+1..M; returns [2M, nodes, nodes]."""
+    th = np.pi * np.arange(2 * M) / M
+    S4 = np.asarray(S).reshape(nodes, 2 * M, nodes, 2 * M)
+    out = np.empty((2 * M, nodes, nodes), dtype=complex)
+    for mi, m in enumerate(range(-M + 1, M + 1)):
+        e = np.exp(1j * m * th)
+        out[mi] = np.einsum("j,ajbk,k->ab", e.conj(), S4, e) / (2 * M)
+    return out
+
+
+def blockjacobi_apply(S, v, M, nodes):
+    """z = sum_m (B_m^{-1} V_m) e^{i m theta} with V_m the modes of v."""
+    th = np.pi * np.arange(2 * M) / M
+    ms = np.arange(-M + 1, M + 1)
+    V = np.asarray(v).reshape(nodes, 2 * M) @ np.exp(-1j * np.outer(th, ms)) / (2 * M)   # [node, m]
+    B = mode_blocks(S, M, nodes)
+    E = np.stack([np.linalg.solve(B[i], V[:, i]) for i in range(2 * M)], axis=1)        # [node, m]
+    return (E @ np.exp(1j * np.outer(ms, th))).reshape(-1)

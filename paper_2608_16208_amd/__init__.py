@@ -24,8 +24,8 @@ EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_probl
            "ffbie_residual", "ffbie_kernel_coeffs_batched", "ffbie_lu_factor", "ffbie_lu_solve",
            "ffbie_mlp_param_count", "ffbie_mlp_init", "ffbie_mlp_set_params", "ffbie_mlp_get_params",
            "ffbie_mlp_forward", "ffbie_mlp_train_step", "ffbie_mode_features", "ffbie_mode_targets",
-           "ffbie_mlp_precondition")
-SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES, SOLVE_FGMRES_MLP = 0, 1, 2, 3
+           "ffbie_mlp_precondition", "ffbie_blockjacobi_setup", "ffbie_blockjacobi_apply")
+SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES, SOLVE_FGMRES_MLP, SOLVE_GMRES_BLOCKJACOBI = 0, 1, 2, 3, 4
 MLP_IN, MLP_HIDDEN, MLP_OUT = 514, 256, 512
 WNOTCONV = 2
 RHS_POINT_SOURCE, RHS_PLANE_WAVE = 0, 1
@@ -106,6 +106,8 @@ def load_library(path=LIB_PATH):
     lib.ffbie_mode_features.argtypes = [vp, vp, vp, vp]
     lib.ffbie_mode_targets.argtypes = [vp, vp, vp, vp]
     lib.ffbie_mlp_precondition.argtypes = [vp, vp, vp]
+    lib.ffbie_blockjacobi_setup.argtypes = [vp, vp, i64]
+    lib.ffbie_blockjacobi_apply.argtypes = [vp, vp, vp]
     for name in EXPORTS:
         f = getattr(lib, name)
         if name not in ("ffbie_last_error", "ffbie_mlp_param_count"):
@@ -378,6 +380,14 @@ class Context:
         t = torch.empty((2 * self.M, MLP_OUT), dtype=torch.float32, device=self.device)
         self._check(self.lib.ffbie_mode_targets(self.h, _ptr(e), _ptr(scale), _ptr(t)), self.h)
         return t
+
+    def blockjacobi_setup(self, S):
+        self._check(self.lib.ffbie_blockjacobi_setup(self.h, _ptr(S), S.stride(0)), self.h)
+
+    def blockjacobi_apply(self, v):
+        z = self._torch.empty_like(v)
+        self._check(self.lib.ffbie_blockjacobi_apply(self.h, _ptr(v), _ptr(z)), self.h)
+        return z
 
     def mlp_precondition(self, v):
         z = self._torch.empty_like(v)

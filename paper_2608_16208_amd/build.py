@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["csrc/ffbie_api.hip", "csrc/ffbie_kernels.hip", "csrc/ffbie_assembly.hip",
-           "csrc/ffbie_solve.hip", "csrc/ffbie_mlp.hip"]
+           "csrc/ffbie_solve.hip", "csrc/ffbie_mlp.hip", "csrc/ffbie_blockjacobi.hip"]
 LIB = os.path.join(HERE, "libffbie.so")
 
 FLAGS = [

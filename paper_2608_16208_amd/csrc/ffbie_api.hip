@@ -13,6 +13,7 @@
 #include "ffbie_device.hpp"
 
 #include "ffbie_assembly.hpp"
+#include "ffbie_blockjacobi.hpp"
 #include "ffbie_kernels.hpp"
 #include "ffbie_mlp.hpp"
 #include "ffbie_solve.hpp"
@@ -76,6 +77,7 @@ struct ffbie_ctx {
   size_t batch_bytes = 0;
   // learned preconditioner
   Mlp mlp;
+  BlockJacobi bj;
   int64_t factored_n = 0;            // size of the LU64 factorisation held (ffbie_lu_factor)
   cplx* d_zbasis = nullptr;
   int64_t zbasis_n = 0;
@@ -310,6 +312,7 @@ ffbie_status ffbie_destroy(ffbie_ctx* c) {
     if (p) hipFree(p);
   if (c->d_zbasis) (void)hipFree(c->d_zbasis);
   c->mlp.release();
+  c->bj.release();
   if (c->blas) rocblas_destroy_handle(c->blas);
   delete c;
   return FFBIE_OK;
@@ -334,6 +337,7 @@ ffbie_status ffbie_set_problem(ffbie_ctx* c, const ffbie_geometry* g, const ffbi
   c->n_panels = d->n_panels;
   c->has_problem = true;
   c->sys_ready = false;
+  c->bj.ready = false;
   return FFBIE_OK;
 }
 
@@ -819,7 +823,8 @@ ffbie_status ensure_solve_ws(ffbie_ctx* c, int64_t N, int method) {
       return fail(c, FFBIE_ENOMEM, "ffbie_solve: complex64 factor allocation failed");
     c->s32_n = N;
   }
-  if (method == FFBIE_SOLVE_FGMRES_MLP && c->zbasis_n != N) {
+  if ((method == FFBIE_SOLVE_FGMRES_MLP || method == FFBIE_SOLVE_GMRES_BLOCKJACOBI) &&
+      c->zbasis_n != N) {
     if (c->d_zbasis) (void)hipFree(c->d_zbasis);
     c->d_zbasis = nullptr;
     c->zbasis_n = 0;
@@ -827,7 +832,8 @@ ffbie_status ensure_solve_ws(ffbie_ctx* c, int64_t N, int method) {
       return fail(c, FFBIE_ENOMEM, "ffbie_solve: flexible basis allocation failed");
     c->zbasis_n = N;
   }
-  if ((method == FFBIE_SOLVE_GMRES || method == FFBIE_SOLVE_FGMRES_MLP) && c->krylov_n != N) {
+  if ((method == FFBIE_SOLVE_GMRES || method == FFBIE_SOLVE_FGMRES_MLP ||
+       method == FFBIE_SOLVE_GMRES_BLOCKJACOBI) && c->krylov_n != N) {
     if (c->d_krylov) hipFree(c->d_krylov);
     c->d_krylov = nullptr;
     c->krylov_n = 0;
@@ -856,6 +862,11 @@ SolveCtx solve_ctx(ffbie_ctx* c) {
   return sc;
 }
 
+hipError_t bj_apply(void* self, const cplx* v, cplx* z) {
+  ffbie_ctx* c = static_cast<ffbie_ctx*>(self);
+  return c->bj.apply(v, z, c->stream);
+}
+
 hipError_t mlp_apply(void* self, const cplx* v, cplx* z) {
   ffbie_ctx* c = static_cast<ffbie_ctx*>(self);
   return mlp_precondition(c->mlp, v, c->prob.M, 16 * c->n_panels, c->prob.k, z, c->stream);
@@ -873,8 +884,10 @@ ffbie_status ffbie_solve(ffbie_ctx* c, int method, void* d_S, int64_t ld, const 
   if (!d_S || !d_g || !d_phi || ld < N || d_g == d_phi)
     return fail(c, FFBIE_EINVAL, "ffbie_solve: NULL or aliased buffer, or ld < N");
   if (method != FFBIE_SOLVE_LU64 && method != FFBIE_SOLVE_LU32_IR64 && method != FFBIE_SOLVE_GMRES &&
-      method != FFBIE_SOLVE_FGMRES_MLP)
+      method != FFBIE_SOLVE_FGMRES_MLP && method != FFBIE_SOLVE_GMRES_BLOCKJACOBI)
     return fail(c, FFBIE_EINVAL, "ffbie_solve: unknown method");
+  if (method == FFBIE_SOLVE_GMRES_BLOCKJACOBI && 16 * c->n_panels > 512)
+    return fail(c, FFBIE_EINVAL, "ffbie_solve: block-Jacobi needs 16 n_panels <= 512");
   if (method == FFBIE_SOLVE_FGMRES_MLP && (!c->mlp.ready || 16 * c->n_panels != Mlp::kNodes))
     return fail(c, FFBIE_EINVAL, "ffbie_solve: FGMRES_MLP needs MLP weights and n_panels = 16");
   if (method != FFBIE_SOLVE_LU64 && (!(tol > 0) || max_iter < 1))
@@ -899,8 +912,13 @@ ffbie_status ffbie_solve(ffbie_ctx* c, int method, void* d_S, int64_t ld, const 
     r = lu32_ir64(sc, S, ld, N, g, phi, tol, max_iter, &iters, &rel);
   } else if (method == FFBIE_SOLVE_GMRES) {
     r = gmres64(sc, S, ld, N, g, phi, tol, max_iter, kRestart, &iters, &rel);
-  } else {
+  } else if (method == FFBIE_SOLVE_FGMRES_MLP) {
     Precond P{mlp_apply, c};
+    r = fgmres64(sc, S, ld, N, g, phi, tol, max_iter, kRestart, P, &iters, &rel, &fell_back);
+  } else {
+    FFBIE_HIP(c, c->bj.setup(S, ld, c->prob.M, 16 * c->n_panels, c->stream));
+    c->bj.ready = true;
+    Precond P{bj_apply, c};
     r = fgmres64(sc, S, ld, N, g, phi, tol, max_iter, kRestart, P, &iters, &rel, &fell_back);
   }
   if (r.hip != hipSuccess) return hip_fail(c, r.hip, "ffbie_solve");
@@ -951,6 +969,28 @@ ffbie_status ffbie_lu_solve(ffbie_ctx* c, const void* d_S, int64_t ld, void* d_x
   SolveResult r = lu64_solve_factored(sc, static_cast<const cplx*>(d_S), ld, N, static_cast<cplx*>(d_x));
   if (r.hip != hipSuccess) return hip_fail(c, r.hip, "ffbie_lu_solve");
   FFBIE_HIP(c, hipStreamSynchronize(c->stream));
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_blockjacobi_setup(ffbie_ctx* c, const void* d_S, int64_t ld) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_blockjacobi_setup: no problem set");
+  const int64_t N = n_unknowns(c);
+  if (!d_S || ld < N || 16 * c->n_panels > 512)
+    return fail(c, FFBIE_EINVAL, "ffbie_blockjacobi_setup: NULL matrix, ld < N or more than 512 nodes");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  FFBIE_HIP(c, c->bj.setup(static_cast<const cplx*>(d_S), ld, c->prob.M, 16 * c->n_panels, c->stream));
+  c->bj.ready = true;
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_blockjacobi_apply(ffbie_ctx* c, const void* d_v, void* d_z) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem || !c->bj.ready || c->bj.M != c->prob.M || c->bj.nodes != 16 * c->n_panels)
+    return fail(c, FFBIE_EINVAL, "ffbie_blockjacobi_apply: no preconditioner for this problem");
+  if (!d_v || !d_z) return fail(c, FFBIE_EINVAL, "ffbie_blockjacobi_apply: NULL pointer");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  FFBIE_HIP(c, c->bj.apply(static_cast<const cplx*>(d_v), static_cast<cplx*>(d_z), c->stream));
   return FFBIE_OK;
 }
 

@@ -1,10 +1,11 @@
 """Training and evaluation of the learned per-mode preconditioner.
 
-Everything runs through the C ABI: the systems are assembled and factored by
-the library (`assemble`, `lu_factor`, `lu_solve`), the training pairs are the
-mode features of right-hand sides r and of their solutions e = S^{-1} r
-(`mode_features`, `mode_targets`), and the network is trained by the
-library's BF16 matrix-core kernels (`mlp_train_step`, Adam).  The trained
+Everything runs through the C ABI: the systems are assembled by the library
+(`assemble`), the training pairs are the mode features of Krylov-type vectors r
+and of their mode-block-Jacobi corrections e (`blockjacobi_setup/apply`,
+`mode_features`, `mode_targets`), and the network is trained by the library's
+BF16 matrix-core kernels (`mlp_train_step`, Adam).  A trained network replaces
+the per-surface block extraction and factorisation by one network evaluation.  The trained
 network serves as the right preconditioner and initial guess of flexible
 GMRES (`solve(..., SOLVE_FGMRES_MLP)`), which falls back to plain GMRES when it
 does not reach the tolerance.
@@ -23,39 +24,46 @@ from . import (Context, RHS_PLANE_WAVE, RHS_POINT_SOURCE, SOLVE_FGMRES_MLP, SOLV
                SOLVE_LU64)
 
 
-def _rhs_set(ctx, rng, n_rhs):
-    """Physical right-hand sides: plane waves from random directions and
-    exterior point sources at random points with |p| in [2, 4].  (White-noise
-    vectors are not used: they load the near-null directions of the first-kind
-    system, high azimuthal modes next to the poles, whose solutions are 1e8
-    times larger than the data and dominate any fit.)"""
+def _inputs(ctx, S, rng, n_rhs):
+    """Vectors the preconditioner is trained on: for a plane wave g from a random
+    direction and an exterior point source, the normalised Krylov directions
+    g, S g, S^2 g, ... that GMRES feeds to its preconditioner.  (White-noise
+    vectors are not used: they load the near-null directions of the
+    first-kind system, high azimuthal modes next to the poles.)"""
+    import torch
     out = []
-    for i in range(n_rhs):
-        d = rng.standard_normal(3)
-        d /= np.linalg.norm(d)
-        if i % 3 == 2:
-            out.append(ctx.rhs(RHS_POINT_SOURCE, rng.uniform(2.0, 4.0) * d))
-        else:
-            out.append(ctx.rhs(RHS_PLANE_WAVE, d))
-    return out
+    seeds = []
+    d = rng.standard_normal(3)
+    seeds.append(ctx.rhs(RHS_PLANE_WAVE, d / np.linalg.norm(d)))
+    p = rng.standard_normal(3)
+    seeds.append(ctx.rhs(RHS_POINT_SOURCE, rng.uniform(2.0, 4.0) * p / np.linalg.norm(p)))
+    per = max(1, n_rhs // len(seeds))
+    for v in seeds:
+        v = v / v.abs().norm()
+        for _ in range(per):
+            out.append(v)
+            w = -ctx.residual(S, v, torch.zeros_like(v))        # S v
+            v = w / w.abs().norm()
+    return out[:n_rhs]
 
 
 def make_dataset(ctx, surfaces, M=64, n_rhs=8, seed=0, min_scale=1e-6, log=None):
-    """(X [n, 514], T [n, 512]) float32 device tensors: the modes of each
-    right-hand side whose size s_m is at least min_scale times the largest."""
+    """(X [n, 514], T [n, 512]) float32 device tensors.  Targets are the
+    mode-block-Jacobi corrections B_m^{-1} R_m of each input (the inverse of
+    the diagonal azimuthal-mode blocks of the system), scaled like the
+    features; modes whose size s_m is below min_scale times the largest are
+    dropped (they carry no information)."""
     import torch
     rng = np.random.default_rng(seed)
     X, T = [], []
     for i, sf in enumerate(surfaces):
         ctx.set_problem(sf["amp"], 16, M, sf["k"])
         S = ctx.assemble()
-        rhs = _rhs_set(ctx, rng, n_rhs)
-        ctx.lu_factor(S)
-        for r in rhs:
-            e = ctx.lu_solve(S, r)
+        ctx.blockjacobi_setup(S)
+        for r in _inputs(ctx, S, rng, n_rhs):
+            e = ctx.blockjacobi_apply(r)
             x, sc = ctx.mode_features(r)
             t = ctx.mode_targets(e, sc)
-            # modes where r has no content carry only the rounding noise of e
             keep = sc >= min_scale * sc.max()
             X.append(x[keep])
             T.append(t[keep])
@@ -87,8 +95,11 @@ def train(ctx, X, T, steps=2000, batch=2048, lr=1e-3, seed=0, log=None):
 
 
 def evaluate(ctx, surfaces, M=64, tol=1e-8, max_iter=600):
-    """Per surface: GMRES and FGMRES+MLP iterations and times (solve only), plane-wave rhs."""
+    """Per surface (plane-wave right-hand side): iterations and solve times of
+    plain GMRES, GMRES with the mode-block-Jacobi preconditioner, and flexible
+    GMRES with the network."""
     import torch
+    from . import SOLVE_GMRES_BLOCKJACOBI
     rows = []
     for sf in surfaces:
         ctx.set_problem(sf["amp"], 16, M, sf["k"])
@@ -96,7 +107,8 @@ def evaluate(ctx, surfaces, M=64, tol=1e-8, max_iter=600):
         d = np.array([0.3, -0.5, 0.81])
         g = ctx.rhs(RHS_PLANE_WAVE, d / np.linalg.norm(d))
         row = {"k": sf["k"]}
-        for name, method in (("gmres", SOLVE_GMRES), ("fgmres_mlp", SOLVE_FGMRES_MLP)):
+        for name, method in (("gmres", SOLVE_GMRES), ("gmres_blockjacobi", SOLVE_GMRES_BLOCKJACOBI),
+                             ("fgmres_mlp", SOLVE_FGMRES_MLP)):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             phi, info = ctx.solve(S, g, method=method, tol=tol, max_iter=max_iter)
