@@ -266,7 +266,7 @@ ffbie_status ensure_ws(ffbie_ctx* c, int64_t n) {
 // waves per workgroup so that the coefficient kernel fits 64 KiB of LDS
 int coeff_waves(const Prob& P, int NF, bool compact, size_t* lds_bytes) {
   const size_t per_wave = sizeof(double) * coeff_lds_per_wave(NF, P.M, P.L, compact);
-  const size_t tab = sizeof(double) * P.tab_n;
+  const size_t tab = sizeof(double) * (P.tab_n + coeff_twiddle_doubles(NF));
   int w = 4;
   while (w > 1 && tab + w * per_wave > 65536) --w;
   *lds_bytes = tab + w * per_wave;
@@ -711,10 +711,13 @@ ffbie_status ffbie_kernel_coeffs_batched(ffbie_ctx* c, int n_items, const ffbie_
   }
   // launch shape: LDS for the largest problem
   const int tab_max = 8 * Mmax;
+  int Mmin = 128;
+  for (int i : order) Mmin = std::min(Mmin, items[i].d.M);
+  const int tw_max = coeff_twiddle_doubles(2 * Mmin);
   const size_t per_wave = sizeof(double) * coeff_lds_per_wave(2 * Mmax, Mmax, 2 * Mmax, true);
   int waves = 4;
-  while (waves > 1 && tab_max * sizeof(double) + waves * per_wave > 65536) --waves;
-  const size_t lds = tab_max * sizeof(double) + waves * per_wave;
+  while (waves > 1 && (tab_max + tw_max) * sizeof(double) + waves * per_wave > 65536) --waves;
+  const size_t lds = (tab_max + tw_max) * sizeof(double) + waves * per_wave;
   const size_t refine_lds =
       tab_max * sizeof(double) + sizeof(double) * coeff_lds_per_wave(4 * Mmax, Mmax, 2 * Mmax, true);
   const int64_t tile = (int64_t)waves * kBatchTile;
@@ -780,6 +783,7 @@ ffbie_status ffbie_kernel_coeffs_batched(ffbie_ctx* c, int n_items, const ffbie_
   b.flag_list = c->d_list;
   b.flag_count = c->d_count;
   b.tab_max = tab_max;
+  b.tw_max = tw_max;
   const size_t root_lds = tab_max * sizeof(double);
   const int64_t blocks = std::min<int64_t>(n_tiles, 1024);
   FFBIE_HIP(c, launch_batch(b, mm, n_root, root_lds, blocks, waves, lds, refine_lds, c->stream, 0));

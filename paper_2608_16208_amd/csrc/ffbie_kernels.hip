@@ -36,6 +36,16 @@ __device__ __forceinline__ void load_table(double* tab, const double* __restrict
   __syncthreads();
 }
 
+// 1/sqrt(x) for x > 0: hardware estimate, then two Newton steps
+// y <- y + (y/2)(1 - x y^2), each roughly squaring the relative error.
+__device__ __forceinline__ double rsqrt_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
 __device__ __forceinline__ double rcp_int(double x) {
   // 1/x for a small positive integer x: hardware estimate + two Newton steps
   double r = __builtin_amdgcn_rcp(x);
@@ -241,6 +251,50 @@ __device__ __forceinline__ void fft_stockham(cplx*& ia, cplx*& oa, cplx*& ib, cp
   }
 }
 
+// Twiddle factors of a transform of NF <= 128 points, one entry per (stage,
+// lane): at stage Ns = 2^st the butterfly jj = lane uses e^{-i pi r / Ns},
+// r = jj mod Ns.  Built once per workgroup into LDS (kTwiddleDoubles doubles),
+// read with one conflict-free 16-byte load per butterfly.
+constexpr int kTwiddleStages = 7;
+
+__device__ __forceinline__ void build_twiddles(cplx* tw, int NF, int M, const double* tab, int mask,
+                                               int quarter) {
+  for (int idx = threadIdx.x; idx < kTwiddleStages * 64; idx += blockDim.x) {
+    const int st = idx >> 6, lane = idx & 63;
+    const int Ns = 1 << st;
+    const int r = lane & (Ns - 1);
+    const int tk = (Ns < NF) ? r * ((4 * M) / Ns) : 0;
+    tw[idx] = mk(tcos(tab, tk, mask, quarter), -tsin(tab, tk, mask));
+  }
+}
+
+// Forward DFT as fft_stockham for NF <= 128 with the twiddles of build_twiddles.
+__device__ __forceinline__ void fft_stockham_small(cplx*& ia, cplx*& oa, cplx*& ib, cplx*& ob,
+                                                   bool two, int NF, const cplx* tw) {
+  const int lane = threadIdx.x & 63;
+  const int half = NF >> 1;
+  for (int st = 0; (1 << st) < NF; ++st) {
+    const int Ns = 1 << st;
+    if (lane < half) {
+      const int jj = lane;
+      const int r = jj & (Ns - 1);
+      const cplx wt = tw[(st << 6) + lane];
+      const int idxD = ((jj - r) << 1) + r;
+      const cplx v0 = ia[jj], v1 = ia[jj + half] * wt;
+      oa[idxD] = v0 + v1;
+      oa[idxD + Ns] = v0 - v1;
+      if (two) {
+        const cplx u0 = ib[jj], u1 = ib[jj + half] * wt;
+        ob[idxD] = u0 + u1;
+        ob[idxD + Ns] = u0 - u1;
+      }
+    }
+    wave_sync();
+    cplx* tmp = ia; ia = oa; oa = tmp;
+    tmp = ib; ib = ob; ob = tmp;
+  }
+}
+
 // Coefficient j of the real sequence packed in the real part of the
 // transform X: (X_j + conj(X_{NF-j})) / (2 NF).
 __device__ __forceinline__ cplx real_part_coeff(const cplx* X, int jj, int NF, double invNF) {
@@ -342,10 +396,11 @@ __device__ __forceinline__ void swap_convolution(const cplx* G, int p, const dou
 // ===========================================================================
 // The coefficient path for the pairs w in [beg, end) of one problem, by one
 // wavefront (indices into a.list when it is set).  `tab` is the problem's angle
-// table in LDS, `wbase` this wavefront's LDS workspace, NF the sample count.
+// table in LDS, `tw` its FFT twiddles in LDS (NF <= 128) or null, `wbase` this
+// wavefront's LDS workspace, NF the sample count.
 template <int MM, bool REFINE>
-__device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* tab, double* wbase,
-                                            int NF, int64_t beg, int64_t end) {
+__device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* tab, const cplx* tw,
+                                            double* wbase, int NF, int64_t beg, int64_t end) {
   const Prob& P = a.P;
   const int M = P.M, M0 = P.M0, L = P.L, mask = P.tab_n - 1, quarter = 2 * M;
   const int lane = threadIdx.x & 63;
@@ -412,14 +467,15 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
       double dx, dy, dz;
       dr_grid<MM>(pg, tab, q * tstride, J, mask, quarter, &dx, &dy, &dz);
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      const double rho = sqrt(r2);
+      const double ri = rsqrt_refined(r2);      // 1/rho
+      const double rho = r2 * ri;
       double skr, ckr;
       sincos_bounded(k * rho, &skr, &ckr);
       const int hidx = (q - qj - qu) * hstep;   // (theta_q - a)/2 = hidx pi/(4M) - ur/2
       const double sh = fma(tsin(tab, hidx, mask), cur, -tcos(tab, hidx, mask, quarter) * sur);
       const double s = fma(omq, omq, 4.0 * eb * sh * sh);
-      const double F = sqrt(s / r2);
-      const double S = (k == 0.0) ? 0.0 : skr / rho;
+      const double F = sqrt(s) * ri;
+      const double S = (k == 0.0) ? 0.0 : skr * ri;
       sumF += F;
       if (paper) {
         z1a[q] = mk(F, ckr);
@@ -431,7 +487,10 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     }
     wave_sync();
     cplx *Z1 = z1a, *free1 = z1b, *Z2 = z2a, *free2 = z2b;
-    fft_stockham(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter);
+    if (tw)
+      fft_stockham_small(Z1, free1, Z2, free2, want_c, NF, tw);
+    else
+      fft_stockham(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter);
 
     // truncation indices of the smooth factors
     const cplx* Fsrc = paper ? Z1 : Z2;
@@ -540,6 +599,12 @@ __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
   extern __shared__ double smem[];
   double* tab = smem;
   load_table(tab, a.tab_g, a.P.tab_n);
+  const int twd = coeff_twiddle_doubles(a.NF);
+  cplx* tw = twd ? reinterpret_cast<cplx*>(smem + a.P.tab_n) : nullptr;
+  if (tw) {
+    build_twiddles(tw, a.NF, a.P.M, tab, a.P.tab_n - 1, 2 * a.P.M);
+    __syncthreads();
+  }
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int waves_per_block = blockDim.x >> 6;
   const bool want_c = a.variant == FFBIE_KAPPA_PAPER_CONV || a.rhoinv != nullptr;
@@ -550,7 +615,8 @@ __global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
   const int64_t gw = (int64_t)blockIdx.x * waves_per_block + wave;
   const int64_t chunk = (count + total_waves - 1) / total_waves;
   const int64_t beg = gw * chunk, end = min(count, beg + chunk);
-  coeff_range<MM, REFINE>(a, tab, smem + a.P.tab_n + (size_t)wave * per_wave, a.NF, beg, end);
+  coeff_range<MM, REFINE>(a, tab, tw, smem + a.P.tab_n + twd + (size_t)wave * per_wave, a.NF, beg,
+                          end);
 }
 
 // ===========================================================================
@@ -585,15 +651,21 @@ __global__ __launch_bounds__(256) void ffbie_coeff_batch_kernel_t(BatchArgs b) {
     if (item >= b.n_items) break;
     const int s = batch_find(b.item_prefix, b.n_probs, item);
     const CoeffArgs& a = b.probs[s];
+    const int NF = 2 * a.P.M;
+    cplx* tw = coeff_twiddle_doubles(NF) ? reinterpret_cast<cplx*>(smem + b.tab_max) : nullptr;
     if (s != cur) {
       load_table(smem, a.tab_g, a.P.tab_n);    // ends with a barrier
+      if (tw) {
+        build_twiddles(tw, NF, a.P.M, smem, a.P.tab_n - 1, 2 * a.P.M);
+        __syncthreads();
+      }
       cur = s;
     }
-    const int NF = 2 * a.P.M;
     const int per_wave = coeff_lds_per_wave(NF, a.P.M, a.P.L, true);
     const int64_t t0 = (item - b.item_prefix[s]) * tile + (int64_t)wave * kBatchTile;
     const int64_t beg = min(a.n, t0), end = min(a.n, t0 + kBatchTile);
-    coeff_range<MM, false>(a, smem, smem + b.tab_max + (size_t)wave * per_wave, NF, beg, end);
+    coeff_range<MM, false>(a, smem, tw, smem + b.tab_max + b.tw_max + (size_t)wave * per_wave, NF,
+                           beg, end);
     __syncthreads();                           // all waves done before item_s / the table change
   }
 }
@@ -613,7 +685,7 @@ __global__ __launch_bounds__(64) void ffbie_coeff_batch_refine_t(BatchArgs b) {
       load_table(smem, a.tab_g, a.P.tab_n);
       cur = s;
     }
-    coeff_range<MM, true>(a, smem, smem + b.tab_max, 4 * a.P.M, pi, pi + 1);
+    coeff_range<MM, true>(a, smem, nullptr, smem + b.tab_max, 4 * a.P.M, pi, pi + 1);
     __syncthreads();
   }
 }

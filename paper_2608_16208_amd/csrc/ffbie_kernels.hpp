@@ -45,6 +45,7 @@ struct BatchArgs {
   int64_t* flag_list;        // refine queue: (problem << 40) | pair
   int32_t* flag_count;
   int tab_max;               // doubles reserved for the angle table at the start of LDS
+  int tw_max;                // doubles reserved after it for FFT twiddles (0 if none)
 };
 
 // Per-wavefront LDS of the coefficient kernel, in doubles.
@@ -53,6 +54,10 @@ struct BatchArgs {
 //   full: four NF-complex buffers and the <rho^-1> buffer (2L + 1 complex)
 //     A_m is stored mirrored, A[-m] = A[m] for m <= NF/2, so it needs M + NF + 2 doubles
 //     (compact) or fits an NF-complex buffer (full, since L <= NF).
+// LDS doubles of the per-workgroup FFT twiddle table (transforms of NF <= 128
+// points: 7 stages x 64 lanes complex), 0 otherwise.
+FFBIE_HD inline int coeff_twiddle_doubles(int NF) { return NF <= 128 ? 7 * 64 * 2 : 0; }
+
 FFBIE_HD inline int coeff_lds_per_wave(int NF, int M, int L, bool compact) {
   if (compact) return 2 * (2 * NF) + 2 * ((M + NF + 2) / 2) + 2 * (M + 1);
   return 2 * (4 * NF + 2 * L + 1);
