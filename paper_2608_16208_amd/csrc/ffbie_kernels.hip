@@ -594,8 +594,13 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
   }
 }
 
+// Surfaces of azimuthal order <= 2 fit 168 VGPRs with a few spilled values, so
+// they ask for three wavefronts per SIMD (more latency hiding); higher orders
+// would spill heavily and keep two.
 template <int MM, bool REFINE>
-__global__ __launch_bounds__(256) void ffbie_coeff_kernel_t(CoeffArgs a) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbie_coeff_kernel_t(
+    CoeffArgs a) {
   extern __shared__ double smem[];
   double* tab = smem;
   load_table(tab, a.tab_g, a.P.tab_n);
