@@ -340,6 +340,11 @@ __device__ __forceinline__ cplx swap_phase(int n, double ur, int Jq, const doubl
   return mk(tcos(tab, n * Jq, mask, quarter), -tsin(tab, n * Jq, mask)) * mk(c1, -s1);
 }
 
+// out[n] = e^{-i n a} sum_{|j| <= p} G_j A_{|n - j|}, n = 0..nmax (eq. (3.25) with
+// the phase split as in swap_phase).  G is Hermitian, G[p - j] = conj(G[p + j]),
+// so the j and -j terms share G_j:
+//   sum_j G_j A_{|n-j|} = G_0 A_n + sum_{j >= 1} [Re G_j (A_{|n-j|} + A_{n+j})
+//                                               + i Im G_j (A_{|n-j|} - A_{n+j})].
 // A must be mirrored: A[-m] = A[m] for m <= p.
 __device__ __forceinline__ void swap_convolution(const cplx* G, int p, const double* A, int nmax,
                                                  double ur, int Jq, const double* tab, int mask,
@@ -349,15 +354,16 @@ __device__ __forceinline__ void swap_convolution(const cplx* G, int p, const dou
   const int cnt = nmax + 1;
   const int rem = cnt & 63;
   const int split = (cnt > 64 && rem <= 4) ? cnt - rem : cnt;
+  const cplx* Gp = G + p;           // Gp[j], j = -p..p
   for (int n = lane; n < split; n += 64) {
-    double accr = 0.0, acci = 0.0;
-    const double* An = A + n + p;     // A is mirrored: An[-i] = A_{|n + p - i|}
+    const double An0 = A[n];
+    double accr = Gp[0].re * An0, acci = Gp[0].im * An0;
 #pragma unroll 4
-    for (int i = 0; i <= 2 * p; ++i) {
-      const cplx g = G[i];
-      const double Av = An[-i];
-      accr = fma(g.re, Av, accr);
-      acci = fma(g.im, Av, acci);
+    for (int j = 1; j <= p; ++j) {
+      const cplx g = Gp[j];
+      const double lo = A[n - j], hi = A[n + j];
+      accr = fma(g.re, lo + hi, accr);
+      acci = fma(g.im, lo - hi, acci);
     }
     const cplx c = swap_phase(n, ur, Jq, tab, mask, quarter) * mk(accr, acci);
     out[n] = c;
@@ -367,7 +373,7 @@ __device__ __forceinline__ void swap_convolution(const cplx* G, int p, const dou
   for (int n = split; n < cnt; ++n) {
     double accr = 0.0, acci = 0.0;
     for (int jj = -p + lane; jj <= p; jj += 64) {
-      const cplx g = G[p + jj];
+      const cplx g = Gp[jj];
       const double Av = A[n - jj];
       accr = fma(g.re, Av, accr);
       acci = fma(g.im, Av, acci);
