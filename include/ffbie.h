@@ -141,6 +141,24 @@ ffbie_status ffbie_kernel_coeffs(ffbie_ctx *ctx, int64_t n_pairs,
                                  void *d_kappa, void *d_rhoinv, double *d_root,
                                  int32_t *d_pair_status);
 
+/* Mixed-precision coefficient path: ffbie_kernel_coeffs with the spectral
+ * stage in FP32.  The surface samples, the complex root (Lemma 3.6), the
+ * recurrences for A_m(b) (eqs. (3.27)-(3.28)) and the swap phases e^{-i n a}
+ * stay in FP64; the FFTs of the sampled smooth factors, the truncation test of
+ * eq. (3.24), the stored A_m and the convolution sums of eq. (3.25) run in
+ * FP32.  Arguments as for ffbie_kernel_coeffs except:
+ *   d_kappa      [n_pairs][2M] complex64 (interleaved float32 re, im),
+ *   d_rhoinv     [n_pairs][M+M0+1] complex64 or NULL.
+ * The truncation threshold is max(eps0, 1e-6): the FP32 transforms carry a
+ * rounding floor of a few 1e-7 of the largest coefficient.  Results agree with
+ * the FP64 path to about 1e-6 of each row's largest coefficient.  Errors as
+ * for ffbie_kernel_coeffs. */
+ffbie_status ffbie_kernel_coeffs_mixed(ffbie_ctx *ctx, int64_t n_pairs,
+                                       const double *d_tgt_t, const int32_t *d_tgt_az,
+                                       const double *d_src_t,
+                                       void *d_kappa, void *d_rhoinv, double *d_root,
+                                       int32_t *d_pair_status);
+
 /* Device-side timing of the kernels ffbie_kernel_coeffs launches.  With
  * timing enabled, HIP events are recorded on the context's stream around the
  * root kernel, the main coefficient pass and the refine pass of every call;

@@ -24,7 +24,8 @@ EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_probl
            "ffbie_residual", "ffbie_kernel_coeffs_batched", "ffbie_lu_factor", "ffbie_lu_solve",
            "ffbie_mlp_param_count", "ffbie_mlp_init", "ffbie_mlp_set_params", "ffbie_mlp_get_params",
            "ffbie_mlp_forward", "ffbie_mlp_train_step", "ffbie_mode_features", "ffbie_mode_targets",
-           "ffbie_mlp_precondition", "ffbie_blockjacobi_setup", "ffbie_blockjacobi_apply")
+           "ffbie_mlp_precondition", "ffbie_blockjacobi_setup", "ffbie_blockjacobi_apply",
+           "ffbie_kernel_coeffs_mixed")
 SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES, SOLVE_FGMRES_MLP, SOLVE_GMRES_BLOCKJACOBI = 0, 1, 2, 3, 4
 MLP_IN, MLP_HIDDEN, MLP_OUT = 514, 256, 512
 WNOTCONV = 2
@@ -78,6 +79,7 @@ def load_library(path=LIB_PATH):
     lib.ffbie_last_error.restype = ctypes.c_char_p
     lib.ffbie_set_problem.argtypes = [vp, ctypes.POINTER(_Geometry), ctypes.POINTER(_Disc), ctypes.c_double]
     lib.ffbie_kernel_coeffs.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
+    lib.ffbie_kernel_coeffs_mixed.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     lib.ffbie_singular_factor.argtypes = [vp, i64, vp, i32, vp]
     lib.ffbie_enable_timing.argtypes = [vp, i32]
     dp = ctypes.POINTER(ctypes.c_double)
@@ -175,11 +177,15 @@ class Context:
         self._check(self.lib.ffbie_set_problem(self.h, ctypes.byref(geo), ctypes.byref(disc), float(k)), self.h)
         self.M, self.M0 = int(M), int(M if M0 is None else M0)
 
-    def kernel_coeffs(self, t, az, ts, rhoinv=False, root=False, status=True, kappa=None):
+    def kernel_coeffs(self, t, az, ts, rhoinv=False, root=False, status=True, kappa=None,
+                      mixed=False):
         """kappa [n, 2M] complex128 (n = -M+1..M); optional <rho^-1> [n, M+M0+1],
-        root [n, 2] (a - theta_j, b) and per-pair status [n] int32."""
+        root [n, 2] (a - theta_j, b) and per-pair status [n] int32.  With
+        mixed=True the FP32 spectral-stage path runs and kappa / <rho^-1> are
+        complex64."""
         torch = self._torch
         dev = self.device
+        cdt = torch.complex64 if mixed else torch.complex128
         t = t.to(dev, torch.float64).contiguous()
         ts = ts.to(dev, torch.float64).contiguous()
         az = az.to(dev, torch.int32).contiguous()
@@ -187,12 +193,16 @@ class Context:
         if az.numel() != n or ts.numel() != n:
             raise FfbieError("t, az and ts must have the same length")
         out = {}
-        out["kappa"] = kappa if kappa is not None else torch.empty((n, 2 * self.M), dtype=torch.complex128, device=dev)
-        out["rhoinv"] = torch.empty((n, self.M + self.M0 + 1), dtype=torch.complex128, device=dev) if rhoinv else None
+        if kappa is not None and (kappa.dtype != cdt or kappa.shape != (n, 2 * self.M)
+                                  or not kappa.is_contiguous()):
+            raise FfbieError("kappa must be a contiguous [n, 2M] %s tensor" % cdt)
+        out["kappa"] = kappa if kappa is not None else torch.empty((n, 2 * self.M), dtype=cdt, device=dev)
+        out["rhoinv"] = torch.empty((n, self.M + self.M0 + 1), dtype=cdt, device=dev) if rhoinv else None
         out["root"] = torch.empty((n, 2), dtype=torch.float64, device=dev) if root else None
         out["status"] = torch.empty((n,), dtype=torch.int32, device=dev) if status else None
-        rc = self.lib.ffbie_kernel_coeffs(self.h, n, _ptr(t), _ptr(az), _ptr(ts), _ptr(out["kappa"]),
-                                          _ptr(out["rhoinv"]), _ptr(out["root"]), _ptr(out["status"]))
+        fn = self.lib.ffbie_kernel_coeffs_mixed if mixed else self.lib.ffbie_kernel_coeffs
+        rc = fn(self.h, n, _ptr(t), _ptr(az), _ptr(ts), _ptr(out["kappa"]), _ptr(out["rhoinv"]),
+                _ptr(out["root"]), _ptr(out["status"]))
         self._check(rc, self.h)
         return out
 

@@ -87,6 +87,11 @@ namespace {
 
 const char* kNoCtx = "ffbie: NULL context";
 
+// Smooth-factor truncation threshold of the mixed-precision path: the FP32
+// transforms leave a rounding floor of a few 1e-7 of the largest coefficient,
+// so a smaller threshold would make p follow the noise.
+constexpr double kEpsMixed = 1e-6;
+
 ffbie_status fail(ffbie_ctx* c, ffbie_status s, const std::string& msg) {
   if (c) c->err = msg;
   return s;
@@ -264,9 +269,9 @@ ffbie_status ensure_ws(ffbie_ctx* c, int64_t n) {
 }
 
 // waves per workgroup so that the coefficient kernel fits 64 KiB of LDS
-int coeff_waves(const Prob& P, int NF, bool compact, size_t* lds_bytes) {
-  const size_t per_wave = sizeof(double) * coeff_lds_per_wave(NF, P.M, P.L, compact);
-  const size_t tab = sizeof(double) * (P.tab_n + coeff_twiddle_doubles(NF));
+int coeff_waves(const Prob& P, int NF, bool compact, bool single, size_t* lds_bytes) {
+  const size_t per_wave = sizeof(double) * coeff_lds_per_wave(NF, P.M, P.L, compact, single);
+  const size_t tab = sizeof(double) * (P.tab_n + coeff_twiddle_doubles(NF, single));
   int w = 4;
   while (w > 1 && tab + w * per_wave > 65536) --w;
   *lds_bytes = tab + w * per_wave;
@@ -346,10 +351,11 @@ ffbie_status ffbie_set_problem(ffbie_ctx* c, const ffbie_geometry* g, const ffbi
 namespace {
 
 // The coefficient path on n pairs: root kernel, main pass (2M samples), refine
-// pass (4M samples).  Inputs validated by the caller.
+// pass (4M samples); `single` selects the FP32 spectral stage (complex64
+// outputs).  Inputs validated by the caller.
 ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_t* d_az,
                         const double* d_ts, void* d_kappa, void* d_rhoinv, double* d_root,
-                        int32_t* d_pair_status) {
+                        int32_t* d_pair_status, bool single = false) {
   ffbie_status s = ensure_ws(c, n);
   if (s != FFBIE_OK) return s;
   const Prob& P = c->prob;
@@ -362,6 +368,7 @@ ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_
   // kernel 2: main pass with 2M samples, then the refine pass with 4M samples
   CoeffArgs a{};
   a.P = P;
+  if (single) a.P.eps0 = std::max(P.eps0, kEpsMixed);
   a.tab_g = c->d_tab;
   a.n = n;
   a.t_in = d_t;
@@ -369,8 +376,8 @@ ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_
   a.ts_in = d_ts;
   a.roots = c->d_roots;
   a.status = status;
-  a.kappa = static_cast<cplx*>(d_kappa);
-  a.rhoinv = static_cast<cplx*>(d_rhoinv);
+  a.kappa = d_kappa;
+  a.rhoinv = d_rhoinv;
   a.variant = c->variant;
   const bool compact = c->variant == FFBIE_KAPPA_SWAP && d_rhoinv == nullptr;
   {
@@ -378,12 +385,12 @@ ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_
     a.flag_list = c->d_list;
     a.flag_count = c->d_count;
     size_t lds;
-    const int w = coeff_waves(P, a.NF, compact, &lds);
+    const int w = coeff_waves(P, a.NF, compact, single, &lds);
     const int64_t pairs_per_wave = 16;
     int64_t blocks = (n + w * pairs_per_wave - 1) / (w * pairs_per_wave);
     if (blocks < 1) blocks = 1;
     if (c->timing) FFBIE_HIP(c, hipEventRecord(c->ev[1], c->stream));
-    FFBIE_HIP(c, launch_coeff(a, blocks, w, lds, c->stream, false));
+    FFBIE_HIP(c, launch_coeff(a, blocks, w, lds, c->stream, false, single));
     if (c->timing) FFBIE_HIP(c, hipEventRecord(c->ev[2], c->stream));
   }
   {
@@ -393,8 +400,8 @@ ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_
     a.flag_list = nullptr;
     a.flag_count = nullptr;
     size_t lds;
-    const int w = coeff_waves(P, a.NF, compact, &lds);
-    FFBIE_HIP(c, launch_coeff(a, 512, w, lds, c->stream, true));
+    const int w = coeff_waves(P, a.NF, compact, single, &lds);
+    FFBIE_HIP(c, launch_coeff(a, 512, w, lds, c->stream, true, single));
     if (c->timing) FFBIE_HIP(c, hipEventRecord(c->ev[3], c->stream));
   }
   if (c->timing) c->timed = true;
@@ -475,6 +482,20 @@ ffbie_status ffbie_kernel_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, con
   if (n > (int64_t)1 << 31) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs: n_pairs > 2^31");
   FFBIE_HIP(c, hipSetDevice(c->device));
   return run_coeffs(c, n, d_t, d_az, d_ts, d_kappa, d_rhoinv, d_root, d_pair_status);
+}
+
+ffbie_status ffbie_kernel_coeffs_mixed(ffbie_ctx* c, int64_t n, const double* d_t,
+                                       const int32_t* d_az, const double* d_ts, void* d_kappa,
+                                       void* d_rhoinv, double* d_root, int32_t* d_pair_status) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_kernel_coeffs_mixed: no problem set");
+  if (n < 0) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_mixed: n_pairs < 0");
+  if (n == 0) return FFBIE_OK;
+  if (!d_t || !d_az || !d_ts || !d_kappa)
+    return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_mixed: NULL input or kappa pointer");
+  if (n > (int64_t)1 << 31) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_mixed: n_pairs > 2^31");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  return run_coeffs(c, n, d_t, d_az, d_ts, d_kappa, d_rhoinv, d_root, d_pair_status, true);
 }
 
 ffbie_status ffbie_builtin_near_rule(ffbie_near_rule* out) {
@@ -713,13 +734,13 @@ ffbie_status ffbie_kernel_coeffs_batched(ffbie_ctx* c, int n_items, const ffbie_
   const int tab_max = 8 * Mmax;
   int Mmin = 128;
   for (int i : order) Mmin = std::min(Mmin, items[i].d.M);
-  const int tw_max = coeff_twiddle_doubles(2 * Mmin);
-  const size_t per_wave = sizeof(double) * coeff_lds_per_wave(2 * Mmax, Mmax, 2 * Mmax, true);
+  const int tw_max = coeff_twiddle_doubles(2 * Mmin, false);
+  const size_t per_wave = sizeof(double) * coeff_lds_per_wave(2 * Mmax, Mmax, 2 * Mmax, true, false);
   int waves = 4;
   while (waves > 1 && (tab_max + tw_max) * sizeof(double) + waves * per_wave > 65536) --waves;
   const size_t lds = (tab_max + tw_max) * sizeof(double) + waves * per_wave;
   const size_t refine_lds =
-      tab_max * sizeof(double) + sizeof(double) * coeff_lds_per_wave(4 * Mmax, Mmax, 2 * Mmax, true);
+      tab_max * sizeof(double) + sizeof(double) * coeff_lds_per_wave(4 * Mmax, Mmax, 2 * Mmax, true, false);
   const int64_t tile = (int64_t)waves * kBatchTile;
   // descriptors
   const int np = (int)order.size();
@@ -740,7 +761,7 @@ ffbie_status ffbie_kernel_coeffs_batched(ffbie_ctx* c, int n_items, const ffbie_
     a.ts_in = it.d_ts;
     a.roots = c->d_roots + off;
     a.status = it.d_pair_status ? it.d_pair_status : c->d_status + off;
-    a.kappa = static_cast<cplx*>(it.d_kappa);
+    a.kappa = it.d_kappa;
     a.rhoinv = nullptr;
     a.NF = 2 * it.d.M;
     a.flag_list = c->d_list;

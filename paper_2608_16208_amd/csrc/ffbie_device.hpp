@@ -65,6 +65,38 @@ FFBIE_HD __forceinline__ cplx cdiv(cplx a, cplx b) {
   double r = b.re / b.im, d = b.re * r + b.im;
   return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
 }
+
+// ----------------------------------------------------------------------------
+// complex float: the spectral stage (transforms, truncation, convolutions) of
+// the mixed-precision coefficient path
+// ----------------------------------------------------------------------------
+struct cplxf {
+  float re, im;
+};
+FFBIE_HD __forceinline__ cplxf operator+(cplxf a, cplxf b) { return {a.re + b.re, a.im + b.im}; }
+FFBIE_HD __forceinline__ cplxf operator-(cplxf a, cplxf b) { return {a.re - b.re, a.im - b.im}; }
+FFBIE_HD __forceinline__ cplxf operator*(cplxf a, cplxf b) {
+  return {fmaf(a.re, b.re, -a.im * b.im), fmaf(a.re, b.im, a.im * b.re)};
+}
+FFBIE_HD __forceinline__ cplxf operator*(float s, cplxf a) { return {s * a.re, s * a.im}; }
+FFBIE_HD __forceinline__ cplxf conj(cplxf a) { return {a.re, -a.im}; }
+FFBIE_HD __forceinline__ float abs2(cplxf a) { return fmaf(a.re, a.re, a.im * a.im); }
+
+// Number types of the spectral stage: Spec<double> (FP64 path) or Spec<float>.
+template <class R>
+struct Spec;
+template <>
+struct Spec<double> {
+  using C = cplx;
+  FFBIE_HD static __forceinline__ cplx narrow(cplx z) { return z; }
+  FFBIE_HD static __forceinline__ cplx wide(cplx z) { return z; }
+};
+template <>
+struct Spec<float> {
+  using C = cplxf;
+  FFBIE_HD static __forceinline__ cplxf narrow(cplx z) { return {(float)z.re, (float)z.im}; }
+  FFBIE_HD static __forceinline__ cplx wide(cplxf z) { return {(double)z.re, (double)z.im}; }
+};
 // sin and cos of a real argument with |x| <= 2^19 pi (all arguments on this
 // path are bounded: k rho, multiples of grid offsets, curve parameters).
 // Cody-Waite reduction x = q pi/2 + r, with pi/2 split into three parts of which
@@ -324,6 +356,14 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 __device__ __forceinline__ double wave_max(double v) {
   for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d));
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+  for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d));
   return v;
 }
 

@@ -105,16 +105,19 @@ __device__ __forceinline__ void mat_mul(double a00, double a01, double a10, doub
   *c11 = fma(a10, b01, a11 * b11);
 }
 
+// A is stored as R (double, or float on the mixed-precision path); the
+// recurrences themselves always run in FP64.
+template <class R>
 __device__ __forceinline__ void singular_factor_wave(double b, double A0, double D1, int mtop,
-                                                     double* A) {
+                                                     R* A) {
   const int lane = threadIdx.x & 63;
   if (!(b > 0) || !(A0 == A0)) {
-    for (int m = lane; m <= mtop; m += 64) A[m] = __builtin_nan("");
+    for (int m = lane; m <= mtop; m += 64) A[m] = (R)__builtin_nan("");
     wave_sync();
     return;
   }
   if (mtop == 0) {
-    if (lane == 0) A[0] = A0;
+    if (lane == 0) A[0] = (R)A0;
     wave_sync();
     return;
   }
@@ -159,9 +162,9 @@ __device__ __forceinline__ void singular_factor_wave(double b, double A0, double
       const double nD = fma(al, wD, be * wA);
       wA = wA + nD;
       wD = nD;
-      A[m + 1] = wA;
+      A[m + 1] = (R)wA;
     }
-    if (lane == 0) { A[0] = A0; A[1] = A0 + D1; }
+    if (lane == 0) { A[0] = (R)A0; A[1] = (R)(A0 + D1); }
     wave_sync();
     return;
   }
@@ -174,7 +177,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double A0, double
     N = (int)floor(640.0 / b);
     meff = min(mtop, max(0, N - 10));
     if (N < 1) {   // b > 640: A_m / A_0 < 1e-270 for every m >= 1
-      for (int m = lane; m <= mtop; m += 64) A[m] = (m == 0) ? A0 : 0.0;
+      for (int m = lane; m <= mtop; m += 64) A[m] = (R)((m == 0) ? A0 : 0.0);
       wave_sync();
       return;
     }
@@ -205,72 +208,95 @@ __device__ __forceinline__ void singular_factor_wave(double b, double A0, double
   if (lane == 63) { q00 = 1; q10 = 0; }
   // state entering the segment: Q_{l+1} (y_s, 0)
   double y0 = q00 * kMillerStart, y1 = q10 * kMillerStart;   // (y_top, y_top+1)
-  for (int m = top; m > lane * S; --m) {
-    if (m > N) continue;
-    const double r = rcp_int(2.0 * m - 1.0);
-    const double yn = (ch4 * m * y0 - (2.0 * m + 1.0) * y1) * r;
-    y1 = y0;
-    y0 = yn;                         // y_{m-1}
-    if (m - 1 <= mtop) A[m - 1] = yn;
+  if constexpr (sizeof(R) == sizeof(double)) {
+    // store the unnormalised values, then scale by A_0 / y_0 with y_0 as replayed
+    for (int m = top; m > lane * S; --m) {
+      if (m > N) continue;
+      const double r = rcp_int(2.0 * m - 1.0);
+      const double yn = (ch4 * m * y0 - (2.0 * m + 1.0) * y1) * r;
+      y1 = y0;
+      y0 = yn;                       // y_{m-1}
+      if (m - 1 <= mtop) A[m - 1] = yn;
+    }
+    wave_sync();
+    const double scale = A0 / A[0];
+    wave_sync();
+    for (int m = lane; m <= mtop; m += 64) A[m] = (m <= meff) ? A[m] * scale : 0.0;
+  } else {
+    // the unnormalised values leave the float range: lane 0 holds the whole
+    // product Q_0, so y_0 = Q_0[0][0] y_N fixes the normalisation first
+    const double scale = A0 / (__shfl(p00, 0) * kMillerStart);
+    for (int m = top; m > lane * S; --m) {
+      if (m > N) continue;
+      const double r = rcp_int(2.0 * m - 1.0);
+      const double yn = (ch4 * m * y0 - (2.0 * m + 1.0) * y1) * r;
+      y1 = y0;
+      y0 = yn;                       // y_{m-1}
+      if (m - 1 <= mtop) A[m - 1] = (R)((m - 1 <= meff) ? yn * scale : 0.0);
+    }
+    for (int m = N + lane; m <= mtop; m += 64) A[m] = (R)0.0;
   }
-  wave_sync();
-  const double scale = A0 / A[0];
-  wave_sync();
-  for (int m = lane; m <= mtop; m += 64) A[m] = (m <= meff) ? A[m] * scale : 0.0;
   wave_sync();
 }
 
 // ===========================================================================
+// Spectral stage, generic over the complex type C (cplx, or cplxf on the
+// mixed-precision path); R is its real type.
+//
 // Forward DFT X_n = sum_q x_q e^{-2 pi i q n / NF} of one or two sequences,
 // radix-2 Stockham autosort in LDS.  On return ia/ib hold the transforms and
 // oa/ob are free.
 // ===========================================================================
-__device__ __forceinline__ void fft_stockham(cplx*& ia, cplx*& oa, cplx*& ib, cplx*& ob, bool two,
-                                             int NF, int M, const double* tab, int mask,
-                                             int quarter) {
+template <class C>
+__device__ __forceinline__ void fft_stockham(C*& ia, C*& oa, C*& ib, C*& ob, bool two, int NF, int M,
+                                             const double* tab, int mask, int quarter) {
+  using R = decltype(C::re);
   const int lane = threadIdx.x & 63;
   const int half = NF >> 1;
   for (int Ns = 1; Ns < NF; Ns <<= 1) {
     for (int jj = lane; jj < half; jj += 64) {
       const int r = jj & (Ns - 1);
       const int tk = r * ((4 * M) / Ns);            // angle pi r / Ns
-      const cplx wt = mk(tcos(tab, tk, mask, quarter), -tsin(tab, tk, mask));
+      const C wt = C{(R)tcos(tab, tk, mask, quarter), (R)-tsin(tab, tk, mask)};
       const int idxD = ((jj - r) << 1) + r;
-      const cplx v0 = ia[jj], v1 = ia[jj + half] * wt;
+      const C v0 = ia[jj], v1 = ia[jj + half] * wt;
       oa[idxD] = v0 + v1;
       oa[idxD + Ns] = v0 - v1;
       if (two) {
-        const cplx u0 = ib[jj], u1 = ib[jj + half] * wt;
+        const C u0 = ib[jj], u1 = ib[jj + half] * wt;
         ob[idxD] = u0 + u1;
         ob[idxD + Ns] = u0 - u1;
       }
     }
     wave_sync();
-    cplx* tmp = ia; ia = oa; oa = tmp;
+    C* tmp = ia; ia = oa; oa = tmp;
     tmp = ib; ib = ob; ob = tmp;
   }
 }
 
 // Twiddle factors of a transform of NF <= 128 points, one entry per (stage,
 // lane): at stage Ns = 2^st the butterfly jj = lane uses e^{-i pi r / Ns},
-// r = jj mod Ns.  Built once per workgroup into LDS (kTwiddleDoubles doubles),
-// read with one conflict-free 16-byte load per butterfly.
+// r = jj mod Ns.  Built once per workgroup into LDS, read with one
+// conflict-free load per butterfly.
 constexpr int kTwiddleStages = 7;
 
-__device__ __forceinline__ void build_twiddles(cplx* tw, int NF, int M, const double* tab, int mask,
+template <class C>
+__device__ __forceinline__ void build_twiddles(C* tw, int NF, int M, const double* tab, int mask,
                                                int quarter) {
+  using R = decltype(C::re);
   for (int idx = threadIdx.x; idx < kTwiddleStages * 64; idx += blockDim.x) {
     const int st = idx >> 6, lane = idx & 63;
     const int Ns = 1 << st;
     const int r = lane & (Ns - 1);
     const int tk = (Ns < NF) ? r * ((4 * M) / Ns) : 0;
-    tw[idx] = mk(tcos(tab, tk, mask, quarter), -tsin(tab, tk, mask));
+    tw[idx] = C{(R)tcos(tab, tk, mask, quarter), (R)-tsin(tab, tk, mask)};
   }
 }
 
 // Forward DFT as fft_stockham for NF <= 128 with the twiddles of build_twiddles.
-__device__ __forceinline__ void fft_stockham_small(cplx*& ia, cplx*& oa, cplx*& ib, cplx*& ob,
-                                                   bool two, int NF, const cplx* tw) {
+template <class C>
+__device__ __forceinline__ void fft_stockham_small(C*& ia, C*& oa, C*& ib, C*& ob, bool two, int NF,
+                                                   const C* tw) {
   const int lane = threadIdx.x & 63;
   const int half = NF >> 1;
   for (int st = 0; (1 << st) < NF; ++st) {
@@ -278,33 +304,35 @@ __device__ __forceinline__ void fft_stockham_small(cplx*& ia, cplx*& oa, cplx*& 
     if (lane < half) {
       const int jj = lane;
       const int r = jj & (Ns - 1);
-      const cplx wt = tw[(st << 6) + lane];
+      const C wt = tw[(st << 6) + lane];
       const int idxD = ((jj - r) << 1) + r;
-      const cplx v0 = ia[jj], v1 = ia[jj + half] * wt;
+      const C v0 = ia[jj], v1 = ia[jj + half] * wt;
       oa[idxD] = v0 + v1;
       oa[idxD + Ns] = v0 - v1;
       if (two) {
-        const cplx u0 = ib[jj], u1 = ib[jj + half] * wt;
+        const C u0 = ib[jj], u1 = ib[jj + half] * wt;
         ob[idxD] = u0 + u1;
         ob[idxD + Ns] = u0 - u1;
       }
     }
     wave_sync();
-    cplx* tmp = ia; ia = oa; oa = tmp;
+    C* tmp = ia; ia = oa; oa = tmp;
     tmp = ib; ib = ob; ob = tmp;
   }
 }
 
 // Coefficient j of the real sequence packed in the real part of the
 // transform X: (X_j + conj(X_{NF-j})) / (2 NF).
-__device__ __forceinline__ cplx real_part_coeff(const cplx* X, int jj, int NF, double invNF) {
-  return (0.5 * invNF) * (X[jj & (NF - 1)] + conj(X[(NF - jj) & (NF - 1)]));
+template <class C>
+__device__ __forceinline__ C real_part_coeff(const C* X, int jj, int NF, decltype(C::re) invNF) {
+  return (decltype(C::re))(0.5 * invNF) * (X[jj & (NF - 1)] + conj(X[(NF - jj) & (NF - 1)]));
 }
 // Coefficient j of the real sequence packed in the imaginary part:
 // (X_j - conj(X_{NF-j})) / (2i NF).
-__device__ __forceinline__ cplx imag_part_coeff(const cplx* X, int jj, int NF, double invNF) {
-  const cplx d = (0.5 * invNF) * (X[jj & (NF - 1)] - conj(X[(NF - jj) & (NF - 1)]));
-  return mk(d.im, -d.re);
+template <class C>
+__device__ __forceinline__ C imag_part_coeff(const C* X, int jj, int NF, decltype(C::re) invNF) {
+  const C d = (decltype(C::re))(0.5 * invNF) * (X[jj & (NF - 1)] - conj(X[(NF - jj) & (NF - 1)]));
+  return C{d.im, -d.re};
 }
 
 // Truncation index of a real sequence's coefficients (the rule of eq. (3.13)
@@ -313,13 +341,15 @@ __device__ __forceinline__ cplx imag_part_coeff(const cplx* X, int jj, int NF, d
 // F cos(k rho) be measured against the size of F itself: |cos(k rho)| <= 1, and
 // where cos(k rho) averages out its coefficients are small while the rounding
 // floor still follows F.
-__device__ __forceinline__ int trunc_index_real(const cplx* X, int NF, double invNF, double eps,
+template <class C>
+__device__ __forceinline__ int trunc_index_real(const C* X, int NF, decltype(C::re) invNF, double eps,
                                                 double ref) {
+  using R = decltype(C::re);
   const int lane = threadIdx.x & 63;
-  double maxv = 0.0;
+  R maxv = 0;
   for (int jj = lane; jj < NF / 2; jj += 64) maxv = fmax(maxv, abs2(real_part_coeff(X, jj, NF, invNF)));
-  maxv = fmax(wave_max(maxv), ref * ref);
-  const double thr = eps * eps * maxv;
+  maxv = fmax(wave_max(maxv), (R)(ref * ref));
+  const R thr = (R)(eps * eps) * maxv;
   int p = 0;
   for (int jj = lane; jj < NF / 2; jj += 64) {
     const uint64_t bal = __ballot(abs2(real_part_coeff(X, jj, NF, invNF)) > thr);
@@ -329,10 +359,10 @@ __device__ __forceinline__ int trunc_index_real(const cplx* X, int NF, double in
 }
 
 // out_n = e^{-i n a} sum_{|j| <= p} G_j A_{|n-j|} for n = 0..nmax, with
-// e^{-i n a} = e^{-i n (theta_j + qu gstep)} e^{-i n ur}.  Outputs are spread
-// over the lanes; when the count exceeds a multiple of 64 by a few, those last
-// outputs are summed cooperatively (terms over lanes, then a wave sum) instead
-// of costing the whole wave another pass.
+// e^{-i n a} = e^{-i n (theta_j + qu gstep)} e^{-i n ur} evaluated in FP64.
+// Outputs are spread over the lanes; when the count exceeds a multiple of 64
+// by a few, those last outputs are summed cooperatively (terms over lanes, then
+// a wave sum) instead of costing the whole wave another pass.
 __device__ __forceinline__ cplx swap_phase(int n, double ur, int Jq, const double* tab, int mask,
                                            int quarter) {
   double s1, c1;
@@ -340,48 +370,48 @@ __device__ __forceinline__ cplx swap_phase(int n, double ur, int Jq, const doubl
   return mk(tcos(tab, n * Jq, mask, quarter), -tsin(tab, n * Jq, mask)) * mk(c1, -s1);
 }
 
-// out[n] = e^{-i n a} sum_{|j| <= p} G_j A_{|n - j|}, n = 0..nmax (eq. (3.25) with
-// the phase split as in swap_phase).  G is Hermitian, G[p - j] = conj(G[p + j]),
-// so the j and -j terms share G_j:
+// G is Hermitian, G[p - j] = conj(G[p + j]), so the j and -j terms share G_j:
 //   sum_j G_j A_{|n-j|} = G_0 A_n + sum_{j >= 1} [Re G_j (A_{|n-j|} + A_{n+j})
-//                                               + i Im G_j (A_{|n-j|} - A_{n+j})].
-// A must be mirrored: A[-m] = A[m] for m <= p.
-__device__ __forceinline__ void swap_convolution(const cplx* G, int p, const double* A, int nmax,
+//                                               + i Im G_j (A_{|n-j|} - A_{n+j})]
+// (the sum of eq. (3.25)).  A must be mirrored: A[-m] = A[m] for m <= p.
+template <class C>
+__device__ __forceinline__ void swap_convolution(const C* G, int p, const decltype(C::re)* A, int nmax,
                                                  double ur, int Jq, const double* tab, int mask,
-                                                 int quarter, cplx* out, cplx* mirror,
-                                                 cplx* global_row) {
+                                                 int quarter, C* out, C* mirror, C* global_row) {
+  using R = decltype(C::re);
+  using SP = Spec<R>;
   const int lane = threadIdx.x & 63;
   const int cnt = nmax + 1;
   const int rem = cnt & 63;
   const int split = (cnt > 64 && rem <= 4) ? cnt - rem : cnt;
-  const cplx* Gp = G + p;           // Gp[j], j = -p..p
+  const C* Gp = G + p;           // Gp[j], j = -p..p
   for (int n = lane; n < split; n += 64) {
-    const double An0 = A[n];
-    double accr = Gp[0].re * An0, acci = Gp[0].im * An0;
+    const R An0 = A[n];
+    R accr = Gp[0].re * An0, acci = Gp[0].im * An0;
 #pragma unroll 4
     for (int j = 1; j <= p; ++j) {
-      const cplx g = Gp[j];
-      const double lo = A[n - j], hi = A[n + j];
+      const C g = Gp[j];
+      const R lo = A[n - j], hi = A[n + j];
       accr = fma(g.re, lo + hi, accr);
       acci = fma(g.im, lo - hi, acci);
     }
-    const cplx c = swap_phase(n, ur, Jq, tab, mask, quarter) * mk(accr, acci);
+    const C c = SP::narrow(swap_phase(n, ur, Jq, tab, mask, quarter) * mk(accr, acci));
     out[n] = c;
     if (mirror) mirror[-n] = conj(c);
     if (global_row) global_row[n] = c;
   }
   for (int n = split; n < cnt; ++n) {
-    double accr = 0.0, acci = 0.0;
+    R accr = 0, acci = 0;
     for (int jj = -p + lane; jj <= p; jj += 64) {
-      const cplx g = Gp[jj];
-      const double Av = A[n - jj];
+      const C g = Gp[jj];
+      const R Av = A[n - jj];
       accr = fma(g.re, Av, accr);
       acci = fma(g.im, Av, acci);
     }
     accr = wave_sum(accr);
     acci = wave_sum(acci);
     if (lane == 0) {
-      const cplx c = swap_phase(n, ur, Jq, tab, mask, quarter) * mk(accr, acci);
+      const C c = SP::narrow(swap_phase(n, ur, Jq, tab, mask, quarter) * mk(accr, acci));
       out[n] = c;
       if (mirror) mirror[-n] = conj(c);
       if (global_row) global_row[n] = c;
@@ -403,34 +433,43 @@ __device__ __forceinline__ void swap_convolution(const cplx* G, int p, const dou
 // The coefficient path for the pairs w in [beg, end) of one problem, by one
 // wavefront (indices into a.list when it is set).  `tab` is the problem's angle
 // table in LDS, `tw` its FFT twiddles in LDS (NF <= 128) or null, `wbase` this
-// wavefront's LDS workspace, NF the sample count.
-template <int MM, bool REFINE>
-__device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* tab, const cplx* tw,
-                                            double* wbase, int NF, int64_t beg, int64_t end) {
+// wavefront's LDS workspace, NF the sample count.  R is the real type of the
+// spectral stage (transforms, truncation, A_m storage, convolutions, outputs):
+// double, or float for the mixed-precision path; geometry, samples, the root
+// and the recurrences for A_m run in FP64 either way.
+template <int MM, bool REFINE, class R>
+__device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* tab,
+                                            const typename Spec<R>::C* tw, double* wbase, int NF,
+                                            int64_t beg, int64_t end) {
+  using C = typename Spec<R>::C;
+  using SP = Spec<R>;
   const Prob& P = a.P;
   const int M = P.M, M0 = P.M0, L = P.L, mask = P.tab_n - 1, quarter = 2 * M;
   const int lane = threadIdx.x & 63;
   const bool paper = a.variant == FFBIE_KAPPA_PAPER_CONV;
   const bool want_c = paper || a.rhoinv != nullptr;
-  cplx* base = reinterpret_cast<cplx*>(wbase);
-  cplx* z1a = base;
-  cplx* z1b = z1a + NF;
+  C* base = reinterpret_cast<C*>(wbase);
+  C* z1a = base;
+  C* z1b = z1a + NF;
   // full layout: z2a, z2b, cb; compact layout: A_m buffer and kc
-  cplx* z2a = z1b + NF;
-  cplx* z2b = z2a + NF;
-  cplx* cb = want_c ? z2b + NF : z1b + NF + (M + NF + 2) / 2;
-  double* Acompact = reinterpret_cast<double*>(z1b + NF);
+  C* z2a = z1b + NF;
+  C* z2b = z2a + NF;
+  C* cb = want_c ? z2b + NF : z1b + NF + (M + NF + 2) / 2;
+  R* Acompact = reinterpret_cast<R*>(z1b + NF);
+  C* kappa = static_cast<C*>(a.kappa);
+  C* rhoinv = static_cast<C*>(a.rhoinv);
 
   const int tstride = (8 * M) / NF;        // table index step of the sample grid
   const int hstep = (4 * M) / NF;          // table index step of half a grid step
   const double nan = __builtin_nan("");
   const double k = P.k;
-  const double invNF = 1.0 / NF;
+  const R invNF = (R)1 / (R)NF;
   // sin(k rho)/rho <= k is packed beside F cos(k rho) = O(1) in one transform;
   // it is scaled by an exact power of two near 1/k so that its size does not
   // raise the rounding floor of the other sequence's coefficients
   const int kexp = (k > 1.0) ? (int)ceil(log2(k)) : 0;
-  const double s_down = ldexp(1.0, -kexp), s_up = ldexp(1.0, kexp);
+  const double s_down = ldexp(1.0, -kexp);
+  const R s_up = (R)ldexp(1.0, kexp);
 
   double t_prev = nan, ts_prev = nan;
   PairGeo<MM> pg;
@@ -441,12 +480,12 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     const int j = a.az_in[pi] & (2 * M - 1);
     const RootRec rr = a.roots[pi];
     int st = a.status[pi] & ((1 << FFBIE_PAIR_P_SHIFT) - 1);
-    cplx* krow = a.kappa + pi * (int64_t)(2 * M);
-    cplx* crow = a.rhoinv ? a.rhoinv + pi * (int64_t)(L + 1) : nullptr;
+    C* krow = kappa + pi * (int64_t)(2 * M);
+    C* crow = rhoinv ? rhoinv + pi * (int64_t)(L + 1) : nullptr;
     if (st & FFBIE_PAIR_SINGULAR) {
-      for (int c = lane; c < 2 * M; c += 64) krow[c] = mk(nan, nan);
+      for (int c = lane; c < 2 * M; c += 64) krow[c] = C{(R)nan, (R)nan};
       if (crow)
-        for (int c = lane; c <= L; c += 64) crow[c] = mk(nan, nan);
+        for (int c = lane; c <= L; c += 64) crow[c] = C{(R)nan, (R)nan};
       continue;
     }
     const int J = 4 * j;
@@ -484,23 +523,23 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
       const double S = (k == 0.0) ? 0.0 : skr * ri;
       sumF += F;
       if (paper) {
-        z1a[q] = mk(F, ckr);
-        z2a[q] = mk(S, 0.0);
+        z1a[q] = C{(R)F, (R)ckr};
+        z2a[q] = C{(R)S, (R)0};
       } else {
-        z1a[q] = mk(F * ckr, S * s_down);
-        if (want_c) z2a[q] = mk(F, 0.0);
+        z1a[q] = C{(R)(F * ckr), (R)(S * s_down)};
+        if (want_c) z2a[q] = C{(R)F, (R)0};
       }
     }
     wave_sync();
-    cplx *Z1 = z1a, *free1 = z1b, *Z2 = z2a, *free2 = z2b;
+    C *Z1 = z1a, *free1 = z1b, *Z2 = z2a, *free2 = z2b;
     if (tw)
       fft_stockham_small(Z1, free1, Z2, free2, want_c, NF, tw);
     else
       fft_stockham(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter);
 
     // truncation indices of the smooth factors
-    const cplx* Fsrc = paper ? Z1 : Z2;
-    const double F0 = wave_sum(sumF) * invNF;   // <F>_0 = max_j |<F>_j| since F > 0
+    const C* Fsrc = paper ? Z1 : Z2;
+    const double F0 = wave_sum(sumF) / NF;      // <F>_0 = max_j |<F>_j| since F > 0
     const int pF = want_c ? trunc_index_real(Fsrc, NF, invNF, P.eps0, 0.0) : 0;
     const int pH = paper ? 0 : trunc_index_real(Z1, NF, invNF, P.eps0, F0);
     if (max(pF, pH) >= NF / 2 - 2) {
@@ -518,21 +557,21 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     const int Jq = J + qu * tstride;          // table index of theta_j + qu * gstep
 
     // ---- weighted coefficient vectors G_j = <f>_j e^{i j a}, |j| <= p
-    cplx* GF = free2;
-    cplx* GH = free1;
-    cplx* Cn = free1 + (M0 - 1);
+    C* GF = free2;
+    C* GH = free1;
+    C* Cn = free1 + (M0 - 1);
     const int pmax = max(pF, pH);
     for (int jj = lane; jj <= pmax; jj += 64) {
       double s1, c1;
       sincos_bounded(jj * ur, &s1, &c1);
       const cplx ph = mk(tcos(tab, jj * Jq, mask, quarter), tsin(tab, jj * Jq, mask)) * mk(c1, s1);
       if (want_c && jj <= pF) {
-        const cplx G = real_part_coeff(Fsrc, jj, NF, invNF) * ph;
+        const C G = SP::narrow(SP::wide(real_part_coeff(Fsrc, jj, NF, invNF)) * ph);
         GF[pF + jj] = G;
         GF[pF - jj] = conj(G);
       }
       if (!paper && jj <= pH) {
-        const cplx G = real_part_coeff(Z1, jj, NF, invNF) * ph;
+        const C G = SP::narrow(SP::wide(real_part_coeff(Z1, jj, NF, invNF)) * ph);
         GH[pH + jj] = G;
         GH[pH - jj] = conj(G);
       }
@@ -540,15 +579,15 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     if (paper) {
       // <cos(k rho)>_n, |n| <= M0 - 1, from the imaginary part of Z1
       for (int n = lane; n < M0; n += 64) {
-        const cplx C = imag_part_coeff(Z1, n, NF, invNF);
-        Cn[n] = C;
-        Cn[-n] = conj(C);
+        const C Cv = imag_part_coeff(Z1, n, NF, invNF);
+        Cn[n] = Cv;
+        Cn[-n] = conj(Cv);
       }
     }
     wave_sync();
     // ---- A_m(b)
-    double* A = (paper ? reinterpret_cast<double*>(Z1)
-                       : (want_c ? reinterpret_cast<double*>(Z2) : Acompact)) + NF / 2;
+    R* A = (paper ? reinterpret_cast<R*>(Z1) : (want_c ? reinterpret_cast<R*>(Z2) : Acompact)) +
+           NF / 2;
     const int mtop = paper ? L + pF : (want_c ? max(L + pF, M + pH) : M + pH);
     singular_factor_wave(b, rr.A0, rr.D1, mtop, A);
     for (int m = 1 + lane; m <= max(pF, pH); m += 64) A[-m] = A[m];
@@ -556,44 +595,44 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
 
     // ---- <rho^-1>_l, l = 0..L (eq. (3.25)) into cb[L + l] (and cb[L - l] = conj)
     if (want_c) {
-      swap_convolution(GF, pF, A, L, ur, Jq, tab, mask, quarter, cb + L, cb + L, crow);
+      swap_convolution<C>(GF, pF, A, L, ur, Jq, tab, mask, quarter, cb + L, cb + L, crow);
       wave_sync();
     }
     // ---- kc_n = <cos(k rho)/rho>_n, n = 0..M
-    cplx* kc = want_c ? free2 : cb;
+    C* kc = want_c ? free2 : cb;
     if (paper) {
       // eq. (3.10): kc_n = sum_{|n'| < M0} C_{n'} c_{n-n'}
       for (int n = lane; n < M; n += 64) {
-        double accr = 0.0, acci = 0.0;
+        R accr = 0, acci = 0;
         for (int np = -(M0 - 1); np <= M0 - 1; ++np) {
-          const cplx C = Cn[np];
-          const cplx c = cb[L + n - np];
-          accr = fma(C.re, c.re, fma(-C.im, c.im, accr));
-          acci = fma(C.re, c.im, fma(C.im, c.re, acci));
+          const C Cv = Cn[np];
+          const C c = cb[L + n - np];
+          accr = fma(Cv.re, c.re, fma(-Cv.im, c.im, accr));
+          acci = fma(Cv.re, c.im, fma(Cv.im, c.re, acci));
         }
-        kc[n] = mk(accr, acci);
+        kc[n] = C{accr, acci};
       }
-      double accr = 0.0, acci = 0.0;
+      R accr = 0, acci = 0;
       for (int np = -(M0 - 1) + lane; np <= M0 - 1; np += 64) {
-        const cplx C = Cn[np];
-        const cplx c = cb[L + M - np];
-        accr = fma(C.re, c.re, fma(-C.im, c.im, accr));
-        acci = fma(C.re, c.im, fma(C.im, c.re, acci));
+        const C Cv = Cn[np];
+        const C c = cb[L + M - np];
+        accr = fma(Cv.re, c.re, fma(-Cv.im, c.im, accr));
+        acci = fma(Cv.re, c.im, fma(Cv.im, c.re, acci));
       }
       accr = wave_sum(accr);
       acci = wave_sum(acci);
-      if (lane == 0) kc[M] = mk(accr, acci);
+      if (lane == 0) kc[M] = C{accr, acci};
     } else {
       // swap applied to cos(k rho)/rho
-      swap_convolution(GH, pH, A, M, ur, Jq, tab, mask, quarter, kc, nullptr, nullptr);
+      swap_convolution<C>(GH, pH, A, M, ur, Jq, tab, mask, quarter, kc, nullptr, nullptr);
     }
     wave_sync();
     // ---- kappa_n = kc_n + i <sin(k rho)/rho>_n, n = -M+1..M at column n + M - 1
     for (int c = lane; c < 2 * M; c += 64) {
       const int n = c - M + 1;
-      const cplx kcn = n >= 0 ? kc[n] : conj(kc[-n]);
-      const cplx S = paper ? invNF * Z2[n & (NF - 1)] : s_up * imag_part_coeff(Z1, n, NF, invNF);
-      krow[c] = mk(kcn.re - S.im, kcn.im + S.re);
+      const C kcn = n >= 0 ? kc[n] : conj(kc[-n]);
+      const C Sn = paper ? invNF * Z2[n & (NF - 1)] : s_up * imag_part_coeff(Z1, n, NF, invNF);
+      krow[c] = C{kcn.re - Sn.im, kcn.im + Sn.re};
     }
     if (lane == 0) a.status[pi] = st | (min(paper ? pF : pH, 0xfff) << FFBIE_PAIR_P_SHIFT);
     wave_sync();
@@ -603,15 +642,17 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
 // Surfaces of azimuthal order <= 2 fit 168 VGPRs with a few spilled values, so
 // they ask for three wavefronts per SIMD (more latency hiding); higher orders
 // would spill heavily and keep two.
-template <int MM, bool REFINE>
+template <int MM, bool REFINE, class R>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbie_coeff_kernel_t(
     CoeffArgs a) {
+  using C = typename Spec<R>::C;
+  constexpr bool single = sizeof(R) == 4;
   extern __shared__ double smem[];
   double* tab = smem;
   load_table(tab, a.tab_g, a.P.tab_n);
-  const int twd = coeff_twiddle_doubles(a.NF);
-  cplx* tw = twd ? reinterpret_cast<cplx*>(smem + a.P.tab_n) : nullptr;
+  const int twd = coeff_twiddle_doubles(a.NF, single);
+  C* tw = twd ? reinterpret_cast<C*>(smem + a.P.tab_n) : nullptr;
   if (tw) {
     build_twiddles(tw, a.NF, a.P.M, tab, a.P.tab_n - 1, 2 * a.P.M);
     __syncthreads();
@@ -619,15 +660,15 @@ __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbi
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int waves_per_block = blockDim.x >> 6;
   const bool want_c = a.variant == FFBIE_KAPPA_PAPER_CONV || a.rhoinv != nullptr;
-  const int per_wave = coeff_lds_per_wave(a.NF, a.P.M, a.P.L, !want_c);
+  const int per_wave = coeff_lds_per_wave(a.NF, a.P.M, a.P.L, !want_c, single);
   int64_t count = a.n;
   if (a.list) count = *a.list_count;
   const int64_t total_waves = (int64_t)gridDim.x * waves_per_block;
   const int64_t gw = (int64_t)blockIdx.x * waves_per_block + wave;
   const int64_t chunk = (count + total_waves - 1) / total_waves;
   const int64_t beg = gw * chunk, end = min(count, beg + chunk);
-  coeff_range<MM, REFINE>(a, tab, tw, smem + a.P.tab_n + twd + (size_t)wave * per_wave, a.NF, beg,
-                          end);
+  coeff_range<MM, REFINE, R>(a, tab, tw, smem + a.P.tab_n + twd + (size_t)wave * per_wave, a.NF,
+                             beg, end);
 }
 
 // ===========================================================================
@@ -663,7 +704,7 @@ __global__ __launch_bounds__(256) void ffbie_coeff_batch_kernel_t(BatchArgs b) {
     const int s = batch_find(b.item_prefix, b.n_probs, item);
     const CoeffArgs& a = b.probs[s];
     const int NF = 2 * a.P.M;
-    cplx* tw = coeff_twiddle_doubles(NF) ? reinterpret_cast<cplx*>(smem + b.tab_max) : nullptr;
+    cplx* tw = coeff_twiddle_doubles(NF, false) ? reinterpret_cast<cplx*>(smem + b.tab_max) : nullptr;
     if (s != cur) {
       load_table(smem, a.tab_g, a.P.tab_n);    // ends with a barrier
       if (tw) {
@@ -672,10 +713,10 @@ __global__ __launch_bounds__(256) void ffbie_coeff_batch_kernel_t(BatchArgs b) {
       }
       cur = s;
     }
-    const int per_wave = coeff_lds_per_wave(NF, a.P.M, a.P.L, true);
+    const int per_wave = coeff_lds_per_wave(NF, a.P.M, a.P.L, true, false);
     const int64_t t0 = (item - b.item_prefix[s]) * tile + (int64_t)wave * kBatchTile;
     const int64_t beg = min(a.n, t0), end = min(a.n, t0 + kBatchTile);
-    coeff_range<MM, false>(a, smem, tw, smem + b.tab_max + b.tw_max + (size_t)wave * per_wave, NF,
+    coeff_range<MM, false, double>(a, smem, tw, smem + b.tab_max + b.tw_max + (size_t)wave * per_wave, NF,
                            beg, end);
     __syncthreads();                           // all waves done before item_s / the table change
   }
@@ -696,7 +737,7 @@ __global__ __launch_bounds__(64) void ffbie_coeff_batch_refine_t(BatchArgs b) {
       load_table(smem, a.tab_g, a.P.tab_n);
       cur = s;
     }
-    coeff_range<MM, true>(a, smem, nullptr, smem + b.tab_max, 4 * a.P.M, pi, pi + 1);
+    coeff_range<MM, true, double>(a, smem, nullptr, smem + b.tab_max, 4 * a.P.M, pi, pi + 1);
     __syncthreads();
   }
 }
@@ -774,19 +815,22 @@ hipError_t launch_root(const Prob& P, const double* tab, int64_t n, const double
 }
 
 hipError_t launch_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t lds,
-                        hipStream_t stream, bool refine) {
+                        hipStream_t stream, bool refine, bool single) {
   switch (mm_bucket(a.P.g.mmax)) {
+#define K(MMV, RF, RT)                                                                           \
+  hipLaunchKernelGGL((ffbie_coeff_kernel_t<MMV, RF, RT>), dim3((unsigned)blocks),               \
+                     dim3(64 * waves), lds, stream, a)
 #define X(MMV)                                                                                   \
   case MMV:                                                                                      \
-    if (refine)                                                                                  \
-      hipLaunchKernelGGL((ffbie_coeff_kernel_t<MMV, true>), dim3((unsigned)blocks),             \
-                         dim3(64 * waves), lds, stream, a);                                      \
-    else                                                                                         \
-      hipLaunchKernelGGL((ffbie_coeff_kernel_t<MMV, false>), dim3((unsigned)blocks),            \
-                         dim3(64 * waves), lds, stream, a);                                      \
+    if (single) {                                                                                \
+      if (refine) K(MMV, true, float); else K(MMV, false, float);                                \
+    } else {                                                                                     \
+      if (refine) K(MMV, true, double); else K(MMV, false, double);                              \
+    }                                                                                            \
     break;
     FFBIE_FOR_MM(X)
 #undef X
+#undef K
   }
   return hipGetLastError();
 }

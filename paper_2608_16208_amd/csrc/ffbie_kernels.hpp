@@ -19,8 +19,8 @@ struct CoeffArgs {
   const double* ts_in;
   const RootRec* roots;
   int32_t* status;
-  cplx* kappa;               // [n][2M]
-  cplx* rhoinv;              // [n][L+1] or null
+  void* kappa;               // [n][2M] complex128, or complex64 on the mixed-precision path
+  void* rhoinv;              // [n][L+1] (same type) or null
   int NF;                    // azimuthal samples: 2M (main pass) or 4M (refine pass)
   const int64_t* list;       // refine pass: pair indices
   const int32_t* list_count; // refine pass: number of indices
@@ -48,26 +48,30 @@ struct BatchArgs {
   int tw_max;                // doubles reserved after it for FFT twiddles (0 if none)
 };
 
-// Per-wavefront LDS of the coefficient kernel, in doubles.
+// Per-wavefront LDS of the coefficient kernel, in doubles, with the spectral
+// stage in FP64 or (single) in FP32; the layout in units of its real type:
 //   compact (default variant without <rho^-1> output):
 //     two NF-complex FFT buffers, A_m (m <= M + NF/2), kc (M + 1 complex)
 //   full: four NF-complex buffers and the <rho^-1> buffer (2L + 1 complex)
-//     A_m is stored mirrored, A[-m] = A[m] for m <= NF/2, so it needs M + NF + 2 doubles
+//     A_m is stored mirrored, A[-m] = A[m] for m <= NF/2, so it needs M + NF + 2 reals
 //     (compact) or fits an NF-complex buffer (full, since L <= NF).
 // LDS doubles of the per-workgroup FFT twiddle table (transforms of NF <= 128
 // points: 7 stages x 64 lanes complex), 0 otherwise.
-FFBIE_HD inline int coeff_twiddle_doubles(int NF) { return NF <= 128 ? 7 * 64 * 2 : 0; }
+FFBIE_HD inline int coeff_twiddle_doubles(int NF, bool single) {
+  return NF <= 128 ? (single ? 7 * 64 : 7 * 64 * 2) : 0;
+}
 
-FFBIE_HD inline int coeff_lds_per_wave(int NF, int M, int L, bool compact) {
-  if (compact) return 2 * (2 * NF) + 2 * ((M + NF + 2) / 2) + 2 * (M + 1);
-  return 2 * (4 * NF + 2 * L + 1);
+FFBIE_HD inline int coeff_lds_per_wave(int NF, int M, int L, bool compact, bool single) {
+  const int reals = compact ? 2 * (2 * NF) + 2 * ((M + NF + 2) / 2) + 2 * (M + 1)
+                            : 2 * (4 * NF + 2 * L + 1);
+  return single ? (reals + 1) / 2 : reals;
 }
 
 hipError_t launch_root(const Prob& P, const double* tab, int64_t n, const double* t,
                        const int32_t* az, const double* ts, RootRec* out, int32_t* status,
                        double* root_out, hipStream_t stream);
 hipError_t launch_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t lds,
-                        hipStream_t stream, bool refine);
+                        hipStream_t stream, bool refine, bool single);
 hipError_t launch_batch(const BatchArgs& b, int mm, int64_t root_blocks, size_t root_lds,
                         int64_t blocks, int waves, size_t lds, size_t refine_lds,
                         hipStream_t stream, int phase);
