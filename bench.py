@@ -26,6 +26,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "kernel coeff pair-modes/s + time-to-1e-8 field error, mixed vs plain FP64 GPU"
 PEAK_FP64_VALU = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+# FP32 VALU issue rate without packed (two-per-lane) instructions, which this
+# build does not generate: the same 256 x 4 x 16 x 2 x 2.4 GHz
+PEAK_FP32_VALU_UNPACKED = 78.6e12
 COEFF_KERNEL = "ffbie_coeff_kernel"
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "coeff_kernel_config2_allpairs_hbm_traffic.md")
 
@@ -56,16 +59,17 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(variant):
-    """HBM bytes per launch of the main coefficient pass from the committed
-    rocprofv3 counter summary, if it was taken from the current kernel source."""
+def measured_traffic(key):
+    """HBM bytes per launch of the main coefficient pass (key "variant0",
+    "variant1" or "mixed") from the committed rocprofv3 counter summary, if it
+    was taken from the current kernel source."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
     txt = open(TRAFFIC_SUMMARY).read()
     m = re.search(r"source_digest:\s*(\w+)", txt)
     if not m or m.group(1) != kernel_source_digest():
         return None
-    m = re.search(rf"variant{variant}_hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    m = re.search(rf"{key}_hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     return float(m.group(1)) if m else None
 
 
@@ -215,6 +219,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=6144)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-second-variant", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision coefficient run")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched many-surface measurement")
     ap.add_argument("--no-solve", action="store_true",
@@ -249,14 +254,16 @@ def main():
     jj = torch.tensor(j, device=dev)
     tss = torch.tensor(ts, device=dev)
     kappa = torch.empty((n, 2 * M), dtype=torch.complex128, device=dev)
+    kappa_mixed = None
     status = torch.empty((n,), dtype=torch.int32, device=dev)
     ctx = ffbie.Context(0)
 
-    def run_variant(variant, steps, warmup):
+    def run_variant(variant, steps, warmup, mixed=False):
         ctx.set_problem(cfg["amp"], cfg["n_panels"], M, cfg["k"], M0=M0, variant=variant)
         ctx.enable_timing(True)
+        kap = kappa_mixed if mixed else kappa
         for _ in range(warmup):
-            ctx.kernel_coeffs(tt, jj, tss, kappa=kappa, status=True)
+            ctx.kernel_coeffs(tt, jj, tss, kappa=kap, status=True, mixed=mixed)
         torch.cuda.synchronize()
         per = []
         e0 = torch.cuda.Event(enable_timing=True)
@@ -265,7 +272,7 @@ def main():
         wall0 = time.perf_counter()
         e0.record()
         for _ in range(steps):
-            out = ctx.kernel_coeffs(tt, jj, tss, kappa=kappa, status=True)
+            out = ctx.kernel_coeffs(tt, jj, tss, kappa=kap, status=True, mixed=mixed)
             per.append(ctx.timing())
         e1.record()
         torch.cuda.synchronize()
@@ -285,7 +292,7 @@ def main():
     w_pair = algorithmic_flops_per_pair(NF, M, M0, p_mean, m0)
     main_ms = float(per[:, 1].mean())
     achieved = w_pair * n / (main_ms * 1e-3)
-    traffic = measured_traffic(args.variant)
+    traffic = measured_traffic("variant%d" % args.variant)
 
     result = {
         "metric": METRIC,
@@ -335,6 +342,32 @@ def main():
             "kappa_variant": "eq. (3.10)" if other == 1 else "swap of cos(k rho)/rho",
             "value": n * 2 * M * max(1, args.steps // 2) / (ms2 * 1e-3),
             "coeff_main_ms": float(per2[:, 1].mean())}
+    if not args.no_mixed:
+        # the same launch with the FP32 spectral stage (complex64 table)
+        kappa_mixed = torch.empty((n, 2 * M), dtype=torch.complex64, device=dev)
+        msx, _, perx, stx = run_variant(0, args.steps, args.warmup, mixed=True)
+        okx = (stx & (ffbie.PAIR_SINGULAR | ffbie.PAIR_UNRESOLVED)) == 0
+        p_mean_x = float(((stx >> ffbie.P_SHIFT) & 0xFFF)[okx].mean())
+        main_x = float(perx[:, 1].mean())
+        ach_x = algorithmic_flops_per_pair(NF, M, M0, p_mean_x, m0) * n / (main_x * 1e-3)
+        worst = 0.0
+        for a in range(0, n, 1 << 20):
+            k64 = kappa[a:a + (1 << 20)]
+            e = (torch.linalg.vector_norm(kappa_mixed[a:a + (1 << 20)].to(torch.complex128) - k64, dim=1)
+                 / torch.linalg.vector_norm(k64, dim=1))
+            worst = max(worst, float(e.max().item()))
+        result["mixed"] = {
+            "value": n * 2 * M * args.steps / (msx * 1e-3), "unit": "pair-modes/s",
+            "ms_per_step": msx / args.steps, "dtype": "f32 spectral stage, f64 samples/root/A_m",
+            "kernels_ms": {"root": float(perx[:, 0].mean()), "coeff_main": main_x,
+                           "coeff_refine": float(perx[:, 2].mean())},
+            "p_mean": p_mean_x, "refined": int(((stx & ffbie.PAIR_REFINED) > 0).sum()),
+            "max_row_rel_err_vs_fp64": worst, "stated_bound": 1e-5,
+            "roofline": {"bound": "alu", "achieved": ach_x / 1e12, "peak": PEAK_FP32_VALU_UNPACKED / 1e12,
+                         "unit": "TFLOP/s", "frac": ach_x / PEAK_FP32_VALU_UNPACKED,
+                         "traffic": measured_traffic("mixed"),
+                         "kernel": COEFF_KERNEL + " (main pass, FP32 spectral stage)"}}
+        del kappa_mixed
     del kappa
     torch.cuda.empty_cache()
     if not args.no_solve:
