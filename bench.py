@@ -166,48 +166,83 @@ def near_set_rate(ctx, cfg, torch):
 
 
 def batch_rate(ctx, torch, n_surfaces=64, arena_bytes=32 << 30):
-    """Batched coefficient path: the near sets of a batch of star surfaces with
-    their own M, k and panel counts, in persistent launches.  The outputs
-    (complex128, ~370 GB for 64 surfaces) go through one reusable arena of
-    `arena_bytes`, a chunk of whole surfaces per batched call."""
+    """Batched coefficient path on the near sets of 64 star surfaces with their
+    own M, k and panel counts, against a per-surface launch loop.  The outputs
+    (~374 GB complex128, ~187 GB complex64) go through one reusable arena of
+    `arena_bytes`, a chunk of whole surfaces per batch plan.  The plans (one per
+    chunk) are built before the clock starts: the first chunk's plan autotunes
+    the launch (FFT radix, pairs per work item, waves per workgroup) and the
+    others take its tuning; each plan's launches are captured in a HIP graph.
+    Timed: executing every chunk's plan (FP64, then the mixed-precision path),
+    and the loop of single-problem calls (set_problem + kernel_coeffs per
+    surface) over the same surfaces."""
     import workloads
     surfs = []
     for s in range(n_surfaces):
         c = workloads.batch_surface(s)
         ctx.set_problem(c["amp"], c["n_panels"], c["M"], c["k"])
         t, az, ts = ctx.near_pairs()
-        surfs.append(dict(amp=c["amp"], M=c["M"], k=c["k"], t=t, az=az, ts=ts))
-    chunks, cur, used = [], [], 0
-    for sf in surfs:
-        b = sf["t"].numel() * 2 * sf["M"] * 16
-        if cur and used + b > arena_bytes:
-            chunks.append(cur)
-            cur, used = [], 0
-        cur.append(sf)
-        used += b
-    chunks.append(cur)
+        surfs.append(dict(amp=c["amp"], M=c["M"], k=c["k"], n_panels=c["n_panels"], t=t, az=az, ts=ts))
+    modes = sum(sf["t"].numel() * 2 * sf["M"] for sf in surfs)
     arena = torch.empty(arena_bytes // 16, dtype=torch.complex128, device=ctx.device)
-    max_pairs = max(sum(sf["t"].numel() for sf in ch) for ch in chunks)
-    status = torch.empty(max_pairs, dtype=torch.int32, device=ctx.device)
+    out = {"surfaces": n_surfaces, "pair_modes": int(modes), "pairs": int(sum(sf["t"].numel() for sf in surfs)),
+           "arena_GB": arena_bytes / 2 ** 30, "unit": "pair-modes/s"}
 
-    def run(ch):
-        items, off, soff = [], 0, 0
+    def chunked(elem_bytes):
+        chunks, cur, used = [], [], 0
+        for sf in surfs:
+            b = sf["t"].numel() * 2 * sf["M"] * elem_bytes
+            if cur and used + b > arena_bytes:
+                chunks.append(cur)
+                cur, used = [], 0
+            cur.append(sf)
+            used += b
+        chunks.append(cur)
+        return chunks
+
+    def views(ch, dtype):
+        flat = arena.view(dtype)
+        items, off = [], 0
         for sf in ch:
             n = sf["t"].numel()
-            kap = arena[off:off + n * 2 * sf["M"]].view(n, 2 * sf["M"])
-            items.append(dict(sf, kappa=kap, status=status[soff:soff + n]))
+            items.append(dict(sf, kappa=flat[off:off + n * 2 * sf["M"]].view(n, 2 * sf["M"])))
             off += n * 2 * sf["M"]
-            soff += n
-        ctx.kernel_coeffs_batched(items)
+        return items
 
-    run(chunks[0])                                   # warm-up
-    _, dt = _timed(torch, lambda: [run(ch) for ch in chunks])
-    modes = sum(sf["t"].numel() * 2 * sf["M"] for sf in surfs)
-    del arena, status
+    # per-surface launch loop (FP64)
+    def loop():
+        for ch in chunked(16):
+            for it in views(ch, torch.complex128):
+                ctx.set_problem(it["amp"], it["n_panels"], it["M"], it["k"])
+                ctx.kernel_coeffs(it["t"], it["az"], it["ts"], kappa=it["kappa"], status=False)
+    loop()
+    _, dt = _timed(torch, loop)
+    out["per_surface_loop"] = {"s": dt, "value": modes / dt}
+
+    for name, mixed, dtype, eb in (("batched", False, torch.complex128, 16),
+                                   ("batched_mixed", True, torch.complex64, 8)):
+        chunks = chunked(eb)
+        t0 = time.perf_counter()
+        first = ctx.batch_plan(views(chunks[0], dtype), autotune=True, graph=True, mixed=mixed)
+        tuning = first.tuning()
+        by_m = {t["M"]: t for t in tuning}
+        plans = [first] + [ctx.batch_plan(views(ch, dtype), graph=True, mixed=mixed, tuning=by_m)
+                           for ch in chunks[1:]]
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        for pl in plans:
+            pl.execute()
+        _, dt = _timed(torch, lambda: [pl.execute() for pl in plans])
+        out[name] = {"s": dt, "value": modes / dt, "chunks": len(chunks), "tuning_by_M": tuning,
+                     "plan_setup_s": setup}
+        for pl in plans:
+            pl.close()
+    del arena
     torch.cuda.empty_cache()
-    return {"surfaces": n_surfaces, "pair_modes": int(modes), "pairs": int(sum(sf["t"].numel() for sf in surfs)),
-            "chunks": len(chunks), "arena_GB": arena_bytes / 2 ** 30, "s": dt,
-            "value": modes / dt, "unit": "pair-modes/s"}
+    out["value"] = out["batched"]["value"]
+    out["s"] = out["batched"]["s"]
+    out["chunks"] = out["batched"]["chunks"]
+    return out
 
 
 def main():

@@ -188,10 +188,11 @@ ffbie_status ffbie_singular_factor(ffbie_ctx *ctx, int64_t n, const double *d_b,
  *   d_pair_status  [n_pairs] int32 output (optional NULL).
  * items is a HOST array of n_items entries.  Results are those of one
  * ffbie_kernel_coeffs call per item.  The problem of ffbie_set_problem is
- * left unchanged.  Work items of 64 pairs are taken from a device-side queue
+ * left unchanged.  Work items (waves_per_block x pairs_per_item pairs of one
+ * problem, from the context's tuning) are taken from a device-side queue
  * ordered by decreasing M, so problems of different cost share the GPU.
- * The call waits for the small descriptor upload to finish (stream sync) before
- * enqueuing the kernels. */
+ * The call waits for the previous batched call's kernels and for the small
+ * descriptor upload (stream syncs) before enqueuing the kernels. */
 typedef struct {
   ffbie_geometry g;
   ffbie_discretization d;
@@ -204,6 +205,69 @@ typedef struct {
   int32_t *d_pair_status;
 } ffbie_batch_item;
 ffbie_status ffbie_kernel_coeffs_batched(ffbie_ctx *ctx, int n_items, const ffbie_batch_item *items);
+
+/* Launch choices of the coefficient kernels:
+ *   fft_radix        2: radix-2 Stockham transforms; 4: radix-4 stages (with
+ *                    one radix-2 stage when log2(N_F) is odd),
+ *   pairs_per_item   pairs a wavefront takes from one batch work item (1..256),
+ *   waves_per_block  wavefronts per workgroup of the batched launch (1, 2, 4;
+ *                    lowered to what fits 64 KiB of LDS).
+ * A context starts with {2, 16, 4}; its fft_radix also applies to
+ * ffbie_kernel_coeffs(_mixed) and the near blocks of ffbie_assemble.  Results
+ * do not depend on the tuning beyond rounding (the transforms differ in
+ * operation order). */
+typedef struct {
+  int fft_radix;
+  int pairs_per_item;
+  int waves_per_block;
+} ffbie_tuning;
+ffbie_status ffbie_set_tuning(ffbie_ctx *ctx, const ffbie_tuning *tuning);
+ffbie_status ffbie_get_tuning(const ffbie_ctx *ctx, ffbie_tuning *tuning);
+
+/* Batch plans: the batched coefficient path of ffbie_kernel_coeffs_batched,
+ * prepared once and executed any number of times (for instance with new pair
+ * data in the same buffers).  The problems are grouped by M; each group (an
+ * "M class") runs its main pass and its refine pass as one persistent launch
+ * over (problem, run of pairs) work items, after one root launch for all.  ffbie_batch_plan_create validates the items
+ * (HOST array; the device buffers they name must stay valid for the plan's
+ * life), orders them, uploads the descriptors and allocates the plan's own
+ * workspace (root records, refine queue, counters: about 44 B per pair).
+ * flags (or-ed):
+ *   FFBIE_PLAN_AUTOTUNE  for each M class of the batch, time its main pass for
+ *                        every candidate tuning (radix {2, 4} x pairs_per_item
+ *                        {8, 16, 32} x waves_per_block {1, 2, 4}) and keep the
+ *                        fastest; the creating call then runs the main pass
+ *                        ~36 times,
+ *   FFBIE_PLAN_GRAPH     capture the launch sequence (counter reset, root,
+ *                        main and refine passes) in a HIP graph that execute
+ *                        replays on the context's stream,
+ *   FFBIE_PLAN_MIXED     FP32 spectral stage as in ffbie_kernel_coeffs_mixed:
+ *                        every item's d_kappa is complex64.
+ * tuning: NULL takes the context's tuning for every class; otherwise an
+ * array of 4 tunings for the classes M = 16, 32, 64, 128 (the tuning used, or
+ * the start point of the autotuner).
+ * execute enqueues on the context's stream and returns; outputs are those of
+ * ffbie_kernel_coeffs_batched.  Executions of one plan must not overlap (they
+ * share its workspace): the stream order guarantees this.  destroy waits for
+ * the context's stream, then frees the plan.  ffbie_batch_plan_classes gives
+ * the number of M classes (0 for an empty batch); get_tuning reports class
+ * m_class's M, the tuning in use and, after autotuning, its main-pass time in
+ * ms (FFBIE_EINVAL for a class out of range).
+ * With timing enabled (ffbie_enable_timing), executing a plan that has no
+ * graph records the root, main and refine passes for ffbie_get_timing.
+ * Destroy every plan before its context. */
+typedef struct ffbie_batch_plan ffbie_batch_plan;
+#define FFBIE_PLAN_GRAPH 1
+#define FFBIE_PLAN_AUTOTUNE 2
+#define FFBIE_PLAN_MIXED 4
+ffbie_status ffbie_batch_plan_create(ffbie_ctx *ctx, int n_items, const ffbie_batch_item *items,
+                                     int flags, const ffbie_tuning *tuning,
+                                     ffbie_batch_plan **out);
+ffbie_status ffbie_batch_plan_execute(ffbie_ctx *ctx, ffbie_batch_plan *plan);
+int ffbie_batch_plan_classes(const ffbie_batch_plan *plan);
+ffbie_status ffbie_batch_plan_get_tuning(const ffbie_batch_plan *plan, int m_class,
+                                         ffbie_tuning *tuning, double *tuned_ms, int *M);
+ffbie_status ffbie_batch_plan_destroy(ffbie_batch_plan *plan);
 
 /* ------------------------------------------------------------------------
  * The discrete single-layer system (Sec. 3.1 and 3.4)

@@ -6,6 +6,7 @@ the stream.  There is no fallback: if the library is missing or no GPU is
 present, the calls raise.
 """
 import ctypes
+import weakref
 import os
 
 import numpy as np
@@ -25,7 +26,9 @@ EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_probl
            "ffbie_mlp_param_count", "ffbie_mlp_init", "ffbie_mlp_set_params", "ffbie_mlp_get_params",
            "ffbie_mlp_forward", "ffbie_mlp_train_step", "ffbie_mode_features", "ffbie_mode_targets",
            "ffbie_mlp_precondition", "ffbie_blockjacobi_setup", "ffbie_blockjacobi_apply",
-           "ffbie_kernel_coeffs_mixed")
+           "ffbie_kernel_coeffs_mixed", "ffbie_set_tuning", "ffbie_get_tuning",
+           "ffbie_batch_plan_create", "ffbie_batch_plan_execute", "ffbie_batch_plan_get_tuning",
+           "ffbie_batch_plan_destroy", "ffbie_batch_plan_classes")
 SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES, SOLVE_FGMRES_MLP, SOLVE_GMRES_BLOCKJACOBI = 0, 1, 2, 3, 4
 MLP_IN, MLP_HIDDEN, MLP_OUT = 514, 256, 512
 WNOTCONV = 2
@@ -50,6 +53,11 @@ class _BatchItem(ctypes.Structure):
     _fields_ = [("g", _Geometry), ("d", _Disc), ("k", ctypes.c_double), ("n_pairs", ctypes.c_int64),
                 ("d_t", ctypes.c_void_p), ("d_az", ctypes.c_void_p), ("d_ts", ctypes.c_void_p),
                 ("d_kappa", ctypes.c_void_p), ("d_pair_status", ctypes.c_void_p)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("fft_radix", ctypes.c_int), ("pairs_per_item", ctypes.c_int),
+                ("waves_per_block", ctypes.c_int)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -95,6 +103,15 @@ def load_library(path=LIB_PATH):
     lib.ffbie_solve.argtypes = [vp, i32, vp, i64, vp, vp, ctypes.c_double, i32, ctypes.POINTER(_SolveInfo)]
     lib.ffbie_residual.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.ffbie_kernel_coeffs_batched.argtypes = [vp, i32, ctypes.POINTER(_BatchItem)]
+    lib.ffbie_set_tuning.argtypes = [vp, ctypes.POINTER(_Tuning)]
+    lib.ffbie_get_tuning.argtypes = [vp, ctypes.POINTER(_Tuning)]
+    lib.ffbie_batch_plan_create.argtypes = [vp, i32, ctypes.POINTER(_BatchItem), i32,
+                                            ctypes.POINTER(_Tuning), ctypes.POINTER(vp)]
+    lib.ffbie_batch_plan_execute.argtypes = [vp, vp]
+    lib.ffbie_batch_plan_get_tuning.argtypes = [vp, i32, ctypes.POINTER(_Tuning), dp,
+                                                ctypes.POINTER(ctypes.c_int)]
+    lib.ffbie_batch_plan_classes.argtypes = [vp]
+    lib.ffbie_batch_plan_destroy.argtypes = [vp]
     lib.ffbie_lu_factor.argtypes = [vp, vp, i64]
     lib.ffbie_lu_solve.argtypes = [vp, vp, i64, vp]
     lib.ffbie_mlp_param_count.argtypes = []
@@ -112,7 +129,7 @@ def load_library(path=LIB_PATH):
     lib.ffbie_blockjacobi_apply.argtypes = [vp, vp, vp]
     for name in EXPORTS:
         f = getattr(lib, name)
-        if name not in ("ffbie_last_error", "ffbie_mlp_param_count"):
+        if name not in ("ffbie_last_error", "ffbie_mlp_param_count", "ffbie_batch_plan_classes"):
             f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -159,6 +176,8 @@ class Context:
         return rc
 
     def close(self):
+        for plan in list(getattr(self, "_plans", ())):
+            plan.close()
         if getattr(self, "h", None):
             self.lib.ffbie_destroy(self.h)
             self.h = None
@@ -206,13 +225,10 @@ class Context:
         self._check(rc, self.h)
         return out
 
-    def kernel_coeffs_batched(self, problems):
-        """Coefficient path for several problems in one launch per phase.
-        problems: list of dicts with amp, M, k, t, az, ts (and optional M0, eps0,
-        kappa [n, 2M] and status [n] output tensors).  Returns a list of dicts
-        with kappa and status."""
+    def _batch_items(self, problems, mixed=False):
         torch = self._torch
         dev = self.device
+        cdt = torch.complex64 if mixed else torch.complex128
         keep, outs = [], []
         arr = (_BatchItem * max(1, len(problems)))()
         for i, pr in enumerate(problems):
@@ -226,11 +242,13 @@ class Context:
                 raise FfbieError("t, az and ts must have the same length")
             kap = pr.get("kappa")
             if kap is None:
-                kap = torch.empty((n, 2 * M), dtype=torch.complex128, device=dev)
+                kap = torch.empty((n, 2 * M), dtype=cdt, device=dev)
+            elif kap.dtype != cdt or tuple(kap.shape) != (n, 2 * M) or not kap.is_contiguous():
+                raise FfbieError("kappa of item %d must be a contiguous [n, 2M] %s tensor" % (i, cdt))
             st = pr.get("status")
             if st is None:
                 st = torch.empty((n,), dtype=torch.int32, device=dev)
-            keep += [a, t, ts, az]
+            keep += [a, t, ts, az, kap, st]
             it = arr[i]
             it.g = _Geometry(a.shape[0], a.shape[1] - 1, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
             it.d = _Disc(1, M, int(pr.get("M0", M)), float(pr.get("eps0", 0.0)), KAPPA_SWAP)
@@ -239,10 +257,33 @@ class Context:
             it.d_t, it.d_az, it.d_ts = t.data_ptr(), az.data_ptr(), ts.data_ptr()
             it.d_kappa, it.d_pair_status = kap.data_ptr(), st.data_ptr()
             outs.append({"kappa": kap, "status": st})
+        return arr, keep, outs
+
+    def kernel_coeffs_batched(self, problems):
+        """Coefficient path for several problems in one launch per phase.
+        problems: list of dicts with amp, M, k, t, az, ts (and optional M0, eps0,
+        kappa [n, 2M] and status [n] output tensors).  Returns a list of dicts
+        with kappa and status."""
+        arr, keep, outs = self._batch_items(problems)
         rc = self.lib.ffbie_kernel_coeffs_batched(self.h, len(problems), arr)
         self._check(rc, self.h)
         self._batch_keep = keep        # inputs stay alive until the stream has used them
         return outs
+
+    def batch_plan(self, problems, graph=False, autotune=False, mixed=False, tuning=None):
+        """A reusable batch plan (see BatchPlan) over `problems` (as for
+        kernel_coeffs_batched; with mixed=True the kappa outputs are complex64)."""
+        return BatchPlan(self, problems, graph, autotune, mixed, tuning)
+
+    def set_tuning(self, fft_radix=2, pairs_per_item=16, waves_per_block=4):
+        t = _Tuning(fft_radix, pairs_per_item, waves_per_block)
+        self._check(self.lib.ffbie_set_tuning(self.h, ctypes.byref(t)), self.h)
+
+    def get_tuning(self):
+        t = _Tuning()
+        self._check(self.lib.ffbie_get_tuning(self.h, ctypes.byref(t)), self.h)
+        return {"fft_radix": t.fft_radix, "pairs_per_item": t.pairs_per_item,
+                "waves_per_block": t.waves_per_block}
 
     def enable_timing(self, on=True):
         self._check(self.lib.ffbie_enable_timing(self.h, int(bool(on))), self.h)
@@ -417,3 +458,60 @@ class Context:
         A = torch.empty((b.numel(), m_max + 1), dtype=torch.float64, device=self.device)
         self._check(self.lib.ffbie_singular_factor(self.h, b.numel(), _ptr(b), int(m_max), _ptr(A)), self.h)
         return A
+
+
+class BatchPlan:
+    """A batch of coefficient problems prepared once (descriptors, workspace,
+    optionally an autotuned launch shape and a captured HIP graph) and executed
+    any number of times; outputs are in .outs (list of {kappa, status})."""
+
+    PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_MIXED = 1, 2, 4
+
+    def __init__(self, ctx, problems, graph=False, autotune=False, mixed=False, tuning=None):
+        self.ctx = ctx
+        self.arr, self._keep, self.outs = ctx._batch_items(problems, mixed)
+        flags = (self.PLAN_GRAPH if graph else 0) | (self.PLAN_AUTOTUNE if autotune else 0) | \
+                (self.PLAN_MIXED if mixed else 0)
+        t = None
+        if tuning is not None:
+            # one dict for every M class, or {M: dict} (classes not named keep
+            # the context's tuning)
+            base = ctx.get_tuning()
+            t = (_Tuning * 4)()
+            for q, M in enumerate((16, 32, 64, 128)):
+                d = tuning.get(M, base) if all(isinstance(k, int) for k in tuning) else tuning
+                t[q] = _Tuning(d["fft_radix"], d["pairs_per_item"], d["waves_per_block"])
+        h = ctypes.c_void_p()
+        rc = ctx.lib.ffbie_batch_plan_create(ctx.h, len(problems), self.arr, flags, t, ctypes.byref(h))
+        ctx._check(rc, ctx.h)
+        self.h = h
+        if not hasattr(ctx, "_plans"):
+            ctx._plans = weakref.WeakSet()
+        ctx._plans.add(self)
+
+    def execute(self):
+        self.ctx._check(self.ctx.lib.ffbie_batch_plan_execute(self.ctx.h, self.h), self.ctx.h)
+        return self.outs
+
+    def tuning(self):
+        """Per M class: {M, fft_radix, pairs_per_item, waves_per_block, tuned_ms}."""
+        out = []
+        for k in range(self.ctx.lib.ffbie_batch_plan_classes(self.h)):
+            t, ms, M = _Tuning(), ctypes.c_double(), ctypes.c_int()
+            rc = self.ctx.lib.ffbie_batch_plan_get_tuning(self.h, k, ctypes.byref(t), ctypes.byref(ms),
+                                                          ctypes.byref(M))
+            self.ctx._check(rc, self.ctx.h)
+            out.append({"M": M.value, "fft_radix": t.fft_radix, "pairs_per_item": t.pairs_per_item,
+                        "waves_per_block": t.waves_per_block, "tuned_ms": ms.value})
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            self.ctx.lib.ffbie_batch_plan_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

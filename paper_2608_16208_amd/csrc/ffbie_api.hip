@@ -73,8 +73,8 @@ struct ffbie_ctx {
   int64_t krylov_n = 0;
   // batched coefficients
   double* d_tabs[4] = {nullptr, nullptr, nullptr, nullptr};   // angle tables for M = 16 .. 128
-  void* d_batch = nullptr;           // descriptors and prefix arrays
-  size_t batch_bytes = 0;
+  ffbie_tuning tune{2, kBatchTile, 4};   // FFT radix, pairs per batch work item, waves per workgroup
+  ffbie_batch_plan* oneshot = nullptr;    // plan of the last ffbie_kernel_coeffs_batched call
   // learned preconditioner
   Mlp mlp;
   BlockJacobi bj;
@@ -86,6 +86,8 @@ struct ffbie_ctx {
 namespace {
 
 const char* kNoCtx = "ffbie: NULL context";
+
+void plan_free(ffbie_batch_plan* pl);
 
 // Smooth-factor truncation threshold of the mixed-precision path: the FP32
 // transforms leave a rounding floor of a few 1e-7 of the largest coefficient,
@@ -301,6 +303,10 @@ ffbie_status ffbie_create(ffbie_ctx** out, int device, void* hip_stream) {
 ffbie_status ffbie_destroy(ffbie_ctx* c) {
   if (!c) return FFBIE_OK;
   hipSetDevice(c->device);
+  if (c->oneshot) {
+    (void)hipStreamSynchronize(c->stream);
+    plan_free(c->oneshot);
+  }
   for (auto& e : c->ev)
     if (e) hipEventDestroy(e);
   if (c->d_tab) hipFree(c->d_tab);
@@ -312,7 +318,7 @@ ffbie_status ffbie_destroy(ffbie_ctx* c) {
                   (void*)c->d_near_az, (void*)c->d_near_ts, (void*)c->d_near_kappa,
                   (void*)c->d_partial, (void*)c->d_ipiv, (void*)c->d_perm, (void*)c->d_info,
                   (void*)c->d_vecs, (void*)c->d_small, c->d_s32, (void*)c->d_krylov,
-                  c->d_batch, (void*)c->d_tabs[0], (void*)c->d_tabs[1], (void*)c->d_tabs[2],
+                  (void*)c->d_tabs[0], (void*)c->d_tabs[1], (void*)c->d_tabs[2],
                   (void*)c->d_tabs[3]})
     if (p) hipFree(p);
   if (c->d_zbasis) (void)hipFree(c->d_zbasis);
@@ -379,6 +385,7 @@ ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_
   a.kappa = d_kappa;
   a.rhoinv = d_rhoinv;
   a.variant = c->variant;
+  a.radix = c->tune.fft_radix;
   const bool compact = c->variant == FFBIE_KAPPA_SWAP && d_rhoinv == nullptr;
   {
     a.NF = 2 * P.M;
@@ -463,6 +470,326 @@ ffbie_status ensure_near_ws(ffbie_ctx* c, int64_t pairs) {
     return fail(c, FFBIE_ENOMEM, "ffbie: near-pair workspace allocation failed");
   c->near_cap = pairs;
   c->near_cap_M = c->prob.M;
+  return FFBIE_OK;
+}
+
+}  // namespace
+
+// Problems of one M inside a batch plan (contiguous in the plan's order).
+struct PlanClass {
+  int M = 0;
+  int lo = 0, hi = 0;                  // problem range
+  int64_t pairs = 0;
+  ffbie_tuning tune{};
+  double tuned_ms = 0.0;
+  int64_t n_items = 0;
+  int waves = 1, refine_waves = 1;
+  size_t lds = 0, refine_lds = 0;
+  int tw = 0;                          // doubles of FFT twiddles in LDS
+};
+
+struct ffbie_batch_plan {
+  ffbie_ctx* ctx = nullptr;
+  int flags = 0;
+  bool single = false;
+  int np = 0;                          // non-empty problems, ordered by decreasing M
+  int mm = 0, Mmax = 16;
+  int64_t total = 0;                   // pairs
+  std::vector<CoeffArgs> args;         // host copy of the descriptors
+  std::vector<int64_t> item_prefix;    // per problem, relative to its class
+  std::vector<PlanClass> cls;
+  int64_t n_root = 0;
+  // device memory owned by the plan
+  CoeffArgs* d_args = nullptr;
+  int64_t* d_item_prefix = nullptr;
+  int64_t* d_root_prefix = nullptr;
+  RootRec* d_roots = nullptr;
+  int32_t* d_status = nullptr;         // status of items without an output array
+  int64_t* d_list = nullptr;           // refine queue
+  int* d_count = nullptr;              // [0] refine queue length, [1 + c] work counter of class c
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// Workgroups x wavefronts of the batched refine pass: the queue length is
+// known only on the device, so a fixed grid walks it.
+constexpr int kRefineWaves = 2048;
+// Upper bound on the workgroups of a persistent main pass.
+constexpr int64_t kMainBlocks = 2048;
+constexpr int kMaxClasses = 4;         // M = 16, 32, 64, 128
+
+bool valid_tuning(const ffbie_tuning& t, std::string* why) {
+  if (t.fft_radix != 2 && t.fft_radix != 4) { *why = "fft_radix must be 2 or 4"; return false; }
+  if (t.pairs_per_item < 1 || t.pairs_per_item > 256) { *why = "pairs_per_item must be in [1, 256]"; return false; }
+  if (t.waves_per_block != 1 && t.waves_per_block != 2 && t.waves_per_block != 4) {
+    *why = "waves_per_block must be 1, 2 or 4";
+    return false;
+  }
+  return true;
+}
+
+void plan_free(ffbie_batch_plan* pl) {
+  if (!pl) return;
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+  for (void* p : {(void*)pl->d_args, (void*)pl->d_item_prefix, (void*)pl->d_root_prefix,
+                  (void*)pl->d_roots, (void*)pl->d_status, (void*)pl->d_list, (void*)pl->d_count})
+    if (p) (void)hipFree(p);
+  delete pl;
+}
+
+// Launch shape and work-item numbering of class k for tuning t; uploads the
+// class's descriptors (radix) and item prefix and waits for the upload.
+ffbie_status plan_shape(ffbie_ctx* c, ffbie_batch_plan* pl, int k, const ffbie_tuning& t) {
+  PlanClass& q = pl->cls[k];
+  const size_t tab = sizeof(double) * 8 * q.M;
+  q.tw = coeff_twiddle_doubles(2 * q.M, pl->single);
+  const size_t per_wave = sizeof(double) * coeff_lds_per_wave(2 * q.M, q.M, 2 * q.M, true, pl->single);
+  int waves = t.waves_per_block;
+  while (waves > 1 && tab + q.tw * sizeof(double) + waves * per_wave > 65536) waves >>= 1;
+  q.tune = t;
+  q.tune.waves_per_block = waves;
+  q.waves = waves;
+  q.lds = tab + q.tw * sizeof(double) + waves * per_wave;
+  const size_t per_wave_r = sizeof(double) * coeff_lds_per_wave(4 * q.M, q.M, 2 * q.M, true, pl->single);
+  q.refine_waves = 4;
+  while (q.refine_waves > 1 && tab + q.refine_waves * per_wave_r > 65536) q.refine_waves >>= 1;
+  q.refine_lds = tab + q.refine_waves * per_wave_r;
+  int64_t n = 0;
+  for (int s = q.lo; s < q.hi; ++s) {
+    pl->args[s].radix = t.fft_radix;
+    pl->item_prefix[s] = n;
+    n += (pl->args[s].n + t.pairs_per_item - 1) / t.pairs_per_item;
+  }
+  q.n_items = n;
+  FFBIE_HIP(c, hipMemcpyAsync(pl->d_args + q.lo, pl->args.data() + q.lo, (q.hi - q.lo) * sizeof(CoeffArgs),
+                              hipMemcpyHostToDevice, c->stream));
+  FFBIE_HIP(c, hipMemcpyAsync(pl->d_item_prefix + q.lo, pl->item_prefix.data() + q.lo,
+                              (q.hi - q.lo) * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  FFBIE_HIP(c, hipStreamSynchronize(c->stream));      // host data may change next
+  return FFBIE_OK;
+}
+
+BatchArgs plan_args(const ffbie_batch_plan* pl) {
+  BatchArgs b{};
+  b.probs = pl->d_args;
+  b.n_probs = pl->np;
+  b.root_prefix = pl->d_root_prefix;
+  b.flag_list = pl->d_list;
+  b.flag_count = pl->d_count;
+  b.tab_max = 8 * pl->Mmax;
+  return b;
+}
+
+hipError_t launch_class_main(const ffbie_batch_plan* pl, int k, hipStream_t stream) {
+  const PlanClass& q = pl->cls[k];
+  BatchArgs b = plan_args(pl);
+  b.probs = pl->d_args + q.lo;
+  b.n_probs = q.hi - q.lo;
+  b.item_prefix = pl->d_item_prefix + q.lo;
+  b.n_items = q.n_items;
+  b.item_counter = pl->d_count + 1 + k;
+  b.tab_max = 8 * q.M;
+  b.tw_max = q.tw;
+  b.tile = q.tune.pairs_per_item;
+  const int64_t blocks = std::min<int64_t>((q.n_items + q.waves - 1) / q.waves, kMainBlocks);
+  return launch_batch(b, pl->mm, blocks, 64 * q.waves, q.lds, stream, 1, pl->single);
+}
+
+hipError_t launch_class_refine(const ffbie_batch_plan* pl, int k, hipStream_t stream) {
+  const PlanClass& q = pl->cls[k];
+  BatchArgs b = plan_args(pl);
+  b.tab_max = 8 * q.M;
+  b.prob_lo = q.lo;
+  b.prob_hi = q.hi;
+  return launch_batch(b, pl->mm, kRefineWaves / q.refine_waves, 64 * q.refine_waves, q.refine_lds,
+                      stream, 2, pl->single);
+}
+
+// Counter reset, root pass, main pass of every M class, refine pass of every
+// class, on `stream`; with `timed`, the context's timing events bracket the
+// root, main and refine passes.
+ffbie_status plan_launch(ffbie_ctx* c, ffbie_batch_plan* pl, hipStream_t stream, bool timed = false) {
+  FFBIE_HIP(c, launch_zero(pl->d_count, 1 + kMaxClasses, stream));
+  if (timed) FFBIE_HIP(c, hipEventRecord(c->ev[0], stream));
+  FFBIE_HIP(c, launch_batch(plan_args(pl), pl->mm, pl->n_root, 256, 8 * pl->Mmax * sizeof(double), stream,
+                            0, pl->single));
+  if (timed) FFBIE_HIP(c, hipEventRecord(c->ev[1], stream));
+  for (int k = 0; k < (int)pl->cls.size(); ++k) FFBIE_HIP(c, launch_class_main(pl, k, stream));
+  if (timed) FFBIE_HIP(c, hipEventRecord(c->ev[2], stream));
+  for (int k = 0; k < (int)pl->cls.size(); ++k) FFBIE_HIP(c, launch_class_refine(pl, k, stream));
+  if (timed) {
+    FFBIE_HIP(c, hipEventRecord(c->ev[3], stream));
+    c->timed = true;
+  }
+  return FFBIE_OK;
+}
+
+ffbie_status plan_build(ffbie_ctx* c, ffbie_batch_plan* pl, int n_items, const ffbie_batch_item* items,
+                        const ffbie_tuning* t) {
+  if (n_items < 0 || (n_items > 0 && !items))
+    return fail(c, FFBIE_EINVAL, "ffbie batch: invalid item array");
+  if (n_items >= (1 << 22)) return fail(c, FFBIE_EINVAL, "ffbie batch: too many items");
+  // validate, and order the non-empty problems by decreasing M
+  std::vector<Prob> probs(n_items);
+  std::vector<int> order;
+  for (int i = 0; i < n_items; ++i) {
+    const ffbie_batch_item& it = items[i];
+    std::string why;
+    if (!make_prob(&it.g, &it.d, it.k, &probs[i], &why))
+      return fail(c, FFBIE_EINVAL, "ffbie batch: item " + std::to_string(i) + ": " + why);
+    if (it.d.kappa_variant != FFBIE_KAPPA_SWAP)
+      return fail(c, FFBIE_EINVAL, "ffbie batch: only FFBIE_KAPPA_SWAP is batched");
+    if (it.n_pairs < 0 || it.n_pairs > ((int64_t)1 << 31))
+      return fail(c, FFBIE_EINVAL, "ffbie batch: n_pairs out of range");
+    if (it.n_pairs == 0) continue;
+    if (!it.d_t || !it.d_az || !it.d_ts || !it.d_kappa)
+      return fail(c, FFBIE_EINVAL, "ffbie batch: NULL pair or kappa pointer");
+    order.push_back(i);
+    pl->total += it.n_pairs;
+    pl->mm = std::max(pl->mm, it.g.mmax);
+    pl->Mmax = std::max(pl->Mmax, it.d.M);
+  }
+  pl->np = (int)order.size();
+  if (pl->np == 0) return FFBIE_OK;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return items[a].d.M > items[b].d.M; });
+  for (int q = 0; q < kMaxClasses; ++q) {
+    const int M = 16 << q;
+    if (c->d_tabs[q]) continue;
+    std::vector<double> tab(8 * M);
+    for (int i = 0; i < 8 * M; ++i) tab[i] = table_sin(i, M);
+    FFBIE_HIP(c, hipMalloc(&c->d_tabs[q], tab.size() * sizeof(double)));
+    FFBIE_HIP(c, hipMemcpy(c->d_tabs[q], tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  const int np = pl->np;
+  const int64_t total = pl->total;
+  if (hipMalloc(&pl->d_args, np * sizeof(CoeffArgs)) != hipSuccess ||
+      hipMalloc(&pl->d_item_prefix, np * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(&pl->d_root_prefix, np * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(&pl->d_roots, total * sizeof(RootRec)) != hipSuccess ||
+      hipMalloc(&pl->d_status, total * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&pl->d_list, total * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(&pl->d_count, (1 + kMaxClasses) * sizeof(int)) != hipSuccess)
+    return fail(c, FFBIE_ENOMEM, "ffbie batch: workspace allocation failed");
+  pl->args.resize(np);
+  pl->item_prefix.resize(np);
+  std::vector<int64_t> root_prefix(np);
+  int64_t off = 0;
+  pl->n_root = 0;
+  for (int q = 0; q < np; ++q) {
+    const ffbie_batch_item& it = items[order[q]];
+    CoeffArgs& a = pl->args[q];
+    a = CoeffArgs{};
+    a.P = probs[order[q]];
+    if (pl->single) a.P.eps0 = std::max(a.P.eps0, kEpsMixed);
+    int qi = 0;
+    while ((16 << qi) != it.d.M) ++qi;
+    a.tab_g = c->d_tabs[qi];
+    a.n = it.n_pairs;
+    a.t_in = it.d_t;
+    a.az_in = it.d_az;
+    a.ts_in = it.d_ts;
+    a.roots = pl->d_roots + off;
+    a.status = it.d_pair_status ? it.d_pair_status : pl->d_status + off;
+    a.kappa = it.d_kappa;
+    a.rhoinv = nullptr;
+    a.NF = 2 * it.d.M;
+    a.flag_list = pl->d_list;
+    a.flag_count = pl->d_count;
+    a.variant = FFBIE_KAPPA_SWAP;
+    a.flag_tag = (int64_t)q << 40;
+    a.radix = t[qi].fft_radix;
+    root_prefix[q] = pl->n_root;
+    pl->n_root += (it.n_pairs + 255) / 256;
+    off += it.n_pairs;
+    if (pl->cls.empty() || pl->cls.back().M != it.d.M) {
+      PlanClass k;
+      k.M = it.d.M;
+      k.lo = q;
+      pl->cls.push_back(k);
+    }
+    pl->cls.back().hi = q + 1;
+    pl->cls.back().pairs += it.n_pairs;
+  }
+  FFBIE_HIP(c, hipMemcpyAsync(pl->d_root_prefix, root_prefix.data(), np * sizeof(int64_t),
+                              hipMemcpyHostToDevice, c->stream));
+  for (int k = 0; k < (int)pl->cls.size(); ++k) {
+    int qi = 0;
+    while ((16 << qi) != pl->cls[k].M) ++qi;
+    const ffbie_status st = plan_shape(c, pl, k, t[qi]);
+    if (st != FFBIE_OK) return st;
+  }
+  return FFBIE_OK;
+}
+
+// For every M class, times the class's main pass for each candidate tuning
+// (FFT radix x pairs per work item x waves per workgroup) and keeps the
+// fastest.  The root pass runs once first; the counters are reset before each
+// run, so the refine queue never holds more than one entry per pair.
+ffbie_status plan_autotune(ffbie_ctx* c, ffbie_batch_plan* pl) {
+  hipEvent_t e0, e1;
+  FFBIE_HIP(c, hipEventCreate(&e0));
+  FFBIE_HIP(c, hipEventCreate(&e1));
+  ffbie_status st = FFBIE_OK;
+  hipError_t e = launch_zero(pl->d_count, 1 + kMaxClasses, c->stream);
+  if (e == hipSuccess)
+    e = launch_batch(plan_args(pl), pl->mm, pl->n_root, 256, 8 * pl->Mmax * sizeof(double), c->stream, 0,
+                     pl->single);
+  if (e != hipSuccess) st = hip_fail(c, e, "autotune root pass");
+  for (int k = 0; k < (int)pl->cls.size() && st == FFBIE_OK; ++k) {
+    ffbie_tuning best = pl->cls[k].tune;
+    float best_ms = -1.0f;
+    for (int radix : {2, 4})
+      for (int ppi : {8, 16, 32})
+        for (int waves : {1, 2, 4}) {
+          if (st != FFBIE_OK) break;
+          if ((st = plan_shape(c, pl, k, ffbie_tuning{radix, ppi, waves})) != FFBIE_OK) break;
+          if (pl->cls[k].waves != waves) continue;          // does not fit the LDS
+          float ms = 0.0f;
+          for (int rep = 0; rep < 2 && st == FFBIE_OK; ++rep) {   // the first run warms up
+            if ((e = launch_zero(pl->d_count, 1 + kMaxClasses, c->stream)) != hipSuccess ||
+                (e = hipEventRecord(e0, c->stream)) != hipSuccess ||
+                (e = launch_class_main(pl, k, c->stream)) != hipSuccess ||
+                (e = hipEventRecord(e1, c->stream)) != hipSuccess ||
+                (e = hipEventSynchronize(e1)) != hipSuccess ||
+                (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
+              st = hip_fail(c, e, "autotune main pass");
+          }
+          if (st == FFBIE_OK && (best_ms < 0 || ms < best_ms)) {
+            best_ms = ms;
+            best = pl->cls[k].tune;
+          }
+        }
+    if (st == FFBIE_OK) {
+      st = plan_shape(c, pl, k, best);
+      pl->cls[k].tuned_ms = best_ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+// Captures the whole launch sequence into a graph on a private stream;
+// execute launches the graph on the context's stream.
+ffbie_status plan_capture(ffbie_ctx* c, ffbie_batch_plan* pl) {
+  FFBIE_HIP(c, hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+  FFBIE_HIP(c, hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+  const ffbie_status st = plan_launch(c, pl, pl->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(pl->cap_stream, &g);
+  if (st != FFBIE_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  FFBIE_HIP(c, e);
+  pl->graph = g;
+  FFBIE_HIP(c, hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0));
   return FFBIE_OK;
 }
 
@@ -689,127 +1016,94 @@ ffbie_status ffbie_singular_factor(ffbie_ctx* c, int64_t n, const double* d_b, i
   return FFBIE_OK;
 }
 
+ffbie_status ffbie_batch_plan_create(ffbie_ctx* c, int n_items, const ffbie_batch_item* items,
+                                     int flags, const ffbie_tuning* tuning, ffbie_batch_plan** out) {
+  if (!c) return FFBIE_EINVAL;
+  if (!out) return fail(c, FFBIE_EINVAL, "ffbie_batch_plan_create: NULL out");
+  *out = nullptr;
+  if (flags & ~(FFBIE_PLAN_GRAPH | FFBIE_PLAN_AUTOTUNE | FFBIE_PLAN_MIXED))
+    return fail(c, FFBIE_EINVAL, "ffbie_batch_plan_create: unknown flag");
+  ffbie_tuning t[kMaxClasses];
+  for (int q = 0; q < kMaxClasses; ++q) {
+    t[q] = tuning ? tuning[q] : c->tune;
+    std::string why;
+    if (!valid_tuning(t[q], &why)) return fail(c, FFBIE_EINVAL, "ffbie_batch_plan_create: " + why);
+  }
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  ffbie_batch_plan* pl = new ffbie_batch_plan();
+  pl->ctx = c;
+  pl->flags = flags;
+  pl->single = (flags & FFBIE_PLAN_MIXED) != 0;
+  ffbie_status st = plan_build(c, pl, n_items, items, t);
+  if (st == FFBIE_OK && pl->np > 0 && (flags & FFBIE_PLAN_AUTOTUNE)) st = plan_autotune(c, pl);
+  if (st == FFBIE_OK && pl->np > 0 && (flags & FFBIE_PLAN_GRAPH)) st = plan_capture(c, pl);
+  if (st != FFBIE_OK) {
+    plan_free(pl);
+    return st;
+  }
+  *out = pl;
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_batch_plan_execute(ffbie_ctx* c, ffbie_batch_plan* pl) {
+  if (!c) return FFBIE_EINVAL;
+  if (!pl || pl->ctx != c) return fail(c, FFBIE_EINVAL, "ffbie_batch_plan_execute: plan of another context");
+  if (pl->np == 0) return FFBIE_OK;
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  if (pl->exec) {
+    FFBIE_HIP(c, hipGraphLaunch(pl->exec, c->stream));
+    return FFBIE_OK;
+  }
+  return plan_launch(c, pl, c->stream, c->timing);
+}
+
+ffbie_status ffbie_batch_plan_get_tuning(const ffbie_batch_plan* pl, int m_class, ffbie_tuning* t,
+                                         double* tuned_ms, int* M) {
+  if (!pl || m_class < 0 || m_class >= (int)pl->cls.size()) return FFBIE_EINVAL;
+  const PlanClass& q = pl->cls[m_class];
+  if (t) *t = q.tune;
+  if (tuned_ms) *tuned_ms = q.tuned_ms;
+  if (M) *M = q.M;
+  return FFBIE_OK;
+}
+
+int ffbie_batch_plan_classes(const ffbie_batch_plan* pl) { return pl ? (int)pl->cls.size() : 0; }
+
+ffbie_status ffbie_batch_plan_destroy(ffbie_batch_plan* pl) {
+  if (!pl) return FFBIE_OK;
+  hipSetDevice(pl->ctx->device);
+  (void)hipStreamSynchronize(pl->ctx->stream);
+  plan_free(pl);
+  return FFBIE_OK;
+}
+
 ffbie_status ffbie_kernel_coeffs_batched(ffbie_ctx* c, int n_items, const ffbie_batch_item* items) {
   if (!c) return FFBIE_EINVAL;
-  if (n_items < 0 || (n_items > 0 && !items))
-    return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_batched: invalid item array");
-  if (n_items >= (1 << 22)) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_batched: too many items");
-  // validate, and order the non-empty problems by decreasing M (cost per pair)
-  std::vector<Prob> probs(n_items);
-  std::vector<int> order;
-  int64_t total = 0;
-  int mm = 0, Mmax = 16;
-  for (int i = 0; i < n_items; ++i) {
-    const ffbie_batch_item& it = items[i];
-    std::string why;
-    if (!make_prob(&it.g, &it.d, it.k, &probs[i], &why))
-      return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_batched: item " + std::to_string(i) + ": " + why);
-    if (it.d.kappa_variant != FFBIE_KAPPA_SWAP)
-      return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_batched: only FFBIE_KAPPA_SWAP is batched");
-    if (it.n_pairs < 0 || it.n_pairs > ((int64_t)1 << 31))
-      return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_batched: n_pairs out of range");
-    if (it.n_pairs == 0) continue;
-    if (!it.d_t || !it.d_az || !it.d_ts || !it.d_kappa)
-      return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_batched: NULL pair or kappa pointer");
-    order.push_back(i);
-    total += it.n_pairs;
-    mm = std::max(mm, it.g.mmax);
-    Mmax = std::max(Mmax, it.d.M);
-  }
-  if (order.empty()) return FFBIE_OK;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return items[a].d.M > items[b].d.M; });
   FFBIE_HIP(c, hipSetDevice(c->device));
-  ffbie_status s = ensure_ws(c, total);
-  if (s != FFBIE_OK) return s;
-  for (int q = 0; q < 4; ++q) {
-    const int M = 16 << q;
-    if (c->d_tabs[q]) continue;
-    std::vector<double> tab(8 * M);
-    for (int i = 0; i < 8 * M; ++i) tab[i] = table_sin(i, M);
-    FFBIE_HIP(c, hipMalloc(&c->d_tabs[q], tab.size() * sizeof(double)));
-    FFBIE_HIP(c, hipMemcpy(c->d_tabs[q], tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (c->oneshot) {                    // the previous call's plan: its kernels may still run
+    FFBIE_HIP(c, hipStreamSynchronize(c->stream));
+    plan_free(c->oneshot);
+    c->oneshot = nullptr;
   }
-  // launch shape: LDS for the largest problem
-  const int tab_max = 8 * Mmax;
-  int Mmin = 128;
-  for (int i : order) Mmin = std::min(Mmin, items[i].d.M);
-  const int tw_max = coeff_twiddle_doubles(2 * Mmin, false);
-  const size_t per_wave = sizeof(double) * coeff_lds_per_wave(2 * Mmax, Mmax, 2 * Mmax, true, false);
-  int waves = 4;
-  while (waves > 1 && (tab_max + tw_max) * sizeof(double) + waves * per_wave > 65536) --waves;
-  const size_t lds = (tab_max + tw_max) * sizeof(double) + waves * per_wave;
-  const size_t refine_lds =
-      tab_max * sizeof(double) + sizeof(double) * coeff_lds_per_wave(4 * Mmax, Mmax, 2 * Mmax, true, false);
-  const int64_t tile = (int64_t)waves * kBatchTile;
-  // descriptors
-  const int np = (int)order.size();
-  std::vector<CoeffArgs> args(np);
-  std::vector<int64_t> item_prefix(np), root_prefix(np);
-  int64_t off = 0, n_tiles = 0, n_root = 0;
-  for (int q = 0; q < np; ++q) {
-    const ffbie_batch_item& it = items[order[q]];
-    CoeffArgs& a = args[q];
-    a = CoeffArgs{};
-    a.P = probs[order[q]];
-    int qi = 0;
-    while ((16 << qi) != it.d.M) ++qi;
-    a.tab_g = c->d_tabs[qi];
-    a.n = it.n_pairs;
-    a.t_in = it.d_t;
-    a.az_in = it.d_az;
-    a.ts_in = it.d_ts;
-    a.roots = c->d_roots + off;
-    a.status = it.d_pair_status ? it.d_pair_status : c->d_status + off;
-    a.kappa = it.d_kappa;
-    a.rhoinv = nullptr;
-    a.NF = 2 * it.d.M;
-    a.flag_list = c->d_list;
-    a.flag_count = c->d_count;
-    a.variant = FFBIE_KAPPA_SWAP;
-    a.flag_tag = (int64_t)q << 40;
-    item_prefix[q] = n_tiles;
-    root_prefix[q] = n_root;
-    n_tiles += (it.n_pairs + tile - 1) / tile;
-    n_root += (it.n_pairs + 255) / 256;
-    off += it.n_pairs;
-  }
-  const size_t bytes = np * sizeof(CoeffArgs) + 2 * np * sizeof(int64_t);
-  if (bytes > c->batch_bytes) {
-    if (c->d_batch) hipFree(c->d_batch);
-    c->d_batch = nullptr;
-    c->batch_bytes = 0;
-    if (hipMalloc(&c->d_batch, bytes) != hipSuccess)
-      return fail(c, FFBIE_ENOMEM, "ffbie_kernel_coeffs_batched: descriptor allocation failed");
-    c->batch_bytes = bytes;
-  }
-  char* base = static_cast<char*>(c->d_batch);
-  CoeffArgs* d_args = reinterpret_cast<CoeffArgs*>(base);
-  int64_t* d_item_prefix = reinterpret_cast<int64_t*>(base + np * sizeof(CoeffArgs));
-  int64_t* d_root_prefix = d_item_prefix + np;
-  FFBIE_HIP(c, hipMemcpyAsync(d_args, args.data(), np * sizeof(CoeffArgs), hipMemcpyHostToDevice, c->stream));
-  FFBIE_HIP(c, hipMemcpyAsync(d_item_prefix, item_prefix.data(), np * sizeof(int64_t),
-                              hipMemcpyHostToDevice, c->stream));
-  FFBIE_HIP(c, hipMemcpyAsync(d_root_prefix, root_prefix.data(), np * sizeof(int64_t),
-                              hipMemcpyHostToDevice, c->stream));
-  FFBIE_HIP(c, hipStreamSynchronize(c->stream));      // host vectors go out of scope
-  FFBIE_HIP(c, hipMemsetAsync(c->d_count, 0, 2 * sizeof(int32_t), c->stream));
-  BatchArgs b{};
-  b.probs = d_args;
-  b.n_probs = np;
-  b.item_prefix = d_item_prefix;
-  b.n_items = n_tiles;
-  b.root_prefix = d_root_prefix;
-  b.item_counter = c->d_count + 1;
-  b.flag_list = c->d_list;
-  b.flag_count = c->d_count;
-  b.tab_max = tab_max;
-  b.tw_max = tw_max;
-  const size_t root_lds = tab_max * sizeof(double);
-  const int64_t blocks = std::min<int64_t>(n_tiles, 1024);
-  FFBIE_HIP(c, launch_batch(b, mm, n_root, root_lds, blocks, waves, lds, refine_lds, c->stream, 0));
-  FFBIE_HIP(c, launch_batch(b, mm, n_root, root_lds, blocks, waves, lds, refine_lds, c->stream, 1));
-  FFBIE_HIP(c, launch_batch(b, mm, n_root, root_lds, 512, waves, lds, refine_lds, c->stream, 2));
+  ffbie_batch_plan* pl = nullptr;
+  ffbie_status st = ffbie_batch_plan_create(c, n_items, items, 0, nullptr, &pl);
+  if (st != FFBIE_OK) return st;
+  c->oneshot = pl;
+  return ffbie_batch_plan_execute(c, pl);
+}
+
+ffbie_status ffbie_set_tuning(ffbie_ctx* c, const ffbie_tuning* t) {
+  if (!c) return FFBIE_EINVAL;
+  if (!t) return fail(c, FFBIE_EINVAL, "ffbie_set_tuning: NULL tuning");
+  std::string why;
+  if (!valid_tuning(*t, &why)) return fail(c, FFBIE_EINVAL, "ffbie_set_tuning: " + why);
+  c->tune = *t;
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_get_tuning(const ffbie_ctx* c, ffbie_tuning* t) {
+  if (!c || !t) return FFBIE_EINVAL;
+  *t = c->tune;
   return FFBIE_OK;
 }
 

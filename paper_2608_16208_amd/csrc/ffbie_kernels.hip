@@ -321,6 +321,81 @@ __device__ __forceinline__ void fft_stockham_small(C*& ia, C*& oa, C*& ib, C*& o
   }
 }
 
+// Forward DFT by radix-4 Stockham stages, with one radix-2 stage at the end
+// when log2(NF) is odd.  Stage Ns (Ns = 1, 4, 16, ...): butterfly jj < NF/4
+// takes x_{jj + r NF/4} w^r (r = 0..3, w = e^{-2 pi i s / (4 Ns)}, s = jj mod Ns),
+// forms their 4-point DFT and writes it to jj' + r Ns, jj' = 4 (jj - s) + s.
+// w comes from the radix-2 twiddle table when one is given (entry s of the
+// stage 2 Ns), else from the angle table; w^2 and w^3 by multiplication.
+template <class C>
+__device__ __forceinline__ void fft_stockham_r4(C*& ia, C*& oa, C*& ib, C*& ob, bool two, int NF, int M,
+                                                const double* tab, int mask, int quarter, const C* tw) {
+  using R = decltype(C::re);
+  const int lane = threadIdx.x & 63;
+  const int q4 = NF >> 2;
+  int Ns = 1, st2 = 1;                 // st2 = log2(2 Ns)
+  for (; 4 * Ns <= NF; Ns <<= 2, st2 += 2) {
+    for (int jj = lane; jj < q4; jj += 64) {
+      const int s = jj & (Ns - 1);
+      C w1;
+      if (tw) {
+        w1 = tw[(st2 << 6) + s];
+      } else {
+        const int tk = s * ((2 * M) / Ns);       // angle pi s / (2 Ns)
+        w1 = C{(R)tcos(tab, tk, mask, quarter), (R)-tsin(tab, tk, mask)};
+      }
+      const C w2 = w1 * w1, w3 = w2 * w1;
+      const int idxD = ((jj - s) << 2) + s;
+      {
+        const C v0 = ia[jj], v1 = ia[jj + q4] * w1, v2 = ia[jj + 2 * q4] * w2, v3 = ia[jj + 3 * q4] * w3;
+        const C s02 = v0 + v2, d02 = v0 - v2, s13 = v1 + v3, d13 = v1 - v3;
+        const C md13 = C{d13.im, -d13.re};      // -i (v1 - v3)
+        oa[idxD] = s02 + s13;
+        oa[idxD + Ns] = d02 + md13;
+        oa[idxD + 2 * Ns] = s02 - s13;
+        oa[idxD + 3 * Ns] = d02 - md13;
+      }
+      if (two) {
+        const C v0 = ib[jj], v1 = ib[jj + q4] * w1, v2 = ib[jj + 2 * q4] * w2, v3 = ib[jj + 3 * q4] * w3;
+        const C s02 = v0 + v2, d02 = v0 - v2, s13 = v1 + v3, d13 = v1 - v3;
+        const C md13 = C{d13.im, -d13.re};
+        ob[idxD] = s02 + s13;
+        ob[idxD + Ns] = d02 + md13;
+        ob[idxD + 2 * Ns] = s02 - s13;
+        ob[idxD + 3 * Ns] = d02 - md13;
+      }
+    }
+    wave_sync();
+    C* tmp = ia; ia = oa; oa = tmp;
+    tmp = ib; ib = ob; ob = tmp;
+  }
+  if (Ns < NF) {                       // NF = 2 Ns: a last radix-2 stage
+    const int half = NF >> 1;
+    for (int jj = lane; jj < half; jj += 64) {
+      const int r = jj & (Ns - 1);
+      C wt;
+      if (tw) {
+        wt = tw[((st2 - 1) << 6) + lane];
+      } else {
+        const int tk = r * ((4 * M) / Ns);      // angle pi r / Ns
+        wt = C{(R)tcos(tab, tk, mask, quarter), (R)-tsin(tab, tk, mask)};
+      }
+      const int idxD = ((jj - r) << 1) + r;
+      const C v0 = ia[jj], v1 = ia[jj + half] * wt;
+      oa[idxD] = v0 + v1;
+      oa[idxD + Ns] = v0 - v1;
+      if (two) {
+        const C u0 = ib[jj], u1 = ib[jj + half] * wt;
+        ob[idxD] = u0 + u1;
+        ob[idxD + Ns] = u0 - u1;
+      }
+    }
+    wave_sync();
+    C* tmp = ia; ia = oa; oa = tmp;
+    tmp = ib; ib = ob; ob = tmp;
+  }
+}
+
 // Coefficient j of the real sequence packed in the real part of the
 // transform X: (X_j + conj(X_{NF-j})) / (2 NF).
 template <class C>
@@ -532,7 +607,9 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     }
     wave_sync();
     C *Z1 = z1a, *free1 = z1b, *Z2 = z2a, *free2 = z2b;
-    if (tw)
+    if (a.radix == 4)
+      fft_stockham_r4(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter, tw);
+    else if (tw)
       fft_stockham_small(Z1, free1, Z2, free2, want_c, NF, tw);
     else
       fft_stockham(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter);
@@ -672,12 +749,13 @@ __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbi
 }
 
 // ===========================================================================
-// Batched coefficient path: many problems (surfaces) in one persistent launch.
-// Work items are tiles of (waves per block) x kBatchTile pairs of one problem,
-// numbered problem by problem; each workgroup takes the next item from a global
-// counter, stages the problem's angle table in LDS when the problem changes,
-// and each wavefront runs its share of the tile.  Every workgroup leaves the
-// loop once the counter passes the last item.
+// Batched coefficient path: many problems (surfaces, panel counts, k) of one
+// M in one persistent launch.  The angle table and the FFT twiddles depend
+// only on M, so each workgroup stages them once.  Work items are runs of
+// b.tile consecutive pairs of one problem, numbered problem by problem; each
+// wavefront takes the next item from a global counter on its own (no
+// workgroup barrier between items) and leaves once the counter passes the last
+// item.
 // ===========================================================================
 __device__ __forceinline__ int batch_find(const int64_t* __restrict__ prefix, int n, int64_t x) {
   int lo = 0, hi = n - 1;                     // last problem with prefix[s] <= x
@@ -688,58 +766,67 @@ __device__ __forceinline__ int batch_find(const int64_t* __restrict__ prefix, in
   return lo;
 }
 
-template <int MM>
-__global__ __launch_bounds__(256) void ffbie_coeff_batch_kernel_t(BatchArgs b) {
+template <int MM, class R>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbie_coeff_batch_kernel_t(
+    BatchArgs b) {
+  using C = typename Spec<R>::C;
+  constexpr bool single = sizeof(R) == 4;
   extern __shared__ double smem[];
-  __shared__ int64_t item_s;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int waves_per_block = blockDim.x >> 6;
-  const int64_t tile = (int64_t)waves_per_block * kBatchTile;
-  int cur = -1;
-  while (true) {
-    if (threadIdx.x == 0) item_s = atomicAdd(b.item_counter, 1);
+  const CoeffArgs& a0 = b.probs[0];
+  const int M = a0.P.M, NF = 2 * M;
+  load_table(smem, a0.tab_g, a0.P.tab_n);
+  C* tw = coeff_twiddle_doubles(NF, single) ? reinterpret_cast<C*>(smem + b.tab_max) : nullptr;
+  if (tw) {
+    build_twiddles(tw, NF, M, smem, a0.P.tab_n - 1, 2 * M);
     __syncthreads();
-    const int64_t item = item_s;
+  }
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int per_wave = coeff_lds_per_wave(NF, M, a0.P.L, true, single);
+  double* wbase = smem + b.tab_max + b.tw_max + (size_t)wave * per_wave;
+  while (true) {
+    int64_t item = 0;
+    if ((threadIdx.x & 63) == 0) item = atomicAdd(b.item_counter, 1);
+    item = __shfl(item, 0);
     if (item >= b.n_items) break;
     const int s = batch_find(b.item_prefix, b.n_probs, item);
     const CoeffArgs& a = b.probs[s];
-    const int NF = 2 * a.P.M;
-    cplx* tw = coeff_twiddle_doubles(NF, false) ? reinterpret_cast<cplx*>(smem + b.tab_max) : nullptr;
-    if (s != cur) {
-      load_table(smem, a.tab_g, a.P.tab_n);    // ends with a barrier
-      if (tw) {
-        build_twiddles(tw, NF, a.P.M, smem, a.P.tab_n - 1, 2 * a.P.M);
-        __syncthreads();
-      }
-      cur = s;
-    }
-    const int per_wave = coeff_lds_per_wave(NF, a.P.M, a.P.L, true, false);
-    const int64_t t0 = (item - b.item_prefix[s]) * tile + (int64_t)wave * kBatchTile;
-    const int64_t beg = min(a.n, t0), end = min(a.n, t0 + kBatchTile);
-    coeff_range<MM, false, double>(a, smem, tw, smem + b.tab_max + b.tw_max + (size_t)wave * per_wave, NF,
-                           beg, end);
-    __syncthreads();                           // all waves done before item_s / the table change
+    const int64_t t0 = (item - b.item_prefix[s]) * b.tile;
+    const int64_t beg = min(a.n, t0), end = min(a.n, t0 + b.tile);
+    coeff_range<MM, false, R>(a, smem, tw, wbase, NF, beg, end);
   }
 }
 
-// Refine pass of a batch: one wavefront per workgroup, entries (problem << 40 | pair).
-template <int MM>
-__global__ __launch_bounds__(64) void ffbie_coeff_batch_refine_t(BatchArgs b) {
+// Refine pass of the problems [b.prob_lo, b.prob_hi) (one M) of a batch:
+// queue entries are (problem << 40 | pair) over the whole batch; each
+// wavefront walks the queue with the grid's stride and takes the entries of
+// its problems.
+template <int MM, class R>
+__global__ __launch_bounds__(256) void ffbie_coeff_batch_refine_t(BatchArgs b) {
   extern __shared__ double smem[];
+  const CoeffArgs& a0 = b.probs[b.prob_lo];
+  load_table(smem, a0.tab_g, a0.P.tab_n);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int waves_per_block = blockDim.x >> 6;
+  const int NF = 4 * a0.P.M;
+  double* wbase = smem + b.tab_max +
+                  (size_t)wave * coeff_lds_per_wave(NF, a0.P.M, a0.P.L, true, sizeof(R) == 4);
   const int count = *b.flag_count;
-  int cur = -1;
-  for (int w = blockIdx.x; w < count; w += gridDim.x) {
+  const int stride = gridDim.x * waves_per_block;
+  for (int w = blockIdx.x * waves_per_block + wave; w < count; w += stride) {
     const int64_t e = b.flag_list[w];
     const int s = (int)(e >> 40);
+    if (s < b.prob_lo || s >= b.prob_hi) continue;
     const int64_t pi = e & ((int64_t(1) << 40) - 1);
-    const CoeffArgs& a = b.probs[s];
-    if (s != cur) {
-      load_table(smem, a.tab_g, a.P.tab_n);
-      cur = s;
-    }
-    coeff_range<MM, true, double>(a, smem, nullptr, smem + b.tab_max, 4 * a.P.M, pi, pi + 1);
-    __syncthreads();
+    coeff_range<MM, true, R>(b.probs[s], smem, nullptr, wbase, NF, pi, pi + 1);
   }
+}
+
+// Zeroes n ints (work counters before a launch; a kernel, so that the launch
+// sequence can be captured in a graph).
+__global__ void ffbie_zero_kernel(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 // Root kernel of a batch: one lane per pair, blocks of 256 pairs of one problem.
@@ -835,25 +922,33 @@ hipError_t launch_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t ld
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchArgs& b, int mm, int64_t root_blocks, size_t root_lds,
-                        int64_t blocks, int waves, size_t lds, size_t refine_lds,
-                        hipStream_t stream, int phase) {
+hipError_t launch_batch(const BatchArgs& b, int mm, int64_t blocks, int threads, size_t lds,
+                        hipStream_t stream, int phase, bool single) {
+  const dim3 grid((unsigned)blocks), block(threads);
   switch (mm_bucket(mm)) {
+#define P12(MMV, RT)                                                                             \
+  if (phase == 1)                                                                                \
+    hipLaunchKernelGGL((ffbie_coeff_batch_kernel_t<MMV, RT>), grid, block, lds, stream, b);     \
+  else                                                                                           \
+    hipLaunchKernelGGL((ffbie_coeff_batch_refine_t<MMV, RT>), grid, block, lds, stream, b)
 #define X(MMV)                                                                                   \
   case MMV:                                                                                      \
     if (phase == 0)                                                                              \
-      hipLaunchKernelGGL(ffbie_root_batch_kernel_t<MMV>, dim3((unsigned)root_blocks), dim3(256), \
-                         root_lds, stream, b);                                                   \
-    else if (phase == 1)                                                                         \
-      hipLaunchKernelGGL(ffbie_coeff_batch_kernel_t<MMV>, dim3((unsigned)blocks),               \
-                         dim3(64 * waves), lds, stream, b);                                      \
+      hipLaunchKernelGGL(ffbie_root_batch_kernel_t<MMV>, grid, block, lds, stream, b);           \
+    else if (single)                                                                             \
+      P12(MMV, float);                                                                           \
     else                                                                                         \
-      hipLaunchKernelGGL(ffbie_coeff_batch_refine_t<MMV>, dim3((unsigned)blocks), dim3(64),     \
-                         refine_lds, stream, b);                                                 \
+      P12(MMV, double);                                                                          \
     break;
     FFBIE_FOR_MM(X)
 #undef X
+#undef P12
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(int* p, int n, hipStream_t stream) {
+  hipLaunchKernelGGL(ffbie_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n);
   return hipGetLastError();
 }
 

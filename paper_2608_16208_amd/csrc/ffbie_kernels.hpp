@@ -28,17 +28,20 @@ struct CoeffArgs {
   int32_t* flag_count;
   int variant;               // FFBIE_KAPPA_SWAP or FFBIE_KAPPA_PAPER_CONV
   int64_t flag_tag;          // or-ed into queued pair indices (problem index << 40 in a batch)
+  int radix;                 // FFT stages: 2 (radix-2 Stockham) or 4 (radix-4, one radix-2 stage if needed)
 };
 
-// Pairs per wavefront and work item of the batched launch.
+// Default pairs per wavefront and work item of the batched launch.
 constexpr int kBatchTile = 16;
 
-// A batch of problems in one launch; probs[s] holds problem s's arguments
-// (its own P, angle table, pair arrays, outputs and workspace slices).
+// Problems of a batch in one launch; probs[s] holds problem s's arguments
+// (its own P, angle table, pair arrays, outputs and workspace slices).  The
+// main and refine passes run once per M class: probs then starts at the class
+// (main pass) or is the whole batch with [prob_lo, prob_hi) the class (refine).
 struct BatchArgs {
-  const CoeffArgs* probs;    // [n_probs], device memory
+  const CoeffArgs* probs;    // device memory
   int n_probs;
-  const int64_t* item_prefix;  // [n_probs] first work item (tile) of each problem
+  const int64_t* item_prefix;  // [n_probs] first work item of each problem (main pass)
   int64_t n_items;
   const int64_t* root_prefix;  // [n_probs] first 256-pair root block of each problem
   int* item_counter;         // work queue head (zeroed before the launch)
@@ -46,6 +49,8 @@ struct BatchArgs {
   int32_t* flag_count;
   int tab_max;               // doubles reserved for the angle table at the start of LDS
   int tw_max;                // doubles reserved after it for FFT twiddles (0 if none)
+  int tile;                  // pairs per work item (one wavefront)
+  int prob_lo, prob_hi;      // refine pass: the class's problems
 };
 
 // Per-wavefront LDS of the coefficient kernel, in doubles, with the spectral
@@ -72,9 +77,10 @@ hipError_t launch_root(const Prob& P, const double* tab, int64_t n, const double
                        double* root_out, hipStream_t stream);
 hipError_t launch_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t lds,
                         hipStream_t stream, bool refine, bool single);
-hipError_t launch_batch(const BatchArgs& b, int mm, int64_t root_blocks, size_t root_lds,
-                        int64_t blocks, int waves, size_t lds, size_t refine_lds,
-                        hipStream_t stream, int phase);
+// phase 0: root pass (threads = 256), 1: main pass, 2: refine pass of one M class.
+hipError_t launch_batch(const BatchArgs& b, int mm, int64_t blocks, int threads, size_t lds,
+                        hipStream_t stream, int phase, bool single);
+hipError_t launch_zero(int* p, int n, hipStream_t stream);
 __global__ void ffbie_singular_factor_kernel(int64_t n, const double* __restrict__ b_in, int mtop,
                                              double* __restrict__ out);
 

@@ -80,3 +80,141 @@ def test_batch_repeated_calls_are_deterministic(ctx):
     b = [o["kappa"].cpu().numpy() for o in ctx.kernel_coeffs_batched(items)]
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def _items(probs):
+    return [dict(amp=p["amp"], M=p["M"], k=p["k"], t=torch.tensor(p["t"]), az=torch.tensor(p["az"]),
+                 ts=torch.tensor(p["ts"])) for p in probs]
+
+
+def _single(ctx, p, mixed=False):
+    dev = ctx.device
+    ctx.set_problem(p["amp"], p["n_panels"], p["M"], p["k"])
+    one = ctx.kernel_coeffs(torch.tensor(p["t"], device=dev), torch.tensor(p["az"], device=dev),
+                            torch.tensor(p["ts"], device=dev), mixed=mixed)
+    return one["kappa"].cpu().numpy(), one["status"].cpu().numpy()
+
+
+def test_plan_graph_replays_match_eager(ctx):
+    """A plan captured in a HIP graph, replayed three times with other work of
+    the program (a single-problem call, torch kernels, host syncs) between the
+    replays: every replay must reproduce the eager batched result bit for bit."""
+    probs = _problems()
+    eager = [o["kappa"].cpu().numpy() for o in ctx.kernel_coeffs_batched(_items(probs))]
+    plan = ctx.batch_plan(_items(probs), graph=True)
+    dev = ctx.device
+    for rep in range(3):
+        for o in plan.outs:
+            o["kappa"].zero_()
+        torch.cuda.synchronize()
+        plan.execute()
+        # unrelated eager work between replays
+        p = probs[1]
+        ctx.set_problem(p["amp"], p["n_panels"], p["M"], p["k"])
+        ctx.kernel_coeffs(torch.tensor(p["t"][:50], device=dev), torch.tensor(p["az"][:50], device=dev),
+                          torch.tensor(p["ts"][:50], device=dev))
+        (torch.ones(1 << 20, device=dev) * rep).sum().item()
+        torch.cuda.synchronize()
+        for e, o in zip(eager, plan.outs):
+            assert np.array_equal(e, o["kappa"].cpu().numpy()), rep
+    plan.close()
+
+
+def test_plan_autotune_picks_a_candidate_and_keeps_results(ctx):
+    """The autotuner times radix x pairs-per-item x waves candidates on each M
+    class of the plan's own batch; with its choices the rows agree with
+    single-problem calls (radix 2) to rounding."""
+    probs = _problems()
+    plan = ctx.batch_plan(_items(probs), autotune=True)
+    tun = plan.tuning()
+    assert sorted(t["M"] for t in tun) == [16, 32, 64, 128]
+    for t in tun:
+        assert t["fft_radix"] in (2, 4) and t["pairs_per_item"] in (8, 16, 32)
+        assert t["waves_per_block"] in (1, 2, 4) and t["tuned_ms"] > 0
+    plan.execute()
+    torch.cuda.synchronize()
+    for p, o in zip(probs, plan.outs):
+        if len(p["t"]) == 0:
+            continue
+        k1, s1 = _single(ctx, p)
+        kb = o["kappa"].cpu().numpy()
+        assert np.array_equal(o["status"].cpu().numpy() & 0xff, s1 & 0xff)
+        err = np.max(np.abs(kb - k1)) / np.max(np.abs(k1))
+        assert err <= 1e-12, err
+    print("autotuned:", tun)
+    plan.close()
+
+
+def test_plan_explicit_tuning_per_M(ctx):
+    """A tuning table by M is applied class by class."""
+    probs = _problems()
+    want = {64: dict(fft_radix=4, pairs_per_item=8, waves_per_block=1),
+            128: dict(fft_radix=2, pairs_per_item=32, waves_per_block=2)}
+    plan = ctx.batch_plan(_items(probs), tuning=want)
+    got = {t["M"]: t for t in plan.tuning()}
+    for M, w in want.items():
+        for key, v in w.items():
+            assert got[M][key] == v, (M, key, got[M])
+    base = ctx.get_tuning()
+    assert got[16]["fft_radix"] == base["fft_radix"]
+    plan.execute()
+    torch.cuda.synchronize()
+    ref = [o["kappa"].cpu().numpy() for o in ctx.kernel_coeffs_batched(_items(probs))]
+    for r, o in zip(ref, plan.outs):
+        if r.size:
+            assert np.max(np.abs(r - o["kappa"].cpu().numpy())) <= 1e-12 * np.max(np.abs(r))
+    plan.close()
+
+
+@pytest.mark.parametrize("cfgi", [1, 2, 3])
+def test_radix4_transforms_match_oracle(ctx, cfgi):
+    """Radix-4 Stockham stages (with a final radix-2 stage for odd log2 N_F)
+    give the same coefficients as the oracle at the FP64 bar."""
+    cfg = workloads.config(cfgi)
+    t, j, ts = workloads.sample_pairs(cfg["n_panels"], cfg["M"], 120, seed=300 + cfgi)
+    p = dict(amp=cfg["amp"], M=cfg["M"], k=cfg["k"], t=t, az=j, ts=ts, n_panels=cfg["n_panels"])
+    saved = ctx.get_tuning()
+    try:
+        ctx.set_tuning(fft_radix=4)
+        k4, s4 = _single(ctx, p)
+    finally:
+        ctx.set_tuning(**saved)
+    assert not (s4 & 8).any()
+    _, ko, _ = ocoeffs.pairs_coeffs(cfg["amp"], cfg["k"], cfg["M"], 2 * cfg["M"], t, j, ts, processes=8)
+    e = np.linalg.norm(k4 - ko, axis=1) / np.linalg.norm(ko, axis=1)
+    print("radix 4, config %d: max rel err %.2e" % (cfgi, e.max()))
+    assert e.max() <= 1e-10, e.max()
+
+
+def test_plan_mixed_matches_single_mixed_calls(ctx):
+    """A mixed-precision plan (complex64 outputs, captured in a graph) gives the
+    rows of single-problem mixed calls.  The batched and single-problem kernels
+    are separate instantiations of the same per-pair routine, and the compiler
+    may fuse and order their FP32 operations differently, so rows are compared
+    to the mixed-precision bound (1e-5 of the row's largest value) and the pair
+    flags exactly."""
+    probs = _problems()
+    plan = ctx.batch_plan(_items(probs), mixed=True, graph=True)
+    plan.execute()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for p, o in zip(probs, plan.outs):
+        assert o["kappa"].dtype == torch.complex64
+        if len(p["t"]) == 0:
+            continue
+        k1, s1 = _single(ctx, p, mixed=True)
+        kb = o["kappa"].cpu().numpy()
+        assert np.array_equal(o["status"].cpu().numpy() & 0xff, s1 & 0xff)
+        err = np.max(np.abs(kb - k1), axis=1) / np.max(np.abs(k1), axis=1)
+        worst = max(worst, float(err.max()))
+    print("mixed plan vs single mixed calls: %.2e" % worst)
+    assert worst <= 1e-5, worst
+    plan.close()
+
+
+def test_tuning_validation(ctx):
+    import paper_2608_16208_amd as ffbie
+    for bad in (dict(fft_radix=3), dict(pairs_per_item=0), dict(waves_per_block=3)):
+        with pytest.raises(ffbie.FfbieError):
+            ctx.set_tuning(**bad)
+    assert ctx.get_tuning()["fft_radix"] in (2, 4)

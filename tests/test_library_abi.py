@@ -11,7 +11,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     txt = open(os.path.join(ROOT, "include", "ffbie.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:ffbie_status|const char \*|int64_t)\s*(ffbie_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:ffbie_status|const char \*|int64_t|int)\s*(ffbie_\w+)\s*\(", txt, re.M)))
 
 
 def test_header_declares_the_entry_points():
