@@ -207,12 +207,14 @@ typedef struct {
 ffbie_status ffbie_kernel_coeffs_batched(ffbie_ctx *ctx, int n_items, const ffbie_batch_item *items);
 
 /* Launch choices of the coefficient kernels:
- *   fft_radix        2: radix-2 Stockham transforms; 4: radix-4 stages (with
- *                    one radix-2 stage when log2(N_F) is odd),
+ *   fft_radix        transforms of the 2M-sample main pass (the 4M-sample
+ *                    refine pass uses radix 2): 2: radix-2 Stockham; 4:
+ *                    radix-4 stages (with one radix-2 stage when log2(N_F) is
+ *                    odd); 0: radix 4 for N_F >= 256 points, else radix 2,
  *   pairs_per_item   pairs a wavefront takes from one batch work item (1..256),
  *   waves_per_block  wavefronts per workgroup of the batched launch (1, 2, 4;
  *                    lowered to what fits 64 KiB of LDS).
- * A context starts with {2, 16, 4}; its fft_radix also applies to
+ * A context starts with {0, 16, 4}; its fft_radix also applies to
  * ffbie_kernel_coeffs(_mixed) and the near blocks of ffbie_assemble.  Results
  * do not depend on the tuning beyond rounding (the transforms differ in
  * operation order). */

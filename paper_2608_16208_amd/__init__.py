@@ -275,7 +275,7 @@ class Context:
         kernel_coeffs_batched; with mixed=True the kappa outputs are complex64)."""
         return BatchPlan(self, problems, graph, autotune, mixed, tuning)
 
-    def set_tuning(self, fft_radix=2, pairs_per_item=16, waves_per_block=4):
+    def set_tuning(self, fft_radix=0, pairs_per_item=16, waves_per_block=4):
         t = _Tuning(fft_radix, pairs_per_item, waves_per_block)
         self._check(self.lib.ffbie_set_tuning(self.h, ctypes.byref(t)), self.h)
 

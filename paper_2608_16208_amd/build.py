@@ -1,7 +1,10 @@
-"""Build the HIP library libffbie.so for gfx950 in-tree with hipcc."""
+"""Build the HIP library libffbie.so for gfx950 in-tree with hipcc: every
+source is compiled to an object in parallel, then the objects are linked."""
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -10,24 +13,39 @@ SOURCES = ["csrc/ffbie_api.hip", "csrc/ffbie_kernels.hip", "csrc/ffbie_assembly.
 LIB = os.path.join(HERE, "libffbie.so")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
 ]
 
 
-def build(verbose=False):
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc] + FLAGS + ["-o", tmp] + [os.path.join(HERE, s) for s in SOURCES] + ["-lrocblas"]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     errs = [l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l]
-    if res.returncode != 0:
-        sys.stderr.write("\n".join(errs) + "\n")
-        raise RuntimeError("hipcc failed building libffbie.so")
+    return res.returncode, "\n".join(errs)
+
+
+def build(verbose=False, jobs=None):
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1, 8)
+    with tempfile.TemporaryDirectory(prefix="ffbie_build_") as tmpd:
+        objs = [os.path.join(tmpd, os.path.basename(s) + ".o") for s in SOURCES]
+        cmds = [[hipcc] + FLAGS + ["-c", os.path.join(HERE, s), "-o", o] for s, o in zip(SOURCES, objs)]
+        with ThreadPoolExecutor(jobs) as ex:
+            results = list(ex.map(lambda c: _run(c, verbose), cmds))
+        for (rc, err), s in zip(results, SOURCES):
+            if rc != 0:
+                sys.stderr.write(err + "\n")
+                raise RuntimeError("hipcc failed compiling " + s)
+        tmp = LIB + ".tmp"
+        rc, err = _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lrocblas"],
+                       verbose)
+        if rc != 0:
+            sys.stderr.write(err + "\n")
+            raise RuntimeError("hipcc failed linking libffbie.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -73,7 +73,7 @@ struct ffbie_ctx {
   int64_t krylov_n = 0;
   // batched coefficients
   double* d_tabs[4] = {nullptr, nullptr, nullptr, nullptr};   // angle tables for M = 16 .. 128
-  ffbie_tuning tune{2, kBatchTile, 4};   // FFT radix, pairs per batch work item, waves per workgroup
+  ffbie_tuning tune{0, kBatchTile, 4};   // FFT radix (0: by N_F), pairs per batch work item, waves per workgroup
   ffbie_batch_plan* oneshot = nullptr;    // plan of the last ffbie_kernel_coeffs_batched call
   // learned preconditioner
   Mlp mlp;
@@ -522,7 +522,10 @@ constexpr int64_t kMainBlocks = 2048;
 constexpr int kMaxClasses = 4;         // M = 16, 32, 64, 128
 
 bool valid_tuning(const ffbie_tuning& t, std::string* why) {
-  if (t.fft_radix != 2 && t.fft_radix != 4) { *why = "fft_radix must be 2 or 4"; return false; }
+  if (t.fft_radix != 0 && t.fft_radix != 2 && t.fft_radix != 4) {
+    *why = "fft_radix must be 0, 2 or 4";
+    return false;
+  }
   if (t.pairs_per_item < 1 || t.pairs_per_item > 256) { *why = "pairs_per_item must be in [1, 256]"; return false; }
   if (t.waves_per_block != 1 && t.waves_per_block != 2 && t.waves_per_block != 4) {
     *why = "waves_per_block must be 1, 2 or 4";
@@ -596,6 +599,7 @@ hipError_t launch_class_main(const ffbie_batch_plan* pl, int k, hipStream_t stre
   b.tab_max = 8 * q.M;
   b.tw_max = q.tw;
   b.tile = q.tune.pairs_per_item;
+  b.radix = (q.tune.fft_radix == 4 || (q.tune.fft_radix == 0 && 2 * q.M >= 256)) ? 4 : 2;
   const int64_t blocks = std::min<int64_t>((q.n_items + q.waves - 1) / q.waves, kMainBlocks);
   return launch_batch(b, pl->mm, blocks, 64 * q.waves, q.lds, stream, 1, pl->single);
 }

@@ -215,22 +215,17 @@ FFBIE_HD __forceinline__ void pair_geo(const Geom& g, double t, double ts, const
   pair_geo_R<MM>(tab, J, mask, quarter, p);
 }
 
-// Delta r = r(t_s, theta_q) - r(t, theta_j) for a source azimuth on the table
-// grid: Kq = table index of theta_q, J = table index of theta_j (both even).
+// Delta r = r(t_s, theta_q) - r(t, theta_j) from the trigonometric values of
+// the grid angles: cq, sq = cos, sin theta_q; dh, cD = sin, cos of
+// (theta_q - theta_j)/2; sS, cS = sin, cos of (theta_q + theta_j)/2.
 template <int MM>
-FFBIE_HD __forceinline__ void dr_grid(const PairGeo<MM>& p, const double* tab, int Kq, int J,
-                                      int mask, int quarter, double* dx, double* dy, double* dz) {
-  const int hd = (Kq - J) >> 1;      // (theta_q - theta_j)/2
-  const int hs = (Kq + J) >> 1;      // (theta_q + theta_j)/2
-  const double cq = tcos(tab, Kq, mask, quarter), sq = tsin(tab, Kq, mask);
-  const double dh = tsin(tab, hd, mask);
-  const double sS = tsin(tab, hs, mask), cS = tcos(tab, hs, mask, quarter);
+FFBIE_HD __forceinline__ void dr_values(const PairGeo<MM>& p, double cq, double sq, double dh, double cD,
+                                        double sS, double cS, double* dx, double* dy, double* dz) {
   const double dcos = -2.0 * sS * dh;   // cos theta_q - cos theta_j
   const double dsin = 2.0 * cS * dh;    // sin theta_q - sin theta_j
   double dR = p.be[0];
   if (MM >= 1) {
     // cos(m theta_q), sin(m hs), sin(m hd) by the Chebyshev recurrences
-    const double cD = MM >= 2 ? tcos(tab, hd, mask, quarter) : 0.0;
     double c_prev = 1.0, c_cur = cq;
     double s_prev = 0.0, s_cur = sS;
     double d_prev = 0.0, d_cur = dh;
@@ -256,6 +251,18 @@ FFBIE_HD __forceinline__ void dr_grid(const PairGeo<MM>& p, const double* tab, i
   *dx = fma(dR, wx, p.R * ox);
   *dy = fma(dR, wy, p.R * oy);
   *dz = fma(dR, wz, p.R * oz);
+}
+
+// Delta r for a source azimuth on the table grid: Kq = table index of theta_q,
+// J = table index of theta_j (both even).
+template <int MM>
+FFBIE_HD __forceinline__ void dr_grid(const PairGeo<MM>& p, const double* tab, int Kq, int J,
+                                      int mask, int quarter, double* dx, double* dy, double* dz) {
+  const int hd = (Kq - J) >> 1;      // (theta_q - theta_j)/2
+  const int hs = (Kq + J) >> 1;      // (theta_q + theta_j)/2
+  dr_values<MM>(p, tcos(tab, Kq, mask, quarter), tsin(tab, Kq, mask), tsin(tab, hd, mask),
+                MM >= 2 ? tcos(tab, hd, mask, quarter) : 0.0, tsin(tab, hs, mask),
+                tcos(tab, hs, mask, quarter), dx, dy, dz);
 }
 
 // rho^2 and its first two derivatives in the source azimuth at a complex

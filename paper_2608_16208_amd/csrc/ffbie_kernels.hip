@@ -512,7 +512,7 @@ __device__ __forceinline__ void swap_convolution(const C* G, int p, const declty
 // spectral stage (transforms, truncation, A_m storage, convolutions, outputs):
 // double, or float for the mixed-precision path; geometry, samples, the root
 // and the recurrences for A_m run in FP64 either way.
-template <int MM, bool REFINE, class R>
+template <int MM, bool REFINE, class R, int RADIX>
 __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* tab,
                                             const typename Spec<R>::C* tw, double* wbase, int NF,
                                             int64_t beg, int64_t end) {
@@ -607,7 +607,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     }
     wave_sync();
     C *Z1 = z1a, *free1 = z1b, *Z2 = z2a, *free2 = z2b;
-    if (a.radix == 4)
+    if constexpr (RADIX == 4)
       fft_stockham_r4(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter, tw);
     else if (tw)
       fft_stockham_small(Z1, free1, Z2, free2, want_c, NF, tw);
@@ -719,7 +719,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
 // Surfaces of azimuthal order <= 2 fit 168 VGPRs with a few spilled values, so
 // they ask for three wavefronts per SIMD (more latency hiding); higher orders
 // would spill heavily and keep two.
-template <int MM, bool REFINE, class R>
+template <int MM, bool REFINE, class R, int RADIX>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbie_coeff_kernel_t(
     CoeffArgs a) {
@@ -744,7 +744,7 @@ __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbi
   const int64_t gw = (int64_t)blockIdx.x * waves_per_block + wave;
   const int64_t chunk = (count + total_waves - 1) / total_waves;
   const int64_t beg = gw * chunk, end = min(count, beg + chunk);
-  coeff_range<MM, REFINE, R>(a, tab, tw, smem + a.P.tab_n + twd + (size_t)wave * per_wave, a.NF,
+  coeff_range<MM, REFINE, R, RADIX>(a, tab, tw, smem + a.P.tab_n + twd + (size_t)wave * per_wave, a.NF,
                              beg, end);
 }
 
@@ -766,7 +766,7 @@ __device__ __forceinline__ int batch_find(const int64_t* __restrict__ prefix, in
   return lo;
 }
 
-template <int MM, class R>
+template <int MM, class R, int RADIX>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbie_coeff_batch_kernel_t(
     BatchArgs b) {
@@ -793,7 +793,7 @@ __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbi
     const CoeffArgs& a = b.probs[s];
     const int64_t t0 = (item - b.item_prefix[s]) * b.tile;
     const int64_t beg = min(a.n, t0), end = min(a.n, t0 + b.tile);
-    coeff_range<MM, false, R>(a, smem, tw, wbase, NF, beg, end);
+    coeff_range<MM, false, R, RADIX>(a, smem, tw, wbase, NF, beg, end);
   }
 }
 
@@ -818,7 +818,7 @@ __global__ __launch_bounds__(256) void ffbie_coeff_batch_refine_t(BatchArgs b) {
     const int s = (int)(e >> 40);
     if (s < b.prob_lo || s >= b.prob_hi) continue;
     const int64_t pi = e & ((int64_t(1) << 40) - 1);
-    coeff_range<MM, true, R>(b.probs[s], smem, nullptr, wbase, NF, pi, pi + 1);
+    coeff_range<MM, true, R, 2>(b.probs[s], smem, nullptr, wbase, NF, pi, pi + 1);
   }
 }
 
@@ -903,20 +903,21 @@ hipError_t launch_root(const Prob& P, const double* tab, int64_t n, const double
 
 hipError_t launch_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t lds,
                         hipStream_t stream, bool refine, bool single) {
+  // refine passes always take radix-2 transforms
+  const bool r4 = !refine && (a.radix == 4 || (a.radix == 0 && a.NF >= 256));
   switch (mm_bucket(a.P.g.mmax)) {
-#define K(MMV, RF, RT)                                                                           \
-  hipLaunchKernelGGL((ffbie_coeff_kernel_t<MMV, RF, RT>), dim3((unsigned)blocks),               \
+#define K(MMV, RF, RT, RX)                                                                       \
+  hipLaunchKernelGGL((ffbie_coeff_kernel_t<MMV, RF, RT, RX>), dim3((unsigned)blocks),           \
                      dim3(64 * waves), lds, stream, a)
+#define KR(MMV, RT)                                                                              \
+  if (refine) K(MMV, true, RT, 2); else if (r4) K(MMV, false, RT, 4); else K(MMV, false, RT, 2)
 #define X(MMV)                                                                                   \
   case MMV:                                                                                      \
-    if (single) {                                                                                \
-      if (refine) K(MMV, true, float); else K(MMV, false, float);                                \
-    } else {                                                                                     \
-      if (refine) K(MMV, true, double); else K(MMV, false, double);                              \
-    }                                                                                            \
+    if (single) { KR(MMV, float); } else { KR(MMV, double); }                                    \
     break;
     FFBIE_FOR_MM(X)
 #undef X
+#undef KR
 #undef K
   }
   return hipGetLastError();
@@ -925,12 +926,15 @@ hipError_t launch_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t ld
 hipError_t launch_batch(const BatchArgs& b, int mm, int64_t blocks, int threads, size_t lds,
                         hipStream_t stream, int phase, bool single) {
   const dim3 grid((unsigned)blocks), block(threads);
+  const bool r4 = b.radix == 4;
   switch (mm_bucket(mm)) {
 #define P12(MMV, RT)                                                                             \
-  if (phase == 1)                                                                                \
-    hipLaunchKernelGGL((ffbie_coeff_batch_kernel_t<MMV, RT>), grid, block, lds, stream, b);     \
+  if (phase == 2)                                                                                \
+    hipLaunchKernelGGL((ffbie_coeff_batch_refine_t<MMV, RT>), grid, block, lds, stream, b);     \
+  else if (r4)                                                                                   \
+    hipLaunchKernelGGL((ffbie_coeff_batch_kernel_t<MMV, RT, 4>), grid, block, lds, stream, b);  \
   else                                                                                           \
-    hipLaunchKernelGGL((ffbie_coeff_batch_refine_t<MMV, RT>), grid, block, lds, stream, b)
+    hipLaunchKernelGGL((ffbie_coeff_batch_kernel_t<MMV, RT, 2>), grid, block, lds, stream, b)
 #define X(MMV)                                                                                   \
   case MMV:                                                                                      \
     if (phase == 0)                                                                              \

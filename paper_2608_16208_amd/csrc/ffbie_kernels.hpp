@@ -28,7 +28,9 @@ struct CoeffArgs {
   int32_t* flag_count;
   int variant;               // FFBIE_KAPPA_SWAP or FFBIE_KAPPA_PAPER_CONV
   int64_t flag_tag;          // or-ed into queued pair indices (problem index << 40 in a batch)
-  int radix;                 // FFT stages: 2 (radix-2 Stockham) or 4 (radix-4, one radix-2 stage if needed)
+  int radix;                 // main-pass FFT stages: 2 (radix-2 Stockham), 4 (radix-4, one radix-2
+                             // stage if needed) or 0 (radix 4 for NF >= 256, else 2); refine
+                             // passes use radix 2
 };
 
 // Default pairs per wavefront and work item of the batched launch.
@@ -51,6 +53,7 @@ struct BatchArgs {
   int tw_max;                // doubles reserved after it for FFT twiddles (0 if none)
   int tile;                  // pairs per work item (one wavefront)
   int prob_lo, prob_hi;      // refine pass: the class's problems
+  int radix;                 // main pass: FFT radix of the class (2 or 4)
 };
 
 // Per-wavefront LDS of the coefficient kernel, in doubles, with the spectral

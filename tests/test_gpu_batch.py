@@ -217,4 +217,4 @@ def test_tuning_validation(ctx):
     for bad in (dict(fft_radix=3), dict(pairs_per_item=0), dict(waves_per_block=3)):
         with pytest.raises(ffbie.FfbieError):
             ctx.set_tuning(**bad)
-    assert ctx.get_tuning()["fft_radix"] in (2, 4)
+    assert ctx.get_tuning()["fft_radix"] in (0, 2, 4)
