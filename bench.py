@@ -100,7 +100,7 @@ def _timed(torch, fn):
     return out, time.perf_counter() - t0
 
 
-def time_to_field_error(ctx, cfg, torch, np, ffbie, target=1e-8):
+def time_to_field_error(ctx, cfg, torch, np, ffbie, target=1e-8, learned_systems=4):
     """Time to a field within `target` (relative l2 over 64 far points) of the
     plain FP64 LU field of the same discretised system: assembly + solve +
     field evaluation, for LU64 (the reference itself), LU32 + FP64 iterative
@@ -135,13 +135,81 @@ def time_to_field_error(ctx, cfg, torch, np, ffbie, target=1e-8):
             out["lu32_ir64"] = {"s": t_asm + t + t_f, "solve_s": t, "refinement_steps": it,
                                 "field_error": e, "rel_residual": info["rel_residual"]}
             break
-    for tol in (1e-7, 3e-8, 1e-8, 3e-9, 1e-9, 1e-10):
-        (phi, info), t = _timed(torch, lambda: ctx.solve(S, g, method=ffbie.SOLVE_GMRES,
-                                                        tol=tol, max_iter=3000))
-        e = err(phi)
-        if e <= target or tol == 1e-10:
-            out["gmres"] = {"s": t_asm + t + t_f, "solve_s": t, "iterations": info["iterations"],
-                            "residual_tol": tol, "field_error": e}
+    for name, method in (("gmres", ffbie.SOLVE_GMRES), ("gmres_blockjacobi", ffbie.SOLVE_GMRES_BLOCKJACOBI),
+                         ("gmres_lu32", ffbie.SOLVE_GMRES_LU32)):
+        for tol in (1e-7, 3e-8, 1e-8, 3e-9, 1e-9, 1e-10):
+            (phi, info), t = _timed(torch, lambda: ctx.solve(S, g, method=method, tol=tol, max_iter=3000))
+            e = err(phi)
+            if e <= target or tol == 1e-10:
+                out[name] = {"s": t_asm + t + t_f, "solve_s": t, "iterations": info["iterations"],
+                             "residual_tol": tol, "field_error": e}
+                break
+    if learned_systems > 0:
+        # the learned form: a network trained (untimed) by the library's own kernels on the
+        # mode-block-Jacobi corrections of star surfaces, then flexible GMRES with it,
+        # falling back to plain GMRES (timed together)
+        import workloads
+        from paper_2608_16208_amd import learned
+        ctx.mlp_init(7)
+
+        def mild(i):
+            r = np.random.default_rng(6000 + i)
+            return dict(amp=workloads.star_amplitudes(4, 4, 0.04, r), k=float(r.uniform(2.0, 6.0)))
+        X, T = learned.make_dataset(ctx, [mild(i) for i in range(learned_systems)], M=cfg["M"], n_rhs=8, seed=1)
+        learned.train(ctx, X, T, steps=400, batch=1024, lr=1e-3)
+        del X, T
+        ctx.set_problem(cfg["amp"], cfg["n_panels"], cfg["M"], cfg["k"])
+        for tol in (1e-8, 1e-9, 1e-10):
+            (phi, info), t = _timed(torch, lambda: ctx.solve(S, g, method=ffbie.SOLVE_FGMRES_MLP, tol=tol,
+                                                            max_iter=300))
+            e = err(phi)
+            if e <= target or tol == 1e-10:
+                out["fgmres_mlp"] = {"s": t_asm + t + t_f, "solve_s": t, "iterations": info["iterations"],
+                                     "fell_back": info["fell_back"], "residual_tol": tol, "field_error": e,
+                                     "trained_on": "%d star surfaces, amplitudes U(-0.04, 0.04), k in [2, 6]"
+                                                   % learned_systems}
+                break
+    del S
+    torch.cuda.empty_cache()
+    return out
+
+
+def config3_solve(ctx, torch, np, ffbie):
+    """Dense solves at the config-3 geometry (20 amplitudes, k = 20, 32 panels)
+    with M = 64 (N = 65536; the FP64 matrix is 69 GB): LU64 against LU32 + FP64
+    refinement, each to a field within 1e-8 of the LU64 field."""
+    import workloads
+    cfg = workloads.config(3)
+    ctx.set_near_rule(None)
+    ctx.set_problem(cfg["amp"], cfg["n_panels"], 64, cfg["k"])
+    S, t_asm = _timed(torch, lambda: ctx.assemble())
+    g = ctx.rhs(ffbie.RHS_PLANE_WAVE, cfg["d"])
+    rng = np.random.default_rng(1)
+    d = rng.standard_normal((64, 3))
+    pts = torch.tensor(d / np.linalg.norm(d, axis=1)[:, None] * rng.uniform(3, 5, 64)[:, None])
+    W = S.clone()
+    (phi, _), t_lu = _timed(torch, lambda: ctx.solve(W, g, method=ffbie.SOLVE_LU64))
+    del W
+    torch.cuda.empty_cache()
+    u_ref = ctx.eval_field(pts, phi)
+    out = {"n_unknowns": int(S.shape[0]), "assembly_s": t_asm, "lu64_s": t_asm + t_lu, "lu64_solve_s": t_lu}
+    for it in range(1, 6):
+        (phi, info), t = _timed(torch, lambda: ctx.solve(S, g, method=ffbie.SOLVE_LU32_IR64, tol=1e-15,
+                                                        max_iter=it))
+        u = ctx.eval_field(pts, phi)
+        e = float(((u - u_ref).abs().norm() / u_ref.abs().norm()).item())
+        if e <= 1e-8 or it == 5:
+            out["lu32_ir64"] = {"s": t_asm + t, "solve_s": t, "refinement_steps": it, "field_error": e,
+                                "rel_residual": info["rel_residual"]}
+            break
+    for tol in (1e-8, 1e-9, 1e-10, 1e-11):
+        (phi, info), t = _timed(torch, lambda: ctx.solve(S, g, method=ffbie.SOLVE_GMRES_LU32, tol=tol,
+                                                        max_iter=200))
+        u = ctx.eval_field(pts, phi)
+        e = float(((u - u_ref).abs().norm() / u_ref.abs().norm()).item())
+        if e <= 1e-8 or tol == 1e-11:
+            out["gmres_lu32"] = {"s": t_asm + t, "solve_s": t, "iterations": info["iterations"],
+                                 "residual_tol": tol, "field_error": e}
             break
     del S
     torch.cuda.empty_cache()
@@ -255,6 +323,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-second-variant", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision coefficient run")
+    ap.add_argument("--config3-solve", action="store_true",
+                    help="also time LU64 against LU32 + IR64 at the config-3 geometry, N = 65536")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched many-surface measurement")
     ap.add_argument("--no-solve", action="store_true",
@@ -408,6 +478,8 @@ def main():
     if not args.no_solve:
         result["time_to_1e-8_field_error"] = time_to_field_error(ctx, cfg, torch, np, ffbie)
         result["near_set"] = near_set_rate(ctx, cfg, torch)
+    if args.config3_solve:
+        result["config3_geometry_solve"] = config3_solve(ctx, torch, np, ffbie)
     if not args.no_batch:
         result["batch_64_surfaces"] = batch_rate(ctx, torch)
     if not args.no_cpu_baseline:

@@ -386,10 +386,16 @@ ffbie_status ffbie_eval_field(ffbie_ctx *ctx, int64_t n_pts, const double *d_pts
  *                          the inverses of the diagonal azimuthal-mode blocks of S
  *                          (see ffbie_blockjacobi_setup), built inside the call;
  *                          phi_0 = P(g).  Needs 16 n_panels <= 512.
+ *   FFBIE_SOLVE_GMRES_LU32 GMRES (restart 100) in complex128 right-preconditioned
+ *                          by the LU factors of a complex64 copy of S
+ *                          (workspace N*N*8 bytes): the GMRES form of mixed-
+ *                          precision iterative refinement, which still converges
+ *                          when the refinement of FFBIE_SOLVE_LU32_IR64 stalls
+ *                          (condition number near 1 / complex64 unit roundoff).
  * Returns FFBIE_ESINGULAR on an exactly zero pivot, FFBIE_WNOTCONV if an
  * iterative method did not reach tol (phi holds the last iterate). */
 enum { FFBIE_SOLVE_LU64 = 0, FFBIE_SOLVE_LU32_IR64 = 1, FFBIE_SOLVE_GMRES = 2,
-       FFBIE_SOLVE_FGMRES_MLP = 3, FFBIE_SOLVE_GMRES_BLOCKJACOBI = 4 };
+       FFBIE_SOLVE_FGMRES_MLP = 3, FFBIE_SOLVE_GMRES_BLOCKJACOBI = 4, FFBIE_SOLVE_GMRES_LU32 = 5 };
 typedef struct {
   int iterations;
   int converged;

@@ -1138,7 +1138,7 @@ ffbie_status ensure_solve_ws(ffbie_ctx* c, int64_t N, int method) {
       return fail(c, FFBIE_ENOMEM, "ffbie_solve: workspace allocation failed");
     c->solve_n = N;
   }
-  if (method == FFBIE_SOLVE_LU32_IR64 && c->s32_n != N) {
+  if ((method == FFBIE_SOLVE_LU32_IR64 || method == FFBIE_SOLVE_GMRES_LU32) && c->s32_n != N) {
     if (c->d_s32) hipFree(c->d_s32);
     c->d_s32 = nullptr;
     c->s32_n = 0;
@@ -1146,8 +1146,8 @@ ffbie_status ensure_solve_ws(ffbie_ctx* c, int64_t N, int method) {
       return fail(c, FFBIE_ENOMEM, "ffbie_solve: complex64 factor allocation failed");
     c->s32_n = N;
   }
-  if ((method == FFBIE_SOLVE_FGMRES_MLP || method == FFBIE_SOLVE_GMRES_BLOCKJACOBI) &&
-      c->zbasis_n != N) {
+  if ((method == FFBIE_SOLVE_FGMRES_MLP || method == FFBIE_SOLVE_GMRES_BLOCKJACOBI ||
+       method == FFBIE_SOLVE_GMRES_LU32) && c->zbasis_n != N) {
     if (c->d_zbasis) (void)hipFree(c->d_zbasis);
     c->d_zbasis = nullptr;
     c->zbasis_n = 0;
@@ -1156,7 +1156,7 @@ ffbie_status ensure_solve_ws(ffbie_ctx* c, int64_t N, int method) {
     c->zbasis_n = N;
   }
   if ((method == FFBIE_SOLVE_GMRES || method == FFBIE_SOLVE_FGMRES_MLP ||
-       method == FFBIE_SOLVE_GMRES_BLOCKJACOBI) && c->krylov_n != N) {
+       method == FFBIE_SOLVE_GMRES_BLOCKJACOBI || method == FFBIE_SOLVE_GMRES_LU32) && c->krylov_n != N) {
     if (c->d_krylov) hipFree(c->d_krylov);
     c->d_krylov = nullptr;
     c->krylov_n = 0;
@@ -1207,7 +1207,8 @@ ffbie_status ffbie_solve(ffbie_ctx* c, int method, void* d_S, int64_t ld, const 
   if (!d_S || !d_g || !d_phi || ld < N || d_g == d_phi)
     return fail(c, FFBIE_EINVAL, "ffbie_solve: NULL or aliased buffer, or ld < N");
   if (method != FFBIE_SOLVE_LU64 && method != FFBIE_SOLVE_LU32_IR64 && method != FFBIE_SOLVE_GMRES &&
-      method != FFBIE_SOLVE_FGMRES_MLP && method != FFBIE_SOLVE_GMRES_BLOCKJACOBI)
+      method != FFBIE_SOLVE_FGMRES_MLP && method != FFBIE_SOLVE_GMRES_BLOCKJACOBI &&
+      method != FFBIE_SOLVE_GMRES_LU32)
     return fail(c, FFBIE_EINVAL, "ffbie_solve: unknown method");
   if (method == FFBIE_SOLVE_GMRES_BLOCKJACOBI && 16 * c->n_panels > 512)
     return fail(c, FFBIE_EINVAL, "ffbie_solve: block-Jacobi needs 16 n_panels <= 512");
@@ -1235,6 +1236,8 @@ ffbie_status ffbie_solve(ffbie_ctx* c, int method, void* d_S, int64_t ld, const 
     r = lu32_ir64(sc, S, ld, N, g, phi, tol, max_iter, &iters, &rel);
   } else if (method == FFBIE_SOLVE_GMRES) {
     r = gmres64(sc, S, ld, N, g, phi, tol, max_iter, kRestart, &iters, &rel);
+  } else if (method == FFBIE_SOLVE_GMRES_LU32) {
+    r = gmres_lu32(sc, S, ld, N, g, phi, tol, max_iter, kRestart, &iters, &rel);
   } else if (method == FFBIE_SOLVE_FGMRES_MLP) {
     Precond P{mlp_apply, c};
     r = fgmres64(sc, S, ld, N, g, phi, tol, max_iter, kRestart, P, &iters, &rel, &fell_back);

@@ -43,6 +43,10 @@ SolveResult lu32_ir64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const 
                       double tol, int max_iter, int* iters, double* rel_res);
 SolveResult gmres64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cplx* g, cplx* x,
                     double tol, int max_iter, int restart, int* iters, double* rel_res);
+// GMRES in complex128 right-preconditioned by the LU factors of a complex64 copy
+// of S (GMRES-based iterative refinement)
+SolveResult gmres_lu32(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cplx* g, cplx* x,
+                       double tol, int max_iter, int restart, int* iters, double* rel_res);
 SolveResult fgmres64(SolveCtx& sc, const cplx* S, int64_t ld, int64_t N, const cplx* g, cplx* x,
                      double tol, int max_iter, int restart, const Precond& P, int* iters,
                      double* rel_res, bool* fell_back);

@@ -36,7 +36,7 @@ def _random_system(n, seed):
 
 
 @pytest.mark.parametrize("n_panels", [1, 3])
-@pytest.mark.parametrize("method", [0, 1, 2])
+@pytest.mark.parametrize("method", [0, 1, 2, 5])
 def test_solvers_match_lapack_on_random_systems(ctx, n_panels, method):
     ctx.set_problem(None, n_panels, 16, 1.0)
     N, _ = ctx.query()
@@ -100,7 +100,7 @@ def test_sphere_lu64_field_matches_mie(ctx, sphere):
     assert err <= 1e-9, err              # discretisation error, measured 2.1e-10
 
 
-@pytest.mark.parametrize("method", [1, 2])
+@pytest.mark.parametrize("method", [1, 2, 5])
 def test_sphere_iterative_field_matches_lu64(ctx, sphere, method):
     cfg, S, g, pts = sphere
     phi_it, info = ctx.solve(S, g, method=method, tol=1e-12, max_iter=300)
@@ -130,3 +130,30 @@ def test_green_identity_star(ctx):
     ref = osolve.point_source(cfg["k"], pts, rs)
     err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
     assert err <= 1e-6, err
+
+
+def test_gmres_lu32_converges_where_refinement_stalls(ctx):
+    """A system with condition number 3e7 (singular values spread
+    geometrically, random unitary factors; 3e7 x the complex64 unit roundoff is
+    about 2): refinement with complex64 LU factors diverges, GMRES
+    preconditioned by the same factors reaches 1e-8 (the attainable FP64
+    residual of this system is a few 1e-9, about u_64 times the condition
+    number)."""
+    import paper_2608_16208_amd as ffbie
+    ctx.set_problem(None, 1, 16, 1.0)
+    N, _ = ctx.query()
+    rng = np.random.default_rng(21)
+    Q1, _ = np.linalg.qr(rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)))
+    A = (Q1 * np.logspace(0, -np.log10(3e7), N)) @ Q2
+    g = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    ref = osolve.lu_solve(A, g)
+    S = torch.tensor(A, device=ctx.device)
+    _, ir = ctx.solve(S, torch.tensor(g), method=ffbie.SOLVE_LU32_IR64, tol=1e-8, max_iter=30)
+    phi, gm = ctx.solve(S, torch.tensor(g), method=ffbie.SOLVE_GMRES_LU32, tol=1e-8, max_iter=200)
+    print("cond 3e7: LU32 refinement rel. residual %.1e after %d steps; GMRES-LU32 %d iterations"
+          % (ir["rel_residual"], ir["iterations"], gm["iterations"]))
+    assert not ir["converged"]
+    assert gm["converged"] and gm["rel_residual"] <= 1e-8, gm
+    x = phi.cpu().numpy()
+    assert np.linalg.norm(A @ x - g) <= 2e-8 * np.linalg.norm(g)
