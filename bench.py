@@ -440,6 +440,16 @@ def main():
         "time_to_1e-8_field_error": None,
         "wall_s_timed": wall,
     }
+    # <rho^-1>_l, l = 0..L, emitted beside the kappa table (the full-layout launch)
+    rho = torch.empty((n, M + M0 + 1), dtype=torch.complex128, device=dev)
+    ctx.set_problem(cfg["amp"], cfg["n_panels"], M, cfg["k"], M0=M0, variant=0)
+    ctx.enable_timing(True)
+    ctx.kernel_coeffs(tt, jj, tss, kappa=kappa, rhoinv_out=rho, status=True)
+    (_, dt_r) = _timed(torch, lambda: ctx.kernel_coeffs(tt, jj, tss, kappa=kappa, rhoinv_out=rho, status=True))
+    result["with_rhoinv"] = {"ms_per_call": 1e3 * dt_r, "rhoinv_coeffs_per_s": n * (M + M0 + 1) / dt_r,
+                             "pair_modes_per_s": n * 2 * M / dt_r,
+                             "coeff_main_ms": float(ctx.timing()[1])}
+    del rho
     if not args.no_second_variant:
         other = 1 - args.variant
         ms2, _, per2, _ = run_variant(other, max(1, args.steps // 2), 1)

@@ -198,7 +198,7 @@ class Context:
         self.M, self.M0 = int(M), int(M if M0 is None else M0)
 
     def kernel_coeffs(self, t, az, ts, rhoinv=False, root=False, status=True, kappa=None,
-                      mixed=False):
+                      mixed=False, rhoinv_out=None):
         """kappa [n, 2M] complex128 (n = -M+1..M); optional <rho^-1> [n, M+M0+1],
         root [n, 2] (a - theta_j, b) and per-pair status [n] int32.  With
         mixed=True the FP32 spectral-stage path runs and kappa / <rho^-1> are
@@ -217,7 +217,13 @@ class Context:
                                   or not kappa.is_contiguous()):
             raise FfbieError("kappa must be a contiguous [n, 2M] %s tensor" % cdt)
         out["kappa"] = kappa if kappa is not None else torch.empty((n, 2 * self.M), dtype=cdt, device=dev)
-        out["rhoinv"] = torch.empty((n, self.M + self.M0 + 1), dtype=cdt, device=dev) if rhoinv else None
+        if rhoinv_out is not None:
+            if rhoinv_out.dtype != cdt or tuple(rhoinv_out.shape) != (n, self.M + self.M0 + 1) \
+                    or not rhoinv_out.is_contiguous():
+                raise FfbieError("rhoinv_out must be a contiguous [n, M+M0+1] %s tensor" % cdt)
+            out["rhoinv"] = rhoinv_out
+        else:
+            out["rhoinv"] = torch.empty((n, self.M + self.M0 + 1), dtype=cdt, device=dev) if rhoinv else None
         out["root"] = torch.empty((n, 2), dtype=torch.float64, device=dev) if root else None
         out["status"] = torch.empty((n,), dtype=torch.int32, device=dev) if status else None
         fn = self.lib.ffbie_kernel_coeffs_mixed if mixed else self.lib.ffbie_kernel_coeffs
