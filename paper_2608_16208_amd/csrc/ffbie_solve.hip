@@ -48,17 +48,39 @@ __device__ __forceinline__ C2<R> csub(C2<R> a, C2<R> b) {
 }
 
 // ---------------------------------------------------------------------------
-// pivot search, interchange and scaling of one column of A (one workgroup)
+// Unblocked LU of a panel of at most kPanel columns of A (the leaves of the
+// recursive factorisation), two launches per column k:
+//   panel_search: the rows r0+k .. r0+m-1 of column c0+k are split into nb
+//     chunks of `chunk` rows, one per workgroup; each writes the largest
+//     |Re| + |Im| of its chunk (first index on ties), that row index and the
+//     row's values on the panel's columns to part[b]; workgroup 0 also saves
+//     row r0+k of the panel in part[nb];
+//   panel_apply: every workgroup reduces part[0..nb) to the pivot row p (the
+//     same result in each) and then updates only its own rows: the interchange
+//     of rows r0+k and p on the panel's columns, the scaling of column k below
+//     the pivot and the rank-1 update of the panel's columns k+1.. .  Rows p
+//     and r0+k come from part, so no workgroup reads a row another one writes.
 // ---------------------------------------------------------------------------
+constexpr int kPanel = 4;
+
 template <typename R>
-__global__ __launch_bounds__(1024) void pivot_kernel(C2<R>* S, int64_t ld, int64_t r0, int64_t m,
-                                                     int64_t c, int64_t* ipiv, int* info) {
-  __shared__ R best[1024];
-  __shared__ int64_t where[1024];
+struct PanelPart {
+  R val;
+  int64_t idx;
+  C2<R> row[kPanel];
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void panel_search_kernel(const C2<R>* S, int64_t ld, int64_t r0,
+                                                           int64_t m, int64_t c0, int nc, int k,
+                                                           int64_t chunk, PanelPart<R>* part, int nb) {
+  __shared__ R best[256];
+  __shared__ int64_t where[256];
+  const C2<R>* col = S + (c0 + k) * ld;
+  const int64_t beg = r0 + k + blockIdx.x * chunk, end = min(r0 + m, beg + chunk);
   R b = -1;
-  int64_t w = r0;
-  const C2<R>* col = S + c * ld;                      // column c of A = S^T
-  for (int64_t r = r0 + threadIdx.x; r < r0 + m; r += blockDim.x) {
+  int64_t w = beg;
+  for (int64_t r = beg + threadIdx.x; r < end; r += blockDim.x) {
     const C2<R> v = col[r];
     const R a = fabs(v.re) + fabs(v.im);
     if (a > b) {
@@ -80,24 +102,97 @@ __global__ __launch_bounds__(1024) void pivot_kernel(C2<R>* S, int64_t ld, int64
     }
     __syncthreads();
   }
-  const int64_t p = where[0];
-  const bool zero = !(best[0] > 0);
+  // an empty chunk keeps val = -1 and reads no row
+  if ((int)threadIdx.x < nc) {
+    const int j = threadIdx.x;
+    if (best[0] >= 0) part[blockIdx.x].row[j] = S[(c0 + j) * ld + where[0]];
+    if (blockIdx.x == 0) part[nb].row[j] = S[(c0 + j) * ld + r0 + k];
+  }
   if (threadIdx.x == 0) {
-    ipiv[c] = p;
-    if (zero && *info == 0) *info = (int)(c + 1);
-    if (p != r0) {
-      const C2<R> t = S[c * ld + r0];
-      S[c * ld + r0] = S[c * ld + p];
-      S[c * ld + p] = t;
+    part[blockIdx.x].val = best[0];
+    part[blockIdx.x].idx = where[0];
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void panel_apply_kernel(C2<R>* S, int64_t ld, int64_t r0, int64_t m,
+                                                          int64_t c0, int nc, int k, int64_t chunk,
+                                                          const PanelPart<R>* part, int nb, int64_t* ipiv,
+                                                          int* info) {
+  __shared__ R best[256];
+  __shared__ int where[256];
+  __shared__ C2<R> prow[kPanel], krow[kPanel];
+  R b = -2;
+  int w = 0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    const R o = part[i].val;
+    if (o > b) {               // chunks are in row order: the first chunk wins ties
+      b = o;
+      w = i;
     }
   }
+  best[threadIdx.x] = b;
+  where[threadIdx.x] = w;
   __syncthreads();
-  if (zero) return;
-  C2<R>* colw = S + c * ld;
-  const C2<R> piv = colw[r0];
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      const R o = best[threadIdx.x + s];
+      const int ow = where[threadIdx.x + s];
+      if (o > best[threadIdx.x] || (o == best[threadIdx.x] && ow < where[threadIdx.x])) {
+        best[threadIdx.x] = o;
+        where[threadIdx.x] = ow;
+      }
+    }
+    __syncthreads();
+  }
+  const int wb = where[0];
+  const int64_t p = part[wb].idx;
+  const bool zero = !(part[wb].val > 0);
+  if ((int)threadIdx.x < nc) {
+    prow[threadIdx.x] = part[wb].row[threadIdx.x];
+    krow[threadIdx.x] = part[nb].row[threadIdx.x];
+  }
+  __syncthreads();
+  const int64_t rk = r0 + k;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ipiv[c0 + k] = p;
+    if (zero && *info == 0) *info = (int)(c0 + k + 1);
+  }
+  if (zero) return;                          // an all-zero column: no interchange, no update
+  const C2<R> piv = prow[k];
   const R den = piv.re * piv.re + piv.im * piv.im;
   const C2<R> inv = {piv.re / den, -piv.im / den};
-  for (int64_t r = r0 + 1 + threadIdx.x; r < r0 + m; r += blockDim.x) colw[r] = cmul(colw[r], inv);
+  const int64_t beg = rk + blockIdx.x * chunk, end = min(r0 + m, beg + chunk);
+  for (int64_t r = beg + threadIdx.x; r < end; r += blockDim.x) {
+    if (r == rk) {
+#pragma unroll
+      for (int j = 0; j < kPanel; ++j)
+        if (j < nc) S[(c0 + j) * ld + r] = prow[j];
+      continue;
+    }
+    const bool is_p = r == p;
+    // the row after the interchange: row p takes old row r0+k (from part)
+    C2<R> v[kPanel];
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j)
+      if (j >= k && j < nc) v[j] = is_p ? krow[j] : S[(c0 + j) * ld + r];
+    C2<R> l = {0, 0};
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j)
+      if (j == k) l = cmul(v[j], inv);
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j) {
+      if (j >= nc) break;
+      if (j < k) {
+        if (is_p) S[(c0 + j) * ld + r] = krow[j];
+      } else if (j == k) {
+        S[(c0 + j) * ld + r] = l;
+      } else {
+        const C2<R> u = cmul(l, prow[j]);
+        S[(c0 + j) * ld + r] = C2<R>{v[j].re - u.re, v[j].im - u.im};
+      }
+    }
+  }
 }
 
 // Row interchanges k0..k1-1 (in order) of A on its columns [c0, c1): one
@@ -323,6 +418,10 @@ __global__ void combine_kernel(const C2<double>* V, int64_t N, int nv, const C2<
 // ---------------------------------------------------------------------------
 inline dim3 grid1(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
 
+// Panel steps: up to kPivotBlocks workgroups of >= kPivotRows rows each.
+constexpr int kPivotBlocks = 128;
+constexpr int64_t kPivotRows = 1024;
+
 // A(rC.., cC..) (m x n) -= A(rA.., cA..) (m x k) * A(rB.., cB..) (k x n), with
 // A(r, c) = S[c*ld + r] the column-major view.
 rocblas_status gemm_sub(rocblas_handle h, C2<double>* S, int64_t ld, int64_t r_a, int64_t c_a,
@@ -378,9 +477,18 @@ template <typename R>
 void getrf_rec(SolveCtx& sc, C2<R>* S, int64_t ld, int64_t r0, int64_t m, int64_t c0, int64_t n,
                int64_t* ipiv, int* info, Err& e) {
   if (!e.ok()) return;
-  if (n == 1) {
-    hipLaunchKernelGGL(pivot_kernel<R>, dim3(1), dim3(1024), 0, sc.stream, S, ld, r0, m, c0, ipiv,
-                       info);
+  if (n <= kPanel) {
+    auto* part = reinterpret_cast<PanelPart<R>*>(sc.partial);
+    for (int k = 0; k < (int)n; ++k) {
+      const int64_t rows = m - k;                      // rows r0+k .. r0+m-1
+      if (rows <= 0) break;
+      const int nb = (int)std::min<int64_t>(kPivotBlocks, (rows + kPivotRows - 1) / kPivotRows);
+      const int64_t chunk = (rows + nb - 1) / nb;
+      hipLaunchKernelGGL(panel_search_kernel<R>, dim3(nb), dim3(256), 0, sc.stream, S, ld, r0, m, c0,
+                         (int)n, k, chunk, part, nb);
+      hipLaunchKernelGGL(panel_apply_kernel<R>, dim3(nb), dim3(256), 0, sc.stream, S, ld, r0, m, c0,
+                         (int)n, k, chunk, part, nb, ipiv, info);
+    }
     e.hip = hipGetLastError();
     return;
   }
