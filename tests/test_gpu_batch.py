@@ -218,3 +218,46 @@ def test_tuning_validation(ctx):
         with pytest.raises(ffbie.FfbieError):
             ctx.set_tuning(**bad)
     assert ctx.get_tuning()["fft_radix"] in (0, 2, 4)
+
+
+def test_batch_surfaces_full_near_sets_as_benchmarked(ctx):
+    """The benchmarked batch configuration: the full near sets of eight of the
+    64 batch surfaces (every M class, k up to 25) through an autotuned batch
+    plan captured in a graph.  Every row is compared with single-problem calls
+    (1e-12 of the row's largest value; different FFT radix or work shape only
+    change rounding), and sampled rows whose smooth factor is resolved (no
+    FFBIE_PAIR_UNRESOLVED flag: small M with large k is not) with the oracle
+    (1e-10)."""
+    surfs, items = [], []
+    for s in (0, 1, 2, 3, 5, 8, 13, 21):
+        c = workloads.batch_surface(s)
+        ctx.set_problem(c["amp"], c["n_panels"], c["M"], c["k"])
+        t, az, ts = ctx.near_pairs()
+        surfs.append(dict(c, t=t, az=az, ts=ts))
+        items.append(dict(amp=c["amp"], M=c["M"], k=c["k"], t=t, az=az, ts=ts))
+    assert len({c["M"] for c in surfs}) >= 3
+    plan = ctx.batch_plan(items, autotune=True, graph=True)
+    plan.execute()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(17)
+    worst, n_oracle = 0.0, 0
+    for c, o in zip(surfs, plan.outs):
+        ctx.set_problem(c["amp"], c["n_panels"], c["M"], c["k"])
+        one = ctx.kernel_coeffs(c["t"], c["az"], c["ts"])
+        k1, kb = one["kappa"], o["kappa"]
+        e = (kb - k1).abs().amax(dim=1) / k1.abs().amax(dim=1)
+        worst = max(worst, float(e.max().item()))
+        assert torch.equal(o["status"] & 0xff, one["status"] & 0xff)
+        resolved = np.where((o["status"].cpu().numpy() & 8) == 0)[0]
+        if resolved.size:
+            idx = np.sort(rng.choice(resolved, min(6, resolved.size), replace=False))
+            t, j, ts = (x.cpu().numpy()[idx] for x in (c["t"], c["az"], c["ts"]))
+            _, ko, _ = ocoeffs.pairs_coeffs(c["amp"], c["k"], c["M"], 2 * c["M"], t, j, ts, processes=8)
+            eo = np.linalg.norm(kb.cpu().numpy()[idx] - ko, axis=1) / np.linalg.norm(ko, axis=1)
+            assert eo.max() <= 1e-10, (c["name"], eo.max())
+            n_oracle += 1
+        del one
+    print("batch surfaces: worst row vs single calls %.2e; %d surfaces also vs the oracle" % (worst, n_oracle))
+    assert worst <= 1e-12, worst
+    assert n_oracle >= 4
+    plan.close()
