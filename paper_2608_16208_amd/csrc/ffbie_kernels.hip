@@ -92,9 +92,9 @@ __global__ __launch_bounds__(256) void ffbie_root_kernel_t(
 // (the three-term recurrence of the half-integer Legendre functions of
 // eq. (3.27)) starts at N >= (m_max + 37/b)/2 and is normalised by A_0.
 // Either recurrence is a product of 2x2 transfer matrices: each lane forms the
-// product over its own segment of indices, a Hillis-Steele scan across the 64
-// lanes composes the segments, and each lane then replays its segment from
-// the state entering it.
+// product over its own segment of indices, a scan across the 64 lanes (DPP
+// row shifts and row broadcasts) composes the segments, and each lane then
+// replays its segment from the state entering it.
 // ===========================================================================
 __device__ __forceinline__ void mat_mul(double a00, double a01, double a10, double a11, double b00,
                                         double b01, double b10, double b11, double* c00,
@@ -103,6 +103,44 @@ __device__ __forceinline__ void mat_mul(double a00, double a01, double a10, doub
   *c01 = fma(a00, b01, a01 * b11);
   *c10 = fma(a10, b00, a11 * b10);
   *c11 = fma(a10, b01, a11 * b11);
+}
+
+// A double moved across lanes by a DPP pattern (two 32-bit moves); lanes the
+// pattern does not write keep `v`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)u, (int)u, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(u >> 32), (int)(u >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// One step of the lane scan: lanes with `take` set become own x (value from
+// the lane the pattern names).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void mat_scan_step(bool take, double& e00, double& e01, double& e10,
+                                              double& e11) {
+  const double o00 = dpp_f64<CTRL, ROW_MASK>(e00), o01 = dpp_f64<CTRL, ROW_MASK>(e01);
+  const double o10 = dpp_f64<CTRL, ROW_MASK>(e10), o11 = dpp_f64<CTRL, ROW_MASK>(e11);
+  if (take) {
+    double n00, n01, n10, n11;
+    mat_mul(e00, e01, e10, e11, o00, o01, o10, o11, &n00, &n01, &n10, &n11);
+    e00 = n00; e01 = n01; e10 = n10; e11 = n11;
+  }
+}
+
+// Inclusive scan of 2x2 matrices over the 64 lanes in lane order,
+// E_l = X_l X_{l-1} ... X_0, with DPP moves instead of LDS permutes: shifts by
+// 1, 2, 4, 8 inside each row of 16 lanes, then the last lane of row 0 (2) into
+// row 1 (3) and the last lane of row 1 into rows 2 and 3.
+__device__ __forceinline__ void mat_scan_lanes(double& e00, double& e01, double& e10, double& e11) {
+  const int lane = threadIdx.x & 63, r = lane & 15, row = lane >> 4;
+  mat_scan_step<0x111, 0xf>(r >= 1, e00, e01, e10, e11);      // row_shr:1
+  mat_scan_step<0x112, 0xf>(r >= 2, e00, e01, e10, e11);      // row_shr:2
+  mat_scan_step<0x114, 0xf>(r >= 4, e00, e01, e10, e11);      // row_shr:4
+  mat_scan_step<0x118, 0xf>(r >= 8, e00, e01, e10, e11);      // row_shr:8
+  mat_scan_step<0x142, 0xa>(row == 1 || row == 3, e00, e01, e10, e11);   // row_bcast:15
+  mat_scan_step<0x143, 0xc>(row >= 2, e00, e01, e10, e11);    // row_bcast:31
 }
 
 // A is stored as R (double, or float on the mixed-precision path); the
@@ -140,15 +178,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double A0, double
       e00 = n00; e01 = n01; e10 = n10; e11 = n11;
     }
     // inclusive prefix scan: E_l = Phi_l ... Phi_0
-    for (int d = 1; d < 64; d <<= 1) {
-      const double o00 = __shfl_up(e00, d), o01 = __shfl_up(e01, d);
-      const double o10 = __shfl_up(e10, d), o11 = __shfl_up(e11, d);
-      if (lane >= d) {
-        double n00, n01, n10, n11;
-        mat_mul(e00, e01, e10, e11, o00, o01, o10, o11, &n00, &n01, &n10, &n11);
-        e00 = n00; e01 = n01; e10 = n10; e11 = n11;
-      }
-    }
+    mat_scan_lanes(e00, e01, e10, e11);
     double x00 = __shfl_up(e00, 1), x01 = __shfl_up(e01, 1);
     double x10 = __shfl_up(e10, 1), x11 = __shfl_up(e11, 1);
     if (lane == 0) { x00 = 1; x01 = 0; x10 = 0; x11 = 1; }
@@ -184,9 +214,12 @@ __device__ __forceinline__ void singular_factor_wave(double b, double A0, double
   }
   const double ch4 = 4.0 * cosh(b);
   const int S = (N + 63) / 64;
-  const int top = lane * S + S;     // segment: transitions m = top .. lane*S + 1
+  // segment g = 63 - lane (the highest indices in lane 0), so that the suffix
+  // products over segments are prefix products in lane order
+  const int seg = 63 - lane;
+  const int top = seg * S + S;      // segment: transitions m = top .. seg*S + 1
   double p00 = 1, p01 = 0, p10 = 0, p11 = 1;
-  for (int m = top; m > lane * S; --m) {
+  for (int m = top; m > seg * S; --m) {
     if (m > N) continue;
     const double r = rcp_int(2.0 * m - 1.0);
     const double al = ch4 * m * r, be = -(2.0 * m + 1.0) * r;
@@ -194,23 +227,15 @@ __device__ __forceinline__ void singular_factor_wave(double b, double A0, double
     mat_mul(al, be, 1.0, 0.0, p00, p01, p10, p11, &n00, &n01, &n10, &n11);
     p00 = n00; p01 = n01; p10 = n10; p11 = n11;
   }
-  // inclusive suffix scan: Q_l = P_l P_{l+1} ... P_63
-  for (int d = 1; d < 64; d <<= 1) {
-    const double o00 = __shfl_down(p00, d), o01 = __shfl_down(p01, d);
-    const double o10 = __shfl_down(p10, d), o11 = __shfl_down(p11, d);
-    if (lane + d < 64) {
-      double n00, n01, n10, n11;
-      mat_mul(p00, p01, p10, p11, o00, o01, o10, o11, &n00, &n01, &n10, &n11);
-      p00 = n00; p01 = n01; p10 = n10; p11 = n11;
-    }
-  }
-  double q00 = __shfl_down(p00, 1), q10 = __shfl_down(p10, 1);
-  if (lane == 63) { q00 = 1; q10 = 0; }
-  // state entering the segment: Q_{l+1} (y_s, 0)
+  // inclusive suffix scan over segments: Q_g = P_g P_{g+1} ... P_63
+  mat_scan_lanes(p00, p01, p10, p11);
+  double q00 = __shfl_up(p00, 1), q10 = __shfl_up(p10, 1);
+  if (lane == 0) { q00 = 1; q10 = 0; }
+  // state entering the segment: Q_{g+1} (y_s, 0)
   double y0 = q00 * kMillerStart, y1 = q10 * kMillerStart;   // (y_top, y_top+1)
   if constexpr (sizeof(R) == sizeof(double)) {
     // store the unnormalised values, then scale by A_0 / y_0 with y_0 as replayed
-    for (int m = top; m > lane * S; --m) {
+    for (int m = top; m > seg * S; --m) {
       if (m > N) continue;
       const double r = rcp_int(2.0 * m - 1.0);
       const double yn = (ch4 * m * y0 - (2.0 * m + 1.0) * y1) * r;
@@ -223,10 +248,10 @@ __device__ __forceinline__ void singular_factor_wave(double b, double A0, double
     wave_sync();
     for (int m = lane; m <= mtop; m += 64) A[m] = (m <= meff) ? A[m] * scale : 0.0;
   } else {
-    // the unnormalised values leave the float range: lane 0 holds the whole
+    // the unnormalised values leave the float range: lane 63 holds the whole
     // product Q_0, so y_0 = Q_0[0][0] y_N fixes the normalisation first
-    const double scale = A0 / (__shfl(p00, 0) * kMillerStart);
-    for (int m = top; m > lane * S; --m) {
+    const double scale = A0 / (__shfl(p00, 63) * kMillerStart);
+    for (int m = top; m > seg * S; --m) {
       if (m > N) continue;
       const double r = rcp_int(2.0 * m - 1.0);
       const double yn = (ch4 * m * y0 - (2.0 * m + 1.0) * y1) * r;
@@ -462,14 +487,25 @@ __device__ __forceinline__ void swap_convolution(const C* G, int p, const declty
   const C* Gp = G + p;           // Gp[j], j = -p..p
   for (int n = lane; n < split; n += 64) {
     const R An0 = A[n];
-    R accr = Gp[0].re * An0, acci = Gp[0].im * An0;
-#pragma unroll 4
-    for (int j = 1; j <= p; ++j) {
+    R accr = Gp[0].re * An0, acci = Gp[0].im * An0, accr2 = 0, acci2 = 0;
+    int j = 1;
+#pragma unroll 2
+    for (; j + 1 <= p; j += 2) {
+      const C g = Gp[j], g2 = Gp[j + 1];
+      const R lo = A[n - j], hi = A[n + j], lo2 = A[n - j - 1], hi2 = A[n + j + 1];
+      accr = fma(g.re, lo + hi, accr);
+      acci = fma(g.im, lo - hi, acci);
+      accr2 = fma(g2.re, lo2 + hi2, accr2);
+      acci2 = fma(g2.im, lo2 - hi2, acci2);
+    }
+    if (j <= p) {
       const C g = Gp[j];
       const R lo = A[n - j], hi = A[n + j];
       accr = fma(g.re, lo + hi, accr);
       acci = fma(g.im, lo - hi, acci);
     }
+    accr += accr2;
+    acci += acci2;
     const C c = SP::narrow(swap_phase(n, ur, Jq, tab, mask, quarter) * mk(accr, acci));
     out[n] = c;
     if (mirror) mirror[-n] = conj(c);
