@@ -357,21 +357,71 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Wave reductions by DPP moves (no LDS traffic): inclusive scans inside each
+// row of 16 lanes by shifts of 1, 2, 4, 8, then the last lane of row 0 (2)
+// into row 1 (3) and the last lane of row 1 into rows 2 and 3, so that lane 63
+// holds the reduction of all 64 lanes; it is then read as a uniform value.
+// `fill` is what lanes without a source contribute (0 for sums, the lane's
+// own value for maxima).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_i32(int fill, int src) {
+  return __builtin_amdgcn_update_dpp(fill, src, CTRL, ROW_MASK, 0xf, false);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64_fill(double fill, double src) {
+  const long long f = __double_as_longlong(fill), u = __double_as_longlong(src);
+  const int lo = dpp_i32<CTRL, ROW_MASK>((int)f, (int)u);
+  const int hi = dpp_i32<CTRL, ROW_MASK>((int)(f >> 32), (int)(u >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f32_fill(float fill, float src) {
+  return __int_as_float(dpp_i32<CTRL, ROW_MASK>(__float_as_int(fill), __float_as_int(src)));
+}
+__device__ __forceinline__ double lane63(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)u, 63), hi = __builtin_amdgcn_readlane((int)(u >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float lane63(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-  return v;
+  v += dpp_f64_fill<0x111, 0xf>(0.0, v);
+  v += dpp_f64_fill<0x112, 0xf>(0.0, v);
+  v += dpp_f64_fill<0x114, 0xf>(0.0, v);
+  v += dpp_f64_fill<0x118, 0xf>(0.0, v);
+  v += dpp_f64_fill<0x142, 0xa>(0.0, v);
+  v += dpp_f64_fill<0x143, 0xc>(0.0, v);
+  return lane63(v);
 }
 __device__ __forceinline__ double wave_max(double v) {
-  for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d));
-  return v;
+  v = fmax(v, dpp_f64_fill<0x111, 0xf>(v, v));
+  v = fmax(v, dpp_f64_fill<0x112, 0xf>(v, v));
+  v = fmax(v, dpp_f64_fill<0x114, 0xf>(v, v));
+  v = fmax(v, dpp_f64_fill<0x118, 0xf>(v, v));
+  v = fmax(v, dpp_f64_fill<0x142, 0xa>(v, v));
+  v = fmax(v, dpp_f64_fill<0x143, 0xc>(v, v));
+  return lane63(v);
 }
 __device__ __forceinline__ float wave_sum(float v) {
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-  return v;
+  v += dpp_f32_fill<0x111, 0xf>(0.0f, v);
+  v += dpp_f32_fill<0x112, 0xf>(0.0f, v);
+  v += dpp_f32_fill<0x114, 0xf>(0.0f, v);
+  v += dpp_f32_fill<0x118, 0xf>(0.0f, v);
+  v += dpp_f32_fill<0x142, 0xa>(0.0f, v);
+  v += dpp_f32_fill<0x143, 0xc>(0.0f, v);
+  return lane63(v);
 }
 __device__ __forceinline__ float wave_max(float v) {
-  for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d));
-  return v;
+  v = fmaxf(v, dpp_f32_fill<0x111, 0xf>(v, v));
+  v = fmaxf(v, dpp_f32_fill<0x112, 0xf>(v, v));
+  v = fmaxf(v, dpp_f32_fill<0x114, 0xf>(v, v));
+  v = fmaxf(v, dpp_f32_fill<0x118, 0xf>(v, v));
+  v = fmaxf(v, dpp_f32_fill<0x142, 0xa>(v, v));
+  v = fmaxf(v, dpp_f32_fill<0x143, 0xc>(v, v));
+  return lane63(v);
 }
 
 }  // namespace ffbie
