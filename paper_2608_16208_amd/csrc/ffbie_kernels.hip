@@ -179,9 +179,9 @@ __device__ __forceinline__ void singular_factor_wave(double b, double A0, double
     }
     // inclusive prefix scan: E_l = Phi_l ... Phi_0
     mat_scan_lanes(e00, e01, e10, e11);
-    double x00 = __shfl_up(e00, 1), x01 = __shfl_up(e01, 1);
-    double x10 = __shfl_up(e10, 1), x11 = __shfl_up(e11, 1);
-    if (lane == 0) { x00 = 1; x01 = 0; x10 = 0; x11 = 1; }
+    // exclusive: E_{l-1} by a DPP wave shift right by one lane, identity in lane 0
+    const double x00 = dpp_f64_fill<0x138, 0xf>(1.0, e00), x01 = dpp_f64_fill<0x138, 0xf>(0.0, e01);
+    const double x10 = dpp_f64_fill<0x138, 0xf>(0.0, e10), x11 = dpp_f64_fill<0x138, 0xf>(1.0, e11);
     const double w1D = D1, w1A = A0 + D1;
     double wD = fma(x00, w1D, x01 * w1A), wA = fma(x10, w1D, x11 * w1A);
     for (int s = 0; s < S; ++s) {
@@ -229,8 +229,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double A0, double
   }
   // inclusive suffix scan over segments: Q_g = P_g P_{g+1} ... P_63
   mat_scan_lanes(p00, p01, p10, p11);
-  double q00 = __shfl_up(p00, 1), q10 = __shfl_up(p10, 1);
-  if (lane == 0) { q00 = 1; q10 = 0; }
+  const double q00 = dpp_f64_fill<0x138, 0xf>(1.0, p00), q10 = dpp_f64_fill<0x138, 0xf>(0.0, p10);
   // state entering the segment: Q_{g+1} (y_s, 0)
   double y0 = q00 * kMillerStart, y1 = q10 * kMillerStart;   // (y_top, y_top+1)
   if constexpr (sizeof(R) == sizeof(double)) {
@@ -250,7 +249,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double A0, double
   } else {
     // the unnormalised values leave the float range: lane 63 holds the whole
     // product Q_0, so y_0 = Q_0[0][0] y_N fixes the normalisation first
-    const double scale = A0 / (__shfl(p00, 63) * kMillerStart);
+    const double scale = A0 / (lane63(p00) * kMillerStart);
     for (int m = top; m > seg * S; --m) {
       if (m > N) continue;
       const double r = rcp_int(2.0 * m - 1.0);
