@@ -378,6 +378,12 @@ template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_f32_fill(float fill, float src) {
   return __int_as_float(dpp_i32<CTRL, ROW_MASK>(__float_as_int(fill), __float_as_int(src)));
 }
+// The value of v in lane `l` (uniform l), as a uniform value.
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)u, l), hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 __device__ __forceinline__ double lane63(double v) {
   const long long u = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)u, 63), hi = __builtin_amdgcn_readlane((int)(u >> 32), 63);

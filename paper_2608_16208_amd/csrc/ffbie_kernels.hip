@@ -105,28 +105,17 @@ __device__ __forceinline__ void mat_mul(double a00, double a01, double a10, doub
   *c11 = fma(a10, b01, a11 * b11);
 }
 
-// A double moved across lanes by a DPP pattern (two 32-bit moves); lanes the
-// pattern does not write keep `v`.
+// One step of the lane scan: every lane multiplies its matrix on the right by
+// the one the DPP pattern brings from a lower lane; lanes that the pattern
+// gives no source (or whose row it does not write) receive the identity, so
+// no per-lane select is needed.
 template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp((int)u, (int)u, CTRL, ROW_MASK, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(u >> 32), (int)(u >> 32), CTRL, ROW_MASK, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-// One step of the lane scan: lanes with `take` set become own x (value from
-// the lane the pattern names).
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ void mat_scan_step(bool take, double& e00, double& e01, double& e10,
-                                              double& e11) {
-  const double o00 = dpp_f64<CTRL, ROW_MASK>(e00), o01 = dpp_f64<CTRL, ROW_MASK>(e01);
-  const double o10 = dpp_f64<CTRL, ROW_MASK>(e10), o11 = dpp_f64<CTRL, ROW_MASK>(e11);
-  if (take) {
-    double n00, n01, n10, n11;
-    mat_mul(e00, e01, e10, e11, o00, o01, o10, o11, &n00, &n01, &n10, &n11);
-    e00 = n00; e01 = n01; e10 = n10; e11 = n11;
-  }
+__device__ __forceinline__ void mat_scan_step(double& e00, double& e01, double& e10, double& e11) {
+  const double o00 = dpp_f64_fill<CTRL, ROW_MASK>(1.0, e00), o01 = dpp_f64_fill<CTRL, ROW_MASK>(0.0, e01);
+  const double o10 = dpp_f64_fill<CTRL, ROW_MASK>(0.0, e10), o11 = dpp_f64_fill<CTRL, ROW_MASK>(1.0, e11);
+  double n00, n01, n10, n11;
+  mat_mul(e00, e01, e10, e11, o00, o01, o10, o11, &n00, &n01, &n10, &n11);
+  e00 = n00; e01 = n01; e10 = n10; e11 = n11;
 }
 
 // Inclusive scan of 2x2 matrices over the 64 lanes in lane order,
@@ -134,20 +123,21 @@ __device__ __forceinline__ void mat_scan_step(bool take, double& e00, double& e0
 // 1, 2, 4, 8 inside each row of 16 lanes, then the last lane of row 0 (2) into
 // row 1 (3) and the last lane of row 1 into rows 2 and 3.
 __device__ __forceinline__ void mat_scan_lanes(double& e00, double& e01, double& e10, double& e11) {
-  const int lane = threadIdx.x & 63, r = lane & 15, row = lane >> 4;
-  mat_scan_step<0x111, 0xf>(r >= 1, e00, e01, e10, e11);      // row_shr:1
-  mat_scan_step<0x112, 0xf>(r >= 2, e00, e01, e10, e11);      // row_shr:2
-  mat_scan_step<0x114, 0xf>(r >= 4, e00, e01, e10, e11);      // row_shr:4
-  mat_scan_step<0x118, 0xf>(r >= 8, e00, e01, e10, e11);      // row_shr:8
-  mat_scan_step<0x142, 0xa>(row == 1 || row == 3, e00, e01, e10, e11);   // row_bcast:15
-  mat_scan_step<0x143, 0xc>(row >= 2, e00, e01, e10, e11);    // row_bcast:31
+  mat_scan_step<0x111, 0xf>(e00, e01, e10, e11);   // row_shr:1
+  mat_scan_step<0x112, 0xf>(e00, e01, e10, e11);   // row_shr:2
+  mat_scan_step<0x114, 0xf>(e00, e01, e10, e11);   // row_shr:4
+  mat_scan_step<0x118, 0xf>(e00, e01, e10, e11);   // row_shr:8
+  mat_scan_step<0x142, 0xa>(e00, e01, e10, e11);   // row_bcast:15 into rows 1 and 3
+  mat_scan_step<0x143, 0xc>(e00, e01, e10, e11);   // row_bcast:31 into rows 2 and 3
 }
 
 // A is stored as R (double, or float on the mixed-precision path); the
-// recurrences themselves always run in FP64.
+// recurrences themselves always run in FP64.  eb = e^{-b} and omq = 1 - e^{-b}
+// (from expm1) give the recurrence coefficients: 4 cosh b = 2 (1/eb + eb) and
+// 8 sinh^2(b/2) = 2 omq^2 / eb, the latter free of cancellation at small b.
 template <class R>
-__device__ __forceinline__ void singular_factor_wave(double b, double A0, double D1, int mtop,
-                                                     R* A) {
+__device__ __forceinline__ void singular_factor_wave(double b, double eb, double omq, double A0,
+                                                     double D1, int mtop, R* A) {
   const int lane = threadIdx.x & 63;
   if (!(b > 0) || !(A0 == A0)) {
     for (int m = lane; m <= mtop; m += 64) A[m] = (R)__builtin_nan("");
@@ -163,7 +153,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double A0, double
     // ---- forward: w_{m+1} = F_m w_m, w = (D, A),
     //      F_m = [[alpha, beta], [alpha, 1 + beta]], alpha = (2m-1)/(2m+1),
     //      beta = 8 m sinh^2(b/2)/(2m+1), for m = 1 .. mtop-1
-    const double sh = sinh(0.5 * b), s2 = 8.0 * sh * sh;
+    const double s2 = 2.0 * omq * omq / eb;
     const int cnt = mtop - 1;
     const int S = cnt > 0 ? (cnt + 63) / 64 : 1;
     const int m_first = 1 + lane * S;
@@ -212,7 +202,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double A0, double
       return;
     }
   }
-  const double ch4 = 4.0 * cosh(b);
+  const double ch4 = 2.0 * (1.0 / eb + eb);
   const int S = (N + 63) / 64;
   // segment g = 63 - lane (the highest indices in lane 0), so that the suffix
   // products over segments are prefix products in lane order
@@ -457,17 +447,13 @@ __device__ __forceinline__ int trunc_index_real(const C* X, int NF, decltype(C::
   return __builtin_amdgcn_readfirstlane(p);
 }
 
-// out_n = e^{-i n a} sum_{|j| <= p} G_j A_{|n-j|} for n = 0..nmax, with
-// e^{-i n a} = e^{-i n (theta_j + qu gstep)} e^{-i n ur} evaluated in FP64.
-// Outputs are spread over the lanes; when the count exceeds a multiple of 64
-// by a few, those last outputs are summed cooperatively (terms over lanes, then
-// a wave sum) instead of costing the whole wave another pass.
-__device__ __forceinline__ cplx swap_phase(int n, double ur, int Jq, const double* tab, int mask,
-                                           int quarter) {
-  double s1, c1;
-  sincos_bounded(n * ur, &s1, &c1);
-  return mk(tcos(tab, n * Jq, mask, quarter), -tsin(tab, n * Jq, mask)) * mk(c1, -s1);
-}
+// out_n = e^{-i n a} sum_{|j| <= p} G_j A_{|n-j|} for n = 0..nmax.  The phases
+// are FP64: ph holds e^{i n a} for n = lane and ph64 = e^{i 64 a}, so that
+// output n = lane + 64 i takes conj(ph ph64^i).  Outputs are spread over the
+// lanes; when the count exceeds a multiple of 64 by a few, those last outputs
+// are summed cooperatively (terms over lanes, then a wave sum) instead of
+// costing the whole wave another pass, with the phase read from the lane that
+// holds it.
 
 // G is Hermitian, G[p - j] = conj(G[p + j]), so the j and -j terms share G_j:
 //   sum_j G_j A_{|n-j|} = G_0 A_n + sum_{j >= 1} [Re G_j (A_{|n-j|} + A_{n+j})
@@ -475,8 +461,7 @@ __device__ __forceinline__ cplx swap_phase(int n, double ur, int Jq, const doubl
 // (the sum of eq. (3.25)).  A must be mirrored: A[-m] = A[m] for m <= p.
 template <class C>
 __device__ __forceinline__ void swap_convolution(const C* G, int p, const decltype(C::re)* A, int nmax,
-                                                 double ur, int Jq, const double* tab, int mask,
-                                                 int quarter, C* out, C* mirror, C* global_row) {
+                                                 cplx ph, cplx ph64, C* out, C* mirror, C* global_row) {
   using R = decltype(C::re);
   using SP = Spec<R>;
   const int lane = threadIdx.x & 63;
@@ -505,11 +490,14 @@ __device__ __forceinline__ void swap_convolution(const C* G, int p, const declty
     }
     accr += accr2;
     acci += acci2;
-    const C c = SP::narrow(swap_phase(n, ur, Jq, tab, mask, quarter) * mk(accr, acci));
+    const C c = SP::narrow(conj(ph) * mk(accr, acci));
     out[n] = c;
     if (mirror) mirror[-n] = conj(c);
     if (global_row) global_row[n] = c;
+    ph = ph * ph64;
   }
+  // split < cnt only when split is a multiple of 64: every lane ran split / 64
+  // passes, so lane t holds e^{i (split + t) a}
   for (int n = split; n < cnt; ++n) {
     R accr = 0, acci = 0;
     for (int jj = -p + lane; jj <= p; jj += 64) {
@@ -520,8 +508,9 @@ __device__ __forceinline__ void swap_convolution(const C* G, int p, const declty
     }
     accr = wave_sum(accr);
     acci = wave_sum(acci);
+    const cplx phn = mk(read_lane(ph.re, n - split), read_lane(ph.im, n - split));
     if (lane == 0) {
-      const C c = SP::narrow(swap_phase(n, ur, Jq, tab, mask, quarter) * mk(accr, acci));
+      const C c = SP::narrow(conj(phn) * mk(accr, acci));
       out[n] = c;
       if (mirror) mirror[-n] = conj(c);
       if (global_row) global_row[n] = c;
@@ -673,10 +662,18 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     C* GH = free1;
     C* Cn = free1 + (M0 - 1);
     const int pmax = max(pF, pH);
-    for (int jj = lane; jj <= pmax; jj += 64) {
+    // e^{i n a} for n = lane (table part times e^{i n ur}) and e^{i 64 a} =
+    // (e^{i 32 a})^2, shared by the coefficient vectors and the convolutions
+    cplx ph_lane, ph64;
+    {
       double s1, c1;
-      sincos_bounded(jj * ur, &s1, &c1);
-      const cplx ph = mk(tcos(tab, jj * Jq, mask, quarter), tsin(tab, jj * Jq, mask)) * mk(c1, s1);
+      sincos_bounded(lane * ur, &s1, &c1);
+      ph_lane = mk(tcos(tab, lane * Jq, mask, quarter), tsin(tab, lane * Jq, mask)) * mk(c1, s1);
+      const cplx h = mk(read_lane(ph_lane.re, 32), read_lane(ph_lane.im, 32));
+      ph64 = h * h;
+    }
+    cplx ph = ph_lane;
+    for (int jj = lane; jj <= pmax; jj += 64, ph = ph * ph64) {
       if (want_c && jj <= pF) {
         const C G = SP::narrow(SP::wide(real_part_coeff(Fsrc, jj, NF, invNF)) * ph);
         GF[pF + jj] = G;
@@ -701,13 +698,13 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     R* A = (paper ? reinterpret_cast<R*>(Z1) : (want_c ? reinterpret_cast<R*>(Z2) : Acompact)) +
            NF / 2;
     const int mtop = paper ? L + pF : (want_c ? max(L + pF, M + pH) : M + pH);
-    singular_factor_wave(b, rr.A0, rr.D1, mtop, A);
+    singular_factor_wave(b, eb, omq, rr.A0, rr.D1, mtop, A);
     for (int m = 1 + lane; m <= max(pF, pH); m += 64) A[-m] = A[m];
     wave_sync();
 
     // ---- <rho^-1>_l, l = 0..L (eq. (3.25)) into cb[L + l] (and cb[L - l] = conj)
     if (want_c) {
-      swap_convolution<C>(GF, pF, A, L, ur, Jq, tab, mask, quarter, cb + L, cb + L, crow);
+      swap_convolution<C>(GF, pF, A, L, ph_lane, ph64, cb + L, cb + L, crow);
       wave_sync();
     }
     // ---- kc_n = <cos(k rho)/rho>_n, n = 0..M
@@ -736,7 +733,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
       if (lane == 0) kc[M] = C{accr, acci};
     } else {
       // swap applied to cos(k rho)/rho
-      swap_convolution<C>(GH, pH, A, M, ur, Jq, tab, mask, quarter, kc, nullptr, nullptr);
+      swap_convolution<C>(GH, pH, A, M, ph_lane, ph64, kc, nullptr, nullptr);
     }
     wave_sync();
     // ---- kappa_n = kc_n + i <sin(k rho)/rho>_n, n = -M+1..M at column n + M - 1
@@ -907,7 +904,7 @@ __global__ __launch_bounds__(256) void ffbie_singular_factor_kernel(int64_t n,
     A0 = M_2_PI * K;
     D1 = M_2_PI * (expm1(b) * K - exp(b) * E);
   }
-  singular_factor_wave(b, A0, D1, mtop, A);
+  singular_factor_wave(b, exp(-b), -expm1(-b), A0, D1, mtop, A);
   for (int m = lane; m <= mtop; m += 64) out[idx * (mtop + 1) + m] = A[m];
 }
 
