@@ -294,17 +294,150 @@ __device__ __forceinline__ void fft_stockham(C*& ia, C*& oa, C*& ib, C*& ob, boo
 // conflict-free load per butterfly.
 constexpr int kTwiddleStages = 7;
 
+// Twiddles e^{-2 pi i k / NF} per (stage, lane), entry st * 64 + lane.  The
+// Stockham layout holds, for stage Ns = 2^st, k = (lane mod Ns) NF / (2 Ns).
+// The layout of fft128_regs (NF = 128) holds the factor by which lane `lane`
+// multiplies at stage st (see there).
 template <class C>
 __device__ __forceinline__ void build_twiddles(C* tw, int NF, int M, const double* tab, int mask,
-                                               int quarter) {
+                                               int quarter, bool reg_layout = false) {
   using R = decltype(C::re);
   for (int idx = threadIdx.x; idx < kTwiddleStages * 64; idx += blockDim.x) {
     const int st = idx >> 6, lane = idx & 63;
-    const int Ns = 1 << st;
-    const int r = lane & (Ns - 1);
-    const int tk = (Ns < NF) ? r * ((4 * M) / Ns) : 0;
+    int tk;
+    if (!reg_layout) {
+      const int Ns = 1 << st;
+      const int r = lane & (Ns - 1);
+      tk = (Ns < NF) ? r * ((4 * M) / Ns) : 0;
+    } else {
+      // exponent k of e^{-2 pi i k / 128}
+      const int l15 = lane & 15, L4 = (lane >> 4) & 1, L5 = (lane >> 5) & 1;
+      int k128;
+      if (st <= 3) k128 = ((lane >> st) & 1) ? (lane & ((1 << st) - 1)) << (6 - st) : 0;
+      else if (st == 4) k128 = l15 << 2;
+      else if (st == 5) k128 = (16 * L5 + l15) << 1;
+      else k128 = 32 * L4 + 16 * L5 + l15;
+      tk = k128 * ((8 * M) / NF);            // angle 2 pi k / 128 on the table
+    }
     tw[idx] = C{(R)tcos(tab, tk, mask, quarter), (R)-tsin(tab, tk, mask)};
   }
+}
+
+// ---------------------------------------------------------------------------
+// 128-point forward DFT held in registers, one wavefront, no LDS passes.
+// Radix-2 decimation in time on bit-reversed input: position p = l + 64 R
+// (lane l, register R) starts with sample bitrev7(p) = 2 brev6(l) + R, which
+// the lane computes itself.  Stage s combines positions p and p + 2^s with the
+// factor e^{-2 pi i (p mod 2^s) / 2^{s+1}}:
+//   s = 0..3: lanes l and l ^ 2^s, both registers; each lane multiplies its
+//             value by its factor (1 in the lower lane), takes the partner's
+//             by a DPP move (quad permutes, row shifts, row rotate) and forms
+//             sum or difference;
+//   s = 4..6: a permlane16 / permlane32 swap exchanges the register bit with
+//             lane bit 4 or 5 so that both members of a pair sit in one lane,
+//             which then does a full butterfly.
+// On return register R of lane l holds X[64 R + 32 L4 + 16 L5 + (l & 15)]
+// (L4, L5 = lane bits 4, 5).
+// ---------------------------------------------------------------------------
+// DPP move for patterns that give every lane a source (no old value kept)
+template <int CTRL>
+__device__ __forceinline__ double dpp_full(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)u, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_full(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+// value of lane l ^ 2^S (S = 0..3)
+template <int S, class T>
+__device__ __forceinline__ T lane_xor(T v, int lane) {
+  if constexpr (S == 0) return dpp_full<0xB1>(v);          // quad_perm [1,0,3,2]
+  else if constexpr (S == 1) return dpp_full<0x4E>(v);     // quad_perm [2,3,0,1]
+  else if constexpr (S == 2) {
+    const T up = dpp_full<0x104>(v), dn = dpp_full<0x114>(v);   // row_shl:4, row_shr:4
+    return (lane & 4) ? dn : up;
+  } else {
+    return dpp_full<0x128>(v);                              // row_ror:8
+  }
+}
+
+template <int S, class C>
+__device__ __forceinline__ void dit_pull_stage(C& x, C w, int lane) {
+  using R = decltype(C::re);
+  const C t = (S == 0) ? x : x * w;
+  const C v = C{lane_xor<S>(t.re, lane), lane_xor<S>(t.im, lane)};
+  const R sg = ((lane >> S) & 1) ? (R)-1 : (R)1;
+  x = C{fma(sg, t.re, v.re), fma(sg, t.im, v.im)};
+}
+
+template <class C>
+__device__ __forceinline__ void dit_lane_stage(C& x0, C& x1, C w) {
+  const C t = x1 * w;
+  x1 = x0 - t;
+  x0 = x0 + t;
+}
+
+__device__ __forceinline__ void swap_words(bool rows16, unsigned& a, unsigned& b) {
+  const auto r = rows16 ? __builtin_amdgcn_permlane16_swap(a, b, false, false)
+                        : __builtin_amdgcn_permlane32_swap(a, b, false, false);
+  a = r[0];
+  b = r[1];
+}
+__device__ __forceinline__ void swap_lanes(bool rows16, double& a, double& b) {
+  const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+  unsigned alo = (unsigned)ua, ahi = (unsigned)(ua >> 32), blo = (unsigned)ub, bhi = (unsigned)(ub >> 32);
+  swap_words(rows16, alo, blo);
+  swap_words(rows16, ahi, bhi);
+  a = __longlong_as_double((long long)(((unsigned long long)ahi << 32) | alo));
+  b = __longlong_as_double((long long)(((unsigned long long)bhi << 32) | blo));
+}
+__device__ __forceinline__ void swap_lanes(bool rows16, float& a, float& b) {
+  unsigned ua = __float_as_uint(a), ub = __float_as_uint(b);
+  swap_words(rows16, ua, ub);
+  a = __uint_as_float(ua);
+  b = __uint_as_float(ub);
+}
+template <class C>
+__device__ __forceinline__ void swap_lanes(bool rows16, C& x0, C& x1) {
+  swap_lanes(rows16, x0.re, x1.re);
+  swap_lanes(rows16, x0.im, x1.im);
+}
+
+template <class C>
+__device__ __forceinline__ void fft128_regs(C& x0, C& x1, const C* tw, int lane) {
+  dit_pull_stage<0>(x0, C{}, lane);
+  dit_pull_stage<0>(x1, C{}, lane);
+  {
+    const C w = tw[64 + lane];
+    dit_pull_stage<1>(x0, w, lane);
+    dit_pull_stage<1>(x1, w, lane);
+  }
+  {
+    const C w = tw[128 + lane];
+    dit_pull_stage<2>(x0, w, lane);
+    dit_pull_stage<2>(x1, w, lane);
+  }
+  {
+    const C w = tw[192 + lane];
+    dit_pull_stage<3>(x0, w, lane);
+    dit_pull_stage<3>(x1, w, lane);
+  }
+  swap_lanes(true, x0, x1);            // register bit <-> lane bit 4
+  dit_lane_stage(x0, x1, tw[256 + lane]);
+  swap_lanes(false, x0, x1);           // register bit <-> lane bit 5
+  dit_lane_stage(x0, x1, tw[320 + lane]);
+  swap_lanes(true, x0, x1);            // register bit <-> lane bit 4
+  dit_lane_stage(x0, x1, tw[384 + lane]);
+}
+
+// Index of the coefficient that fft128_regs leaves in register 0 of this lane
+// (register 1 holds the one 64 above).
+__device__ __forceinline__ int fft128_out_index(int lane) {
+  return 32 * ((lane >> 4) & 1) + 16 * ((lane >> 5) & 1) + (lane & 15);
 }
 
 // Forward DFT as fft_stockham for NF <= 128 with the twiddles of build_twiddles.
@@ -547,6 +680,9 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
   const int lane = threadIdx.x & 63;
   const bool paper = a.variant == FFBIE_KAPPA_PAPER_CONV;
   const bool want_c = paper || a.rhoinv != nullptr;
+  // the 128-point transform in registers where the twiddles are laid out for
+  // it and only one transform is taken
+  const bool reg_fft = RADIX == 2 && NF == 128 && tw != nullptr && !want_c;
   C* base = reinterpret_cast<C*>(wbase);
   C* z1a = base;
   C* z1b = z1a + NF;
@@ -605,9 +741,10 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     const double eb = exp(-b), omq = -expm1(-b);
     const int qj = j * (NF / (2 * M));
 
-    // ---- samples on the NF-point grid
+    // ---- samples on the NF-point grid: sample(q, z1, z2) gives the inputs of
+    //      the transforms (z2 only where a second transform is taken)
     double sumF = 0.0;
-    for (int q = lane; q < NF; q += 64) {
+    auto sample = [&](int q, C& z1, C& z2) {
       double dx, dy, dz;
       dr_grid<MM>(pg, tab, q * tstride, J, mask, quarter, &dx, &dy, &dz);
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
@@ -622,21 +759,54 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
       const double S = (k == 0.0) ? 0.0 : skr * ri;
       sumF += F;
       if (paper) {
-        z1a[q] = C{(R)F, (R)ckr};
-        z2a[q] = C{(R)S, (R)0};
+        z1 = C{(R)F, (R)ckr};
+        z2 = C{(R)S, (R)0};
       } else {
-        z1a[q] = C{(R)(F * ckr), (R)(S * s_down)};
-        if (want_c) z2a[q] = C{(R)F, (R)0};
+        z1 = C{(R)(F * ckr), (R)(S * s_down)};
+        z2 = C{(R)F, (R)0};
+      }
+    };
+    C *Z1 = z1a, *free1 = z1b, *Z2 = z2a, *free2 = z2b;
+    // With the transforms in registers the lane's two samples are the
+    // bit-reversed positions lane and lane + 64 (samples 2 brev6(lane) + i) and
+    // stay in registers; otherwise sample q = lane + 64 i goes to LDS.  The lane
+    // index is made opaque so that the lane constants of the register transform
+    // (signs, sample and output indices) are formed where they are used rather
+    // than hoisted out of the pair loop and held in registers throughout it.
+    int fl = lane;
+    asm volatile("" : "+v"(fl));
+    const int q0 = (int)(__builtin_bitreverse32((unsigned)fl) >> 25);
+    C a0, a1;
+#pragma unroll 1
+    for (int i = 0; i < (reg_fft ? 2 : (NF + 63) / 64); ++i) {
+      const int q = reg_fft ? q0 + i : lane + 64 * i;
+      if (q < NF) {
+        C z1, z2;
+        sample(q, z1, z2);
+        if (reg_fft) {
+          if (i == 0) a0 = z1; else a1 = z1;
+        } else {
+          z1a[q] = z1;
+          if (want_c) z2a[q] = z2;
+        }
       }
     }
-    wave_sync();
-    C *Z1 = z1a, *free1 = z1b, *Z2 = z2a, *free2 = z2b;
-    if constexpr (RADIX == 4)
-      fft_stockham_r4(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter, tw);
-    else if (tw)
-      fft_stockham_small(Z1, free1, Z2, free2, want_c, NF, tw);
-    else
-      fft_stockham(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter);
+    if (reg_fft) {
+      fft128_regs(a0, a1, tw, fl);
+      const int o = fft128_out_index(fl);
+      z1a[o] = a0;
+      z1a[o + 64] = a1;
+      wave_sync();
+    } else {
+      wave_sync();
+      // at NF = 128 the radix-2 twiddle table is in the register layout
+      if constexpr (RADIX == 4)
+        fft_stockham_r4(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter, tw);
+      else if (tw && NF != 128)
+        fft_stockham_small(Z1, free1, Z2, free2, want_c, NF, tw);
+      else
+        fft_stockham(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter);
+    }
 
     // truncation indices of the smooth factors
     const C* Fsrc = paper ? Z1 : Z2;
@@ -763,7 +933,7 @@ __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbi
   const int twd = coeff_twiddle_doubles(a.NF, single);
   C* tw = twd ? reinterpret_cast<C*>(smem + a.P.tab_n) : nullptr;
   if (tw) {
-    build_twiddles(tw, a.NF, a.P.M, tab, a.P.tab_n - 1, 2 * a.P.M);
+    build_twiddles(tw, a.NF, a.P.M, tab, a.P.tab_n - 1, 2 * a.P.M, RADIX == 2 && a.NF == 128);
     __syncthreads();
   }
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -810,7 +980,7 @@ __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbi
   load_table(smem, a0.tab_g, a0.P.tab_n);
   C* tw = coeff_twiddle_doubles(NF, single) ? reinterpret_cast<C*>(smem + b.tab_max) : nullptr;
   if (tw) {
-    build_twiddles(tw, NF, M, smem, a0.P.tab_n - 1, 2 * M);
+    build_twiddles(tw, NF, M, smem, a0.P.tab_n - 1, 2 * M, RADIX == 2 && NF == 128);
     __syncthreads();
   }
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

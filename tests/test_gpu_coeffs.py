@@ -175,3 +175,29 @@ def test_singular_factor_matches_oracle(ctx):
         ref = ospecial.singular_factor(b, m_max)
         err = np.max(np.abs(A[i] - ref)) / ref[0]
         assert err <= 1e-13, (b, err)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_main_pass_resolves_pairs_with_and_without_rhoinv(ctx, mixed):
+    """The 4M-sample pass is a fallback for the few pairs next to a pole.  With
+    and without the <rho^-1> table (different transform code paths), the main
+    pass must resolve all but a small fraction of config-2 pairs and agree on
+    the truncation index of each pair; a transform with wrong twiddles would
+    push most pairs to the fallback while the results still matched."""
+    cfg = workloads.config(2)
+    t, j, ts = workloads.sample_pairs(cfg["n_panels"], cfg["M"], 4096, seed=77)
+    ctx.set_problem(cfg["amp"], cfg["n_panels"], cfg["M"], cfg["k"])
+    dev = ctx.device
+    tt, jj, tss = (torch.tensor(v, device=dev) for v in (t, j, ts))
+    sts = []
+    for rho in (False, True):
+        out = ctx.kernel_coeffs(tt, jj, tss, rhoinv=rho, mixed=mixed)
+        torch.cuda.synchronize()
+        sts.append(out["status"].cpu().numpy())
+    import paper_2608_16208_amd as ffbie
+    p_shift = ffbie.P_SHIFT
+    for st in sts:
+        refined = ((st & 4) > 0).mean()
+        assert refined < 0.01, refined
+    pa, pb = sts[0] >> p_shift, sts[1] >> p_shift
+    assert (pa == pb).mean() >= 0.99, (pa != pb).sum()
