@@ -139,6 +139,12 @@ FFBIE_HD __forceinline__ void sincos_bounded(double x, double* s, double* c) {
 FFBIE_HD __forceinline__ void csincos(cplx z, cplx* s, cplx* c) {
   double sx, cx;
   sincos_bounded(z.re, &sx, &cx);
+  if (z.im == 0.0) {
+    // real argument (sinh 0 = 0, cosh 0 = 1), the same values without expm1
+    *s = {sx, cx * 0.0};
+    *c = {cx, -sx * 0.0};
+    return;
+  }
   // sinh via expm1 keeps full relative accuracy for small |Im z|
   const double em = expm1(z.im), emm = expm1(-z.im);
   const double sh = 0.5 * (em - emm);
@@ -166,7 +172,7 @@ FFBIE_HD __forceinline__ double tcos(const double* tab, int i, int mask, int qua
 // ----------------------------------------------------------------------------
 template <int MM>
 struct PairGeo {
-  double st, sts, cts;        // sin t, sin t_s, cos t_s
+  double st, ct, sts, cts;    // sin t, cos t, sin t_s, cos t_s
   double S1, C1;              // sin t_s - sin t, cos t_s - cos t (product forms)
   double R;                   // R(t, theta_j)
   double al[MM + 1], be[MM + 1], ga[MM + 1];
@@ -190,7 +196,7 @@ FFBIE_HD __forceinline__ void pair_geo(const Geom& g, double t, double ts, const
   sincos_bounded(ts, &sts, &cts);
   sincos_bounded(0.5 * (ts - t), &shd, &chd);
   sincos_bounded(0.5 * (ts + t), &shs, &chs);
-  p->st = st; p->sts = sts; p->cts = cts;
+  p->st = st; p->ct = ct; p->sts = sts; p->cts = cts;
   p->S1 = 2.0 * chs * shd;
   p->C1 = -2.0 * shs * shd;
 #pragma unroll

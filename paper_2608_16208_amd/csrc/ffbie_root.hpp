@@ -18,13 +18,37 @@ FFBIE_HD inline RootRec find_root(const Prob& P, const double* tab, double t, in
   PairGeo<MM> pg;
   pair_geo<MM>(P.g, t, ts, tab, J, mask, quarter, &pg);
 
-  // (1) grid minimiser of rho^2 over the 2M azimuths theta_q = pi q / M
+  // (1) grid minimiser of rho^2 over the 2M azimuths theta_q = pi q / M.  Only
+  //     the index of the smallest value is wanted, so rho^2 is expanded
+  //     directly: with r_s = R_s(theta) w(theta), |w| = 1, and the target point
+  //     r_t, rho^2 = R_s (R_s - 2 w . r_t) + |r_t|^2.  Its rounding error
+  //     (~1e-16 absolute) only matters between grid values that agree to that
+  //     level, where either is a valid start for the Newton steps below.  The
+  //     angle values of theta_q are the same for every pair.
+  const double sj = tsin(tab, J, mask), cj = tcos(tab, J, mask, quarter);
+  const double Rt = pg.R;
+  const double wa = pg.sts * (Rt * pg.st * cj), wb = pg.sts * (Rt * pg.st * sj);
+  const double wc = pg.cts * (Rt * pg.ct);
+  const double Rs0 = 1.0 + pg.al[0], Rt2 = Rt * Rt;
   double best = 1e300;
   int qbest = j;
   for (int q = 0; q < 2 * M; ++q) {
-    double dx, dy, dz;
-    dr_grid<MM>(pg, tab, 4 * q, J, mask, quarter, &dx, &dy, &dz);
-    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double cq = tcos(tab, 4 * q, mask, quarter), sq = tsin(tab, 4 * q, mask);
+    double Rs = Rs0;
+    if (MM >= 1) {
+      double c_prev = 1.0, c_cur = cq;
+#pragma unroll
+      for (int m = 1; m <= MM; ++m) {
+        if (m >= 2) {
+          const double cn = 2.0 * cq * c_cur - c_prev;
+          c_prev = c_cur;
+          c_cur = cn;
+        }
+        Rs = fma(pg.al[m], c_cur, Rs);
+      }
+    }
+    const double d = fma(wa, cq, fma(wb, sq, wc));
+    const double r2 = fma(Rs, fma(-2.0, d, Rs), Rt2);
     if (r2 < best) { best = r2; qbest = q; }
   }
   int dq = (qbest - j) & (2 * M - 1);
@@ -38,7 +62,6 @@ FFBIE_HD inline RootRec find_root(const Prob& P, const double* tab, double t, in
     smj[m] = tsin(tab, m * J, mask);
     cmj[m] = tcos(tab, m * J, mask, quarter);
   }
-  const double sj = tsin(tab, J, mask), cj = tcos(tab, J, mask, quarter);
 
   // (2) real minimiser a0 by Newton on d rho^2 / d theta_s, kept within the grid cell
   const double lo = x - h, hi = x + h;
