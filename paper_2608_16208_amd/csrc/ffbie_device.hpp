@@ -364,11 +364,11 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Wave reductions by DPP moves (no LDS traffic): inclusive scans inside each
-// row of 16 lanes by shifts of 1, 2, 4, 8, then the last lane of row 0 (2)
-// into row 1 (3) and the last lane of row 1 into rows 2 and 3, so that lane 63
-// holds the reduction of all 64 lanes; it is then read as a uniform value.
-// `fill` is what lanes without a source contribute (0 for sums, the lane's
-// own value for maxima).
+// row of 16 lanes by shifts of 1, 2, 4, 8, then the last lane of row 2 into
+// row 3 and the last lane of row 1 into row 3, so that lane 63 holds the
+// reduction of all 64 lanes; it is then read as a uniform value.
+// dpp_i32 / dpp_f64_fill: lanes without a source, or in rows that ROW_MASK
+// does not write, keep `fill`.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ int dpp_i32(int fill, int src) {
   return __builtin_amdgcn_update_dpp(fill, src, CTRL, ROW_MASK, 0xf, false);
@@ -399,41 +399,45 @@ __device__ __forceinline__ float lane63(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_f64_fill<0x111, 0xf>(0.0, v);
-  v += dpp_f64_fill<0x112, 0xf>(0.0, v);
-  v += dpp_f64_fill<0x114, 0xf>(0.0, v);
-  v += dpp_f64_fill<0x118, 0xf>(0.0, v);
-  v += dpp_f64_fill<0x142, 0xa>(0.0, v);
-  v += dpp_f64_fill<0x143, 0xc>(0.0, v);
+// Moves for the reductions: every row is written and lanes without a source
+// read 0 (bound_ctrl), so no old value has to be materialised.  Only lane 63's
+// result is used: it is the sum (maximum) over all lanes whatever the row
+// broadcasts leave in rows 0-2.
+template <int CTRL>
+__device__ __forceinline__ double dpp_zero(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)u, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_zero(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+template <class T>
+__device__ __forceinline__ T wave_sum_t(T v) {
+  v += dpp_zero<0x111>(v);   // row_shr:1
+  v += dpp_zero<0x112>(v);   // row_shr:2
+  v += dpp_zero<0x114>(v);   // row_shr:4
+  v += dpp_zero<0x118>(v);   // row_shr:8
+  v += dpp_zero<0x142>(v);   // row_bcast:15
+  v += dpp_zero<0x143>(v);   // row_bcast:31
   return lane63(v);
 }
-__device__ __forceinline__ double wave_max(double v) {
-  v = fmax(v, dpp_f64_fill<0x111, 0xf>(v, v));
-  v = fmax(v, dpp_f64_fill<0x112, 0xf>(v, v));
-  v = fmax(v, dpp_f64_fill<0x114, 0xf>(v, v));
-  v = fmax(v, dpp_f64_fill<0x118, 0xf>(v, v));
-  v = fmax(v, dpp_f64_fill<0x142, 0xa>(v, v));
-  v = fmax(v, dpp_f64_fill<0x143, 0xc>(v, v));
+// maximum of nonnegative values (lanes without a source contribute 0)
+template <class T>
+__device__ __forceinline__ T wave_max_t(T v) {
+  v = fmax(v, dpp_zero<0x111>(v));
+  v = fmax(v, dpp_zero<0x112>(v));
+  v = fmax(v, dpp_zero<0x114>(v));
+  v = fmax(v, dpp_zero<0x118>(v));
+  v = fmax(v, dpp_zero<0x142>(v));
+  v = fmax(v, dpp_zero<0x143>(v));
   return lane63(v);
 }
-__device__ __forceinline__ float wave_sum(float v) {
-  v += dpp_f32_fill<0x111, 0xf>(0.0f, v);
-  v += dpp_f32_fill<0x112, 0xf>(0.0f, v);
-  v += dpp_f32_fill<0x114, 0xf>(0.0f, v);
-  v += dpp_f32_fill<0x118, 0xf>(0.0f, v);
-  v += dpp_f32_fill<0x142, 0xa>(0.0f, v);
-  v += dpp_f32_fill<0x143, 0xc>(0.0f, v);
-  return lane63(v);
-}
-__device__ __forceinline__ float wave_max(float v) {
-  v = fmaxf(v, dpp_f32_fill<0x111, 0xf>(v, v));
-  v = fmaxf(v, dpp_f32_fill<0x112, 0xf>(v, v));
-  v = fmaxf(v, dpp_f32_fill<0x114, 0xf>(v, v));
-  v = fmaxf(v, dpp_f32_fill<0x118, 0xf>(v, v));
-  v = fmaxf(v, dpp_f32_fill<0x142, 0xa>(v, v));
-  v = fmaxf(v, dpp_f32_fill<0x143, 0xc>(v, v));
-  return lane63(v);
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_t(v); }
+__device__ __forceinline__ float wave_sum(float v) { return wave_sum_t(v); }
+__device__ __forceinline__ double wave_max(double v) { return wave_max_t(v); }
+__device__ __forceinline__ float wave_max(float v) { return wave_max_t(v); }
 
 }  // namespace ffbie

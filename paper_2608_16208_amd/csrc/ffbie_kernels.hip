@@ -109,10 +109,26 @@ __device__ __forceinline__ void mat_mul(double a00, double a01, double a10, doub
 // the one the DPP pattern brings from a lower lane; lanes that the pattern
 // gives no source (or whose row it does not write) receive the identity, so
 // no per-lane select is needed.
+// A diagonal entry moved by a row shift: lanes without a source read 1.0
+// (low word 0 by bound_ctrl, high word kept from the fill).
+template <int CTRL>
+__device__ __forceinline__ double dpp_one(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)u, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0x3ff00000, (int)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ void mat_scan_step(double& e00, double& e01, double& e10, double& e11) {
-  const double o00 = dpp_f64_fill<CTRL, ROW_MASK>(1.0, e00), o01 = dpp_f64_fill<CTRL, ROW_MASK>(0.0, e01);
-  const double o10 = dpp_f64_fill<CTRL, ROW_MASK>(0.0, e10), o11 = dpp_f64_fill<CTRL, ROW_MASK>(1.0, e11);
+  double o00, o01, o10, o11;
+  if constexpr (ROW_MASK == 0xf) {
+    // row shifts: every row written, only missing sources need the identity
+    o00 = dpp_one<CTRL>(e00); o01 = dpp_zero<CTRL>(e01);
+    o10 = dpp_zero<CTRL>(e10); o11 = dpp_one<CTRL>(e11);
+  } else {
+    o00 = dpp_f64_fill<CTRL, ROW_MASK>(1.0, e00); o01 = dpp_f64_fill<CTRL, ROW_MASK>(0.0, e01);
+    o10 = dpp_f64_fill<CTRL, ROW_MASK>(0.0, e10); o11 = dpp_f64_fill<CTRL, ROW_MASK>(1.0, e11);
+  }
   double n00, n01, n10, n11;
   mat_mul(e00, e01, e10, e11, o00, o01, o10, o11, &n00, &n01, &n10, &n11);
   e00 = n00; e01 = n01; e10 = n10; e11 = n11;
