@@ -393,7 +393,9 @@ ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_
     a.flag_count = c->d_count;
     size_t lds;
     const int w = coeff_waves(P, a.NF, compact, single, &lds);
-    const int64_t pairs_per_wave = 16;
+    // 32 consecutive pairs per wavefront: fewer wavefronts share out the
+    // per-wavefront set-up (tables, spilled constants) without a long tail
+    const int64_t pairs_per_wave = 32;
     int64_t blocks = (n + w * pairs_per_wave - 1) / (w * pairs_per_wave);
     if (blocks < 1) blocks = 1;
     if (c->timing) FFBIE_HIP(c, hipEventRecord(c->ev[1], c->stream));

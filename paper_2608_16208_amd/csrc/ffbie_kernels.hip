@@ -46,6 +46,21 @@ __device__ __forceinline__ double rsqrt_refined(double x) {
   return fma(0.5 * y, e, y);
 }
 
+// sqrt(x) for a normal positive x (no denormal scaling, no zero or infinity
+// handling): hardware 1/sqrt estimate y, g = x y and h = y/2 refined by one
+// coupled Newton step, then two corrections g += (x - g^2) h.
+__device__ __forceinline__ double sqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
 __device__ __forceinline__ double rcp_int(double x) {
   // 1/x for a small positive integer x: hardware estimate + two Newton steps
   double r = __builtin_amdgcn_rcp(x);
@@ -771,7 +786,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
       const int hidx = (q - qj - qu) * hstep;   // (theta_q - a)/2 = hidx pi/(4M) - ur/2
       const double sh = fma(tsin(tab, hidx, mask), cur, -tcos(tab, hidx, mask, quarter) * sur);
       const double s = fma(omq, omq, 4.0 * eb * sh * sh);
-      const double F = sqrt(s) * ri;
+      const double F = sqrt_pos(s) * ri;       // s >= (1 - e^{-b})^2 > 0
       const double S = (k == 0.0) ? 0.0 : skr * ri;
       sumF += F;
       if (paper) {
