@@ -61,8 +61,8 @@ __device__ __forceinline__ double sqrt_pos(double x) {
   return fma(d, h, g);
 }
 
-__device__ __forceinline__ double rcp_int(double x) {
-  // 1/x for a small positive integer x: hardware estimate + two Newton steps
+__device__ __forceinline__ double rcp_refined(double x) {
+  // 1/x for a normal positive x: hardware estimate + two Newton steps
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
   r = fma(r, e, r);
@@ -192,7 +192,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double eb, double
     for (int s = 0; s < S; ++s) {
       const int m = m_first + s;
       if (m > mtop - 1) break;
-      const double r = rcp_int(2.0 * m + 1.0);
+      const double r = rcp_refined(2.0 * m + 1.0);
       const double al = (2.0 * m - 1.0) * r, be = s2 * m * r;
       double n00, n01, n10, n11;
       mat_mul(al, be, al, 1.0 + be, e00, e01, e10, e11, &n00, &n01, &n10, &n11);
@@ -208,7 +208,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double eb, double
     for (int s = 0; s < S; ++s) {
       const int m = m_first + s;
       if (m > mtop - 1) break;
-      const double r = rcp_int(2.0 * m + 1.0);
+      const double r = rcp_refined(2.0 * m + 1.0);
       const double al = (2.0 * m - 1.0) * r, be = s2 * m * r;
       const double nD = fma(al, wD, be * wA);
       wA = wA + nD;
@@ -222,7 +222,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double eb, double
   // ---- Miller, backward: v_{m-1} = T_m v_m, v_m = (y_m, y_{m+1}),
   //      T_m = [[4 m cosh b/(2m-1), -(2m+1)/(2m-1)], [1, 0]], m = N .. 1
   int meff = mtop;
-  int N = max(mtop + 10, (int)ceil(0.5 * (mtop + 37.0 / b)) + 10);
+  int N = max(mtop + 10, (int)ceil(0.5 * (mtop + 37.0 * rcp_refined(b))) + 10);
   if (b * N > 640.0) {
     // the recurrence would leave the double range; A_m < e^{-630} A_0 is set to 0
     N = (int)floor(640.0 / b);
@@ -233,7 +233,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double eb, double
       return;
     }
   }
-  const double ch4 = 2.0 * (1.0 / eb + eb);
+  const double ch4 = 2.0 * (rcp_refined(eb) + eb);
   const int S = (N + 63) / 64;
   // segment g = 63 - lane (the highest indices in lane 0), so that the suffix
   // products over segments are prefix products in lane order
@@ -242,7 +242,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double eb, double
   double p00 = 1, p01 = 0, p10 = 0, p11 = 1;
   for (int m = top; m > seg * S; --m) {
     if (m > N) continue;
-    const double r = rcp_int(2.0 * m - 1.0);
+    const double r = rcp_refined(2.0 * m - 1.0);
     const double al = ch4 * m * r, be = -(2.0 * m + 1.0) * r;
     double n00, n01, n10, n11;
     mat_mul(al, be, 1.0, 0.0, p00, p01, p10, p11, &n00, &n01, &n10, &n11);
@@ -257,14 +257,14 @@ __device__ __forceinline__ void singular_factor_wave(double b, double eb, double
     // store the unnormalised values, then scale by A_0 / y_0 with y_0 as replayed
     for (int m = top; m > seg * S; --m) {
       if (m > N) continue;
-      const double r = rcp_int(2.0 * m - 1.0);
+      const double r = rcp_refined(2.0 * m - 1.0);
       const double yn = (ch4 * m * y0 - (2.0 * m + 1.0) * y1) * r;
       y1 = y0;
       y0 = yn;                       // y_{m-1}
       if (m - 1 <= mtop) A[m - 1] = yn;
     }
     wave_sync();
-    const double scale = A0 / A[0];
+    const double scale = A0 * rcp_refined(A[0]);
     wave_sync();
     for (int m = lane; m <= mtop; m += 64) A[m] = (m <= meff) ? A[m] * scale : 0.0;
   } else {
@@ -273,7 +273,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double eb, double
     const double scale = A0 / (lane63(p00) * kMillerStart);
     for (int m = top; m > seg * S; --m) {
       if (m > N) continue;
-      const double r = rcp_int(2.0 * m - 1.0);
+      const double r = rcp_refined(2.0 * m - 1.0);
       const double yn = (ch4 * m * y0 - (2.0 * m + 1.0) * y1) * r;
       y1 = y0;
       y0 = yn;                       // y_{m-1}
@@ -737,6 +737,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
   const double s_down = ldexp(1.0, -kexp);
   const R s_up = (R)ldexp(1.0, kexp);
 
+  const double inv_gstep = NF / (2.0 * M_PI);   // 1 / (2 pi / NF)
   double t_prev = nan, ts_prev = nan;
   PairGeo<MM> pg;
 
@@ -763,13 +764,24 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     }
     const double u = rr.u, b = rr.b;
     // a = theta_j + qu * (2 pi / NF) + ur,  |ur| <= pi / NF
-    const double gstep = 2.0 * M_PI / NF;
-    const double qu_d = rint(u / gstep);
+    const double gstep = 2.0 * M_PI / NF;   // any rounding of qu is exact in ur
+    const double qu_d = rint(u * inv_gstep);
     const int qu = (int)qu_d;
     const double ur = fma(-qu_d, gstep, u);
     double sur, cur;
     sincos_bounded(0.5 * ur, &sur, &cur);
-    const double eb = exp(-b), omq = -expm1(-b);
+    // e^{-b} and 1 - e^{-b} from one transcendental, each to full relative
+    // accuracy: below b = 1/2 from expm1 (e^{-b} > 0.6), above from exp
+    // (1 - e^{-b} > 0.39); b is the same in every lane
+    double eb, omq;
+    if (b < 0.5) {
+      const double em = expm1(-b);
+      eb = 1.0 + em;
+      omq = -em;
+    } else {
+      eb = exp(-b);
+      omq = 1.0 - eb;
+    }
     const int qj = j * (NF / (2 * M));
 
     // ---- samples on the NF-point grid: sample(q, z1, z2) gives the inputs of
