@@ -738,6 +738,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
   const R s_up = (R)ldexp(1.0, kexp);
 
   const double inv_gstep = NF / (2.0 * M_PI);   // 1 / (2 pi / NF)
+  const double inv_NF = 1.0 / NF;
   double t_prev = nan, ts_prev = nan;
   PairGeo<MM> pg;
 
@@ -851,11 +852,24 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
         fft_stockham(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter);
     }
 
-    // truncation indices of the smooth factors
+    // truncation indices of the smooth factors.  With one transform and
+    // NF <= 128 lane j holds coefficient j < NF/2 of the smooth factor, kept
+    // for the coefficient vector below.
     const C* Fsrc = paper ? Z1 : Z2;
-    const double F0 = wave_sum(sumF) / NF;      // <F>_0 = max_j |<F>_j| since F > 0
+    const double F0 = wave_sum(sumF) * inv_NF;  // <F>_0 = max_j |<F>_j| since F > 0
+    const bool one_tf = !paper && !want_c && NF <= 128;
+    C c_own = C{(R)0, (R)0};
+    int pH;
+    if (one_tf) {
+      if (lane < NF / 2) c_own = real_part_coeff(Z1, lane, NF, invNF);
+      const R a2 = abs2(c_own);
+      const R maxv = fmax(wave_max(a2), (R)(F0 * F0));
+      const uint64_t bal = __ballot(a2 > (R)(P.eps0 * P.eps0) * maxv);
+      pH = __builtin_amdgcn_readfirstlane(bal ? 63 - __clzll(bal) : 0);
+    } else {
+      pH = paper ? 0 : trunc_index_real(Z1, NF, invNF, P.eps0, F0);
+    }
     const int pF = want_c ? trunc_index_real(Fsrc, NF, invNF, P.eps0, 0.0) : 0;
-    const int pH = paper ? 0 : trunc_index_real(Z1, NF, invNF, P.eps0, F0);
     if (max(pF, pH) >= NF / 2 - 2) {
       if (!REFINE && a.flag_list) {
         // not resolved on this grid: queue for the 4M-sample pass
@@ -893,7 +907,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
         GF[pF - jj] = conj(G);
       }
       if (!paper && jj <= pH) {
-        const C G = SP::narrow(SP::wide(real_part_coeff(Z1, jj, NF, invNF)) * ph);
+        const C G = SP::narrow(SP::wide(one_tf ? c_own : real_part_coeff(Z1, jj, NF, invNF)) * ph);
         GH[pH + jj] = G;
         GH[pH - jj] = conj(G);
       }
