@@ -166,19 +166,24 @@ __device__ __forceinline__ void mat_scan_lanes(double& e00, double& e01, double&
 // recurrences themselves always run in FP64.  eb = e^{-b} and omq = 1 - e^{-b}
 // (from expm1) give the recurrence coefficients: 4 cosh b = 2 (1/eb + eb) and
 // 8 sinh^2(b/2) = 2 omq^2 / eb, the latter free of cancellation at small b.
+//
+// Returns the factor by which A still has to be multiplied: 1, except on the
+// FP64 Miller path with `defer` set, where the values stay as the recurrence
+// left them and the caller applies A_0 / y_0 (to a linear function of A) itself.
 template <class R>
-__device__ __forceinline__ void singular_factor_wave(double b, double eb, double omq, double A0,
-                                                     double D1, int mtop, R* A) {
+__device__ __forceinline__ double singular_factor_wave(double b, double eb, double omq, double A0,
+                                                       double D1, int mtop, R* A,
+                                                       bool defer = false) {
   const int lane = threadIdx.x & 63;
   if (!(b > 0) || !(A0 == A0)) {
     for (int m = lane; m <= mtop; m += 64) A[m] = (R)__builtin_nan("");
     wave_sync();
-    return;
+    return 1.0;
   }
   if (mtop == 0) {
     if (lane == 0) A[0] = (R)A0;
     wave_sync();
-    return;
+    return 1.0;
   }
   if ((double)mtop * b <= kTauFwd) {
     // ---- forward: w_{m+1} = F_m w_m, w = (D, A),
@@ -217,7 +222,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double eb, double
     }
     if (lane == 0) { A[0] = (R)A0; A[1] = (R)(A0 + D1); }
     wave_sync();
-    return;
+    return 1.0;
   }
   // ---- Miller, backward: v_{m-1} = T_m v_m, v_m = (y_m, y_{m+1}),
   //      T_m = [[4 m cosh b/(2m-1), -(2m+1)/(2m-1)], [1, 0]], m = N .. 1
@@ -230,7 +235,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double eb, double
     if (N < 1) {   // b > 640: A_m / A_0 < 1e-270 for every m >= 1
       for (int m = lane; m <= mtop; m += 64) A[m] = (R)((m == 0) ? A0 : 0.0);
       wave_sync();
-      return;
+      return 1.0;
     }
   }
   const double ch4 = 2.0 * (rcp_refined(eb) + eb);
@@ -265,6 +270,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double eb, double
     }
     wave_sync();
     const double scale = A0 * rcp_refined(A[0]);
+    if (defer && meff == mtop) return scale;
     wave_sync();
     for (int m = lane; m <= mtop; m += 64) A[m] = (m <= meff) ? A[m] * scale : 0.0;
   } else {
@@ -282,6 +288,7 @@ __device__ __forceinline__ void singular_factor_wave(double b, double eb, double
     for (int m = N + lane; m <= mtop; m += 64) A[m] = (R)0.0;
   }
   wave_sync();
+  return 1.0;
 }
 
 // ===========================================================================
@@ -925,13 +932,16 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     R* A = (paper ? reinterpret_cast<R*>(Z1) : (want_c ? reinterpret_cast<R*>(Z2) : Acompact)) +
            NF / 2;
     const int mtop = paper ? L + pF : (want_c ? max(L + pF, M + pH) : M + pH);
-    singular_factor_wave(b, eb, omq, rr.A0, rr.D1, mtop, A);
+    // on the FP64 path A may come back unnormalised: its factor rides on the
+    // phases of the convolutions, which are linear in A
+    const double asc = singular_factor_wave(b, eb, omq, rr.A0, rr.D1, mtop, A, true);
+    const cplx ph_conv = ph_lane * asc;
     for (int m = 1 + lane; m <= max(pF, pH); m += 64) A[-m] = A[m];
     wave_sync();
 
     // ---- <rho^-1>_l, l = 0..L (eq. (3.25)) into cb[L + l] (and cb[L - l] = conj)
     if (want_c) {
-      swap_convolution<C>(GF, pF, A, L, ph_lane, ph64, cb + L, cb + L, crow);
+      swap_convolution<C>(GF, pF, A, L, ph_conv, ph64, cb + L, cb + L, crow);
       wave_sync();
     }
     // ---- kc_n = <cos(k rho)/rho>_n, n = 0..M
@@ -960,7 +970,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
       if (lane == 0) kc[M] = C{accr, acci};
     } else {
       // swap applied to cos(k rho)/rho
-      swap_convolution<C>(GH, pH, A, M, ph_lane, ph64, kc, nullptr, nullptr);
+      swap_convolution<C>(GH, pH, A, M, ph_conv, ph64, kc, nullptr, nullptr);
     }
     wave_sync();
     // ---- kappa_n = kc_n + i <sin(k rho)/rho>_n, n = -M+1..M at column n + M - 1
