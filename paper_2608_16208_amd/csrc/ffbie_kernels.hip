@@ -172,9 +172,8 @@ __device__ __forceinline__ void mat_scan_lanes(double& e00, double& e01, double&
 // left them and the caller applies A_0 / y_0 (to a linear function of A) itself.
 template <class R>
 __device__ __forceinline__ double singular_factor_wave(double b, double eb, double omq, double A0,
-                                                       double D1, int mtop, R* A,
-                                                       bool defer = false) {
-  const int lane = threadIdx.x & 63;
+                                                       double D1, int mtop, R* A, bool defer,
+                                                       int lane) {
   if (!(b > 0) || !(A0 == A0)) {
     for (int m = lane; m <= mtop; m += 64) A[m] = (R)__builtin_nan("");
     wave_sync();
@@ -301,9 +300,8 @@ __device__ __forceinline__ double singular_factor_wave(double b, double eb, doub
 // ===========================================================================
 template <class C>
 __device__ __forceinline__ void fft_stockham(C*& ia, C*& oa, C*& ib, C*& ob, bool two, int NF, int M,
-                                             const double* tab, int mask, int quarter) {
+                                             const double* tab, int mask, int quarter, int lane) {
   using R = decltype(C::re);
-  const int lane = threadIdx.x & 63;
   const int half = NF >> 1;
   for (int Ns = 1; Ns < NF; Ns <<= 1) {
     for (int jj = lane; jj < half; jj += 64) {
@@ -481,8 +479,7 @@ __device__ __forceinline__ int fft128_out_index(int lane) {
 // Forward DFT as fft_stockham for NF <= 128 with the twiddles of build_twiddles.
 template <class C>
 __device__ __forceinline__ void fft_stockham_small(C*& ia, C*& oa, C*& ib, C*& ob, bool two, int NF,
-                                                   const C* tw) {
-  const int lane = threadIdx.x & 63;
+                                                   const C* tw, int lane) {
   const int half = NF >> 1;
   for (int st = 0; (1 << st) < NF; ++st) {
     const int Ns = 1 << st;
@@ -514,9 +511,9 @@ __device__ __forceinline__ void fft_stockham_small(C*& ia, C*& oa, C*& ib, C*& o
 // stage 2 Ns), else from the angle table; w^2 and w^3 by multiplication.
 template <class C>
 __device__ __forceinline__ void fft_stockham_r4(C*& ia, C*& oa, C*& ib, C*& ob, bool two, int NF, int M,
-                                                const double* tab, int mask, int quarter, const C* tw) {
+                                                const double* tab, int mask, int quarter, const C* tw,
+                                                int lane) {
   using R = decltype(C::re);
-  const int lane = threadIdx.x & 63;
   const int q4 = NF >> 2;
   int Ns = 1, st2 = 1;                 // st2 = log2(2 Ns)
   for (; 4 * Ns <= NF; Ns <<= 2, st2 += 2) {
@@ -603,9 +600,8 @@ __device__ __forceinline__ C imag_part_coeff(const C* X, int jj, int NF, decltyp
 // floor still follows F.
 template <class C>
 __device__ __forceinline__ int trunc_index_real(const C* X, int NF, decltype(C::re) invNF, double eps,
-                                                double ref) {
+                                                double ref, int lane) {
   using R = decltype(C::re);
-  const int lane = threadIdx.x & 63;
   R maxv = 0;
   for (int jj = lane; jj < NF / 2; jj += 64) maxv = fmax(maxv, abs2(real_part_coeff(X, jj, NF, invNF)));
   maxv = fmax(wave_max(maxv), (R)(ref * ref));
@@ -632,10 +628,10 @@ __device__ __forceinline__ int trunc_index_real(const C* X, int NF, decltype(C::
 // (the sum of eq. (3.25)).  A must be mirrored: A[-m] = A[m] for m <= p.
 template <class C>
 __device__ __forceinline__ void swap_convolution(const C* G, int p, const decltype(C::re)* A, int nmax,
-                                                 cplx ph, cplx ph64, C* out, C* mirror, C* global_row) {
+                                                 cplx ph, cplx ph64, C* out, C* mirror, C* global_row,
+                                                 int lane) {
   using R = decltype(C::re);
   using SP = Spec<R>;
-  const int lane = threadIdx.x & 63;
   const int cnt = nmax + 1;
   const int rem = cnt & 63;
   const int split = (cnt > 64 && rem <= 4) ? cnt - rem : cnt;
@@ -715,7 +711,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
   using SP = Spec<R>;
   const Prob& P = a.P;
   const int M = P.M, M0 = P.M0, L = P.L, mask = P.tab_n - 1, quarter = 2 * M;
-  const int lane = threadIdx.x & 63;
+  const int lane0 = threadIdx.x & 63;
   const bool paper = a.variant == FFBIE_KAPPA_PAPER_CONV;
   const bool want_c = paper || a.rhoinv != nullptr;
   // the 128-point transform in registers where the twiddles are laid out for
@@ -750,6 +746,12 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
   PairGeo<MM> pg;
 
   for (int64_t w = beg; w < end; ++w) {
+    // The lane index is made opaque once per pair so that lane-derived
+    // constants (LDS and global addresses, transform signs and indices) are
+    // formed where they are used rather than hoisted out of this loop and held,
+    // or spilled, throughout it.
+    int lane = lane0;
+    asm volatile("" : "+v"(lane));
     const int64_t pi = a.list ? a.list[w] : w;
     const double t = a.t_in[pi], ts = a.ts_in[pi];
     const int j = a.az_in[pi] & (2 * M - 1);
@@ -820,12 +822,8 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     C *Z1 = z1a, *free1 = z1b, *Z2 = z2a, *free2 = z2b;
     // With the transforms in registers the lane's two samples are the
     // bit-reversed positions lane and lane + 64 (samples 2 brev6(lane) + i) and
-    // stay in registers; otherwise sample q = lane + 64 i goes to LDS.  The lane
-    // index is made opaque so that the lane constants of the register transform
-    // (signs, sample and output indices) are formed where they are used rather
-    // than hoisted out of the pair loop and held in registers throughout it.
-    int fl = lane;
-    asm volatile("" : "+v"(fl));
+    // stay in registers; otherwise sample q = lane + 64 i goes to LDS.
+    const int fl = lane;
     const int q0 = (int)(__builtin_bitreverse32((unsigned)fl) >> 25);
     C a0, a1;
 #pragma unroll 1
@@ -852,11 +850,11 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
       wave_sync();
       // at NF = 128 the radix-2 twiddle table is in the register layout
       if constexpr (RADIX == 4)
-        fft_stockham_r4(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter, tw);
+        fft_stockham_r4(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter, tw, lane);
       else if (tw && NF != 128)
-        fft_stockham_small(Z1, free1, Z2, free2, want_c, NF, tw);
+        fft_stockham_small(Z1, free1, Z2, free2, want_c, NF, tw, lane);
       else
-        fft_stockham(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter);
+        fft_stockham(Z1, free1, Z2, free2, want_c, NF, M, tab, mask, quarter, lane);
     }
 
     // truncation indices of the smooth factors.  With one transform and
@@ -874,9 +872,9 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
       const uint64_t bal = __ballot(a2 > (R)(P.eps0 * P.eps0) * maxv);
       pH = __builtin_amdgcn_readfirstlane(bal ? 63 - __clzll(bal) : 0);
     } else {
-      pH = paper ? 0 : trunc_index_real(Z1, NF, invNF, P.eps0, F0);
+      pH = paper ? 0 : trunc_index_real(Z1, NF, invNF, P.eps0, F0, lane);
     }
-    const int pF = want_c ? trunc_index_real(Fsrc, NF, invNF, P.eps0, 0.0) : 0;
+    const int pF = want_c ? trunc_index_real(Fsrc, NF, invNF, P.eps0, 0.0, lane) : 0;
     if (max(pF, pH) >= NF / 2 - 2) {
       if (!REFINE && a.flag_list) {
         // not resolved on this grid: queue for the 4M-sample pass
@@ -934,14 +932,14 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     const int mtop = paper ? L + pF : (want_c ? max(L + pF, M + pH) : M + pH);
     // on the FP64 path A may come back unnormalised: its factor rides on the
     // phases of the convolutions, which are linear in A
-    const double asc = singular_factor_wave(b, eb, omq, rr.A0, rr.D1, mtop, A, true);
+    const double asc = singular_factor_wave(b, eb, omq, rr.A0, rr.D1, mtop, A, true, lane);
     const cplx ph_conv = ph_lane * asc;
     for (int m = 1 + lane; m <= max(pF, pH); m += 64) A[-m] = A[m];
     wave_sync();
 
     // ---- <rho^-1>_l, l = 0..L (eq. (3.25)) into cb[L + l] (and cb[L - l] = conj)
     if (want_c) {
-      swap_convolution<C>(GF, pF, A, L, ph_conv, ph64, cb + L, cb + L, crow);
+      swap_convolution<C>(GF, pF, A, L, ph_conv, ph64, cb + L, cb + L, crow, lane);
       wave_sync();
     }
     // ---- kc_n = <cos(k rho)/rho>_n, n = 0..M
@@ -970,7 +968,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
       if (lane == 0) kc[M] = C{accr, acci};
     } else {
       // swap applied to cos(k rho)/rho
-      swap_convolution<C>(GH, pH, A, M, ph_conv, ph64, kc, nullptr, nullptr);
+      swap_convolution<C>(GH, pH, A, M, ph_conv, ph64, kc, nullptr, nullptr, lane);
     }
     wave_sync();
     // ---- kappa_n = kc_n + i <sin(k rho)/rho>_n, n = -M+1..M at column n + M - 1
@@ -1141,7 +1139,7 @@ __global__ __launch_bounds__(256) void ffbie_singular_factor_kernel(int64_t n,
     A0 = M_2_PI * K;
     D1 = M_2_PI * (expm1(b) * K - exp(b) * E);
   }
-  singular_factor_wave(b, exp(-b), -expm1(-b), A0, D1, mtop, A);
+  singular_factor_wave(b, exp(-b), -expm1(-b), A0, D1, mtop, A, false, lane);
   for (int m = lane; m <= mtop; m += 64) out[idx * (mtop + 1) + m] = A[m];
 }
 
