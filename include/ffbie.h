@@ -213,8 +213,12 @@ ffbie_status ffbie_kernel_coeffs_batched(ffbie_ctx *ctx, int n_items, const ffbi
  *                    odd); 0: radix 4 for N_F >= 256 points, else radix 2,
  *   pairs_per_item   pairs a wavefront takes from one batch work item (1..256),
  *   waves_per_block  wavefronts per workgroup of the batched launch (1, 2, 4;
- *                    lowered to what fits 64 KiB of LDS).
- * A context starts with {0, 16, 4}; its fft_radix also applies to
+ *                    lowered to what fits 64 KiB of LDS),
+ *   persistent       batched main pass: 1 = a bounded grid whose wavefronts
+ *                    take work items from a queue until it is empty; 0 = one
+ *                    wavefront per work item (taken as 1 when that grid would
+ *                    exceed 2^32 work-items).
+ * A context starts with {0, 16, 4, 0}; its fft_radix also applies to
  * ffbie_kernel_coeffs(_mixed) and the near blocks of ffbie_assemble.  Results
  * do not depend on the tuning beyond rounding (the transforms differ in
  * operation order). */
@@ -222,6 +226,7 @@ typedef struct {
   int fft_radix;
   int pairs_per_item;
   int waves_per_block;
+  int persistent;
 } ffbie_tuning;
 ffbie_status ffbie_set_tuning(ffbie_ctx *ctx, const ffbie_tuning *tuning);
 ffbie_status ffbie_get_tuning(const ffbie_ctx *ctx, ffbie_tuning *tuning);
@@ -229,17 +234,18 @@ ffbie_status ffbie_get_tuning(const ffbie_ctx *ctx, ffbie_tuning *tuning);
 /* Batch plans: the batched coefficient path of ffbie_kernel_coeffs_batched,
  * prepared once and executed any number of times (for instance with new pair
  * data in the same buffers).  The problems are grouped by M; each group (an
- * "M class") runs its main pass and its refine pass as one persistent launch
- * over (problem, run of pairs) work items, after one root launch for all.  ffbie_batch_plan_create validates the items
+ * "M class") runs its main pass as one launch over (problem, run of pairs)
+ * work items (persistent or one wavefront per item, see ffbie_tuning) and its
+ * refine pass as one persistent launch, after one root launch for all.  ffbie_batch_plan_create validates the items
  * (HOST array; the device buffers they name must stay valid for the plan's
  * life), orders them, uploads the descriptors and allocates the plan's own
  * workspace (root records, refine queue, counters: about 44 B per pair).
  * flags (or-ed):
  *   FFBIE_PLAN_AUTOTUNE  for each M class of the batch, time its main pass for
  *                        every candidate tuning (radix {2, 4} x pairs_per_item
- *                        {8, 16, 32} x waves_per_block {1, 2, 4}) and keep the
- *                        fastest; the creating call then runs the main pass
- *                        ~36 times,
+ *                        {8, 16, 32} x waves_per_block {1, 2, 4} x persistent
+ *                        {0, 1}) and keep the fastest; the creating call then
+ *                        runs the main pass ~72 times,
  *   FFBIE_PLAN_GRAPH     capture the launch sequence (counter reset, root,
  *                        main and refine passes) in a HIP graph that execute
  *                        replays on the context's stream,

@@ -58,7 +58,7 @@ class _BatchItem(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("fft_radix", ctypes.c_int), ("pairs_per_item", ctypes.c_int),
-                ("waves_per_block", ctypes.c_int)]
+                ("waves_per_block", ctypes.c_int), ("persistent", ctypes.c_int)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -282,15 +282,15 @@ class Context:
         kernel_coeffs_batched; with mixed=True the kappa outputs are complex64)."""
         return BatchPlan(self, problems, graph, autotune, mixed, tuning)
 
-    def set_tuning(self, fft_radix=0, pairs_per_item=16, waves_per_block=4):
-        t = _Tuning(fft_radix, pairs_per_item, waves_per_block)
+    def set_tuning(self, fft_radix=0, pairs_per_item=16, waves_per_block=4, persistent=0):
+        t = _Tuning(fft_radix, pairs_per_item, waves_per_block, persistent)
         self._check(self.lib.ffbie_set_tuning(self.h, ctypes.byref(t)), self.h)
 
     def get_tuning(self):
         t = _Tuning()
         self._check(self.lib.ffbie_get_tuning(self.h, ctypes.byref(t)), self.h)
         return {"fft_radix": t.fft_radix, "pairs_per_item": t.pairs_per_item,
-                "waves_per_block": t.waves_per_block}
+                "waves_per_block": t.waves_per_block, "persistent": t.persistent}
 
     def enable_timing(self, on=True):
         self._check(self.lib.ffbie_enable_timing(self.h, int(bool(on))), self.h)
@@ -487,7 +487,8 @@ class BatchPlan:
             t = (_Tuning * 4)()
             for q, M in enumerate((16, 32, 64, 128)):
                 d = tuning.get(M, base) if all(isinstance(k, int) for k in tuning) else tuning
-                t[q] = _Tuning(d["fft_radix"], d["pairs_per_item"], d["waves_per_block"])
+                t[q] = _Tuning(d["fft_radix"], d["pairs_per_item"], d["waves_per_block"],
+                               d.get("persistent", 0))
         h = ctypes.c_void_p()
         rc = ctx.lib.ffbie_batch_plan_create(ctx.h, len(problems), self.arr, flags, t, ctypes.byref(h))
         ctx._check(rc, ctx.h)
@@ -501,7 +502,8 @@ class BatchPlan:
         return self.outs
 
     def tuning(self):
-        """Per M class: {M, fft_radix, pairs_per_item, waves_per_block, tuned_ms}."""
+        """Per M class: {M, fft_radix, pairs_per_item, waves_per_block, persistent,
+        tuned_ms}."""
         out = []
         for k in range(self.ctx.lib.ffbie_batch_plan_classes(self.h)):
             t, ms, M = _Tuning(), ctypes.c_double(), ctypes.c_int()
@@ -509,7 +511,8 @@ class BatchPlan:
                                                           ctypes.byref(M))
             self.ctx._check(rc, self.ctx.h)
             out.append({"M": M.value, "fft_radix": t.fft_radix, "pairs_per_item": t.pairs_per_item,
-                        "waves_per_block": t.waves_per_block, "tuned_ms": ms.value})
+                        "waves_per_block": t.waves_per_block, "persistent": t.persistent,
+                        "tuned_ms": ms.value})
         return out
 
     def close(self):

@@ -73,7 +73,9 @@ struct ffbie_ctx {
   int64_t krylov_n = 0;
   // batched coefficients
   double* d_tabs[4] = {nullptr, nullptr, nullptr, nullptr};   // angle tables for M = 16 .. 128
-  ffbie_tuning tune{0, kBatchTile, 4};   // FFT radix (0: by N_F), pairs per batch work item, waves per workgroup
+  // FFT radix (0: by N_F), pairs per batch work item, waves per workgroup,
+  // persistent batch launches
+  ffbie_tuning tune{0, kBatchTile, 4, 0};
   ffbie_batch_plan* oneshot = nullptr;    // plan of the last ffbie_kernel_coeffs_batched call
   // learned preconditioner
   Mlp mlp;
@@ -533,6 +535,7 @@ bool valid_tuning(const ffbie_tuning& t, std::string* why) {
     *why = "waves_per_block must be 1, 2 or 4";
     return false;
   }
+  if (t.persistent != 0 && t.persistent != 1) { *why = "persistent must be 0 or 1"; return false; }
   return true;
 }
 
@@ -602,7 +605,12 @@ hipError_t launch_class_main(const ffbie_batch_plan* pl, int k, hipStream_t stre
   b.tw_max = q.tw;
   b.tile = q.tune.pairs_per_item;
   b.radix = (q.tune.fft_radix == 4 || (q.tune.fft_radix == 0 && 2 * q.M >= 256)) ? 4 : 2;
-  const int64_t blocks = std::min<int64_t>((q.n_items + q.waves - 1) / q.waves, kMainBlocks);
+  b.persistent = q.tune.persistent;
+  // persistent: at most kMainBlocks workgroups loop over the items; otherwise
+  // one wavefront per item
+  int64_t blocks = (q.n_items + q.waves - 1) / q.waves;
+  if (blocks * 64 * q.waves >= ((int64_t)1 << 32)) b.persistent = 1;   // grid size limit
+  if (b.persistent) blocks = std::min<int64_t>(blocks, kMainBlocks);
   return launch_batch(b, pl->mm, blocks, 64 * q.waves, q.lds, stream, 1, pl->single);
 }
 
@@ -752,9 +760,10 @@ ffbie_status plan_autotune(ffbie_ctx* c, ffbie_batch_plan* pl) {
     float best_ms = -1.0f;
     for (int radix : {2, 4})
       for (int ppi : {8, 16, 32})
-        for (int waves : {1, 2, 4}) {
+        for (int waves : {1, 2, 4})
+          for (int pers : {0, 1}) {
           if (st != FFBIE_OK) break;
-          if ((st = plan_shape(c, pl, k, ffbie_tuning{radix, ppi, waves})) != FFBIE_OK) break;
+          if ((st = plan_shape(c, pl, k, ffbie_tuning{radix, ppi, waves, pers})) != FFBIE_OK) break;
           if (pl->cls[k].waves != waves) continue;          // does not fit the LDS
           float ms = 0.0f;
           for (int rep = 0; rep < 2 && st == FFBIE_OK; ++rep) {   // the first run warms up

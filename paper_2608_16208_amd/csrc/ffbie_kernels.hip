@@ -1017,12 +1017,13 @@ __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbi
 
 // ===========================================================================
 // Batched coefficient path: many problems (surfaces, panel counts, k) of one
-// M in one persistent launch.  The angle table and the FFT twiddles depend
-// only on M, so each workgroup stages them once.  Work items are runs of
-// b.tile consecutive pairs of one problem, numbered problem by problem; each
-// wavefront takes the next item from a global counter on its own (no
-// workgroup barrier between items) and leaves once the counter passes the last
-// item.
+// M in one launch.  The angle table and the FFT twiddles depend only on M, so
+// each workgroup stages them once.  Work items are runs of b.tile consecutive
+// pairs of one problem, numbered problem by problem.  PERSIST: each wavefront
+// takes the next item from a global counter on its own (no workgroup barrier
+// between items) and leaves once the counter passes the last item; otherwise
+// the grid has one wavefront per item and the hardware dispatcher balances
+// the load (no loop around the pair loop, so nothing held across items).
 // ===========================================================================
 __device__ __forceinline__ int batch_find(const int64_t* __restrict__ prefix, int n, int64_t x) {
   int lo = 0, hi = n - 1;                     // last problem with prefix[s] <= x
@@ -1033,7 +1034,7 @@ __device__ __forceinline__ int batch_find(const int64_t* __restrict__ prefix, in
   return lo;
 }
 
-template <int MM, class R, int RADIX>
+template <int MM, class R, int RADIX, bool PERSIST>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbie_coeff_batch_kernel_t(
     BatchArgs b) {
@@ -1051,16 +1052,24 @@ __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbi
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int per_wave = coeff_lds_per_wave(NF, M, a0.P.L, true, single);
   double* wbase = smem + b.tab_max + b.tw_max + (size_t)wave * per_wave;
-  while (true) {
-    int64_t item = 0;
-    if ((threadIdx.x & 63) == 0) item = atomicAdd(b.item_counter, 1);
-    item = __shfl(item, 0);
-    if (item >= b.n_items) break;
+  auto run_item = [&](int64_t item) {
     const int s = batch_find(b.item_prefix, b.n_probs, item);
     const CoeffArgs& a = b.probs[s];
     const int64_t t0 = (item - b.item_prefix[s]) * b.tile;
     const int64_t beg = min(a.n, t0), end = min(a.n, t0 + b.tile);
     coeff_range<MM, false, R, RADIX>(a, smem, tw, wbase, NF, beg, end);
+  };
+  if constexpr (PERSIST) {
+    while (true) {
+      int64_t item = 0;
+      if ((threadIdx.x & 63) == 0) item = atomicAdd(b.item_counter, 1);
+      item = __shfl(item, 0);
+      if (item >= b.n_items) break;
+      run_item(item);
+    }
+  } else {
+    const int64_t item = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (item < b.n_items) run_item(item);
   }
 }
 
@@ -1198,10 +1207,14 @@ hipError_t launch_batch(const BatchArgs& b, int mm, int64_t blocks, int threads,
 #define P12(MMV, RT)                                                                             \
   if (phase == 2)                                                                                \
     hipLaunchKernelGGL((ffbie_coeff_batch_refine_t<MMV, RT>), grid, block, lds, stream, b);     \
+  else if (r4 && b.persistent)                                                                   \
+    hipLaunchKernelGGL((ffbie_coeff_batch_kernel_t<MMV, RT, 4, true>), grid, block, lds, stream, b); \
   else if (r4)                                                                                   \
-    hipLaunchKernelGGL((ffbie_coeff_batch_kernel_t<MMV, RT, 4>), grid, block, lds, stream, b);  \
+    hipLaunchKernelGGL((ffbie_coeff_batch_kernel_t<MMV, RT, 4, false>), grid, block, lds, stream, b); \
+  else if (b.persistent)                                                                         \
+    hipLaunchKernelGGL((ffbie_coeff_batch_kernel_t<MMV, RT, 2, true>), grid, block, lds, stream, b); \
   else                                                                                           \
-    hipLaunchKernelGGL((ffbie_coeff_batch_kernel_t<MMV, RT, 2>), grid, block, lds, stream, b)
+    hipLaunchKernelGGL((ffbie_coeff_batch_kernel_t<MMV, RT, 2, false>), grid, block, lds, stream, b)
 #define X(MMV)                                                                                   \
   case MMV:                                                                                      \
     if (phase == 0)                                                                              \

@@ -54,6 +54,8 @@ struct BatchArgs {
   int tile;                  // pairs per work item (one wavefront)
   int prob_lo, prob_hi;      // refine pass: the class's problems
   int radix;                 // main pass: FFT radix of the class (2 or 4)
+  int persistent;            // main pass: 1 = wavefronts loop over work items taken
+                             // from item_counter; 0 = work item = global wavefront index
 };
 
 // Per-wavefront LDS of the coefficient kernel, in doubles, with the spectral

@@ -131,6 +131,7 @@ def test_plan_autotune_picks_a_candidate_and_keeps_results(ctx):
     for t in tun:
         assert t["fft_radix"] in (2, 4) and t["pairs_per_item"] in (8, 16, 32)
         assert t["waves_per_block"] in (1, 2, 4) and t["tuned_ms"] > 0
+        assert t["persistent"] in (0, 1)
     plan.execute()
     torch.cuda.synchronize()
     for p, o in zip(probs, plan.outs):
@@ -148,8 +149,8 @@ def test_plan_autotune_picks_a_candidate_and_keeps_results(ctx):
 def test_plan_explicit_tuning_per_M(ctx):
     """A tuning table by M is applied class by class."""
     probs = _problems()
-    want = {64: dict(fft_radix=4, pairs_per_item=8, waves_per_block=1),
-            128: dict(fft_radix=2, pairs_per_item=32, waves_per_block=2)}
+    want = {64: dict(fft_radix=4, pairs_per_item=8, waves_per_block=1, persistent=1),
+            128: dict(fft_radix=2, pairs_per_item=32, waves_per_block=2, persistent=0)}
     plan = ctx.batch_plan(_items(probs), tuning=want)
     got = {t["M"]: t for t in plan.tuning()}
     for M, w in want.items():
@@ -212,9 +213,32 @@ def test_plan_mixed_matches_single_mixed_calls(ctx):
     plan.close()
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_persistent_and_per_item_launches_agree(ctx, mixed):
+    """The batched main pass as a persistent launch (wavefronts loop over a
+    work queue) and as one wavefront per work item run the same per-pair
+    routine: the rows agree to rounding and the pair flags exactly."""
+    probs = _problems()
+    outs = []
+    for pers in (0, 1):
+        tun = dict(fft_radix=2, pairs_per_item=16, waves_per_block=4, persistent=pers)
+        plan = ctx.batch_plan(_items(probs), mixed=mixed, tuning=tun)
+        assert all(t["persistent"] == pers for t in plan.tuning())
+        plan.execute()
+        torch.cuda.synchronize()
+        outs.append([(o["kappa"].cpu().numpy(), o["status"].cpu().numpy()) for o in plan.outs])
+        plan.close()
+    tol = 1e-5 if mixed else 1e-12
+    for (ka, sa), (kb, sb) in zip(*outs):
+        assert np.array_equal(sa & 0xff, sb & 0xff)
+        if ka.size:
+            assert np.max(np.abs(ka - kb)) <= tol * np.max(np.abs(ka))
+
+
 def test_tuning_validation(ctx):
     import paper_2608_16208_amd as ffbie
-    for bad in (dict(fft_radix=3), dict(pairs_per_item=0), dict(waves_per_block=3)):
+    for bad in (dict(fft_radix=3), dict(pairs_per_item=0), dict(waves_per_block=3),
+                dict(persistent=2)):
         with pytest.raises(ffbie.FfbieError):
             ctx.set_tuning(**bad)
     assert ctx.get_tuning()["fft_radix"] in (0, 2, 4)
