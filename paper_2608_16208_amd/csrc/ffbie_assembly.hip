@@ -20,6 +20,7 @@
 //   field, rhs    one workgroup per (point, source chunk) with a fixed-order
 //                 reduction; one thread per collocation point
 #include "ffbie_assembly.hpp"
+#include "ffbie_fft128.hpp"
 
 namespace ffbie {
 
@@ -119,6 +120,8 @@ __global__ __launch_bounds__(256) void near_pairs_kernel(SysDims d, NearChunk ch
 
 constexpr int kFarRows = 8;
 
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
 __global__ __launch_bounds__(256) void far_kernel(SysDims d, double k, Colloc c,
                                                   cplx* __restrict__ S, int64_t ld) {
   const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -133,11 +136,15 @@ __global__ __launch_bounds__(256) void far_kernel(SysDims d, double k, Colloc c,
     const int pr = (int)(r / per_panel);
     if (abs(pr - pc) <= 1) continue;
     const double dx = xc - c.x[r], dy = yc - c.y[r], dz = zc - c.z[r];
-    const double rho = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
-    const double f = wc / rho;
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double ri = rsqrt_refined(r2);             // far points are distinct: r2 > 0
+    const double rho = r2 * ri;
+    const double f = wc * ri;
     double s, co;
     sincos_bounded(k * rho, &s, &co);
-    S[r * ld + col] = mk(f * co, f * s);
+    // S is written once here and not read back by this pass: streaming stores
+    const dbl2 v = {f * co, f * s};
+    __builtin_nontemporal_store(v, reinterpret_cast<dbl2*>(S + r * ld + col));
   }
 }
 
@@ -223,6 +230,75 @@ __global__ __launch_bounds__(256) void near_kernel(SysDims d, NearChunk ch,
       srow[(int64_t)(g0 + s) * NF + jp] = src[s * NF + jp];
     }
     __syncthreads();
+  }
+}
+
+// The same near block for N_F = 128 (M = 64).  The contraction gives each
+// thread one column and 8 of the 16 rows, so a coefficient is read from memory
+// by two threads instead of by one per row; the inverse DFT of each row,
+// w_j' = sum_n c_n e^{+2 pi i n j' / 128} = conj(FFT(conj(c)))_j', is done by one
+// wavefront in registers (fft128_regs), whose result goes straight to S.  The
+// twiddles come from the angle table in global memory (no LDS copy of it).
+__global__ __launch_bounds__(256) void near_kernel128(SysDims d, NearChunk ch,
+                                                      const cplx* __restrict__ kappa,
+                                                      const double* __restrict__ wl,
+                                                      const double* __restrict__ tab_g,
+                                                      cplx* __restrict__ S, int64_t ld) {
+  constexpr int NF = 128;
+  __shared__ double w_s[kNodes * kNodes];
+  __shared__ cplx tw[7 * 64];
+  __shared__ cplx buf[kNodes * NF];
+  const int M = d.M;
+  const int64_t tgt = blockIdx.x / 3;
+  const int slot = blockIdx.x % 3;
+  const int j = (int)(tgt % NF);
+  const int l = (int)((tgt / NF) % kNodes);
+  const int i = ch.p0 + (int)(tgt / ((int64_t)NF * kNodes));
+  const int nrel = near_relations(i, d.n_panels);
+  if (slot >= nrel) return;                          // uniform over the block
+  const int rel = (i > 0) ? slot - 1 : slot;
+  const int64_t p0 = near_pairs_before(i, d) - ch.pair_base +
+                     (((int64_t)l * NF + j) * nrel + slot) * kNodes;
+  const cplx* krow = kappa + p0 * NF;                // 16 rows of NF coefficients
+  const double* W = wl + (size_t)(l * 3 + rel + 1) * kNodes * kNodes;   // [q][l']
+  const int mask = 8 * M - 1, quarter = 2 * M;
+  for (int x = threadIdx.x; x < kNodes * kNodes; x += blockDim.x) w_s[x] = W[x];
+  for (int x = threadIdx.x; x < 7 * 64; x += blockDim.x) {
+    const int tk = fft128_twiddle_k(x >> 6, x & 63) * ((8 * M) / NF);
+    tw[x] = mk(tab_g[(tk + quarter) & mask], -tab_g[tk & mask]);
+  }
+  __syncthreads();
+
+  // contraction over the rule nodes, into natural frequency order
+  const int col = threadIdx.x & (NF - 1), s0 = (threadIdx.x >> 7) * 8;
+  cplx acc[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) acc[r] = mk(0.0, 0.0);
+#pragma unroll 4
+  for (int q = 0; q < kNodes; ++q) {
+    const cplx kv = krow[q * NF + col];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const double wv = w_s[q * kNodes + s0 + r];
+      acc[r].re = fma(wv, kv.re, acc[r].re);
+      acc[r].im = fma(wv, kv.im, acc[r].im);
+    }
+  }
+  const int pos = (col - M + 1 + NF) & (NF - 1);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) buf[(s0 + r) * NF + pos] = acc[r];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q0 = (int)(__builtin_bitreverse32((unsigned)lane) >> 25);
+  const int o = fft128_out_index(lane);
+  const int64_t row = ((int64_t)i * kNodes + l) * NF + j;
+  cplx* srow = S + row * ld + (int64_t)(i + rel) * kNodes * NF;
+  for (int s = wave; s < kNodes; s += 4) {
+    cplx x0 = conj(buf[s * NF + q0]), x1 = conj(buf[s * NF + q0 + 1]);
+    fft128_regs(x0, x1, tw, lane);
+    srow[(int64_t)s * NF + o] = conj(x0);
+    srow[(int64_t)s * NF + o + 64] = conj(x1);
   }
 }
 
@@ -341,6 +417,11 @@ hipError_t launch_near_assembly(const SysDims& d, const NearChunk& ch, const cpl
   const int NF = 2 * d.M;
   const size_t lds = sizeof(double) * (8 * d.M + kNodes * kNodes) + sizeof(cplx) * 2 * G * NF;
   const int64_t blocks = (int64_t)(ch.p1 - ch.p0) * kNodes * NF * 3;
+  if (NF == 128) {
+    hipLaunchKernelGGL(near_kernel128, dim3((unsigned)blocks), dim3(256), 0, s, d, ch, kappa, wl, tab,
+                       S, ld);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(near_kernel, dim3((unsigned)blocks), dim3(256), lds, s, d, ch, kappa, wl, tab,
                      S, ld, G);
   return hipGetLastError();

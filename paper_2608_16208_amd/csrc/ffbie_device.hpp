@@ -356,6 +356,43 @@ FFBIE_HD inline void ellip_KE(double m, double sqrt_1m, double* K, double* E) {
 }
 
 // ----------------------------------------------------------------------------
+// Refined hardware estimates (device only)
+// ----------------------------------------------------------------------------
+// 1/sqrt(x) for x > 0: hardware estimate, then two Newton steps
+// y <- y + (y/2)(1 - x y^2), each roughly squaring the relative error.
+__device__ __forceinline__ double rsqrt_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// sqrt(x) for a normal positive x (no denormal scaling, no zero or infinity
+// handling): hardware 1/sqrt estimate y, g = x y and h = y/2 refined by one
+// coupled Newton step, then two corrections g += (x - g^2) h.
+__device__ __forceinline__ double sqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
+__device__ __forceinline__ double rcp_refined(double x) {
+  // 1/x for a normal positive x: hardware estimate + two Newton steps
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// ----------------------------------------------------------------------------
 // Wave-level helpers
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ void wave_sync() {
