@@ -10,7 +10,7 @@ R = 1 + 0.2 sin(3t) cos(2 theta), k = 5, 16 panels x 16 Gauss-Legendre nodes
 azimuth, source node) pair with t_s != t: 8,355,840 pairs, 2M = 128
 coefficients each.  Inputs are resident in HBM before the timed region.
 
-Prints one JSON line (rank 0); see the design doc for the roofline accounting.
+Prints one JSON line (rank 0) with the roofline of the main coefficient pass.
 """
 import argparse
 import hashlib
@@ -333,7 +333,7 @@ def main():
                     help="first run a plain 2 GiB device copy (reference dispatch for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
