@@ -26,8 +26,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "kernel coeff pair-modes/s + time-to-1e-8 field error, mixed vs plain FP64 GPU"
 PEAK_FP64_VALU = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
-# FP32 VALU issue rate without packed (two-per-lane) instructions, which this
-# build does not generate: the same 256 x 4 x 16 x 2 x 2.4 GHz
+# FP32 VALU issue rate without packed (two-per-lane) instructions, which the
+# library's kernels are compiled without: the same 256 x 4 x 16 x 2 x 2.4 GHz
 PEAK_FP32_VALU_UNPACKED = 78.6e12
 COEFF_KERNEL = "ffbie_coeff_kernel"
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "coeff_kernel_config2_allpairs_hbm_traffic.md")
