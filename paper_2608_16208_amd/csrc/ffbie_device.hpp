@@ -104,6 +104,20 @@ struct Spec<float> {
 // then the Taylor series of sin (to r^17) and cos (to r^16) on |r| <= pi/4,
 // whose truncation errors are below 1e-19 and 3e-18.  The split and the
 // coefficients 1/n! were evaluated in 50-digit arithmetic.
+// fma for polynomial steps c + a b whose constant c is kept in a register
+// across loops: on the device one three-address v_fma_f64 (the same single
+// rounding as fma), where the compiler's two-address v_fmac_f64 form would
+// first copy the constant into the destination.
+FFBIE_HD __forceinline__ double poly_fma(double a, double b, double c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+  return d;
+#else
+  return fma(a, b, c);
+#endif
+}
+
 FFBIE_HD __forceinline__ void sincos_bounded(double x, double* s, double* c) {
   const double qf = rint(x * 0.6366197723675814);           // x * 2/pi
   double r = fma(-qf, 1.5707963267341256, x);
@@ -111,22 +125,22 @@ FFBIE_HD __forceinline__ void sincos_bounded(double x, double* s, double* c) {
   r = fma(-qf, 2.0222662487959506e-21, r);
   const double r2 = r * r;
   double ps = 2.8114572543455206e-15;                         // 1/17!
-  ps = fma(ps, r2, -7.647163731819816e-13);                  // -1/15!
-  ps = fma(ps, r2, 1.6059043836821613e-10);                  //  1/13!
-  ps = fma(ps, r2, -2.505210838544172e-08);                  // -1/11!
-  ps = fma(ps, r2, 2.7557319223985893e-06);                  //  1/9!
-  ps = fma(ps, r2, -0.0001984126984126984);                  // -1/7!
-  ps = fma(ps, r2, 0.008333333333333333);                    //  1/5!
-  ps = fma(ps, r2, -0.16666666666666666);                    // -1/3!
+  ps = poly_fma(ps, r2, -7.647163731819816e-13);                  // -1/15!
+  ps = poly_fma(ps, r2, 1.6059043836821613e-10);                  //  1/13!
+  ps = poly_fma(ps, r2, -2.505210838544172e-08);                  // -1/11!
+  ps = poly_fma(ps, r2, 2.7557319223985893e-06);                  //  1/9!
+  ps = poly_fma(ps, r2, -0.0001984126984126984);                  // -1/7!
+  ps = poly_fma(ps, r2, 0.008333333333333333);                    //  1/5!
+  ps = poly_fma(ps, r2, -0.16666666666666666);                    // -1/3!
   const double sr = fma(ps * r2, r, r);
   double pc = 4.779477332387385e-14;                          // 1/16!
-  pc = fma(pc, r2, -1.1470745597729725e-11);                 // -1/14!
-  pc = fma(pc, r2, 2.08767569878681e-09);                    //  1/12!
-  pc = fma(pc, r2, -2.755731922398589e-07);                  // -1/10!
-  pc = fma(pc, r2, 2.48015873015873e-05);                    //  1/8!
-  pc = fma(pc, r2, -0.001388888888888889);                   // -1/6!
-  pc = fma(pc, r2, 0.041666666666666664);                    //  1/4!
-  pc = fma(pc, r2, -0.5);                                    // -1/2!
+  pc = poly_fma(pc, r2, -1.1470745597729725e-11);                 // -1/14!
+  pc = poly_fma(pc, r2, 2.08767569878681e-09);                    //  1/12!
+  pc = poly_fma(pc, r2, -2.755731922398589e-07);                  // -1/10!
+  pc = poly_fma(pc, r2, 2.48015873015873e-05);                    //  1/8!
+  pc = poly_fma(pc, r2, -0.001388888888888889);                   // -1/6!
+  pc = poly_fma(pc, r2, 0.041666666666666664);                    //  1/4!
+  pc = poly_fma(pc, r2, -0.5);                                    // -1/2!
   const double cr = fma(pc, r2, 1.0);
   const int q = static_cast<int>(static_cast<long long>(qf) & 3);
   const double ss = (q & 1) ? cr : sr;
