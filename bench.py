@@ -313,6 +313,36 @@ def batch_rate(ctx, torch, n_surfaces=64, arena_bytes=32 << 30):
     return out
 
 
+def hbm_ceilings(torch, gib=14):
+    """What plain device kernels (torch fill, copy, reduction) reach on this
+    GPU: the practical ceilings the HBM-bound kernels of the path are measured
+    against beside the nominal 8 TB/s (TB/s, best of 5 HIP-event-timed runs)."""
+    dev = torch.device("cuda", 0)
+    n = gib * 2**30 // 16
+    x = torch.empty(n, dtype=torch.complex128, device=dev)
+    y = torch.empty(n // 2, dtype=torch.complex128, device=dev)
+
+    def best(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(5):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return min(ms)
+    out = {"bytes": n * 16,
+           "write_TBps": n * 16 / best(lambda: x.fill_(1.0 + 2.0j)) / 1e9,
+           "copy_TBps": n * 16 / best(lambda: y.copy_(x[: n // 2])) / 1e9,
+           "read_TBps": n * 16 / best(lambda: torch.sum(x.real)) / 1e9}
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +355,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision coefficient run")
     ap.add_argument("--config3-solve", action="store_true",
                     help="also time LU64 against LU32 + IR64 at the config-3 geometry, N = 65536")
+    ap.add_argument("--no-ceilings", action="store_true", help="skip the plain-kernel HBM ceilings")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched many-surface measurement")
     ap.add_argument("--no-solve", action="store_true",
@@ -492,6 +523,8 @@ def main():
         result["config3_geometry_solve"] = config3_solve(ctx, torch, np, ffbie)
     if not args.no_batch:
         result["batch_64_surfaces"] = batch_rate(ctx, torch)
+    if not args.no_ceilings:
+        result["hbm_ceilings"] = hbm_ceilings(torch)
     if not args.no_cpu_baseline:
         procs = min(16, os.cpu_count() or 1)
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample, procs)
