@@ -459,29 +459,42 @@ __device__ __forceinline__ int trunc_index_real(const C* X, int NF, decltype(C::
   return __builtin_amdgcn_readfirstlane(p);
 }
 
-// out_n = e^{-i n a} sum_{|j| <= p} G_j A_{|n-j|} for n = 0..nmax.  The phases
-// are FP64: ph holds e^{i n a} for n = lane and ph64 = e^{i 64 a}, so that
-// output n = lane + 64 i takes conj(ph ph64^i).  Outputs are spread over the
-// lanes; when the count exceeds a multiple of 64 by a few, those last outputs
-// are summed cooperatively (terms over lanes, then a wave sum) instead of
-// costing the whole wave another pass, with the phase read from the lane that
-// holds it.
-
+// out_n = s e^{-i n a} sum_{|j| <= p} G_j A_{|n-j|} for n = 0..nmax, s the
+// factor A still carries.  The phases are FP64: ph holds e^{i n a} for
+// n = lane and ph64 = e^{i 64 a}.  Output 0 is one real dot product: G_0 is
+// real (the mean of a real sequence, phase 1) and the j and -j terms pair to
+// 2 Re G_j A_j.  Outputs n = 1..nmax are spread over the lanes (n = lane + 1
+// + 64 i, phase e^{i (lane + 1) a} e^{i 64 a}^i); when their count exceeds a
+// multiple of 64 by a few, those last outputs are summed cooperatively (terms
+// over lanes, then a wave sum) instead of costing the whole wave another pass,
+// with the phase read from the lane that holds it.
 // G is Hermitian, G[p - j] = conj(G[p + j]), so the j and -j terms share G_j:
 //   sum_j G_j A_{|n-j|} = G_0 A_n + sum_{j >= 1} [Re G_j (A_{|n-j|} + A_{n+j})
 //                                               + i Im G_j (A_{|n-j|} - A_{n+j})]
 // (the sum of eq. (3.25)).  A must be mirrored: A[-m] = A[m] for m <= p.
 template <class C>
 __device__ __forceinline__ void swap_convolution(const C* G, int p, const decltype(C::re)* A, int nmax,
-                                                 cplx ph, cplx ph64, C* out, C* mirror, C* global_row,
-                                                 int lane) {
+                                                 cplx ph, cplx ph64, double scale, C* out, C* mirror,
+                                                 C* global_row, int lane) {
   using R = decltype(C::re);
   using SP = Spec<R>;
-  const int cnt = nmax + 1;
+  const C* Gp = G + p;           // Gp[j], j = -p..p
+  {
+    R acc0 = 0;
+    for (int jj = lane; jj <= p; jj += 64) acc0 = fma(jj == 0 ? Gp[0].re : (R)2 * Gp[jj].re, A[jj], acc0);
+    acc0 = wave_sum(acc0);
+    if (lane == 0) {
+      const C c = SP::narrow(mk(scale * (double)acc0, 0.0));
+      out[0] = c;
+      if (global_row) global_row[0] = c;
+    }
+  }
+  const int cnt = nmax;          // outputs 1..nmax
   const int rem = cnt & 63;
   const int split = (cnt > 64 && rem <= 4) ? cnt - rem : cnt;
-  const C* Gp = G + p;           // Gp[j], j = -p..p
-  for (int n = lane; n < split; n += 64) {
+  ph = ph * mk(read_lane(ph.re, 1), read_lane(ph.im, 1)) * scale;   // e^{i (lane + 1) a} s
+  for (int i = lane; i < split; i += 64) {
+    const int n = i + 1;
     const R An0 = A[n];
     R accr = Gp[0].re * An0, acci = Gp[0].im * An0, accr2 = 0, acci2 = 0;
     int j = 1;
@@ -509,8 +522,9 @@ __device__ __forceinline__ void swap_convolution(const C* G, int p, const declty
     ph = ph * ph64;
   }
   // split < cnt only when split is a multiple of 64: every lane ran split / 64
-  // passes, so lane t holds e^{i (split + t) a}
-  for (int n = split; n < cnt; ++n) {
+  // passes, so lane t holds the phase of output split + 1 + t
+  for (int i = split; i < cnt; ++i) {
+    const int n = i + 1;
     R accr = 0, acci = 0;
     for (int jj = -p + lane; jj <= p; jj += 64) {
       const C g = Gp[jj];
@@ -520,7 +534,7 @@ __device__ __forceinline__ void swap_convolution(const C* G, int p, const declty
     }
     accr = wave_sum(accr);
     acci = wave_sum(acci);
-    const cplx phn = mk(read_lane(ph.re, n - split), read_lane(ph.im, n - split));
+    const cplx phn = mk(read_lane(ph.re, i - split), read_lane(ph.im, i - split));
     if (lane == 0) {
       const C c = SP::narrow(conj(phn) * mk(accr, acci));
       out[n] = c;
@@ -778,13 +792,12 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     // on the FP64 path A may come back unnormalised: its factor rides on the
     // phases of the convolutions, which are linear in A
     const double asc = singular_factor_wave(b, eb, omq, rr.A0, rr.D1, mtop, A, true, lane);
-    const cplx ph_conv = ph_lane * asc;
     for (int m = 1 + lane; m <= max(pF, pH); m += 64) A[-m] = A[m];
     wave_sync();
 
     // ---- <rho^-1>_l, l = 0..L (eq. (3.25)) into cb[L + l] (and cb[L - l] = conj)
     if (want_c) {
-      swap_convolution<C>(GF, pF, A, L, ph_conv, ph64, cb + L, cb + L, crow, lane);
+      swap_convolution<C>(GF, pF, A, L, ph_lane, ph64, asc, cb + L, cb + L, crow, lane);
       wave_sync();
     }
     // ---- kc_n = <cos(k rho)/rho>_n, n = 0..M
@@ -813,7 +826,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
       if (lane == 0) kc[M] = C{accr, acci};
     } else {
       // swap applied to cos(k rho)/rho
-      swap_convolution<C>(GH, pH, A, M, ph_conv, ph64, kc, nullptr, nullptr, lane);
+      swap_convolution<C>(GH, pH, A, M, ph_lane, ph64, asc, kc, nullptr, nullptr, lane);
     }
     wave_sync();
     // ---- kappa_n = kc_n + i <sin(k rho)/rho>_n, n = -M+1..M at column n + M - 1
