@@ -104,10 +104,12 @@ struct Spec<float> {
 // then the Taylor series of sin (to r^17) and cos (to r^16) on |r| <= pi/4,
 // whose truncation errors are below 1e-19 and 3e-18.  The split and the
 // coefficients 1/n! were evaluated in 50-digit arithmetic.
-// fma for polynomial steps c + a b whose constant c is kept in a register
-// across loops: on the device one three-address v_fma_f64 (the same single
-// rounding as fma), where the compiler's two-address v_fmac_f64 form would
-// first copy the constant into the destination.
+// fma for polynomial steps c + a b with a constant coefficient c: on the
+// device one three-address v_fma_f64 (the same single rounding as fma) that
+// takes c from an SGPR pair, where the compiler's two-address v_fmac_f64 form
+// would first copy a register-held constant into the destination.  c must be
+// the same in every lane (a literal): an SGPR operand holds one value per
+// wavefront.
 FFBIE_HD __forceinline__ double poly_fma(double a, double b, double c) {
 #if defined(__HIP_DEVICE_COMPILE__)
   double d;
