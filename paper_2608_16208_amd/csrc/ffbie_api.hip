@@ -273,8 +273,8 @@ ffbie_status ensure_ws(ffbie_ctx* c, int64_t n) {
 }
 
 // waves per workgroup so that the coefficient kernel fits 64 KiB of LDS
-int coeff_waves(const Prob& P, int NF, bool compact, bool single, size_t* lds_bytes) {
-  const size_t per_wave = sizeof(double) * coeff_lds_per_wave(NF, P.M, P.L, compact, single);
+int coeff_waves(const Prob& P, int NF, int layout, bool single, size_t* lds_bytes) {
+  const size_t per_wave = sizeof(double) * coeff_lds_per_wave(NF, P.M, P.L, layout, single);
   const size_t tab = sizeof(double) * (P.tab_n + coeff_twiddle_doubles(NF, single));
   int w = 4;
   while (w > 1 && tab + w * per_wave > 65536) --w;
@@ -388,13 +388,14 @@ ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_
   a.rhoinv = d_rhoinv;
   a.variant = c->variant;
   a.radix = c->tune.fft_radix;
-  const bool compact = c->variant == FFBIE_KAPPA_SWAP && d_rhoinv == nullptr;
+  const int layout = c->variant == FFBIE_KAPPA_PAPER_CONV ? kLdsFull
+                     : (d_rhoinv != nullptr ? kLdsTransforms : kLdsCompact);
   {
     a.NF = 2 * P.M;
     a.flag_list = c->d_list;
     a.flag_count = c->d_count;
     size_t lds;
-    const int w = coeff_waves(P, a.NF, compact, single, &lds);
+    const int w = coeff_waves(P, a.NF, layout, single, &lds);
     // 32 consecutive pairs per wavefront: fewer wavefronts share out the
     // per-wavefront set-up (tables, spilled constants) without a long tail
     const int64_t pairs_per_wave = 32;
@@ -411,7 +412,7 @@ ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_
     a.flag_list = nullptr;
     a.flag_count = nullptr;
     size_t lds;
-    const int w = coeff_waves(P, a.NF, compact, single, &lds);
+    const int w = coeff_waves(P, a.NF, layout, single, &lds);
     FFBIE_HIP(c, launch_coeff(a, 512, w, lds, c->stream, true, single));
     if (c->timing) FFBIE_HIP(c, hipEventRecord(c->ev[3], c->stream));
   }
@@ -556,14 +557,14 @@ ffbie_status plan_shape(ffbie_ctx* c, ffbie_batch_plan* pl, int k, const ffbie_t
   PlanClass& q = pl->cls[k];
   const size_t tab = sizeof(double) * 8 * q.M;
   q.tw = coeff_twiddle_doubles(2 * q.M, pl->single);
-  const size_t per_wave = sizeof(double) * coeff_lds_per_wave(2 * q.M, q.M, 2 * q.M, true, pl->single);
+  const size_t per_wave = sizeof(double) * coeff_lds_per_wave(2 * q.M, q.M, 2 * q.M, kLdsCompact, pl->single);
   int waves = t.waves_per_block;
   while (waves > 1 && tab + q.tw * sizeof(double) + waves * per_wave > 65536) waves >>= 1;
   q.tune = t;
   q.tune.waves_per_block = waves;
   q.waves = waves;
   q.lds = tab + q.tw * sizeof(double) + waves * per_wave;
-  const size_t per_wave_r = sizeof(double) * coeff_lds_per_wave(4 * q.M, q.M, 2 * q.M, true, pl->single);
+  const size_t per_wave_r = sizeof(double) * coeff_lds_per_wave(4 * q.M, q.M, 2 * q.M, kLdsCompact, pl->single);
   q.refine_waves = 4;
   while (q.refine_waves > 1 && tab + q.refine_waves * per_wave_r > 65536) q.refine_waves >>= 1;
   q.refine_lds = tab + q.refine_waves * per_wave_r;

@@ -547,11 +547,13 @@ __device__ __forceinline__ void swap_convolution(const C* G, int p, const declty
 // ===========================================================================
 // Kernel 2: coefficients (one wavefront per pair)
 //
-// LDS per wave: four NF-complex buffers (FFT ping-pong) and cb (2L+1 complex).
+// LDS per wave: NF-complex buffers z1a, z1b (FFT ping-pong), then either A_m
+// and kc (compact layout) or z2a, z2b (and cb, 2L+1 complex, for eq. (3.10)).
 // After the FFT, Z1 (and Z2) hold transforms and free1/free2 are free:
-//   default path:   Z1 = FFT(F cos(k rho) + i sin(k rho)/rho), Z2 = FFT(F) if <rho^-1> wanted
-//                   GH -> free1, GF -> free2, A -> free2 (no <rho^-1>) or Z2,
-//                   <rho^-1> -> cb, kc -> cb (no <rho^-1>) or free2
+//   default path:   Z1 = FFT(F cos(k rho) + i sin(k rho)/rho); GH -> free1;
+//                   no <rho^-1>: A -> after z1b, kc -> cb after A;
+//                   <rho^-1>: Z2 = FFT(F), GF -> free2, A -> Z2, <rho^-1> -> the
+//                   output row, kc -> free2 (after the first convolution)
 //   eq. (3.10):     Z1 = FFT(F + i cos(k rho)), Z2 = FFT(sin(k rho)/rho)
 //                   C -> free1, GF -> free2, A -> Z1, <rho^-1> -> cb, kc -> free2
 // ===========================================================================
@@ -573,16 +575,17 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
   const int lane0 = threadIdx.x & 63;
   const bool paper = a.variant == FFBIE_KAPPA_PAPER_CONV;
   const bool want_c = paper || a.rhoinv != nullptr;
-  // the 128-point transform in registers where the twiddles are laid out for
-  // it and only one transform is taken
-  const bool reg_fft = RADIX == 2 && NF == 128 && tw != nullptr && !want_c;
+  // the 128-point transforms in registers where the twiddles are laid out for
+  // them
+  const bool reg_fft = RADIX == 2 && NF == 128 && tw != nullptr;
   C* base = reinterpret_cast<C*>(wbase);
   C* z1a = base;
   C* z1b = z1a + NF;
-  // full layout: z2a, z2b, cb; compact layout: A_m buffer and kc
+  // transforms / full layout: z2a, z2b (and cb, full); compact layout: A_m
+  // buffer and kc
   C* z2a = z1b + NF;
   C* z2b = z2a + NF;
-  C* cb = want_c ? z2b + NF : z1b + NF + (M + NF + 2) / 2;
+  C* cb = paper ? z2b + NF : z1b + NF + (M + NF + 2) / 2;
   R* Acompact = reinterpret_cast<R*>(z1b + NF);
   C* kappa = static_cast<C*>(a.kappa);
   C* rhoinv = static_cast<C*>(a.rhoinv);
@@ -681,7 +684,8 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     C *Z1 = z1a, *free1 = z1b, *Z2 = z2a, *free2 = z2b;
     // With the transforms in registers the lane's two samples are the
     // bit-reversed positions lane and lane + 64 (samples 2 brev6(lane) + i) and
-    // stay in registers; otherwise sample q = lane + 64 i goes to LDS.
+    // stay in registers (those of a second transform wait in the lane's own
+    // slots of z2a); otherwise sample q = lane + 64 i goes to LDS.
     const int fl = lane;
     const int q0 = (int)(__builtin_bitreverse32((unsigned)fl) >> 25);
     C a0, a1;
@@ -693,6 +697,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
         sample(q, z1, z2);
         if (reg_fft) {
           if (i == 0) a0 = z1; else a1 = z1;
+          if (want_c) z2a[fl + 64 * i] = z2;
         } else {
           z1a[q] = z1;
           if (want_c) z2a[q] = z2;
@@ -704,6 +709,15 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
       const int o = fft128_out_index(fl);
       z1a[o] = a0;
       z1a[o + 64] = a1;
+      if (want_c) {
+        // every lane has read its own two samples before any lane stores
+        // (the transform's cross-lane steps run in lockstep)
+        a0 = z2a[fl];
+        a1 = z2a[fl + 64];
+        fft128_regs(a0, a1, tw, fl);
+        z2a[o] = a0;
+        z2a[o + 64] = a1;
+      }
       wave_sync();
     } else {
       wave_sync();
@@ -795,10 +809,13 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     for (int m = 1 + lane; m <= max(pF, pH); m += 64) A[-m] = A[m];
     wave_sync();
 
-    // ---- <rho^-1>_l, l = 0..L (eq. (3.25)) into cb[L + l] (and cb[L - l] = conj)
-    if (want_c) {
+    // ---- <rho^-1>_l, l = 0..L (eq. (3.25)): for eq. (3.10) into cb[L + l]
+    //      (and cb[L - l] = conj), otherwise straight to the output row
+    if (paper) {
       swap_convolution<C>(GF, pF, A, L, ph_lane, ph64, asc, cb + L, cb + L, crow, lane);
       wave_sync();
+    } else if (want_c) {
+      swap_convolution<C>(GF, pF, A, L, ph_lane, ph64, asc, crow, nullptr, nullptr, lane);
     }
     // ---- kc_n = <cos(k rho)/rho>_n, n = 0..M
     C* kc = want_c ? free2 : cb;
@@ -862,7 +879,9 @@ __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbi
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int waves_per_block = blockDim.x >> 6;
   const bool want_c = a.variant == FFBIE_KAPPA_PAPER_CONV || a.rhoinv != nullptr;
-  const int per_wave = coeff_lds_per_wave(a.NF, a.P.M, a.P.L, !want_c, single);
+  const int layout = a.variant == FFBIE_KAPPA_PAPER_CONV ? kLdsFull
+                     : (a.rhoinv != nullptr ? kLdsTransforms : kLdsCompact);
+  const int per_wave = coeff_lds_per_wave(a.NF, a.P.M, a.P.L, layout, single);
   int64_t count = a.n;
   if (a.list) count = *a.list_count;
   const int64_t total_waves = (int64_t)gridDim.x * waves_per_block;
@@ -908,7 +927,7 @@ __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbi
     __syncthreads();
   }
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int per_wave = coeff_lds_per_wave(NF, M, a0.P.L, true, single);
+  const int per_wave = coeff_lds_per_wave(NF, M, a0.P.L, kLdsCompact, single);
   double* wbase = smem + b.tab_max + b.tw_max + (size_t)wave * per_wave;
   auto run_item = [&](int64_t item) {
     const int s = batch_find(b.item_prefix, b.n_probs, item);
@@ -944,7 +963,7 @@ __global__ __launch_bounds__(256) void ffbie_coeff_batch_refine_t(BatchArgs b) {
   const int waves_per_block = blockDim.x >> 6;
   const int NF = 4 * a0.P.M;
   double* wbase = smem + b.tab_max +
-                  (size_t)wave * coeff_lds_per_wave(NF, a0.P.M, a0.P.L, true, sizeof(R) == 4);
+                  (size_t)wave * coeff_lds_per_wave(NF, a0.P.M, a0.P.L, kLdsCompact, sizeof(R) == 4);
   const int count = *b.flag_count;
   const int stride = gridDim.x * waves_per_block;
   for (int w = blockIdx.x * waves_per_block + wave; w < count; w += stride) {

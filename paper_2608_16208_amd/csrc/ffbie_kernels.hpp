@@ -62,18 +62,23 @@ struct BatchArgs {
 // stage in FP64 or (single) in FP32; the layout in units of its real type:
 //   compact (default variant without <rho^-1> output):
 //     two NF-complex FFT buffers, A_m (m <= M + NF/2), kc (M + 1 complex)
-//   full: four NF-complex buffers and the <rho^-1> buffer (2L + 1 complex)
+//   transforms (default variant with <rho^-1> output): four NF-complex buffers;
+//     <rho^-1>_l goes straight to the output row
+//   full (eq. (3.10) variant): four NF-complex buffers and the <rho^-1> buffer
+//     (2L + 1 complex) that the second convolution reads
 //     A_m is stored mirrored, A[-m] = A[m] for m <= NF/2, so it needs M + NF + 2 reals
-//     (compact) or fits an NF-complex buffer (full, since L <= NF).
+//     (compact) or fits an NF-complex buffer (transforms and full, since L <= NF).
+enum { kLdsCompact = 0, kLdsTransforms = 1, kLdsFull = 2 };
 // LDS doubles of the per-workgroup FFT twiddle table (transforms of NF <= 128
 // points: 7 stages x 64 lanes complex), 0 otherwise.
 FFBIE_HD inline int coeff_twiddle_doubles(int NF, bool single) {
   return NF <= 128 ? (single ? 7 * 64 : 7 * 64 * 2) : 0;
 }
 
-FFBIE_HD inline int coeff_lds_per_wave(int NF, int M, int L, bool compact, bool single) {
-  const int reals = compact ? 2 * (2 * NF) + 2 * ((M + NF + 2) / 2) + 2 * (M + 1)
-                            : 2 * (4 * NF + 2 * L + 1);
+FFBIE_HD inline int coeff_lds_per_wave(int NF, int M, int L, int layout, bool single) {
+  const int reals = layout == kLdsCompact ? 2 * (2 * NF) + 2 * ((M + NF + 2) / 2) + 2 * (M + 1)
+                    : layout == kLdsTransforms ? 2 * (4 * NF)
+                                               : 2 * (4 * NF + 2 * L + 1);
   return single ? (reals + 1) / 2 : reals;
 }
 
