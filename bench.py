@@ -53,8 +53,10 @@ def algorithmic_flops_per_pair(NF, M, M0, p, m0, newton_iters=6.0, miller_extra=
 
 def kernel_source_digest():
     h = hashlib.sha256()
-    for f in ("ffbie_kernels.hip", "ffbie_device.hpp", "ffbie_kernels.hpp", "ffbie_root.hpp"):
-        with open(os.path.join(ROOT, "paper_2608_16208_amd", "csrc", f), "rb") as fh:
+    # the kernel sources and the build script (its flags shape the code too)
+    for f in ("csrc/ffbie_kernels.hip", "csrc/ffbie_device.hpp", "csrc/ffbie_kernels.hpp",
+              "csrc/ffbie_root.hpp", "build.py"):
+        with open(os.path.join(ROOT, "paper_2608_16208_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

@@ -18,6 +18,12 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
 ]
+# Per-source additions.  The coefficient kernels are built without machine-level
+# loop-invariant hoisting: their pair loops then recompute cheap invariants
+# instead of holding them in registers, which frees the VGPRs for a fourth
+# wavefront per SIMD (and removes the SGPR spills the hoisted sincos
+# coefficients caused).
+EXTRA = {"csrc/ffbie_kernels.hip": ["-mllvm", "-disable-machine-licm"]}
 
 
 def _run(cmd, verbose):
@@ -33,7 +39,8 @@ def build(verbose=False, jobs=None):
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 1, 8)
     with tempfile.TemporaryDirectory(prefix="ffbie_build_") as tmpd:
         objs = [os.path.join(tmpd, os.path.basename(s) + ".o") for s in SOURCES]
-        cmds = [[hipcc] + FLAGS + ["-c", os.path.join(HERE, s), "-o", o] for s, o in zip(SOURCES, objs)]
+        cmds = [[hipcc] + FLAGS + EXTRA.get(s, []) + ["-c", os.path.join(HERE, s), "-o", o]
+                for s, o in zip(SOURCES, objs)]
         with ThreadPoolExecutor(jobs) as ex:
             results = list(ex.map(lambda c: _run(c, verbose), cmds))
         for (rc, err), s in zip(results, SOURCES):

@@ -858,12 +858,26 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
   }
 }
 
-// Surfaces of azimuthal order <= 2 fit 168 VGPRs with a few spilled values, so
-// they ask for three wavefronts per SIMD (more latency hiding); higher orders
-// would spill heavily and keep two.
+// Wavefronts per SIMD asked of the coefficient kernels.  This file is built
+// without machine-level loop-invariant hoisting, so the pair loop recomputes
+// cheap invariants instead of holding them (or the SGPR pairs of the sincos
+// coefficients) in registers: the FP64 kernel for surfaces of azimuthal order
+// <= 4 then fits the 128 VGPRs of four wavefronts without spilling, order 8
+// the 168 of three, and the FP32 spectral stage for order <= 2 the 96 of five.
+template <int MM, class R>
+constexpr int coeff_waves_per_simd() {
+  return sizeof(R) == 4 && MM <= 2 ? 5 : (MM <= 4 ? 4 : 3);
+}
+// The persistent batch kernel, whose loop over work items holds more
+// registers, asks for fewer.
+template <int MM>
+constexpr int coeff_persist_waves_per_simd() {
+  return MM <= 4 ? 3 : 2;
+}
+
 template <int MM, bool REFINE, class R, int RADIX>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbie_coeff_kernel_t(
+__attribute__((amdgpu_waves_per_eu(coeff_waves_per_simd<MM, R>(), coeff_waves_per_simd<MM, R>()))) void ffbie_coeff_kernel_t(
     CoeffArgs a) {
   using C = typename Spec<R>::C;
   constexpr bool single = sizeof(R) == 4;
@@ -913,7 +927,9 @@ __device__ __forceinline__ int batch_find(const int64_t* __restrict__ prefix, in
 
 template <int MM, class R, int RADIX, bool PERSIST>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(MM <= 2 ? 3 : 2, MM <= 2 ? 3 : 2))) void ffbie_coeff_batch_kernel_t(
+__attribute__((amdgpu_waves_per_eu(PERSIST ? coeff_persist_waves_per_simd<MM>() : coeff_waves_per_simd<MM, R>(),
+                                   PERSIST ? coeff_persist_waves_per_simd<MM>() : coeff_waves_per_simd<MM, R>()))) void
+ffbie_coeff_batch_kernel_t(
     BatchArgs b) {
   using C = typename Spec<R>::C;
   constexpr bool single = sizeof(R) == 4;
