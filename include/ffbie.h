@@ -37,7 +37,6 @@ typedef enum {
   FFBIE_ENOMEM = -4,         /* device allocation of a workspace failed             */
   FFBIE_EDEVICE = -5,        /* a HIP runtime call failed                           */
   FFBIE_ENOPROBLEM = -7,     /* ffbie_set_problem has not been called               */
-  FFBIE_EBLAS = -8,          /* a rocBLAS GEMM call failed                          */
   FFBIE_WNOTCONV = 2         /* warning: an iterative solve stopped at max_iter     */
 } ffbie_status;
 
@@ -455,6 +454,18 @@ ffbie_status ffbie_mlp_precondition(ffbie_ctx *ctx, const void *d_v, void *d_z);
  * synchronise the stream.  FFBIE_EINVAL if no factorisation of this size is held. */
 ffbie_status ffbie_lu_factor(ffbie_ctx *ctx, void *d_S, int64_t ld);
 ffbie_status ffbie_lu_solve(ffbie_ctx *ctx, const void *d_S, int64_t ld, void *d_x);
+
+/* The trailing-update product of the LU factorisations (FFBIE_SOLVE_LU64,
+ * LU32_IR64, GMRES_LU32, ffbie_lu_factor): C -= A B on the matrix cores for
+ * complex column-major blocks with the common leading dimension ld (in complex
+ * elements): A is m x k, B is k x n, C is m x n, element (r, c) of each at
+ * index c * ld + r.  complex64 = 0: complex128 with FP64 MFMA; complex64 != 0:
+ * complex64 with FP32 MFMA and FP32 accumulation.  A and B are read only and
+ * must not overlap C.  Enqueued on the context's stream; needs no problem set.
+ * FFBIE_EINVAL for negative sizes, sizes above 2^31 - 1, ld < max(m, k, 1) or
+ * a NULL pointer when m n k > 0. */
+ffbie_status ffbie_gemm_sub(ffbie_ctx *ctx, int complex64, int64_t m, int64_t n, int64_t k,
+                            const void *d_A, const void *d_B, void *d_C, int64_t ld);
 
 /* Mode-block-Jacobi preconditioner.  In the azimuthal Fourier basis
  * phi[(b, j)] = sum_m Phi_m[b] e^{i m theta_j} (m = -M+1..M) the matrix S splits

@@ -28,7 +28,7 @@ EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_probl
            "ffbie_mlp_precondition", "ffbie_blockjacobi_setup", "ffbie_blockjacobi_apply",
            "ffbie_kernel_coeffs_mixed", "ffbie_set_tuning", "ffbie_get_tuning",
            "ffbie_batch_plan_create", "ffbie_batch_plan_execute", "ffbie_batch_plan_get_tuning",
-           "ffbie_batch_plan_destroy", "ffbie_batch_plan_classes")
+           "ffbie_batch_plan_destroy", "ffbie_batch_plan_classes", "ffbie_gemm_sub")
 SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES, SOLVE_FGMRES_MLP, SOLVE_GMRES_BLOCKJACOBI = 0, 1, 2, 3, 4
 SOLVE_GMRES_LU32 = 5
 MLP_IN, MLP_HIDDEN, MLP_OUT = 514, 256, 512
@@ -128,6 +128,7 @@ def load_library(path=LIB_PATH):
     lib.ffbie_mlp_precondition.argtypes = [vp, vp, vp]
     lib.ffbie_blockjacobi_setup.argtypes = [vp, vp, i64]
     lib.ffbie_blockjacobi_apply.argtypes = [vp, vp, vp]
+    lib.ffbie_gemm_sub.argtypes = [vp, i32, i64, i64, i64, vp, vp, vp, i64]
     for name in EXPORTS:
         f = getattr(lib, name)
         if name not in ("ffbie_last_error", "ffbie_mlp_param_count", "ffbie_batch_plan_classes"):
@@ -458,6 +459,18 @@ class Context:
         self._check(self.lib.ffbie_residual(self.h, _ptr(S), S.stride(0), _ptr(phi), _ptr(g), _ptr(r)),
                     self.h)
         return r
+
+    def gemm_sub(self, C, A, B, m, n, k, ld):
+        """C -= A B on complex column-major blocks with leading dimension ld:
+        A, B and C are device tensors (complex128 or complex64, all the same)
+        whose storage starts at the blocks' first elements."""
+        torch = self._torch
+        dt = C.dtype
+        if dt not in (torch.complex128, torch.complex64) or A.dtype != dt or B.dtype != dt:
+            raise FfbieError("gemm_sub needs complex128 or complex64 tensors of one dtype")
+        rc = self.lib.ffbie_gemm_sub(self.h, int(dt == torch.complex64), int(m), int(n), int(k),
+                                     _ptr(A), _ptr(B), _ptr(C), int(ld))
+        self._check(rc, self.h)
 
     def singular_factor(self, b, m_max):
         torch = self._torch

@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["csrc/ffbie_api.hip", "csrc/ffbie_kernels.hip", "csrc/ffbie_assembly.hip",
-           "csrc/ffbie_solve.hip", "csrc/ffbie_mlp.hip", "csrc/ffbie_blockjacobi.hip"]
+           "csrc/ffbie_solve.hip", "csrc/ffbie_gemm.hip", "csrc/ffbie_mlp.hip", "csrc/ffbie_blockjacobi.hip"]
 LIB = os.path.join(HERE, "libffbie.so")
 
 FLAGS = [
@@ -48,7 +48,7 @@ def build(verbose=False, jobs=None):
                 sys.stderr.write(err + "\n")
                 raise RuntimeError("hipcc failed compiling " + s)
         tmp = LIB + ".tmp"
-        rc, err = _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lrocblas"],
+        rc, err = _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs,
                        verbose)
         if rc != 0:
             sys.stderr.write(err + "\n")

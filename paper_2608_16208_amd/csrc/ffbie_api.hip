@@ -14,6 +14,7 @@
 
 #include "ffbie_assembly.hpp"
 #include "ffbie_blockjacobi.hpp"
+#include "ffbie_gemm.hpp"
 #include "ffbie_kernels.hpp"
 #include "ffbie_mlp.hpp"
 #include "ffbie_solve.hpp"
@@ -60,7 +61,6 @@ struct ffbie_ctx {
   cplx* d_partial = nullptr;         // field partial sums
   int64_t partial_cap = 0;
   // dense solvers
-  rocblas_handle blas = nullptr;
   int64_t solve_n = 0;               // size the vector workspaces were made for
   int64_t* d_ipiv = nullptr;
   int64_t* d_perm = nullptr;
@@ -326,7 +326,6 @@ ffbie_status ffbie_destroy(ffbie_ctx* c) {
   if (c->d_zbasis) (void)hipFree(c->d_zbasis);
   c->mlp.release();
   c->bj.release();
-  if (c->blas) rocblas_destroy_handle(c->blas);
   delete c;
   return FFBIE_OK;
 }
@@ -1130,12 +1129,6 @@ namespace {
 constexpr int kRestart = 100;
 
 ffbie_status ensure_solve_ws(ffbie_ctx* c, int64_t N, int method) {
-  if (!c->blas) {
-    if (rocblas_create_handle(&c->blas) != rocblas_status_success)
-      return fail(c, FFBIE_EBLAS, "ffbie_solve: rocblas_create_handle failed");
-  }
-  if (rocblas_set_stream(c->blas, c->stream) != rocblas_status_success)
-    return fail(c, FFBIE_EBLAS, "ffbie_solve: rocblas_set_stream failed");
   if (c->solve_n != N) {
     for (void* p : {(void*)c->d_ipiv, (void*)c->d_perm, (void*)c->d_info, (void*)c->d_vecs,
                     (void*)c->d_small})
@@ -1182,7 +1175,6 @@ ffbie_status ensure_solve_ws(ffbie_ctx* c, int64_t N, int method) {
 SolveCtx solve_ctx(ffbie_ctx* c) {
   SolveCtx sc;
   sc.stream = c->stream;
-  sc.blas = c->blas;
   sc.ipiv = c->d_ipiv;
   sc.perm = c->d_perm;
   sc.info = c->d_info;
@@ -1260,7 +1252,6 @@ ffbie_status ffbie_solve(ffbie_ctx* c, int method, void* d_S, int64_t ld, const 
     r = fgmres64(sc, S, ld, N, g, phi, tol, max_iter, kRestart, P, &iters, &rel, &fell_back);
   }
   if (r.hip != hipSuccess) return hip_fail(c, r.hip, "ffbie_solve");
-  if (r.blas != 0) return fail(c, FFBIE_EBLAS, "ffbie_solve: rocBLAS GEMM failed");
   FFBIE_HIP(c, hipStreamSynchronize(c->stream));
   if (info) {
     info->iterations = iters;
@@ -1288,7 +1279,6 @@ ffbie_status ffbie_lu_factor(ffbie_ctx* c, void* d_S, int64_t ld) {
   c->factored_n = 0;
   SolveResult r = lu64_factor_solve(sc, static_cast<cplx*>(d_S), ld, N, y);
   if (r.hip != hipSuccess) return hip_fail(c, r.hip, "ffbie_lu_factor");
-  if (r.blas != 0) return fail(c, FFBIE_EBLAS, "ffbie_lu_factor: rocBLAS GEMM failed");
   FFBIE_HIP(c, hipStreamSynchronize(c->stream));
   if (r.singular_col != 0) return fail(c, FFBIE_ESINGULAR, "ffbie_lu_factor: exactly zero pivot");
   c->factored_n = N;
@@ -1307,6 +1297,25 @@ ffbie_status ffbie_lu_solve(ffbie_ctx* c, const void* d_S, int64_t ld, void* d_x
   SolveResult r = lu64_solve_factored(sc, static_cast<const cplx*>(d_S), ld, N, static_cast<cplx*>(d_x));
   if (r.hip != hipSuccess) return hip_fail(c, r.hip, "ffbie_lu_solve");
   FFBIE_HIP(c, hipStreamSynchronize(c->stream));
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_gemm_sub(ffbie_ctx* c, int complex64, int64_t m, int64_t n, int64_t k,
+                            const void* d_A, const void* d_B, void* d_C, int64_t ld) {
+  if (!c) return FFBIE_EINVAL;
+  if (m < 0 || n < 0 || k < 0 || ld < 1 || ld < m || ld < k)
+    return fail(c, FFBIE_EINVAL, "ffbie_gemm_sub: negative size or ld < max(m, k)");
+  if (m > 2147483647 || n > 2147483647 || k > 2147483647)
+    return fail(c, FFBIE_EINVAL, "ffbie_gemm_sub: size above 2^31 - 1");
+  if (m == 0 || n == 0 || k == 0) return FFBIE_OK;
+  if (!d_A || !d_B || !d_C) return fail(c, FFBIE_EINVAL, "ffbie_gemm_sub: NULL pointer");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  if (complex64)
+    FFBIE_HIP(c, gemm_sub_c64(c->stream, static_cast<float*>(d_C), static_cast<const float*>(d_A),
+                              static_cast<const float*>(d_B), ld, m, n, k));
+  else
+    FFBIE_HIP(c, gemm_sub_c128(c->stream, static_cast<double*>(d_C), static_cast<const double*>(d_A),
+                               static_cast<const double*>(d_B), ld, m, n, k));
   return FFBIE_OK;
 }
 

@@ -1,7 +1,5 @@
 // Interface of the dense solvers (row-major complex matrices).
 #pragma once
-#include <rocblas/rocblas.h>
-
 #include "ffbie_device.hpp"
 
 namespace ffbie {
@@ -9,7 +7,6 @@ namespace ffbie {
 // Device workspaces and handles the solvers use; owned by the context.
 struct SolveCtx {
   hipStream_t stream;
-  rocblas_handle blas;
   int64_t* ipiv;       // [N] pivot rows
   int64_t* perm;       // [N] permutation of the right-hand side
   int* info;           // first zero pivot (1-based), 0 if none
@@ -31,7 +28,6 @@ struct Precond {
 
 struct SolveResult {
   hipError_t hip = hipSuccess;
-  int blas = 0;              // rocblas_status of a failed GEMM
   int singular_col = 0;      // 1-based column of an exactly zero pivot
   bool converged = true;
 };
