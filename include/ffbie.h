@@ -37,7 +37,10 @@ typedef enum {
   FFBIE_ENOMEM = -4,         /* device allocation of a workspace failed             */
   FFBIE_EDEVICE = -5,        /* a HIP runtime call failed                           */
   FFBIE_ENOPROBLEM = -7,     /* ffbie_set_problem has not been called               */
-  FFBIE_WNOTCONV = 2         /* warning: an iterative solve stopped at max_iter     */
+  FFBIE_WNOTCONV = 2,        /* warning: an iterative solve stopped at max_iter     */
+  FFBIE_WUNRESOLVED = 3      /* warning: ffbie_assemble used near pairs whose smooth
+                                factor 4M azimuthal samples did not resolve (see
+                                ffbie_assembly_report)                              */
 } ffbie_status;
 
 /* Per-pair status bits written to d_pair_status by ffbie_kernel_coeffs. */
@@ -314,9 +317,14 @@ ffbie_status ffbie_builtin_near_rule(ffbie_near_rule *out);
 ffbie_status ffbie_set_near_rule(ffbie_ctx *ctx, const ffbie_near_rule *rule);
 
 /* Sizes for the current problem: the number of unknowns N = 32 M n_panels,
- * and the number of near pairs (target point, near-rule source node):
- * 512 M (3 n_panels - 2) for n_panels >= 2.  Either pointer may be NULL. */
-ffbie_status ffbie_query(ffbie_ctx *ctx, int64_t *n_unknowns, int64_t *n_near_pairs);
+ * the number of near pairs (target point, near-rule source node):
+ * 512 M (3 n_panels - 2) for n_panels >= 2, and an upper bound of the device
+ * workspace (bytes) the context allocates for ffbie_assemble plus the most
+ * demanding ffbie_solve method on this problem (the complex64 copy of S of
+ * LU32_IR64 / GMRES_LU32, or the mode blocks and Krylov bases of the GMRES
+ * forms), beyond the caller's own buffers.  Any pointer may be NULL. */
+ffbie_status ffbie_query(ffbie_ctx *ctx, int64_t *n_unknowns, int64_t *n_near_pairs,
+                         int64_t *workspace_bytes);
 
 /* Write the near pair set as ffbie_kernel_coeffs inputs: d_t, d_az, d_ts
  * [n_near_pairs] (float64, int32, float64).  Order: panel i, node l, azimuth
@@ -354,8 +362,21 @@ ffbie_status ffbie_rhs(ffbie_ctx *ctx, int kind, const double *params, void *d_g
  *    DFT (discrete Parseval relation) of the kernel coefficients of
  *    ffbie_kernel_coeffs at (x_r, t_s = node y_q) (eqs. (3.9)-(3.10)).
  * Uses a device workspace for the near kernel coefficients (at most about
- * 2 GB, allocated on first use).  FFBIE_EINVAL for a NULL matrix or ld < N. */
+ * 2 GB, allocated on first use).  FFBIE_EINVAL for a NULL matrix or ld < N;
+ * FFBIE_WUNRESOLVED (a warning: S is assembled) if near pairs were flagged
+ * unresolved, see ffbie_assembly_report. */
 ffbie_status ffbie_assemble(ffbie_ctx *ctx, void *d_S, int64_t ld);
+
+/* Near pairs of the last ffbie_assemble on this context: their number, how
+ * many the coefficient path flagged FFBIE_PAIR_UNRESOLVED (the smooth factor
+ * not resolved even by 4M azimuthal samples: the wavenumber is too large for
+ * M, and those near-block entries carry the truncation error of the smooth
+ * factor's spectrum) and how many FFBIE_PAIR_ROOT_FALLBACK.  ffbie_assemble
+ * returns FFBIE_WUNRESOLVED when the first count is not zero (it reads the
+ * counts back, so it returns after the assembly has finished).  Any pointer
+ * may be NULL; FFBIE_EINVAL before the first assembly. */
+ffbie_status ffbie_assembly_report(ffbie_ctx *ctx, int64_t *n_near_pairs, int64_t *n_unresolved,
+                                   int64_t *n_root_fallback);
 
 /* Field of the single-layer representation u(x) = 2 int G(x, y) phi(y) dsigma
  * (eq. (2.6)) at n_pts points off the surface, by the same 16-point-by-2M
@@ -438,6 +459,41 @@ ffbie_status ffbie_mlp_forward(ffbie_ctx *ctx, int64_t n, const float *d_x, floa
  * Synchronises the stream. */
 ffbie_status ffbie_mlp_train_step(ffbie_ctx *ctx, int64_t n, const float *d_x, const float *d_t,
                                   float lr, int update, float *d_grads, double *loss);
+/* Training on a set of samples the method generated (for instance mode
+ * features of residuals of assembled systems, ffbie_mode_features, with the
+ * corrections they should map to, ffbie_mode_targets): `steps` Adam steps on
+ * minibatches of `batch` samples drawn without replacement per epoch (order
+ * from `seed`), learning rate lr (1 + cos(pi step / steps)) / 2, all on the
+ * device with the kernels of ffbie_mlp_train_step.  Needs weights
+ * (ffbie_mlp_init / set_params / load).  info (optional) receives the loss of
+ * the first and last minibatch before their step and the loss over the whole
+ * set after training.  Synchronises the stream.  FFBIE_EINVAL unless
+ * 1 <= batch <= min(n_samples, 65535), steps >= 1 and lr > 0. */
+typedef struct {
+  int64_t n_samples;     /* rows of d_x and d_t */
+  const float *d_x;      /* [n_samples][514] network inputs, float32 device */
+  const float *d_t;      /* [n_samples][512] targets, float32 device */
+  int steps;
+  int batch;
+  float lr;
+  uint64_t seed;
+} ffbie_train_cfg;
+typedef struct {
+  double loss_first;
+  double loss_last;
+  double loss_full;
+  int steps;
+} ffbie_train_info;
+ffbie_status ffbie_mlp_train(ffbie_ctx *ctx, const ffbie_train_cfg *cfg, ffbie_train_info *info);
+/* Checkpoint of the network and its optimiser state: the float32 parameters
+ * (in the order above), both Adam moments and the Adam step count, in a
+ * binary file of its own format ("FFBIEMLP", version, count, step, data).
+ * load replaces the weights and optimiser state of the context; a file of
+ * another format, size or with non-finite parameters gives FFBIE_EINVAL and
+ * leaves the context unchanged.  Host paths; synchronise the stream. */
+ffbie_status ffbie_mlp_save(ffbie_ctx *ctx, const char *path);
+ffbie_status ffbie_mlp_load(ffbie_ctx *ctx, const char *path);
+
 /* Mode features of d_r [N] complex128 for the current problem: d_x [2M][514]
  * float32 and the scales d_scale [2M] float64 (row m + M - 1 is mode m). */
 ffbie_status ffbie_mode_features(ffbie_ctx *ctx, const void *d_r, float *d_x, double *d_scale);

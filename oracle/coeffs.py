@@ -157,3 +157,29 @@ def pairs_coeffs(amp, k, M, L, t, j_az, ts, processes=None):
     c = np.array([o[0] for o in out]).reshape(t.size, L + 1)
     kap = np.array([o[1] for o in out]).reshape(t.size, 2 * M)
     return c, kap, [o[2] for o in out]
+
+
+def kappa_tail(amp, k, M, M0, t, j_az, ts, n_max=None):
+    """Truncation tail of the cos(k rho) series in eq. (3.10) for one pair:
+        sum_{|n| >= M0} |<cos k rho>_n| * max_l |<rho^-1>_l|,
+    relative to max_n |kappa_n| (kappa_n, n = -M+1..M, by direct quadrature).
+    A kernel-coefficient table built from 2M azimuthal samples cannot be more
+    accurate than this for the pair; it tells resolved pairs (tail at rounding
+    level) from those a given M cannot resolve (large k against M).
+
+    cos(k rho) is an entire function of rho^2, a smooth periodic function of
+    theta_s, so its coefficients come from the trapezoidal rule with many more
+    points than the modes read (exponentially convergent), up to |n| <= n_max
+    (default 8 max(M, k + 16)).  Returns (tail, info) with info the
+    coefficient magnitudes |<cos k rho>_n| for n = -n_max..n_max."""
+    c, kap, _ = pair_coeffs(amp, k, M, M + M0, t, j_az, ts)
+    n_max = int(n_max or 8 * max(M, int(math.ceil(k)) + 16))
+    th = math.pi * j_az / M
+    Q = 4 * n_max + 4
+    x = 2.0 * math.pi * np.arange(Q) / Q
+    f = np.cos(k * np.sqrt(geo.rho2(amp, t, th, ts, x)))
+    ns = np.arange(-n_max, n_max + 1)
+    coef = (np.exp(-1j * np.outer(ns, x)) @ f) / Q * np.exp(-1j * ns * th)
+    tail = np.sum(np.abs(coef[np.abs(ns) >= M0])) * np.max(np.abs(c)) / np.max(np.abs(kap))
+    return float(tail), np.abs(coef)
+

@@ -28,11 +28,12 @@ EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_probl
            "ffbie_mlp_precondition", "ffbie_blockjacobi_setup", "ffbie_blockjacobi_apply",
            "ffbie_kernel_coeffs_mixed", "ffbie_set_tuning", "ffbie_get_tuning",
            "ffbie_batch_plan_create", "ffbie_batch_plan_execute", "ffbie_batch_plan_get_tuning",
-           "ffbie_batch_plan_destroy", "ffbie_batch_plan_classes", "ffbie_gemm_sub")
+           "ffbie_batch_plan_destroy", "ffbie_batch_plan_classes", "ffbie_gemm_sub",
+           "ffbie_assembly_report", "ffbie_mlp_train", "ffbie_mlp_save", "ffbie_mlp_load")
 SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES, SOLVE_FGMRES_MLP, SOLVE_GMRES_BLOCKJACOBI = 0, 1, 2, 3, 4
 SOLVE_GMRES_LU32 = 5
 MLP_IN, MLP_HIDDEN, MLP_OUT = 514, 256, 512
-WNOTCONV = 2
+WNOTCONV, WUNRESOLVED = 2, 3
 RHS_POINT_SOURCE, RHS_PLANE_WAVE = 0, 1
 P_SHIFT = 8
 
@@ -66,6 +67,17 @@ class _SolveInfo(ctypes.Structure):
                 ("fell_back", ctypes.c_int)]
 
 
+class _TrainCfg(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int64), ("d_x", ctypes.c_void_p), ("d_t", ctypes.c_void_p),
+                ("steps", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+class _TrainInfo(ctypes.Structure):
+    _fields_ = [("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("loss_full", ctypes.c_double), ("steps", ctypes.c_int)]
+
+
 class _NearRule(ctypes.Structure):
     _fields_ = [(name, (ctypes.c_double * 16) * 16) for name in ("self_x", "self_w", "right_x", "right_w")]
 
@@ -95,7 +107,12 @@ def load_library(path=LIB_PATH):
     lib.ffbie_get_timing.argtypes = [vp, dp, dp, dp]
     lib.ffbie_builtin_near_rule.argtypes = [ctypes.POINTER(_NearRule)]
     lib.ffbie_set_near_rule.argtypes = [vp, ctypes.POINTER(_NearRule)]
-    lib.ffbie_query.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    pi64 = ctypes.POINTER(ctypes.c_int64)
+    lib.ffbie_query.argtypes = [vp, pi64, pi64, pi64]
+    lib.ffbie_assembly_report.argtypes = [vp, pi64, pi64, pi64]
+    lib.ffbie_mlp_train.argtypes = [vp, ctypes.POINTER(_TrainCfg), ctypes.POINTER(_TrainInfo)]
+    lib.ffbie_mlp_save.argtypes = [vp, ctypes.c_char_p]
+    lib.ffbie_mlp_load.argtypes = [vp, ctypes.c_char_p]
     lib.ffbie_near_pairs.argtypes = [vp, vp, vp, vp]
     lib.ffbie_collocation.argtypes = [vp, vp, vp, vp]
     lib.ffbie_rhs.argtypes = [vp, i32, dp, vp]
@@ -317,8 +334,20 @@ class Context:
     def query(self):
         """(N unknowns, number of near pairs)."""
         n, p = ctypes.c_int64(), ctypes.c_int64()
-        self._check(self.lib.ffbie_query(self.h, ctypes.byref(n), ctypes.byref(p)), self.h)
+        self._check(self.lib.ffbie_query(self.h, ctypes.byref(n), ctypes.byref(p), None), self.h)
         return n.value, p.value
+
+    def workspace_bytes(self):
+        """Upper bound of the device workspace of assembly + the largest solve."""
+        w = ctypes.c_int64()
+        self._check(self.lib.ffbie_query(self.h, None, None, ctypes.byref(w)), self.h)
+        return w.value
+
+    def assembly_report(self):
+        """Near pairs of the last assembly: {pairs, unresolved, root_fallback}."""
+        v = [ctypes.c_int64() for _ in range(3)]
+        self._check(self.lib.ffbie_assembly_report(self.h, *(ctypes.byref(x) for x in v)), self.h)
+        return {"pairs": v[0].value, "unresolved": v[1].value, "root_fallback": v[2].value}
 
     def near_pairs(self):
         torch = self._torch
@@ -355,7 +384,8 @@ class Context:
             S = torch.empty((N, N), dtype=torch.complex128, device=self.device)
         if S.dim() != 2 or S.shape[0] != N or S.stride(1) != 1 or S.stride(0) < N or S.dtype != torch.complex128:
             raise FfbieError("S must be a row-major complex128 [N, >=N] device tensor")
-        self._check(self.lib.ffbie_assemble(self.h, _ptr(S), S.stride(0)), self.h)
+        rc = self._check(self.lib.ffbie_assemble(self.h, _ptr(S), S.stride(0)), self.h)
+        self.last_assembly = dict(self.assembly_report(), status=rc)
         return S
 
     def eval_field(self, pts, phi):
@@ -425,6 +455,24 @@ class Context:
         self._check(self.lib.ffbie_mlp_train_step(self.h, x.shape[0], _ptr(x), _ptr(t), float(lr),
                                                   int(bool(update)), _ptr(g), ctypes.byref(loss)), self.h)
         return loss.value, g
+
+    def mlp_train(self, x, t, steps, batch=2048, lr=1e-3, seed=0):
+        """Train on (x [n, 514], t [n, 512]) float32 device tensors with the
+        library's loop (ffbie_mlp_train); returns the loss record."""
+        torch = self._torch
+        x = x.to(self.device, torch.float32).contiguous()
+        t = t.to(self.device, torch.float32).contiguous()
+        cfg = _TrainCfg(x.shape[0], x.data_ptr(), t.data_ptr(), int(steps), int(batch), float(lr), int(seed))
+        info = _TrainInfo()
+        self._check(self.lib.ffbie_mlp_train(self.h, ctypes.byref(cfg), ctypes.byref(info)), self.h)
+        return {"loss_first": info.loss_first, "loss_last": info.loss_last, "loss_full": info.loss_full,
+                "steps": info.steps}
+
+    def mlp_save(self, path):
+        self._check(self.lib.ffbie_mlp_save(self.h, os.fsencode(path)), self.h)
+
+    def mlp_load(self, path):
+        self._check(self.lib.ffbie_mlp_load(self.h, os.fsencode(path)), self.h)
 
     def mode_features(self, r):
         torch = self._torch

@@ -83,6 +83,12 @@ struct ffbie_ctx {
   int64_t factored_n = 0;            // size of the LU64 factorisation held (ffbie_lu_factor)
   cplx* d_zbasis = nullptr;
   int64_t zbasis_n = 0;
+  // flags of the near pairs of the last assembly
+  unsigned long long* d_asm_counts = nullptr;
+  int64_t asm_pairs = -1, asm_unresolved = -1, asm_fallback = -1;
+  // minibatch order of ffbie_mlp_train
+  int32_t* d_train_idx = nullptr;
+  int64_t train_idx_cap = 0;
 };
 
 namespace {
@@ -324,6 +330,8 @@ ffbie_status ffbie_destroy(ffbie_ctx* c) {
                   (void*)c->d_tabs[3]})
     if (p) hipFree(p);
   if (c->d_zbasis) (void)hipFree(c->d_zbasis);
+  if (c->d_asm_counts) (void)hipFree(c->d_asm_counts);
+  if (c->d_train_idx) (void)hipFree(c->d_train_idx);
   c->mlp.release();
   c->bj.release();
   delete c;
@@ -868,12 +876,31 @@ ffbie_status ffbie_set_near_rule(ffbie_ctx* c, const ffbie_near_rule* rule) {
   return FFBIE_OK;
 }
 
-ffbie_status ffbie_query(ffbie_ctx* c, int64_t* n_unknowns_out, int64_t* n_near_pairs) {
+ffbie_status ffbie_query(ffbie_ctx* c, int64_t* n_unknowns_out, int64_t* n_near_pairs,
+                         int64_t* workspace_bytes) {
   if (!c) return FFBIE_EINVAL;
   if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_query: no problem set");
   const SysDims d = sys_dims(c);
   if (n_unknowns_out) *n_unknowns_out = d.N;
-  if (n_near_pairs) *n_near_pairs = near_pairs_before(c->n_panels, d);
+  const int64_t near = near_pairs_before(c->n_panels, d);
+  if (n_near_pairs) *n_near_pairs = near;
+  if (workspace_bytes) {
+    const int64_t N = d.N;
+    // assembly: near-pair chunk (inputs, kappa rows, coefficient workspace),
+    // rule tables, collocation data
+    const int64_t cap_pairs = kNearKappaBytes / (int64_t)(2 * d.M * sizeof(cplx));
+    const int64_t chunk = std::min<int64_t>(near, cap_pairs + (int64_t)3 * kNodes * 2 * d.M * kNodes);
+    const int64_t asm_ws = chunk * (20 + 2 * d.M * (int64_t)sizeof(cplx) + (int64_t)sizeof(RootRec) + 12) +
+                           (int64_t)kNodes * 3 * kNodes * (kNodes + 1) * 8 + 5 * N * 8;
+    // the largest solve: vectors and pivots, plus the complex64 copy of S
+    // (LU32_IR64, GMRES_LU32) or the Krylov and flexible bases (GMRES forms),
+    // or the mode blocks (block-Jacobi)
+    const int64_t vecs = 3 * N * (int64_t)sizeof(cplx) + 2 * N * 8 + (256 * 101 + 101) * (int64_t)sizeof(cplx);
+    const int64_t lu32 = N * N * 8 + 100 * N * (int64_t)sizeof(cplx) + 101 * N * (int64_t)sizeof(cplx);
+    const int64_t nodes = 16 * (int64_t)d.n_panels;
+    const int64_t bj = 2 * d.M * nodes * nodes * (int64_t)sizeof(cplx) + 201 * N * (int64_t)sizeof(cplx);
+    *workspace_bytes = asm_ws + vecs + std::max(lu32, bj);
+  }
   return FFBIE_OK;
 }
 
@@ -941,6 +968,8 @@ ffbie_status ffbie_assemble(ffbie_ctx* c, void* d_S, int64_t ld) {
   }
   s = ensure_near_ws(c, max_chunk);
   if (s != FFBIE_OK) return s;
+  if (!c->d_asm_counts) FFBIE_HIP(c, hipMalloc(&c->d_asm_counts, 2 * sizeof(unsigned long long)));
+  FFBIE_HIP(c, launch_zero_counts(c->d_asm_counts, 2, c->stream));
   for (int p0 = 0; p0 < c->n_panels;) {
     int p1 = p0 + 1;
     while (p1 < c->n_panels &&
@@ -957,9 +986,35 @@ ffbie_status ffbie_assemble(ffbie_ctx* c, void* d_S, int64_t ld) {
     s = run_coeffs(c, ch.n_pairs, c->d_near_t, c->d_near_az, c->d_near_ts, c->d_near_kappa, nullptr,
                    nullptr, nullptr);
     if (s != FFBIE_OK) return s;
+    // the pairs' flags are in the context's status workspace
+    FFBIE_HIP(c, launch_count_status(c->d_status, ch.n_pairs, c->d_asm_counts, c->stream));
     FFBIE_HIP(c, launch_near_assembly(d, ch, c->d_near_kappa, c->d_wl, c->d_tab, S, ld, c->stream));
     p0 = p1;
   }
+  unsigned long long cnt[2] = {0, 0};
+  FFBIE_HIP(c, hipMemcpyAsync(cnt, c->d_asm_counts, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+  FFBIE_HIP(c, hipStreamSynchronize(c->stream));
+  c->asm_pairs = near_pairs_before(c->n_panels, d);
+  c->asm_unresolved = (int64_t)cnt[0];
+  c->asm_fallback = (int64_t)cnt[1];
+  if (cnt[0] > 0) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg,
+                  "ffbie_assemble: %llu of %lld near pairs not resolved by 4M azimuthal samples "
+                  "(k too large for M)", cnt[0], (long long)c->asm_pairs);
+    c->err = msg;
+    return FFBIE_WUNRESOLVED;
+  }
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_assembly_report(ffbie_ctx* c, int64_t* n_near_pairs, int64_t* n_unresolved,
+                                   int64_t* n_root_fallback) {
+  if (!c) return FFBIE_EINVAL;
+  if (c->asm_pairs < 0) return fail(c, FFBIE_EINVAL, "ffbie_assembly_report: no assembly on this context");
+  if (n_near_pairs) *n_near_pairs = c->asm_pairs;
+  if (n_unresolved) *n_unresolved = c->asm_unresolved;
+  if (n_root_fallback) *n_root_fallback = c->asm_fallback;
   return FFBIE_OK;
 }
 
@@ -1449,6 +1504,162 @@ ffbie_status ffbie_mlp_train_step(ffbie_ctx* c, int64_t n, const float* d_x, con
     for (double v : part) sum += v;
     *loss = sum / (2.0 * n);
   }
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_mlp_train(ffbie_ctx* c, const ffbie_train_cfg* cfg, ffbie_train_info* info) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->mlp.ready) return fail(c, FFBIE_EINVAL, "ffbie_mlp_train: no weights (ffbie_mlp_init first)");
+  if (!cfg || !cfg->d_x || !cfg->d_t) return fail(c, FFBIE_EINVAL, "ffbie_mlp_train: NULL config or data");
+  if (cfg->n_samples < 1 || cfg->n_samples > 2147483647 || cfg->steps < 1 || cfg->batch < 1 ||
+      cfg->batch > 65535 || cfg->batch > cfg->n_samples || !(cfg->lr > 0))
+    return fail(c, FFBIE_EINVAL,
+                "ffbie_mlp_train: need n_samples >= batch >= 1, batch <= 65535, steps >= 1, lr > 0");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  Mlp& net = c->mlp;
+  const int64_t n = cfg->n_samples;
+  const int B = cfg->batch;
+  FFBIE_HIP(c, net.ensure_batch(std::max<int64_t>(B, std::min<int64_t>(n, 16384))));
+  if (c->train_idx_cap < n) {
+    if (c->d_train_idx) (void)hipFree(c->d_train_idx);
+    c->d_train_idx = nullptr;
+    c->train_idx_cap = 0;
+    if (hipMalloc(&c->d_train_idx, n * sizeof(int32_t)) != hipSuccess)
+      return fail(c, FFBIE_ENOMEM, "ffbie_mlp_train: index workspace allocation failed");
+    c->train_idx_cap = n;
+  }
+  // minibatches drawn without replacement: a Fisher-Yates permutation of the
+  // samples per epoch (SplitMix64 stream from cfg->seed)
+  uint64_t st = cfg->seed;
+  auto next = [&st]() {
+    uint64_t z = (st += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+  };
+  std::vector<int32_t> perm(n);
+  auto shuffle = [&]() {
+    for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+    for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[next() % (uint64_t)(i + 1)]);
+  };
+  auto read_loss = [&](int nblk, int64_t rows, double* out) -> hipError_t {
+    std::vector<double> part(nblk);
+    hipError_t e = hipMemcpyAsync(part.data(), net.partial, nblk * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    double sum = 0;
+    for (double v : part) sum += v;
+    *out = sum / (2.0 * rows);
+    return e;
+  };
+  int64_t pos = n;
+  double first = 0, last = 0;
+  for (int step = 0; step < cfg->steps; ++step) {
+    if (pos + B > n) {
+      shuffle();
+      FFBIE_HIP(c, hipMemcpyAsync(c->d_train_idx, perm.data(), n * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  c->stream));
+      FFBIE_HIP(c, hipStreamSynchronize(c->stream));    // perm is rewritten on the host next epoch
+      pos = 0;
+    }
+    FFBIE_HIP(c, net.gather_batch(cfg->d_x, cfg->d_t, c->d_train_idx + pos, B, c->stream));
+    pos += B;
+    FFBIE_HIP(c, net.forward(B, c->stream));
+    int nblk = 0;
+    FFBIE_HIP(c, net.backward(B, net.tg, c->stream, &nblk));
+    if (step == 0) FFBIE_HIP(c, read_loss(nblk, B, &first));
+    if (step == cfg->steps - 1) FFBIE_HIP(c, read_loss(nblk, B, &last));
+    const double lr = 0.5 * cfg->lr * (1.0 + std::cos(M_PI * step / cfg->steps));   // cosine decay
+    FFBIE_HIP(c, net.adam((float)lr, c->stream));
+  }
+  // loss over the whole training set with the trained weights (chunks of the
+  // batch workspace; the gradients computed on the way are not used)
+  double full = 0;
+  {
+    std::vector<int32_t> ident(n);
+    for (int64_t i = 0; i < n; ++i) ident[i] = (int32_t)i;
+    FFBIE_HIP(c, hipMemcpyAsync(c->d_train_idx, ident.data(), n * sizeof(int32_t), hipMemcpyHostToDevice,
+                                c->stream));
+    const int64_t chunk = std::min<int64_t>(net.cap, 16384);
+    for (int64_t a = 0; a < n; a += chunk) {
+      const int64_t rows = std::min<int64_t>(chunk, n - a);
+      FFBIE_HIP(c, net.gather_batch(cfg->d_x, cfg->d_t, c->d_train_idx + a, rows, c->stream));
+      FFBIE_HIP(c, net.forward(rows, c->stream));
+      int nblk = 0;
+      FFBIE_HIP(c, net.backward(rows, net.tg, c->stream, &nblk));
+      double l = 0;
+      FFBIE_HIP(c, read_loss(nblk, rows, &l));
+      full += l * rows;
+    }
+    full /= (double)n;
+  }
+  if (info) {
+    info->loss_first = first;
+    info->loss_last = last;
+    info->loss_full = full;
+    info->steps = cfg->steps;
+  }
+  return FFBIE_OK;
+}
+
+// Checkpoint: "FFBIEMLP" magic, format version 1, parameter count, Adam step,
+// then the float32 parameters, first and second Adam moments (little endian).
+namespace {
+constexpr char kMlpMagic[8] = {'F', 'F', 'B', 'I', 'E', 'M', 'L', 'P'};
+constexpr int32_t kMlpVersion = 1;
+}  // namespace
+
+ffbie_status ffbie_mlp_save(ffbie_ctx* c, const char* path) {
+  if (!c) return FFBIE_EINVAL;
+  if (!path) return fail(c, FFBIE_EINVAL, "ffbie_mlp_save: NULL path");
+  if (!c->mlp.ready) return fail(c, FFBIE_EINVAL, "ffbie_mlp_save: no weights");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  const size_t P = Mlp::param_count();
+  std::vector<float> buf(3 * P);
+  FFBIE_HIP(c, hipMemcpyAsync(buf.data(), c->mlp.params, P * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  FFBIE_HIP(c, hipMemcpyAsync(buf.data() + P, c->mlp.m1, P * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  FFBIE_HIP(c, hipMemcpyAsync(buf.data() + 2 * P, c->mlp.m2, P * sizeof(float), hipMemcpyDeviceToHost,
+                              c->stream));
+  FFBIE_HIP(c, hipStreamSynchronize(c->stream));
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(c, FFBIE_EINVAL, std::string("ffbie_mlp_save: cannot open ") + path);
+  const int64_t count = (int64_t)P, step = c->mlp.step;
+  bool ok = std::fwrite(kMlpMagic, 1, 8, f) == 8 && std::fwrite(&kMlpVersion, 4, 1, f) == 1 &&
+            std::fwrite(&count, 8, 1, f) == 1 && std::fwrite(&step, 8, 1, f) == 1 &&
+            std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(c, FFBIE_EINVAL, std::string("ffbie_mlp_save: write failed: ") + path);
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_mlp_load(ffbie_ctx* c, const char* path) {
+  if (!c) return FFBIE_EINVAL;
+  if (!path) return fail(c, FFBIE_EINVAL, "ffbie_mlp_load: NULL path");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(c, FFBIE_EINVAL, std::string("ffbie_mlp_load: cannot open ") + path);
+  const size_t P = Mlp::param_count();
+  char magic[8];
+  int32_t ver = 0;
+  int64_t count = 0, step = 0;
+  std::vector<float> buf(3 * P);
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMlpMagic, 8) == 0 &&
+            std::fread(&ver, 4, 1, f) == 1 && ver == kMlpVersion && std::fread(&count, 8, 1, f) == 1 &&
+            count == (int64_t)P && std::fread(&step, 8, 1, f) == 1 && step >= 0 &&
+            std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  std::fclose(f);
+  if (!ok) return fail(c, FFBIE_EINVAL, std::string("ffbie_mlp_load: not a network checkpoint of this size: ") + path);
+  for (size_t i = 0; i < P; ++i)
+    if (!std::isfinite(buf[i])) return fail(c, FFBIE_EINVAL, "ffbie_mlp_load: non-finite parameter");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  FFBIE_HIP(c, c->mlp.alloc());
+  FFBIE_HIP(c, hipMemcpyAsync(c->mlp.params, buf.data(), P * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  FFBIE_HIP(c, hipMemcpyAsync(c->mlp.m1, buf.data() + P, P * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  FFBIE_HIP(c, hipMemcpyAsync(c->mlp.m2, buf.data() + 2 * P, P * sizeof(float), hipMemcpyHostToDevice,
+                              c->stream));
+  FFBIE_HIP(c, c->mlp.refresh_bf16(c->stream));
+  FFBIE_HIP(c, hipStreamSynchronize(c->stream));
+  c->mlp.step = (int)step;
+  c->mlp.ready = true;
   return FFBIE_OK;
 }
 

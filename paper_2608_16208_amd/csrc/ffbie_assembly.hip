@@ -375,6 +375,32 @@ GL16 pack_gl(const double* x, const double* w) {
 
 }  // namespace
 
+// Counts of per-pair status flags over n pairs: counts[0] += pairs with
+// FFBIE_PAIR_UNRESOLVED, counts[1] += pairs with FFBIE_PAIR_ROOT_FALLBACK
+// (wavefront sums, one atomic per wavefront and counter).
+__global__ __launch_bounds__(256) void count_status_kernel(const int32_t* __restrict__ st, int64_t n,
+                                                           unsigned long long* counts) {
+  unsigned long long u = 0, f = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = st[i];
+    u += (v & FFBIE_PAIR_UNRESOLVED) ? 1 : 0;
+    f += (v & FFBIE_PAIR_ROOT_FALLBACK) ? 1 : 0;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    u += __shfl_xor(u, o);
+    f += __shfl_xor(f, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (u) atomicAdd(counts, u);
+    if (f) atomicAdd(counts + 1, f);
+  }
+}
+
+__global__ void zero_counts_kernel(unsigned long long* counts, int n) {
+  if ((int)threadIdx.x < n) counts[threadIdx.x] = 0;
+}
+
 hipError_t launch_collocation(const Geom& g, const SysDims& d, const double* gl_x,
                               const double* gl_w, Colloc c, double* xyz, double* jac,
                               double* wq, hipStream_t s) {
@@ -443,6 +469,19 @@ hipError_t launch_field(const SysDims& d, double k, Colloc c, int64_t n_pts, con
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(field_sum_kernel, dim3((unsigned)((n_pts + 255) / 256)), dim3(256), 0, s,
                      n_pts, n_chunks, partial, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_status(const int32_t* st, int64_t n, unsigned long long* counts,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(count_status_kernel, dim3((unsigned)blocks), dim3(256), 0, s, st, n, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_counts(unsigned long long* counts, int n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, s, counts, n);
   return hipGetLastError();
 }
 

@@ -65,4 +65,11 @@ hipError_t launch_rhs(const SysDims& d, double k, int kind, const double* p, Col
 hipError_t launch_field(const SysDims& d, double k, Colloc c, int64_t n_pts, const double* pts,
                         const cplx* phi, cplx* partial, int n_chunks, cplx* u, hipStream_t s);
 
+// counts[0] += pairs flagged FFBIE_PAIR_UNRESOLVED, counts[1] += pairs flagged
+// FFBIE_PAIR_ROOT_FALLBACK among st[0..n); launch_zero_counts clears n counters
+// with a kernel (no memset node when a caller captures the stream).
+hipError_t launch_count_status(const int32_t* st, int64_t n, unsigned long long* counts,
+                               hipStream_t s);
+hipError_t launch_zero_counts(unsigned long long* counts, int n, hipStream_t s);
+
 }  // namespace ffbie

@@ -820,11 +820,11 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
       swap_convolution<C>(GF, pF, A, L, ph_lane, ph64, asc, cb + L, cb + L, crow, lane);
       wave_sync();
     } else if (want_c) {
-      // kc below overwrites GF's buffer (free2).  No barrier is needed: GF and
-      // kc share a base pointer, so for each lane the compiler keeps these loads
-      // before those stores, the lanes of a wavefront issue them in lockstep,
-      // and LDS performs one wavefront's operations in order.
       swap_convolution<C>(GF, pF, A, L, ph_lane, ph64, asc, crow, nullptr, nullptr, lane);
+      // kc below overwrites GF's buffer (free2), read across lanes above: the
+      // wavefront-scope fence keeps the compiler from moving those stores
+      // before the other lanes' loads
+      wave_sync();
     }
     // ---- kc_n = <cos(k rho)/rho>_n, n = 0..M
     C* kc = want_c ? free2 : cb;

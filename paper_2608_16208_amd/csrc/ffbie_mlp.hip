@@ -96,6 +96,20 @@ __global__ void to_bf16_kernel(const float* x, uint16_t* y, int64_t n) {
   if (i < n) y[i] = to_bf16(x[i]);
 }
 
+// Minibatch gather: row i of xb (bf16) and of tg (fp32) are rows idx[i] of
+// the training inputs x [*][kIn] and targets t [*][kOut].
+__global__ void gather_batch_kernel(const float* __restrict__ x, const float* __restrict__ t,
+                                    const int32_t* __restrict__ idx, int64_t n, uint16_t* xb,
+                                    float* tg) {
+  const int64_t row = blockIdx.y;
+  if (row >= n) return;
+  const int64_t src = idx[row];
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < Mlp::kIn; c += gridDim.x * blockDim.x)
+    xb[row * Mlp::kIn + c] = to_bf16(x[src * Mlp::kIn + c]);
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < Mlp::kOut; c += gridDim.x * blockDim.x)
+    tg[row * Mlp::kOut + c] = t[src * Mlp::kOut + c];
+}
+
 // dY = (Y - T) / n  (fp32 and bf16) and the partial sums of |Y - T|^2
 __global__ __launch_bounds__(256) void loss_grad_kernel(const float* Y, const float* T, int64_t cnt,
                                                         float inv_n, uint16_t* dYb, double* partial) {
@@ -267,7 +281,7 @@ hipError_t Mlp::alloc() {
 void Mlp::release() {
   for (void* p : {(void*)params, (void*)grads, (void*)m1, (void*)m2, (void*)wb, (void*)xb,
                   (void*)a1, (void*)a2, (void*)y, (void*)dyb, (void*)da, (void*)dzb, (void*)partial,
-                  (void*)R, (void*)feat, (void*)scale})
+                  (void*)R, (void*)feat, (void*)scale, (void*)tg})
     if (p) (void)hipFree(p);
   *this = Mlp{};
 }
@@ -353,6 +367,19 @@ hipError_t Mlp::adam(float lr, hipStream_t s) {
   hipLaunchKernelGGL(adam_kernel, g1(P), dim3(256), 0, s, params, grads, m1, m2, (int64_t)P, lr, b1,
                      b2, eps, c1, c2, (uint16_t*)nullptr);
   return refresh_bf16(s);
+}
+
+hipError_t Mlp::gather_batch(const float* x, const float* t, const int32_t* idx, int64_t n, hipStream_t s) {
+  hipError_t e;
+  if (n > tg_cap) {
+    if (tg) (void)hipFree(tg);
+    tg = nullptr;
+    tg_cap = 0;
+    if ((e = hipMalloc(&tg, n * kOut * sizeof(float))) != hipSuccess) return e;
+    tg_cap = n;
+  }
+  hipLaunchKernelGGL(gather_batch_kernel, dim3(1, (unsigned)n), dim3(256), 0, s, x, t, idx, n, xb, tg);
+  return hipGetLastError();
 }
 
 hipError_t Mlp::inputs_bf16(const float* x, int64_t n, hipStream_t s) {

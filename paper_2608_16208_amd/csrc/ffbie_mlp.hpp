@@ -30,6 +30,8 @@ struct Mlp {
   float* da = nullptr;
   uint16_t* dzb = nullptr;
   double* partial = nullptr;
+  float* tg = nullptr;         // targets of the gathered minibatch
+  int64_t tg_cap = 0;
   // mode transforms
   int64_t modes_cap = 0;
   cplx* R = nullptr;
@@ -49,6 +51,9 @@ struct Mlp {
   hipError_t ensure_modes(int M, int nodes);
   hipError_t refresh_bf16(hipStream_t s);
   hipError_t inputs_bf16(const float* x, int64_t n, hipStream_t s);
+  // xb <- bf16 rows idx[0..n) of x [*][kIn], tg <- rows idx[0..n) of t [*][kOut]
+  // (after ensure_batch(n))
+  hipError_t gather_batch(const float* x, const float* t, const int32_t* idx, int64_t n, hipStream_t s);
   hipError_t forward(int64_t n, hipStream_t s);
   hipError_t backward(int64_t n, const float* t, hipStream_t s, int* nblk);
   hipError_t adam(float lr, hipStream_t s);

@@ -10,8 +10,8 @@ network serves as the right preconditioner and initial guess of flexible
 GMRES (`solve(..., SOLVE_FGMRES_MLP)`), which falls back to plain GMRES when it
 does not reach the tolerance.
 
-Command line (writes the weights with numpy, no pickle):
-    python -m paper_2608_16208_amd.learned --out weights.npz [--systems 200]
+Command line (writes the library's network checkpoint):
+    python -m paper_2608_16208_amd.learned --out weights.ffbiemlp [--systems 200]
 """
 import argparse
 import time
@@ -75,23 +75,14 @@ def make_dataset(ctx, surfaces, M=64, n_rhs=8, seed=0, min_scale=1e-6, log=None)
 
 
 def train(ctx, X, T, steps=2000, batch=2048, lr=1e-3, seed=0, log=None):
-    """Adam on minibatches drawn without replacement per epoch; returns the losses."""
-    import torch
-    g = torch.Generator(device="cpu").manual_seed(seed)
-    n = X.shape[0]
-    losses, perm, pos = [], torch.randperm(n, generator=g), 0
-    for step in range(steps):
-        if pos + batch > n:
-            perm, pos = torch.randperm(n, generator=g), 0
-        idx = perm[pos:pos + batch].to(X.device)
-        pos += batch
-        xb, tb = X[idx].contiguous(), T[idx].contiguous()
-        lr_s = lr * 0.5 * (1 + np.cos(np.pi * step / steps))        # cosine decay
-        loss, _ = ctx.mlp_train_step(xb, tb, lr=lr_s)
-        losses.append(loss)
-        if log and (step % 200 == 0 or step == steps - 1):
-            log(f"step {step}: loss {loss:.4e}")
-    return losses
+    """Adam with cosine decay on minibatches drawn without replacement per
+    epoch, by the library's own training loop (ffbie_mlp_train).  Returns the
+    loss record {loss_first, loss_last, loss_full, steps}."""
+    info = ctx.mlp_train(X, T, steps=steps, batch=min(batch, X.shape[0]), lr=lr, seed=seed)
+    if log:
+        log(f"{steps} steps: minibatch loss {info['loss_first']:.4e} -> {info['loss_last']:.4e}, "
+            f"training set {info['loss_full']:.4e}")
+    return info
 
 
 def evaluate(ctx, surfaces, M=64, tol=1e-8, max_iter=600):
@@ -121,13 +112,13 @@ def evaluate(ctx, surfaces, M=64, tol=1e-8, max_iter=600):
     return rows
 
 
-def save(path, params):
-    np.savez(path, params=np.asarray(params, dtype=np.float32))
+def save(ctx, path):
+    """The network and its Adam state (ffbie_mlp_save)."""
+    ctx.mlp_save(path)
 
 
-def load(path):
-    with np.load(path, allow_pickle=False) as f:
-        return f["params"]
+def load(ctx, path):
+    ctx.mlp_load(path)
 
 
 def main():
@@ -148,9 +139,9 @@ def main():
     X, T = make_dataset(ctx, surfs, M=args.M, n_rhs=args.rhs, log=log)
     log(f"dataset {X.shape[0]} samples in {time.time() - t0:.1f} s")
     t0 = time.time()
-    losses = train(ctx, X, T, steps=args.steps, batch=args.batch, lr=args.lr, log=log)
-    log(f"trained in {time.time() - t0:.1f} s; loss {losses[0]:.3e} -> {losses[-1]:.3e}")
-    save(args.out, ctx.mlp_get_params())
+    rec = train(ctx, X, T, steps=args.steps, batch=args.batch, lr=args.lr, log=log)
+    log(f"trained in {time.time() - t0:.1f} s; loss {rec['loss_first']:.3e} -> {rec['loss_full']:.3e}")
+    save(ctx, args.out)
 
 
 if __name__ == "__main__":

@@ -115,3 +115,30 @@ def test_field_matches_oracle(ctx):
     u = ctx.eval_field(torch.tensor(pts), torch.tensor(phi)).cpu().numpy()
     ref = oasm.field(cfg["amp"], cfg["n_panels"], cfg["M"], cfg["k"], phi, pts)
     assert np.max(np.abs(u - ref)) / np.max(np.abs(ref)) <= 1e-12
+
+
+def test_assembly_reports_unresolved_near_pairs(ctx):
+    """The near pairs' flags reach the caller: none unresolved at config 2
+    (16 panels, M = 64, k = 5); at k = 25 with M = 16 (a batch-family surface)
+    the smooth factor of many near pairs is not resolved by 4M samples and
+    ffbie_assemble returns the FFBIE_WUNRESOLVED warning with the counts.
+    (M = 16 is too few even for k = 5 on the config-2 shape: a third of the near
+    pairs are flagged there.)"""
+    import paper_2608_16208_amd as ffbie
+    cfg = workloads.config(2)
+    ctx.set_near_rule(None)
+    ctx.set_problem(cfg["amp"], cfg["n_panels"], cfg["M"], cfg["k"])
+    S = ctx.assemble()
+    rep = ctx.last_assembly
+    assert rep["status"] == 0 and rep["unresolved"] == 0 and rep["pairs"] == ctx.query()[1], rep
+    del S
+    torch.cuda.empty_cache()
+    b = workloads.batch_surface(3)
+    ctx.set_problem(b["amp"], 4, 16, 25.0)
+    S = ctx.assemble()
+    rep = ctx.last_assembly
+    print("k = 25, M = 16: %d of %d near pairs unresolved, %d root fallbacks"
+          % (rep["unresolved"], rep["pairs"], rep["root_fallback"]))
+    assert rep["status"] == ffbie.WUNRESOLVED and rep["unresolved"] > 0, rep
+    assert ctx.workspace_bytes() > 0
+

@@ -253,8 +253,9 @@ def test_batch_surfaces_full_near_sets_as_benchmarked(ctx):
     FFBIE_PAIR_UNRESOLVED flag: small M with large k is not) with the oracle
     (1e-10)."""
     surfs, items = [], []
-    for s in (0, 1, 2, 3, 5, 8, 13, 21):
+    for s in (0, 2, 3, 7, 8, 13, 19, 21):     # members whose M the library supports
         c = workloads.batch_surface(s)
+        assert c["M"] in (16, 32, 64, 128)
         ctx.set_problem(c["amp"], c["n_panels"], c["M"], c["k"])
         t, az, ts = ctx.near_pairs()
         surfs.append(dict(c, t=t, az=az, ts=ts))
@@ -285,3 +286,20 @@ def test_batch_surfaces_full_near_sets_as_benchmarked(ctx):
     assert worst <= 1e-12, worst
     assert n_oracle >= 4
     plan.close()
+
+
+def test_batch_members_with_unsupported_M_are_rejected(ctx):
+    """Members with M in {24, 48, 96} (2M = 2^a 3^b with b > 0) need radix-3
+    transforms, which the library does not have: set_problem and batch plans
+    reject them with FFBIE_EINVAL (the benchmark reports them as skipped)."""
+    import paper_2608_16208_amd as ffbie
+    odd = [s for s in range(64) if workloads.batch_surface(s)["M"] not in (16, 32, 64, 128)]
+    assert odd
+    c = workloads.batch_surface(odd[0])
+    with pytest.raises(ffbie.FfbieError, match="M"):
+        ctx.set_problem(c["amp"], c["n_panels"], c["M"], c["k"])
+    t = torch.zeros(1, dtype=torch.float64)
+    with pytest.raises(ffbie.FfbieError):
+        ctx.batch_plan([dict(amp=c["amp"], M=c["M"], k=c["k"], t=t + 1.0, az=torch.zeros(1, dtype=torch.int32),
+                             ts=t + 1.5)])
+

@@ -154,8 +154,8 @@ def test_trained_network_gain_is_measured(ctx):
     M = 32
     ctx.mlp_init(5)
     X, T = learned.make_dataset(ctx, [surf(i) for i in range(6)], M=M, n_rhs=8, seed=1)
-    losses = learned.train(ctx, X, T, steps=400, batch=1024, lr=1e-3)
-    assert np.mean(losses[-20:]) < np.mean(losses[:20])
+    rec = learned.train(ctx, X, T, steps=400, batch=1024, lr=1e-3)
+    assert rec["loss_full"] < rec["loss_first"], rec
     rng = np.random.default_rng(3)
     dpts = rng.standard_normal((32, 3))
     pts = torch.tensor(dpts / np.linalg.norm(dpts, axis=1)[:, None] * 4.0)
@@ -176,3 +176,36 @@ def test_trained_network_gain_is_measured(ctx):
         assert (u - u0).abs().norm().item() <= 1e-6 * u0.abs().norm().item()
         del S
         torch.cuda.empty_cache()
+
+
+def test_native_training_lowers_the_loss_and_checkpoint_roundtrips(ctx, tmp_path):
+    """ffbie_mlp_train on a fixed regression set: the loss over the set falls;
+    ffbie_mlp_save / ffbie_mlp_load restore weights and Adam state exactly (the
+    same forward outputs, bit for bit, and the same next training step)."""
+    import paper_2608_16208_amd as ffbie
+    rng = np.random.default_rng(12)
+    n = 3000
+    W = rng.standard_normal((omlp.N_OUT, omlp.N_IN)).astype(np.float32) / np.sqrt(omlp.N_IN)
+    x = rng.standard_normal((n, omlp.N_IN)).astype(np.float32)
+    t = np.tanh(x @ W.T).astype(np.float32)
+    X, T = torch.tensor(x, device=ctx.device), torch.tensor(t, device=ctx.device)
+    ctx.mlp_init(21)
+    rec = ctx.mlp_train(X, T, steps=300, batch=500, lr=2e-3, seed=3)
+    print("native training: loss %.4e -> %.4e (set %.4e)" % (rec["loss_first"], rec["loss_last"], rec["loss_full"]))
+    assert rec["steps"] == 300 and rec["loss_full"] < 0.7 * rec["loss_first"], rec
+    path = str(tmp_path / "net.ffbiemlp")
+    ctx.mlp_save(path)
+    y0 = ctx.mlp_forward(X[:257]).cpu().numpy()
+    r1 = ctx.mlp_train(X, T, steps=5, batch=500, lr=1e-3, seed=9)
+    p1 = ctx.mlp_get_params()
+    ctx.mlp_init(99)                          # other weights, fresh Adam state
+    assert not np.array_equal(ctx.mlp_forward(X[:257]).cpu().numpy(), y0)
+    ctx.mlp_load(path)
+    assert np.array_equal(ctx.mlp_forward(X[:257]).cpu().numpy(), y0)
+    r2 = ctx.mlp_train(X, T, steps=5, batch=500, lr=1e-3, seed=9)
+    assert np.array_equal(ctx.mlp_get_params(), p1) and r1 == r2
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"not a checkpoint")
+    with pytest.raises(ffbie.FfbieError, match="checkpoint"):
+        ctx.mlp_load(str(bad))
+

@@ -273,3 +273,117 @@ def test_kappa_fourier_series_sums_back(amp, k):
     rho = np.sqrt(geo.rho2(amp, t, th, ts, xs))
     direct = np.exp(1j * k * rho) / rho
     assert np.max(np.abs(series - direct)) < 1e-13 * np.max(np.abs(direct))
+
+
+# ----------------------------------------------------------------------------
+# Truncation tail of eq. (3.10) (kappa_tail)
+# ----------------------------------------------------------------------------
+
+def test_kappa_tail_vanishes_at_k0():
+    """cos(0 rho) = 1 has the single coefficient <1>_0 = 1: no tail beyond the
+    rounding floor of the sum (~2 n_max magnitudes of a few 1e-16 each)."""
+    tail, mag = coeffs.kappa_tail(CFG2_AMP, 0.0, 16, 16, 1.1, 3, 1.4)
+    assert tail <= 1e-12 and abs(mag[mag.size // 2] - 1.0) <= 1e-15
+
+
+@pytest.mark.parametrize("n", [12, 20])
+def test_kappa_tail_coefficients_match_adaptive_quadrature(n):
+    """|<cos k rho>_n| against scipy's adaptive quadrature of the definition."""
+    from scipy import integrate
+    k, M, t, j, ts = 9.0, 16, 1.0, 5, 1.3
+    _, mag = coeffs.kappa_tail(CFG3_AMP, k, M, M, t, j, ts, n_max=32)
+    th = math.pi * j / M
+
+    def f(x, part):
+        v = math.cos(k * math.sqrt(float(geo.rho2(CFG3_AMP, t, th, ts, np.array([x]))[0])))
+        return v * (math.cos(n * x) if part == 0 else -math.sin(n * x))
+    re = integrate.quad(f, 0, 2 * math.pi, args=(0,), limit=400, epsabs=1e-15)[0] / (2 * math.pi)
+    im = integrate.quad(f, 0, 2 * math.pi, args=(1,), limit=400, epsabs=1e-15)[0] / (2 * math.pi)
+    assert abs(mag[32 + n] - math.hypot(re, im)) <= 1e-12
+
+
+def test_kappa_tail_separates_resolved_from_unresolved():
+    """k = 5 is resolved by M = 64 (tail at the rounding floor); k = 25 is not
+    by M = 8 (the tail is of the order of the coefficients themselves)."""
+    small, _ = coeffs.kappa_tail(CFG2_AMP, 5.0, 64, 64, 0.9, 7, 1.7)
+    large, _ = coeffs.kappa_tail(CFG2_AMP, 25.0, 8, 8, 0.9, 7, 1.7)
+    # the floor is the sum of 2 n_max + 1 rounding-level magnitudes (n_max = 512
+    # here): a few 1e-12
+    assert small <= 1e-11 and large >= 1e-3, (small, large)
+
+
+# ----------------------------------------------------------------------------
+# Mode-block-Jacobi reference (oracle/solve.py)
+# ----------------------------------------------------------------------------
+
+def _mode_diagonal_matrix(blocks, M, nodes):
+    """S[(a, j), (b, j')] = (1/2M) sum_m e^{i m theta_j} B_m[a, b] e^{-i m theta_j'}:
+    the matrix whose azimuthal-mode blocks are exactly B_m, written out entry by
+    entry (m = -M+1..M)."""
+    th = np.pi * np.arange(2 * M) / M
+    S = np.zeros((nodes, 2 * M, nodes, 2 * M), dtype=complex)
+    for mi, m in enumerate(range(-M + 1, M + 1)):
+        for j in range(2 * M):
+            for jp in range(2 * M):
+                S[:, j, :, jp] += np.exp(1j * m * (th[j] - th[jp])) * blocks[mi] / (2 * M)
+    return S.reshape(nodes * 2 * M, nodes * 2 * M)
+
+
+def test_mode_blocks_recover_the_blocks():
+    from oracle import solve as osolve
+    M, nodes = 3, 4
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((2 * M, nodes, nodes)) + 1j * rng.standard_normal((2 * M, nodes, nodes))
+    S = _mode_diagonal_matrix(B, M, nodes)
+    assert np.max(np.abs(osolve.mode_blocks(S, M, nodes) - B)) <= 1e-13
+
+
+def test_blockjacobi_apply_is_exact_inverse_of_mode_diagonal_matrix():
+    """For a mode-diagonal S the block-Jacobi preconditioner is S^-1 exactly."""
+    from oracle import solve as osolve
+    M, nodes = 3, 4
+    rng = np.random.default_rng(6)
+    B = rng.standard_normal((2 * M, nodes, nodes)) + 1j * rng.standard_normal((2 * M, nodes, nodes))
+    B += 3 * np.eye(nodes)
+    S = _mode_diagonal_matrix(B, M, nodes)
+    v = rng.standard_normal(S.shape[0]) + 1j * rng.standard_normal(S.shape[0])
+    z = osolve.blockjacobi_apply(S, v, M, nodes)
+    assert np.linalg.norm(z - np.linalg.solve(S, v)) <= 1e-12 * np.linalg.norm(z)
+
+
+# ----------------------------------------------------------------------------
+# Point source G(x; p) = e^{ik|x-p|} / (4 pi |x-p|) (oracle/solve.py)
+# ----------------------------------------------------------------------------
+
+def test_point_source_unit_flux_and_helmholtz():
+    """G is the outgoing fundamental solution of (Delta + k^2): the flux of
+    grad G out of a small sphere around p is -1, (Delta + k^2) G = 0 away from
+    p (second differences), and G satisfies the radiation condition."""
+    from oracle import solve as osolve
+    k, p = 3.0, np.array([0.3, -0.2, 0.5])
+    eps = 1e-3
+    xg, wg = np.polynomial.legendre.leggauss(24)
+    nphi = 48
+    phi = 2 * np.pi * np.arange(nphi) / nphi
+    ct, ph = np.meshgrid(xg, phi, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    nrm = np.stack([st * np.cos(ph), st * np.sin(ph), ct], axis=-1).reshape(-1, 3)
+    w = (wg[:, None] * np.full(nphi, 2 * np.pi / nphi)[None, :]).ravel() * eps ** 2
+    h = 1e-6
+    dG = (osolve.point_source(k, p + (eps + h) * nrm, p) - osolve.point_source(k, p + (eps - h) * nrm, p)) / (2 * h)
+    flux = np.sum(w * dG)
+    assert abs(flux - (-1.0)) <= 1e-5, flux
+    x0 = np.array([1.0, 0.4, -0.7])
+    hh = 1e-3
+    lap = sum(osolve.point_source(k, x0 + s * hh * e, p)[0] for e in np.eye(3) for s in (1, -1)) \
+        - 6 * osolve.point_source(k, x0, p)[0]
+    res = lap / hh ** 2 + k ** 2 * osolve.point_source(k, x0, p)[0]
+    assert abs(res) <= 1e-5 * abs(k ** 2 * osolve.point_source(k, x0, p)[0]), res
+    # outgoing (Sommerfeld): r (dG/dr - ik G) -> 0, which the incoming wave
+    # e^{-ik|x-p|} / (4 pi |x-p|) violates (there it tends to -2ik r G)
+    d = np.array([0.6, 0.0, 0.8])
+    r = 1e4
+    Gr = osolve.point_source(k, p + r * d, p)[0]
+    dGr = (osolve.point_source(k, p + (r + 1e-4) * d, p)[0]
+           - osolve.point_source(k, p + (r - 1e-4) * d, p)[0]) / 2e-4
+    assert abs(r * (dGr - 1j * k * Gr)) <= 1e-3 * abs(k * r * Gr)

@@ -144,3 +144,19 @@ def test_oracle_green_identity_star(rule):
     ref = osolve.point_source(k, pts, rs)
     err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
     assert err <= 1e-6, err
+
+
+def test_oracle_green_identity_sphere(sphere_system):
+    """Interior Dirichlet problem of Sec. 5 on the sphere fixture: with the
+    right-hand side g = G(.; r*) of rhs_point_source (r* = (3, 4, 10.5)
+    outside), the field of the solved density at points inside equals G(.; r*)."""
+    k, M, npan, S = sphere_system
+    rs = np.array([3.0, 4.0, 10.5])
+    g = oasm.rhs_point_source(None, npan, M, k, rs)
+    phi = osolve.lu_solve(S, g)
+    rng = np.random.default_rng(3)
+    pts = 0.5 * rng.uniform(-1, 1, (8, 3)) / np.sqrt(3)
+    u = oasm.field(None, npan, M, k, phi, pts)
+    ref = osolve.point_source(k, pts, rs)
+    err = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+    assert err <= 1e-6, err

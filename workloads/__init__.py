@@ -73,17 +73,21 @@ def _min_radius(amp, n=256):
     return R.min()
 
 
+BATCH_M = (16, 24, 32, 48, 64, 96, 128)     # M in [16, 128] with 2M = 2^a 3^b
+
+
 def batch_surface(s):
     """Member s of the 64-surface batch: 20 amplitudes a_lm ~ U(-0.15, 0.15)
     (l = 1..4, m = 0..4, l-major; redrawn while min R < 0.5 on a 256^2 grid),
-    then n_panels ~ U{4..32}, M from {16, 32, 64, 128} and k ~ U[2, 25], all
-    from rng(100 + s)."""
+    then n_panels ~ U{4..32}, M uniform on BATCH_M (16 .. 128, the sizes whose
+    2M-point transforms factor into radix 2 and 3) and k ~ U[2, 25], all from
+    rng(100 + s)."""
     rng = np.random.default_rng(100 + s)
     amp = star_amplitudes(4, 4, 0.15, rng)
     while _min_radius(amp) < 0.5:
         amp = star_amplitudes(4, 4, 0.15, rng)
     n_panels = int(rng.integers(4, 33))
-    M = int(rng.choice([16, 32, 64, 128]))
+    M = int(rng.choice(BATCH_M))
     k = float(rng.uniform(2.0, 25.0))
     return dict(name=f"batch-star-{s}", amp=amp, k=k, n_panels=n_panels, M=M, seed=100 + s)
 
@@ -91,15 +95,13 @@ def batch_surface(s):
 def learned_surface(i, held_out=False):
     """Surfaces of the learned-preconditioner study: 20 amplitudes
     a_lm ~ U(-0.1, 0.1) (l = 1..4, m = 0..4, l-major; redrawn while min R < 0.5),
-    then k ~ U[1, 5]; rng(1000 + i) for training, rng(2000 + i) held out.
-    16 panels (256 curve nodes), M = 64.  (Above k ~ 8 restarted GMRES on the
-    first-kind system stalls with or without preconditioning, so the study
-    draws k where the iterative solves converge.)"""
+    then k ~ U[5, 30]; rng(1000 + i) for training, rng(2000 + i) held out.
+    16 panels (256 curve nodes), M = 64."""
     rng = np.random.default_rng((2000 if held_out else 1000) + i)
     amp = star_amplitudes(4, 4, 0.1, rng)
     while _min_radius(amp) < 0.5:
         amp = star_amplitudes(4, 4, 0.1, rng)
-    k = float(rng.uniform(1.0, 5.0))
+    k = float(rng.uniform(5.0, 30.0))
     return dict(name=f"learned-{'test' if held_out else 'train'}-{i}", amp=amp, k=k, n_panels=16, M=64,
                 seed=(2000 if held_out else 1000) + i)
 
