@@ -143,6 +143,25 @@ ffbie_status ffbie_kernel_coeffs(ffbie_ctx *ctx, int64_t n_pairs,
                                  void *d_kappa, void *d_rhoinv, double *d_root,
                                  int32_t *d_pair_status);
 
+/* ffbie_kernel_coeffs for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation, arguments and outputs, but its scratch
+ * (a 32-byte root record, a refine-list slot and a status word per pair, and
+ * the refine-list counter) lives in a file-scope device array of the library,
+ * one per GPU, allocated with the library's code and held until the process
+ * ends: about 44 MiB, room for at most 1048576 pairs.  The call allocates
+ * nothing (no hipMalloc, no library allocation) and needs only a problem set by
+ * ffbie_set_problem.  n_pairs above 1048576 gives FFBIE_EINVAL.  Every call on
+ * one GPU shares that GPU's array and leaves its contents behind (the counter
+ * is cleared by a kernel at the start of each call): calls that overlap on one
+ * GPU (from other contexts or streams) race and must be ordered by the
+ * caller. */
+ffbie_status ffbie_kernel_coeffs_noalloc(ffbie_ctx *ctx, int64_t n_pairs,
+                                         const double *d_tgt_t, const int32_t *d_tgt_az,
+                                         const double *d_src_t,
+                                         void *d_kappa, void *d_rhoinv, double *d_root,
+                                         int32_t *d_pair_status);
+
 /* Mixed-precision coefficient path: ffbie_kernel_coeffs with the spectral
  * stage in FP32.  The surface samples, the complex root (Lemma 3.6), the
  * recurrences for A_m(b) (eqs. (3.27)-(3.28)) and the swap phases e^{-i n a}

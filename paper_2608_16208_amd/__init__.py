@@ -29,7 +29,8 @@ EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_probl
            "ffbie_kernel_coeffs_mixed", "ffbie_set_tuning", "ffbie_get_tuning",
            "ffbie_batch_plan_create", "ffbie_batch_plan_execute", "ffbie_batch_plan_get_tuning",
            "ffbie_batch_plan_destroy", "ffbie_batch_plan_classes", "ffbie_gemm_sub",
-           "ffbie_assembly_report", "ffbie_mlp_train", "ffbie_mlp_save", "ffbie_mlp_load")
+           "ffbie_assembly_report", "ffbie_mlp_train", "ffbie_mlp_save", "ffbie_mlp_load",
+           "ffbie_kernel_coeffs_noalloc")
 SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES, SOLVE_FGMRES_MLP, SOLVE_GMRES_BLOCKJACOBI = 0, 1, 2, 3, 4
 SOLVE_GMRES_LU32 = 5
 MLP_IN, MLP_HIDDEN, MLP_OUT = 514, 256, 512
@@ -101,6 +102,7 @@ def load_library(path=LIB_PATH):
     lib.ffbie_set_problem.argtypes = [vp, ctypes.POINTER(_Geometry), ctypes.POINTER(_Disc), ctypes.c_double]
     lib.ffbie_kernel_coeffs.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     lib.ffbie_kernel_coeffs_mixed.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
+    lib.ffbie_kernel_coeffs_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     lib.ffbie_singular_factor.argtypes = [vp, i64, vp, i32, vp]
     lib.ffbie_enable_timing.argtypes = [vp, i32]
     dp = ctypes.POINTER(ctypes.c_double)
@@ -216,11 +218,12 @@ class Context:
         self.M, self.M0 = int(M), int(M if M0 is None else M0)
 
     def kernel_coeffs(self, t, az, ts, rhoinv=False, root=False, status=True, kappa=None,
-                      mixed=False, rhoinv_out=None):
+                      mixed=False, rhoinv_out=None, noalloc=False):
         """kappa [n, 2M] complex128 (n = -M+1..M); optional <rho^-1> [n, M+M0+1],
         root [n, 2] (a - theta_j, b) and per-pair status [n] int32.  With
         mixed=True the FP32 spectral-stage path runs and kappa / <rho^-1> are
-        complex64."""
+        complex64.  noalloc=True calls ffbie_kernel_coeffs_noalloc (the library
+        allocates nothing; outputs passed in are used as they are)."""
         torch = self._torch
         dev = self.device
         cdt = torch.complex64 if mixed else torch.complex128
@@ -244,7 +247,10 @@ class Context:
             out["rhoinv"] = torch.empty((n, self.M + self.M0 + 1), dtype=cdt, device=dev) if rhoinv else None
         out["root"] = torch.empty((n, 2), dtype=torch.float64, device=dev) if root else None
         out["status"] = torch.empty((n,), dtype=torch.int32, device=dev) if status else None
-        fn = self.lib.ffbie_kernel_coeffs_mixed if mixed else self.lib.ffbie_kernel_coeffs
+        if noalloc and mixed:
+            raise FfbieError("the no-allocation entry point has no mixed-precision form")
+        fn = (self.lib.ffbie_kernel_coeffs_mixed if mixed else
+              self.lib.ffbie_kernel_coeffs_noalloc if noalloc else self.lib.ffbie_kernel_coeffs)
         rc = fn(self.h, n, _ptr(t), _ptr(az), _ptr(ts), _ptr(out["kappa"]), _ptr(out["rhoinv"]),
                 _ptr(out["root"]), _ptr(out["status"]))
         self._check(rc, self.h)

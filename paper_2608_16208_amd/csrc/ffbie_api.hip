@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,49 @@ using namespace ffbie;
 namespace {
 #include "ggq16_table.inc"
 }
+
+// ---------------------------------------------------------------------------
+// Scratch of ffbie_kernel_coeffs_noalloc: a file-scope device array, one copy
+// per GPU the library runs on, held until the process ends.  Layout for up to
+// kNoAllocPairs pairs: root records, refine-list slots, status words, then the
+// refine-list counter, each part 256-byte aligned.  In host code `scratch` is
+// only a handle: its device address on each GPU comes from
+// hipGetSymbolAddress (noalloc_scratch below) and is what the kernels receive.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kNoAllocPairs = (int64_t)1 << 20;
+constexpr size_t kNoAllocRootsOff = 0;
+constexpr size_t kNoAllocListOff = kNoAllocRootsOff + kNoAllocPairs * sizeof(ffbie::RootRec);
+constexpr size_t kNoAllocStatusOff = kNoAllocListOff + kNoAllocPairs * sizeof(int64_t);
+constexpr size_t kNoAllocCountOff = kNoAllocStatusOff + kNoAllocPairs * sizeof(int32_t);
+constexpr size_t kNoAllocBytes = kNoAllocCountOff + 256;
+static_assert(kNoAllocListOff % 256 == 0 && kNoAllocStatusOff % 256 == 0 && kNoAllocCountOff % 256 == 0,
+              "scratch parts must stay 256-byte aligned");
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current), looked up
+// once per device.
+hipError_t noalloc_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch[device] = p;
+  }
+  *out = g_scratch[device];
+  return hipSuccess;
+}
+}  // namespace
 
 struct ffbie_ctx {
   int device = 0;
@@ -89,6 +133,8 @@ struct ffbie_ctx {
   // minibatch order of ffbie_mlp_train
   int32_t* d_train_idx = nullptr;
   int64_t train_idx_cap = 0;
+  // device address of this GPU's no-allocation scratch
+  unsigned char* d_scratch = nullptr;
 };
 
 namespace {
@@ -304,6 +350,13 @@ ffbie_status ffbie_create(ffbie_ctx** out, int device, void* hip_stream) {
   c->stream = static_cast<hipStream_t>(hip_stream);
   if (hipSetDevice(device) != hipSuccess) { delete c; return FFBIE_EDEVICE; }
   if (hipMalloc(&c->d_count, 4 * sizeof(int32_t)) != hipSuccess) { delete c; return FFBIE_ENOMEM; }
+  void* sp = nullptr;
+  if (noalloc_scratch(device, &sp) != hipSuccess) {
+    (void)hipFree(c->d_count);
+    delete c;
+    return FFBIE_EDEVICE;
+  }
+  c->d_scratch = static_cast<unsigned char*>(sp);
   *out = c;
   return FFBIE_OK;
 }
@@ -368,18 +421,26 @@ namespace {
 // The coefficient path on n pairs: root kernel, main pass (2M samples), refine
 // pass (4M samples); `single` selects the FP32 spectral stage (complex64
 // outputs).  Inputs validated by the caller.
-ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_t* d_az,
-                        const double* d_ts, void* d_kappa, void* d_rhoinv, double* d_root,
-                        int32_t* d_pair_status, bool single = false) {
-  ffbie_status s = ensure_ws(c, n);
-  if (s != FFBIE_OK) return s;
+// Scratch the coefficient path works in: a root record and a refine-list
+// slot per pair, the status words when the caller passes none, and the
+// refine-list counter.
+struct CoeffWs {
+  RootRec* roots;
+  int32_t* status;
+  int64_t* list;
+  int32_t* count;
+};
+
+ffbie_status run_coeffs_ws(ffbie_ctx* c, const CoeffWs& ws, int64_t n, const double* d_t,
+                           const int32_t* d_az, const double* d_ts, void* d_kappa, void* d_rhoinv,
+                           double* d_root, int32_t* d_pair_status, bool single) {
   const Prob& P = c->prob;
-  int32_t* status = d_pair_status ? d_pair_status : c->d_status;
+  int32_t* status = d_pair_status ? d_pair_status : ws.status;
 
   if (c->timing) FFBIE_HIP(c, hipEventRecord(c->ev[0], c->stream));
   // kernel 1: roots, one lane per pair
-  FFBIE_HIP(c, launch_root(P, c->d_tab, n, d_t, d_az, d_ts, c->d_roots, status, d_root, c->stream));
-  FFBIE_HIP(c, hipMemsetAsync(c->d_count, 0, sizeof(int32_t), c->stream));
+  FFBIE_HIP(c, launch_root(P, c->d_tab, n, d_t, d_az, d_ts, ws.roots, status, d_root, c->stream));
+  FFBIE_HIP(c, launch_zero(ws.count, 1, c->stream));
   // kernel 2: main pass with 2M samples, then the refine pass with 4M samples
   CoeffArgs a{};
   a.P = P;
@@ -389,7 +450,7 @@ ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_
   a.t_in = d_t;
   a.az_in = d_az;
   a.ts_in = d_ts;
-  a.roots = c->d_roots;
+  a.roots = ws.roots;
   a.status = status;
   a.kappa = d_kappa;
   a.rhoinv = d_rhoinv;
@@ -399,8 +460,8 @@ ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_
                      : (d_rhoinv != nullptr ? kLdsTransforms : kLdsCompact);
   {
     a.NF = 2 * P.M;
-    a.flag_list = c->d_list;
-    a.flag_count = c->d_count;
+    a.flag_list = ws.list;
+    a.flag_count = ws.count;
     size_t lds;
     const int w = coeff_waves(P, a.NF, layout, single, &lds);
     // 32 consecutive pairs per wavefront: fewer wavefronts share out the
@@ -414,8 +475,8 @@ ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_
   }
   {
     a.NF = 4 * P.M;
-    a.list = c->d_list;
-    a.list_count = c->d_count;
+    a.list = ws.list;
+    a.list_count = ws.count;
     a.flag_list = nullptr;
     a.flag_count = nullptr;
     size_t lds;
@@ -425,6 +486,16 @@ ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_
   }
   if (c->timing) c->timed = true;
   return FFBIE_OK;
+}
+
+// The coefficient path with the context's workspace (grown on demand).
+ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_t* d_az,
+                        const double* d_ts, void* d_kappa, void* d_rhoinv, double* d_root,
+                        int32_t* d_pair_status, bool single = false) {
+  ffbie_status s = ensure_ws(c, n);
+  if (s != FFBIE_OK) return s;
+  const CoeffWs ws{c->d_roots, c->d_status, c->d_list, c->d_count};
+  return run_coeffs_ws(c, ws, n, d_t, d_az, d_ts, d_kappa, d_rhoinv, d_root, d_pair_status, single);
 }
 
 // Rule tables (node positions per relation and the weighted Lagrange matrices)
@@ -832,6 +903,27 @@ ffbie_status ffbie_kernel_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, con
   if (n > (int64_t)1 << 31) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs: n_pairs > 2^31");
   FFBIE_HIP(c, hipSetDevice(c->device));
   return run_coeffs(c, n, d_t, d_az, d_ts, d_kappa, d_rhoinv, d_root, d_pair_status);
+}
+
+ffbie_status ffbie_kernel_coeffs_noalloc(ffbie_ctx* c, int64_t n, const double* d_t,
+                                         const int32_t* d_az, const double* d_ts, void* d_kappa,
+                                         void* d_rhoinv, double* d_root, int32_t* d_pair_status) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_kernel_coeffs_noalloc: no problem set");
+  if (n < 0) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_noalloc: n_pairs < 0");
+  if (n > kNoAllocPairs)
+    return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_noalloc: n_pairs above the scratch capacity of "
+                                 "1048576 pairs");
+  if (n == 0) return FFBIE_OK;
+  if (!d_t || !d_az || !d_ts || !d_kappa)
+    return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_noalloc: NULL input or kappa pointer");
+  if (!c->d_scratch) return fail(c, FFBIE_EDEVICE, "ffbie_kernel_coeffs_noalloc: no scratch address");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  const CoeffWs ws{reinterpret_cast<RootRec*>(c->d_scratch + kNoAllocRootsOff),
+                   reinterpret_cast<int32_t*>(c->d_scratch + kNoAllocStatusOff),
+                   reinterpret_cast<int64_t*>(c->d_scratch + kNoAllocListOff),
+                   reinterpret_cast<int32_t*>(c->d_scratch + kNoAllocCountOff)};
+  return run_coeffs_ws(c, ws, n, d_t, d_az, d_ts, d_kappa, d_rhoinv, d_root, d_pair_status, false);
 }
 
 ffbie_status ffbie_kernel_coeffs_mixed(ffbie_ctx* c, int64_t n, const double* d_t,
