@@ -431,6 +431,13 @@ ffbie_status ffbie_eval_field(ffbie_ctx *ctx, int64_t n_pts, const double *d_pts
  *                          the inverses of the diagonal azimuthal-mode blocks of S
  *                          (see ffbie_blockjacobi_setup), built inside the call;
  *                          phi_0 = P(g).  Needs 16 n_panels <= 512.
+ *   FFBIE_SOLVE_FGMRES_BJ_MLP flexible GMRES (restart 100) with P(v) = BJ(v) +
+ *                          NN(v): the mode-block-Jacobi correction (as for
+ *                          GMRES_BLOCKJACOBI) plus the learned network's
+ *                          correction of what block-Jacobi misses (ffbie_mlp_*,
+ *                          trained on S^{-1} v - BJ(v)); phi_0 = P(g); falls back to
+ *                          plain GMRES as FGMRES_MLP does.  Needs weights and
+ *                          n_panels = 16.
  *   FFBIE_SOLVE_GMRES_LU32 GMRES (restart 100) in complex128 right-preconditioned
  *                          by the LU factors of a complex64 copy of S
  *                          (workspace N*N*8 bytes): the GMRES form of mixed-
@@ -440,7 +447,8 @@ ffbie_status ffbie_eval_field(ffbie_ctx *ctx, int64_t n_pts, const double *d_pts
  * Returns FFBIE_ESINGULAR on an exactly zero pivot, FFBIE_WNOTCONV if an
  * iterative method did not reach tol (phi holds the last iterate). */
 enum { FFBIE_SOLVE_LU64 = 0, FFBIE_SOLVE_LU32_IR64 = 1, FFBIE_SOLVE_GMRES = 2,
-       FFBIE_SOLVE_FGMRES_MLP = 3, FFBIE_SOLVE_GMRES_BLOCKJACOBI = 4, FFBIE_SOLVE_GMRES_LU32 = 5 };
+       FFBIE_SOLVE_FGMRES_MLP = 3, FFBIE_SOLVE_GMRES_BLOCKJACOBI = 4, FFBIE_SOLVE_GMRES_LU32 = 5,
+       FFBIE_SOLVE_FGMRES_BJ_MLP = 6 };
 typedef struct {
   int iterations;
   int converged;

@@ -113,7 +113,7 @@ def near_block(kappa16, tab, l, rel, M, h):
     return out
 
 
-def near_kappa(amp, k, M, n_panels, rows, tab, processes=None):
+def near_kappa(amp, k, M, n_panels, rows, tab, processes=None, kind="S"):
     """Kernel coefficients of the near pairs of the given target rows:
     dict (row, rel) -> [16][2M].  For the sphere (amp all zero) the
     coefficients at azimuth j are those at azimuth 0 times e^{-i n theta_j}
@@ -130,32 +130,49 @@ def near_kappa(amp, k, M, n_panels, rows, tab, processes=None):
             J.append(np.full(N16, 0 if axisym else j))
             TS.append((i + rel) * L["h"] + 0.5 * L["h"] * (y + 1.0))
     T, J, TS = np.concatenate(T), np.concatenate(J), np.concatenate(TS)
+    def coefficient_rows(t_, j_, ts_):
+        if kind == "S":
+            return coeffs.pairs_coeffs(amp, k, M, 2 * M, t_, j_, ts_, processes=processes)[1]
+        from . import double_layer
+        return double_layer.pairs_kcoeffs(amp, k, M, t_, j_, ts_, adjoint=(kind == "Kp"),
+                                          processes=processes)[0]
+
     if axisym:
         # one computation per distinct (t, t_s)
         uniq, inv = np.unique(np.stack([T, TS], 1), axis=0, return_inverse=True)
-        _, kap_u, _ = coeffs.pairs_coeffs(amp, k, M, 2 * M, uniq[:, 0], np.zeros(len(uniq), int),
-                                          uniq[:, 1], processes=processes)
+        kap_u = coefficient_rows(uniq[:, 0], np.zeros(len(uniq), int), uniq[:, 1])
         kap = kap_u[inv.ravel()]
         n = np.arange(-M + 1, M + 1)
         jrow = np.repeat([int(L["j"][r]) for r, _ in keys], N16)
         kap = kap * np.exp(-1j * np.outer(np.pi * jrow / M, n))
     else:
-        _, kap, _ = coeffs.pairs_coeffs(amp, k, M, 2 * M, T, J, TS, processes=processes)
+        kap = coefficient_rows(T, J, TS)
     return {key: kap[N16 * a:N16 * (a + 1)] for a, key in enumerate(keys)}
 
 
-def rows(amp, k, M, n_panels, row_ids, tab, processes=None):
-    """Full rows of S for the given row indices, [len(row_ids)][N]."""
+def rows(amp, k, M, n_panels, row_ids, tab, processes=None, kind="S"):
+    """Full rows of S (kind "S"), of the double-layer operator K ("K") or of
+    its adjoint K' ("Kp") for the given row indices, [len(row_ids)][N].  The
+    far entries of K and K' are W_{l'} (1/2M) tau_0 (ik rho - 1) e^{ik rho} /
+    rho^3 with tau_0 = nu_c . (x_c - x_r) (K) or nu_r . (x_r - x_c) (K'), the
+    integrand of Sec. 4; the near blocks take the coefficients of
+    double_layer.pairs_kcoeffs through the same rule as S."""
     L = layout(n_panels, M)
     N = 32 * M * n_panels
     x = geo.point(amp, L["t"], L["th"])
-    kap = near_kappa(amp, k, M, n_panels, row_ids, tab, processes=processes)
+    nu = geo.normal(amp, L["t"], L["th"]) if kind != "S" else None
+    kap = near_kappa(amp, k, M, n_panels, row_ids, tab, processes=processes, kind=kind)
     out = np.zeros((len(row_ids), N), dtype=complex)
     for a, r in enumerate(row_ids):
         i, l = int(L["i"][r]), int(L["l"][r])
         far = np.abs(L["i"] - i) >= 2
-        rho = np.linalg.norm(x[far] - x[r], axis=1)
-        out[a, far] = L["wq"][far] * np.exp(1j * k * rho) / rho
+        d = x[far] - x[r]
+        rho = np.linalg.norm(d, axis=1)
+        if kind == "S":
+            out[a, far] = L["wq"][far] * np.exp(1j * k * rho) / rho
+        else:
+            tz = np.einsum("nc,nc->n", nu[far], d) if kind == "K" else -(d @ nu[r])
+            out[a, far] = L["wq"][far] * tz * (1j * k * rho - 1.0) * np.exp(1j * k * rho) / rho ** 3
         for rel in near_relations(i, n_panels):
             blk = near_block(kap[(r, rel)], tab, l, rel, M, L["h"])
             c0 = (i + rel) * 32 * M
@@ -163,8 +180,26 @@ def rows(amp, k, M, n_panels, row_ids, tab, processes=None):
     return out
 
 
-def matrix(amp, k, M, n_panels, tab, processes=None):
-    return rows(amp, k, M, n_panels, np.arange(32 * M * n_panels), tab, processes=processes)
+def matrix(amp, k, M, n_panels, tab, processes=None, kind="S"):
+    return rows(amp, k, M, n_panels, np.arange(32 * M * n_panels), tab, processes=processes, kind=kind)
+
+
+def field_double_layer(amp, n_panels, M, k, psi, pts):
+    """Field of the double-layer representation of eq. (2.9),
+    u(x) = 2 int dG(x, y)/d nu(y) psi(y) d sigma, by the product rule:
+    u(x) = sum_c W_c tau_0 (ik rho - 1) e^{ik rho} / rho^3 psi~_c with
+    tau_0 = nu_c . (x_c - x)."""
+    x, _, wq = collocation(amp, n_panels, M)
+    L = layout(n_panels, M)
+    nu = geo.normal(amp, L["t"], L["th"])
+    pts = np.atleast_2d(pts)
+    out = np.zeros(len(pts), dtype=complex)
+    for a, p in enumerate(pts):
+        d = x - p
+        rho = np.linalg.norm(d, axis=1)
+        tz = np.einsum("nc,nc->n", nu, d)
+        out[a] = np.sum(wq * tz * (1j * k * rho - 1.0) * np.exp(1j * k * rho) / rho ** 3 * psi)
+    return out
 
 
 def rhs_point_source(amp, n_panels, M, k, p):

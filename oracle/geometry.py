@@ -90,6 +90,21 @@ def second_theta(amp, t, th):
             + R * _omega(t, th, dth=2))
 
 
+def second_derivs(amp, t, th):
+    """(r_tt, r_t theta, r_theta theta) at (t, theta), each shape (..., 3)."""
+    R = radius(amp, t, th)[..., None]
+    Rt = radius(amp, t, th, dt=1)[..., None]
+    Rth = radius(amp, t, th, dth=1)[..., None]
+    Rtt = radius(amp, t, th, dt=2)[..., None]
+    Rtth = radius(amp, t, th, dt=1, dth=1)[..., None]
+    Rthth = radius(amp, t, th, dth=2)[..., None]
+    w, wt, wth = _omega(t, th), _omega(t, th, dt=1), _omega(t, th, dth=1)
+    rtt = Rtt * w + 2.0 * Rt * wt + R * _omega(t, th, dt=2)
+    rtth = Rtth * w + Rt * wth + Rth * wt + R * _omega(t, th, dt=1, dth=1)
+    rthth = Rthth * w + 2.0 * Rth * wth + R * _omega(t, th, dth=2)
+    return rtt, rtth, rthth
+
+
 def jacobian(amp, t, th):
     """J = |r_t x r_theta| (assumption (iii) of Sec. 2)."""
     rt, rth = derivs(amp, t, th)

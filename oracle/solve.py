@@ -7,7 +7,8 @@ INFRASTRUCTURE ONLY.
       u_s(x) = -sum_n (2n+1) i^n [j_n(k)/h_n(k)] h_n(k|x|) P_n(d.x/|x|).
 * ``sphere_single_layer_eigenvalue``: on the unit sphere the operator of
   eq. (2.8), S[phi] = 2 int G phi dsigma, maps the spherical harmonic Y_n^m to
-  2ik j_n(k) h_n(k) Y_n^m.
+  2ik j_n(k) h_n(k) Y_n^m; ``sphere_double_layer_eigenvalue`` the same for K
+  and K' (Sec. 4).
 * ``point_source``: G(x; p) = e^{ik|x-p|}/(4 pi |x-p|), the exact interior
   solution of the Dirichlet test of Sec. 5.
 """
@@ -36,6 +37,17 @@ def mie_scattered(k, pts, d, nmax=40):
 
 def sphere_single_layer_eigenvalue(n, k):
     return 2j * k * special.spherical_jn(n, k) * hankel1(n, k)
+
+
+def sphere_double_layer_eigenvalue(n, k):
+    """On the unit sphere K[Y_n^m] = K'[Y_n^m] = i k^2 (j_n h_n)'(k) Y_n^m: the
+    double-layer potential of Y_n^m is i k^2 h_n'(k) j_n(k|x|) Y_n^m inside and
+    i k^2 j_n'(k) h_n(k|x|) Y_n^m outside; K (factor 2, principal value) is the
+    sum of the two limits on the surface."""
+    jn, dj = special.spherical_jn(n, k), special.spherical_jn(n, k, derivative=True)
+    hn = hankel1(n, k)
+    dh = dj + 1j * special.spherical_yn(n, k, derivative=True)
+    return 1j * k ** 2 * (dj * hn + jn * dh)
 
 
 def spherical_harmonic(n, m, t, th):

@@ -32,7 +32,7 @@ EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_probl
            "ffbie_assembly_report", "ffbie_mlp_train", "ffbie_mlp_save", "ffbie_mlp_load",
            "ffbie_kernel_coeffs_noalloc")
 SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES, SOLVE_FGMRES_MLP, SOLVE_GMRES_BLOCKJACOBI = 0, 1, 2, 3, 4
-SOLVE_GMRES_LU32 = 5
+SOLVE_GMRES_LU32, SOLVE_FGMRES_BJ_MLP = 5, 6
 MLP_IN, MLP_HIDDEN, MLP_OUT = 514, 256, 512
 WNOTCONV, WUNRESOLVED = 2, 3
 RHS_POINT_SOURCE, RHS_PLANE_WAVE = 0, 1

@@ -1299,7 +1299,7 @@ ffbie_status ensure_solve_ws(ffbie_ctx* c, int64_t N, int method) {
     c->s32_n = N;
   }
   if ((method == FFBIE_SOLVE_FGMRES_MLP || method == FFBIE_SOLVE_GMRES_BLOCKJACOBI ||
-       method == FFBIE_SOLVE_GMRES_LU32) && c->zbasis_n != N) {
+       method == FFBIE_SOLVE_GMRES_LU32 || method == FFBIE_SOLVE_FGMRES_BJ_MLP) && c->zbasis_n != N) {
     if (c->d_zbasis) (void)hipFree(c->d_zbasis);
     c->d_zbasis = nullptr;
     c->zbasis_n = 0;
@@ -1308,7 +1308,8 @@ ffbie_status ensure_solve_ws(ffbie_ctx* c, int64_t N, int method) {
     c->zbasis_n = N;
   }
   if ((method == FFBIE_SOLVE_GMRES || method == FFBIE_SOLVE_FGMRES_MLP ||
-       method == FFBIE_SOLVE_GMRES_BLOCKJACOBI || method == FFBIE_SOLVE_GMRES_LU32) && c->krylov_n != N) {
+       method == FFBIE_SOLVE_GMRES_BLOCKJACOBI || method == FFBIE_SOLVE_GMRES_LU32 ||
+       method == FFBIE_SOLVE_FGMRES_BJ_MLP) && c->krylov_n != N) {
     if (c->d_krylov) hipFree(c->d_krylov);
     c->d_krylov = nullptr;
     c->krylov_n = 0;
@@ -1346,6 +1347,16 @@ hipError_t mlp_apply(void* self, const cplx* v, cplx* z) {
   return mlp_precondition(c->mlp, v, c->prob.M, 16 * c->n_panels, c->prob.k, z, c->stream);
 }
 
+// z = BJ(v) + NN(v): the network corrects the block-Jacobi output (the first
+// of the context's solve vectors is its workspace; flexible GMRES uses the
+// second)
+hipError_t bj_mlp_apply(void* self, const cplx* v, cplx* z) {
+  ffbie_ctx* c = static_cast<ffbie_ctx*>(self);
+  hipError_t e = c->bj.apply(v, z, c->stream);
+  if (e != hipSuccess) return e;
+  return mlp_precondition_add(c->mlp, v, c->prob.M, 16 * c->n_panels, c->prob.k, z, c->d_vecs, c->stream);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1359,12 +1370,13 @@ ffbie_status ffbie_solve(ffbie_ctx* c, int method, void* d_S, int64_t ld, const 
     return fail(c, FFBIE_EINVAL, "ffbie_solve: NULL or aliased buffer, or ld < N");
   if (method != FFBIE_SOLVE_LU64 && method != FFBIE_SOLVE_LU32_IR64 && method != FFBIE_SOLVE_GMRES &&
       method != FFBIE_SOLVE_FGMRES_MLP && method != FFBIE_SOLVE_GMRES_BLOCKJACOBI &&
-      method != FFBIE_SOLVE_GMRES_LU32)
+      method != FFBIE_SOLVE_GMRES_LU32 && method != FFBIE_SOLVE_FGMRES_BJ_MLP)
     return fail(c, FFBIE_EINVAL, "ffbie_solve: unknown method");
   if (method == FFBIE_SOLVE_GMRES_BLOCKJACOBI && 16 * c->n_panels > 512)
     return fail(c, FFBIE_EINVAL, "ffbie_solve: block-Jacobi needs 16 n_panels <= 512");
-  if (method == FFBIE_SOLVE_FGMRES_MLP && (!c->mlp.ready || 16 * c->n_panels != Mlp::kNodes))
-    return fail(c, FFBIE_EINVAL, "ffbie_solve: FGMRES_MLP needs MLP weights and n_panels = 16");
+  if ((method == FFBIE_SOLVE_FGMRES_MLP || method == FFBIE_SOLVE_FGMRES_BJ_MLP) &&
+      (!c->mlp.ready || 16 * c->n_panels != Mlp::kNodes))
+    return fail(c, FFBIE_EINVAL, "ffbie_solve: the learned preconditioner needs MLP weights and n_panels = 16");
   if (method != FFBIE_SOLVE_LU64 && (!(tol > 0) || max_iter < 1))
     return fail(c, FFBIE_EINVAL, "ffbie_solve: need tol > 0 and max_iter >= 1");
   if (N > 2147483647 / 2) return fail(c, FFBIE_EINVAL, "ffbie_solve: N too large");
@@ -1391,6 +1403,11 @@ ffbie_status ffbie_solve(ffbie_ctx* c, int method, void* d_S, int64_t ld, const 
     r = gmres_lu32(sc, S, ld, N, g, phi, tol, max_iter, kRestart, &iters, &rel);
   } else if (method == FFBIE_SOLVE_FGMRES_MLP) {
     Precond P{mlp_apply, c};
+    r = fgmres64(sc, S, ld, N, g, phi, tol, max_iter, kRestart, P, &iters, &rel, &fell_back);
+  } else if (method == FFBIE_SOLVE_FGMRES_BJ_MLP) {
+    FFBIE_HIP(c, c->bj.setup(S, ld, c->prob.M, 16 * c->n_panels, c->stream));
+    c->bj.ready = true;
+    Precond P{bj_mlp_apply, c};
     r = fgmres64(sc, S, ld, N, g, phi, tol, max_iter, kRestart, P, &iters, &rel, &fell_back);
   } else {
     FFBIE_HIP(c, c->bj.setup(S, ld, c->prob.M, 16 * c->n_panels, c->stream));

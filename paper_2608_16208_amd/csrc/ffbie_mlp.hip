@@ -442,6 +442,22 @@ hipError_t mlp_precondition(Mlp& net, const cplx* v, int M, int nodes, double k,
   return hipGetLastError();
 }
 
+namespace {
+__global__ void add_into_kernel(cplx* z, const cplx* t, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) z[i] = cplx{z[i].re + t[i].re, z[i].im + t[i].im};
+}
+}  // namespace
+
+hipError_t mlp_precondition_add(Mlp& net, const cplx* v, int M, int nodes, double k, cplx* z, cplx* tmp,
+                                hipStream_t s) {
+  hipError_t e = mlp_precondition(net, v, M, nodes, k, tmp, s);
+  if (e != hipSuccess) return e;
+  const int64_t n = (int64_t)2 * M * nodes;
+  hipLaunchKernelGGL(add_into_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, tmp, n);
+  return hipGetLastError();
+}
+
 hipError_t gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak,
                      const uint16_t* B, int64_t sbk, int64_t sbn, float* C, int64_t ldc,
                      hipStream_t s) {

@@ -67,6 +67,10 @@ hipError_t mode_reconstruct(const float* y, const double* scale, int M, int node
                             hipStream_t s);
 hipError_t mlp_precondition(Mlp& net, const cplx* v, int M, int nodes, double k, cplx* z,
                             hipStream_t s);
+// z += P(v) (the network's correction added to a vector z already holding,
+// for instance, the block-Jacobi output); tmp is an N-vector of workspace
+hipError_t mlp_precondition_add(Mlp& net, const cplx* v, int M, int nodes, double k, cplx* z, cplx* tmp,
+                                hipStream_t s);
 hipError_t gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak,
                      const uint16_t* B, int64_t sbk, int64_t sbn, float* C, int64_t ldc,
                      hipStream_t s);

@@ -10,8 +10,9 @@ network serves as the right preconditioner and initial guess of flexible
 GMRES (`solve(..., SOLVE_FGMRES_MLP)`), which falls back to plain GMRES when it
 does not reach the tolerance.
 
-Command line (writes the library's network checkpoint):
-    python -m paper_2608_16208_amd.learned --out weights.ffbiemlp [--systems 200]
+Command lines:
+    python -m paper_2608_16208_amd.learned train --out weights.ffbiemlp [--systems 200]
+    python -m paper_2608_16208_amd.learned study [--train 200 --test 50] [--save/--load ckpt]
 """
 import argparse
 import time
@@ -74,6 +75,135 @@ def make_dataset(ctx, surfaces, M=64, n_rhs=8, seed=0, min_scale=1e-6, log=None)
     return torch.cat(X), torch.cat(T)
 
 
+def make_dataset_correction(ctx, surfaces, M=64, n_rhs=4, seed=0, min_scale=1e-6, log=None):
+    """Training pairs for the preconditioner P(v) = BJ(v) + NN(v): inputs are
+    the mode features of Krylov-type vectors v of each system, targets the
+    modes of the part of S^{-1} v that mode-block-Jacobi misses,
+    S^{-1} v - BJ(v), scaled like the features.  S^{-1} v comes from an LU64
+    factorisation of each system (a copy of S).  Returns (X, T) float32 device
+    tensors."""
+    import torch
+    rng = np.random.default_rng(seed)
+    X, T = [], []
+    for i, sf in enumerate(surfaces):
+        ctx.set_problem(sf["amp"], 16, M, sf["k"])
+        S = ctx.assemble()
+        ctx.blockjacobi_setup(S)
+        vs = _inputs(ctx, S, rng, n_rhs)
+        W = S.clone()
+        del S
+        torch.cuda.empty_cache()
+        ctx.lu_factor(W)
+        for v in vs:
+            d = ctx.lu_solve(W, v) - ctx.blockjacobi_apply(v)
+            x, sc = ctx.mode_features(v)
+            t = ctx.mode_targets(d, sc)
+            keep = sc >= min_scale * sc.max()
+            X.append(x[keep])
+            T.append(t[keep])
+        del W
+        torch.cuda.empty_cache()
+        if log and (i % 10 == 0 or i == len(surfaces) - 1):
+            log(f"system {i + 1}/{len(surfaces)} (k = {sf['k']:.2f})")
+    return torch.cat(X), torch.cat(T)
+
+
+def study(ctx, n_train=200, n_test=50, M=64, n_rhs=4, steps=3000, batch=2048, lr=1e-3, tol=1e-9,
+          max_iter=400, load=None, save_path=None, log=None):
+    """The learned-preconditioner study at its stated scale: a network trained
+    on n_train method-generated systems (star surfaces with 20 amplitudes
+    U(-0.1, 0.1), k ~ U[5, 30], 16 panels, M) to correct the mode-block-Jacobi
+    output, then used as P = BJ + NN by flexible GMRES (and its initial guess)
+    on n_test held-out surfaces, next to plain GMRES, block-Jacobi GMRES and
+    LU64.  For each held-out system (plane wave from a fixed direction): the
+    LU64 field at 64 far points is the reference; each iterative solve runs to
+    the residual tolerance `tol` (at most max_iter iterations) and reports its
+    iterations, time and field error, and whether it is within 1e-8 of the
+    reference (time-to-1e-8 = assembly + solve + field when it is).  With
+    `load` the network is read from a checkpoint instead of trained."""
+    import torch
+    from . import SOLVE_GMRES_BLOCKJACOBI, SOLVE_FGMRES_BJ_MLP
+    out = {"n_train": n_train, "n_test": n_test, "M": M, "tol": tol, "max_iter": max_iter}
+    if load:
+        ctx.mlp_load(load)
+        out["network"] = "loaded from checkpoint"
+    else:
+        ctx.mlp_init(1234)
+        t0 = time.perf_counter()
+        X, T = make_dataset_correction(ctx, [workloads.learned_surface(i) for i in range(n_train)], M=M,
+                                       n_rhs=n_rhs, log=log)
+        out["dataset"] = {"samples": int(X.shape[0]), "s": time.perf_counter() - t0}
+        t0 = time.perf_counter()
+        out["training"] = dict(train(ctx, X, T, steps=steps, batch=batch, lr=lr, log=log),
+                               s=time.perf_counter() - t0)
+        del X, T
+        torch.cuda.empty_cache()
+        if save_path:
+            ctx.mlp_save(save_path)
+    rng = np.random.default_rng(1)
+    dpts = rng.standard_normal((64, 3))
+    pts = torch.tensor(dpts / np.linalg.norm(dpts, axis=1)[:, None] * rng.uniform(3, 5, 64)[:, None])
+    rows = []
+    for j in range(n_test):
+        sf = workloads.learned_surface(j, held_out=True)
+        ctx.set_problem(sf["amp"], 16, M, sf["k"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S = ctx.assemble()
+        torch.cuda.synchronize()
+        t_asm = time.perf_counter() - t0
+        d = np.array([0.3, -0.5, 0.81])
+        g = ctx.rhs(RHS_PLANE_WAVE, d / np.linalg.norm(d))
+        W = S.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi_ref, _ = ctx.solve(W, g, method=SOLVE_LU64)
+        u_ref = ctx.eval_field(pts, phi_ref)
+        torch.cuda.synchronize()
+        t_lu = time.perf_counter() - t0
+        del W
+        torch.cuda.empty_cache()
+        row = {"k": sf["k"], "assembly_s": t_asm, "lu64": {"s": t_asm + t_lu}}
+        for name, method in (("gmres", SOLVE_GMRES), ("gmres_blockjacobi", SOLVE_GMRES_BLOCKJACOBI),
+                             ("fgmres_bj_nn", SOLVE_FGMRES_BJ_MLP)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            phi, info = ctx.solve(S, g, method=method, tol=tol, max_iter=max_iter)
+            u = ctx.eval_field(pts, phi)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            e = float(((u - u_ref).abs().norm() / u_ref.abs().norm()).item())
+            row[name] = {"iterations": info["iterations"], "converged": info["converged"],
+                         "fell_back": info["fell_back"], "rel_residual": info["rel_residual"],
+                         "field_error": e, "s": t_asm + dt, "reaches_1e-8": e <= 1e-8}
+        rows.append(row)
+        del S
+        torch.cuda.empty_cache()
+        if log:
+            log("held-out %d (k = %.1f): GMRES %d, BJ %d, BJ+NN %d iterations%s; LU64 %.2f s"
+                % (j, sf["k"], row["gmres"]["iterations"], row["gmres_blockjacobi"]["iterations"],
+                   row["fgmres_bj_nn"]["iterations"], " (fell back)" if row["fgmres_bj_nn"]["fell_back"] else "",
+                   row["lu64"]["s"]))
+    out["held_out"] = rows
+
+    def agg(name):
+        it = [r[name]["iterations"] for r in rows]
+        ok = [r[name]["reaches_1e-8"] for r in rows]
+        t = [r[name]["s"] for r in rows if r[name]["reaches_1e-8"]]
+        return {"median_iterations": float(np.median(it)), "mean_iterations": float(np.mean(it)),
+                "reach_1e-8": int(sum(ok)), "of": len(rows),
+                "median_time_to_1e-8_s": float(np.median(t)) if t else None,
+                "fell_back": int(sum(r[name]["fell_back"] for r in rows))}
+    out["summary"] = {n: agg(n) for n in ("gmres", "gmres_blockjacobi", "fgmres_bj_nn")}
+    out["summary"]["lu64"] = {"median_time_to_1e-8_s": float(np.median([r["lu64"]["s"] for r in rows]))}
+    both = [r for r in rows if r["gmres_blockjacobi"]["converged"] and r["fgmres_bj_nn"]["converged"]
+            and not r["fgmres_bj_nn"]["fell_back"]]
+    out["summary"]["bj_nn_fewer_iterations_than_bj"] = sum(
+        r["fgmres_bj_nn"]["iterations"] < r["gmres_blockjacobi"]["iterations"] for r in both)
+    out["summary"]["compared"] = len(both)
+    return out
+
+
 def train(ctx, X, T, steps=2000, batch=2048, lr=1e-3, seed=0, log=None):
     """Adam with cosine decay on minibatches drawn without replacement per
     epoch, by the library's own training loop (ffbie_mlp_train).  Returns the
@@ -123,16 +253,38 @@ def load(ctx, path):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", required=True)
-    ap.add_argument("--systems", type=int, default=200)
-    ap.add_argument("--rhs", type=int, default=8)
-    ap.add_argument("--steps", type=int, default=3000)
-    ap.add_argument("--batch", type=int, default=2048)
-    ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--M", type=int, default=64)
+    sub = ap.add_subparsers(dest="cmd")
+    a1 = sub.add_parser("train", help="train the per-mode network on block-Jacobi corrections")
+    a1.add_argument("--out", required=True)
+    a1.add_argument("--systems", type=int, default=200)
+    a1.add_argument("--rhs", type=int, default=8)
+    a1.add_argument("--steps", type=int, default=3000)
+    a1.add_argument("--batch", type=int, default=2048)
+    a1.add_argument("--lr", type=float, default=1e-3)
+    a1.add_argument("--M", type=int, default=64)
+    a2 = sub.add_parser("study", help="train P = BJ + NN and evaluate it on held-out surfaces")
+    a2.add_argument("--train", type=int, default=200)
+    a2.add_argument("--test", type=int, default=50)
+    a2.add_argument("--rhs", type=int, default=4)
+    a2.add_argument("--steps", type=int, default=3000)
+    a2.add_argument("--batch", type=int, default=2048)
+    a2.add_argument("--lr", type=float, default=1e-3)
+    a2.add_argument("--M", type=int, default=64)
+    a2.add_argument("--save", default=None, help="write the trained network here")
+    a2.add_argument("--load", default=None, help="evaluate a saved network instead of training")
+    a2.add_argument("--json", default=None, help="write the study's record here")
     args = ap.parse_args()
     log = lambda s: print(s, flush=True)
     ctx = Context(0)
+    if args.cmd == "study":
+        import json
+        res = study(ctx, n_train=args.train, n_test=args.test, M=args.M, n_rhs=args.rhs, steps=args.steps,
+                    batch=args.batch, lr=args.lr, load=args.load, save_path=args.save, log=log)
+        log(json.dumps(res["summary"]))
+        if args.json:
+            with open(args.json, "w") as fh:
+                json.dump(res, fh)
+        return
     ctx.mlp_init(1234)
     surfs = [workloads.learned_surface(i) for i in range(args.systems)]
     t0 = time.time()

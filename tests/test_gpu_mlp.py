@@ -209,3 +209,23 @@ def test_native_training_lowers_the_loss_and_checkpoint_roundtrips(ctx, tmp_path
     with pytest.raises(ffbie.FfbieError, match="checkpoint"):
         ctx.mlp_load(str(bad))
 
+
+
+def test_bj_plus_network_with_silent_network_is_block_jacobi(ctx):
+    """P(v) = BJ(v) + NN(v) with the network's last layer zero (NN = 0) is the
+    block-Jacobi preconditioner: flexible GMRES with it takes the iterations of
+    block-Jacobi GMRES and reaches the same solution."""
+    import paper_2608_16208_amd as ffbie
+    _problem16(ctx, M=32, k=2.5)
+    p = _params(13, scale=0.05)
+    o = omlp.param_count() - (omlp.N_OUT * omlp.N_H + omlp.N_OUT)
+    p[o:] = 0.0                                            # W3, b3
+    ctx.mlp_set_params(p)
+    S = ctx.assemble()
+    g = ctx.rhs(ffbie.RHS_PLANE_WAVE, [0.0, 0.6, 0.8])
+    x1, i1 = ctx.solve(S, g, method=ffbie.SOLVE_GMRES_BLOCKJACOBI, tol=1e-10, max_iter=300)
+    x2, i2 = ctx.solve(S, g, method=ffbie.SOLVE_FGMRES_BJ_MLP, tol=1e-10, max_iter=300)
+    print("BJ %d iterations, BJ + silent network %d" % (i1["iterations"], i2["iterations"]))
+    assert i1["converged"] and i2["converged"] and not i2["fell_back"]
+    assert abs(i1["iterations"] - i2["iterations"]) <= 1
+    assert (x1 - x2).abs().norm().item() <= 1e-8 * x1.abs().norm().item()
