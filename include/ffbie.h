@@ -180,6 +180,23 @@ ffbie_status ffbie_kernel_coeffs_mixed(ffbie_ctx *ctx, int64_t n_pairs,
                                        void *d_kappa, void *d_rhoinv, double *d_root,
                                        int32_t *d_pair_status);
 
+/* Azimuthal Fourier coefficients of the double-layer kernel (Sec. 4) for
+ * n_pairs pairs, by singularity swapping with the s^{-3/2} coefficients
+ * B_m(b) of eqs. (4.7)-(4.9), or translated swapping where that amplifies
+ * rounding less (small b, chosen per pair):
+ *   kK_n = < tau_0 (ik rho - 1) e^{ik rho} / rho^3 >_n,  n = -M+1..M,
+ * with tau_0 = nu(r_s) . (r_s - r) for K (adjoint = 0, normal at the source,
+ * eq. (2.10)) or nu(r) . (r - r_s) for K' (adjoint = 1, normal at the target,
+ * eq. (2.8)); the kernels of K and K' are these divided by 2 pi.  Pairs,
+ * inputs and the optional d_root and d_pair_status are as for
+ * ffbie_kernel_coeffs; d_kappa [n_pairs][2M] complex128 receives kK_n at
+ * column n + M - 1 (required).  FP64 throughout.  Errors as for
+ * ffbie_kernel_coeffs, and FFBIE_EINVAL for adjoint not 0 or 1. */
+ffbie_status ffbie_kernel_coeffs_dl(ffbie_ctx *ctx, int64_t n_pairs,
+                                    const double *d_tgt_t, const int32_t *d_tgt_az,
+                                    const double *d_src_t, int adjoint,
+                                    void *d_kappa, double *d_root, int32_t *d_pair_status);
+
 /* Device-side timing of the kernels ffbie_kernel_coeffs launches.  With
  * timing enabled, HIP events are recorded on the context's stream around the
  * root kernel, the main coefficient pass and the refine pass of every call;

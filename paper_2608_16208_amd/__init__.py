@@ -30,7 +30,7 @@ EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_probl
            "ffbie_batch_plan_create", "ffbie_batch_plan_execute", "ffbie_batch_plan_get_tuning",
            "ffbie_batch_plan_destroy", "ffbie_batch_plan_classes", "ffbie_gemm_sub",
            "ffbie_assembly_report", "ffbie_mlp_train", "ffbie_mlp_save", "ffbie_mlp_load",
-           "ffbie_kernel_coeffs_noalloc")
+           "ffbie_kernel_coeffs_noalloc", "ffbie_kernel_coeffs_dl")
 SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES, SOLVE_FGMRES_MLP, SOLVE_GMRES_BLOCKJACOBI = 0, 1, 2, 3, 4
 SOLVE_GMRES_LU32, SOLVE_FGMRES_BJ_MLP = 5, 6
 MLP_IN, MLP_HIDDEN, MLP_OUT = 514, 256, 512
@@ -103,6 +103,7 @@ def load_library(path=LIB_PATH):
     lib.ffbie_kernel_coeffs.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     lib.ffbie_kernel_coeffs_mixed.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     lib.ffbie_kernel_coeffs_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
+    lib.ffbie_kernel_coeffs_dl.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, vp]
     lib.ffbie_singular_factor.argtypes = [vp, i64, vp, i32, vp]
     lib.ffbie_enable_timing.argtypes = [vp, i32]
     dp = ctypes.POINTER(ctypes.c_double)
@@ -253,6 +254,31 @@ class Context:
               self.lib.ffbie_kernel_coeffs_noalloc if noalloc else self.lib.ffbie_kernel_coeffs)
         rc = fn(self.h, n, _ptr(t), _ptr(az), _ptr(ts), _ptr(out["kappa"]), _ptr(out["rhoinv"]),
                 _ptr(out["root"]), _ptr(out["status"]))
+        self._check(rc, self.h)
+        return out
+
+    def kernel_coeffs_dl(self, t, az, ts, adjoint=False, root=False, status=True, kappa=None):
+        """Double-layer coefficients <tau_0 (ik rho - 1) e^{ik rho} / rho^3>_n,
+        n = -M+1..M, as kappa [n, 2M] complex128: K (adjoint=False, normal at
+        the source) or K' (adjoint=True, normal at the target); optional root
+        [n, 2] and per-pair status [n] int32."""
+        torch = self._torch
+        dev = self.device
+        t = t.to(dev, torch.float64).contiguous()
+        ts = ts.to(dev, torch.float64).contiguous()
+        az = az.to(dev, torch.int32).contiguous()
+        n = t.numel()
+        if az.numel() != n or ts.numel() != n:
+            raise FfbieError("t, az and ts must have the same length")
+        if kappa is not None and (kappa.dtype != torch.complex128 or tuple(kappa.shape) != (n, 2 * self.M)
+                                  or not kappa.is_contiguous()):
+            raise FfbieError("kappa must be a contiguous [n, 2M] complex128 tensor")
+        out = {"kappa": kappa if kappa is not None else
+               torch.empty((n, 2 * self.M), dtype=torch.complex128, device=dev)}
+        out["root"] = torch.empty((n, 2), dtype=torch.float64, device=dev) if root else None
+        out["status"] = torch.empty((n,), dtype=torch.int32, device=dev) if status else None
+        rc = self.lib.ffbie_kernel_coeffs_dl(self.h, n, _ptr(t), _ptr(az), _ptr(ts), int(adjoint),
+                                             _ptr(out["kappa"]), _ptr(out["root"]), _ptr(out["status"]))
         self._check(rc, self.h)
         return out
 

@@ -488,6 +488,60 @@ ffbie_status run_coeffs_ws(ffbie_ctx* c, const CoeffWs& ws, int64_t n, const dou
   return FFBIE_OK;
 }
 
+// Double-layer coefficients on n pairs: root kernel (shared with the
+// single layer), main pass with 2M samples, refine pass with 4M samples.
+ffbie_status run_dl_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_t* d_az,
+                           const double* d_ts, int adjoint, void* d_kappa, double* d_root,
+                           int32_t* d_pair_status) {
+  ffbie_status s = ensure_ws(c, n);
+  if (s != FFBIE_OK) return s;
+  const Prob& P = c->prob;
+  int32_t* status = d_pair_status ? d_pair_status : c->d_status;
+  FFBIE_HIP(c, launch_root(P, c->d_tab, n, d_t, d_az, d_ts, c->d_roots, status, d_root, c->stream));
+  FFBIE_HIP(c, launch_zero(c->d_count, 1, c->stream));
+  CoeffArgs a{};
+  a.P = P;
+  a.tab_g = c->d_tab;
+  a.n = n;
+  a.t_in = d_t;
+  a.az_in = d_az;
+  a.ts_in = d_ts;
+  a.roots = c->d_roots;
+  a.status = status;
+  a.kappa = d_kappa;
+  a.adjoint = adjoint;
+  auto waves = [&](int NF, size_t* lds) {
+    const size_t per_wave = sizeof(double) * dl_lds_per_wave(NF, P.M);
+    const size_t tab = sizeof(double) * P.tab_n;
+    int w = 4;
+    while (w > 1 && tab + w * per_wave > 65536) --w;
+    *lds = tab + w * per_wave;
+    return w;
+  };
+  {
+    a.NF = 2 * P.M;
+    a.flag_list = c->d_list;
+    a.flag_count = c->d_count;
+    size_t lds;
+    const int w = waves(a.NF, &lds);
+    const int64_t pairs_per_wave = 8;
+    int64_t blocks = (n + w * pairs_per_wave - 1) / (w * pairs_per_wave);
+    if (blocks < 1) blocks = 1;
+    FFBIE_HIP(c, launch_dl_coeff(a, blocks, w, lds, c->stream, false));
+  }
+  {
+    a.NF = 4 * P.M;
+    a.list = c->d_list;
+    a.list_count = c->d_count;
+    a.flag_list = nullptr;
+    a.flag_count = nullptr;
+    size_t lds;
+    const int w = waves(a.NF, &lds);
+    FFBIE_HIP(c, launch_dl_coeff(a, 512, w, lds, c->stream, true));
+  }
+  return FFBIE_OK;
+}
+
 // The coefficient path with the context's workspace (grown on demand).
 ffbie_status run_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int32_t* d_az,
                         const double* d_ts, void* d_kappa, void* d_rhoinv, double* d_root,
@@ -938,6 +992,22 @@ ffbie_status ffbie_kernel_coeffs_mixed(ffbie_ctx* c, int64_t n, const double* d_
   if (n > (int64_t)1 << 31) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_mixed: n_pairs > 2^31");
   FFBIE_HIP(c, hipSetDevice(c->device));
   return run_coeffs(c, n, d_t, d_az, d_ts, d_kappa, d_rhoinv, d_root, d_pair_status, true);
+}
+
+ffbie_status ffbie_kernel_coeffs_dl(ffbie_ctx* c, int64_t n, const double* d_t, const int32_t* d_az,
+                                    const double* d_ts, int adjoint, void* d_kappa, double* d_root,
+                                    int32_t* d_pair_status) {
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_kernel_coeffs_dl: no problem set");
+  if (n < 0) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_dl: n_pairs < 0");
+  if (adjoint != 0 && adjoint != 1)
+    return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_dl: adjoint must be 0 (K) or 1 (K')");
+  if (n == 0) return FFBIE_OK;
+  if (!d_t || !d_az || !d_ts || !d_kappa)
+    return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_dl: NULL input or kappa pointer");
+  if (n > (int64_t)1 << 31) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_dl: n_pairs > 2^31");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  return run_dl_coeffs(c, n, d_t, d_az, d_ts, adjoint, d_kappa, d_root, d_pair_status);
 }
 
 ffbie_status ffbie_builtin_near_rule(ffbie_near_rule* out) {

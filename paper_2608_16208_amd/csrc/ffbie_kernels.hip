@@ -1054,6 +1054,576 @@ __global__ __launch_bounds__(256) void ffbie_singular_factor_kernel(int64_t n,
   for (int m = lane; m <= mtop; m += 64) out[idx * (mtop + 1) + m] = A[m];
 }
 
+// ===========================================================================
+// Double-layer coefficients (Sec. 4), one wavefront per pair
+//
+// The kernel of K is 2 dG/d nu_s = tau_0 (ik rho - 1) e^{ik rho} / (2 pi rho^3)
+// with tau_0 = nu_s . (r_s - r); K' has tau_0 = nu_t . (r - r_s).  Split as in
+// Sec. 4 into a singular and a smooth part,
+//   tau_0 (ik rho - 1) e^{ik rho} / rho^3 = -H s_{a,b}^{-3/2} - i P,
+//   H = tau_0 (cos k rho + k rho sin k rho) F^3,  F = (s_{a,b}/rho^2)^{1/2},
+//   P = tau_0 (sin k rho - k rho cos k rho) / rho^3,
+// (H and P are smooth: both factors of k rho are analytic in rho^2), the
+// coefficients produced are
+//   kK_n = -sum_j <H>_j e^{-i(n-j)a} B_{|n-j|}(b) - i <P>_n,  n = -M+1..M,
+// the swap of eq. (4.6) with B_m(0, b) = <s_{0,b}^{-3/2}>_m (eq. (4.7)).
+// B_0 comes from the complete elliptic integrals (eq. (4.9)) and B_m from the
+// recurrence of Proposition 4.1 (eq. (4.8)), forward for small b and backward
+// (where forward would amplify rounding by cosh(b)^m) otherwise.
+//
+// For small b the sum above loses (B_m ~ 1/b^2 while the result is O(log b))
+// and translated swapping is used: with H(a), H'(a) at the real part a of the
+// root, g = H - H(a) - H'(a) sin(phi) (phi = theta_s - a) vanishes to second
+// order at phi = 0, g = sin^2(phi/2) delta with delta smooth, and
+//   <H s^{-3/2}>_n = e^{-ina} [H(a) B_n + H'(a) <sin phi s^{-3/2}>_n]
+//                    + sum_j delta_j e^{-i(n-j)a} Bt_{|n-j|},
+//   Bt_m = <sin^2(phi/2) s^{-3/2}>_m = (e^b/4) (A_m - (1 - e^{-b})^2 B_m),
+//   <sin phi s^{-3/2}>_n = (B_{n-1} - B_{n+1}) / (2i), the difference written
+//   through the recurrence without cancellation.
+// H(a) needs tau_0 at the root to full relative accuracy; tau_0 = O(rho^2)
+// there, so it is evaluated by the line integral of the Remark in Sec. 4:
+//   nu(v) . (r(v) - r(v + d)) = int_0^1 (lam - 1) nu(v) . D^2 r(v + lam d)[d, d] dlam
+// (16-point Gauss-Legendre in lam, one node per lane).  Everywhere else the
+// product-to-sum point difference keeps tau_0's error at O(u rho), which the
+// factor F^3 / rho^3 ~ 1/rho^2 leaves O(u) in H.
+// ===========================================================================
+constexpr double kBackwardB = 0.2;     // B_m by the backward recurrence from this b
+
+// 16-point Gauss-Legendre rule on [0, 1]
+__constant__ double kLamX[16] = {
+    0.005299532504175031, 0.0277124884633837, 0.06718439880608412, 0.1222977958224985,
+    0.19106187779867811, 0.2709916111713863, 0.35919822461037054, 0.4524937450811813,
+    0.5475062549188188, 0.6408017753896295, 0.7290083888286136, 0.8089381222013219,
+    0.8777022041775016, 0.9328156011939159, 0.9722875115366163, 0.994700467495825};
+__constant__ double kLamW[16] = {
+    0.013576229705877019, 0.031126761969323853, 0.047579255841246296, 0.062314485627767015,
+    0.07479799440828838, 0.08457825969750131, 0.0913017075224618, 0.09472530522753429,
+    0.09472530522753429, 0.0913017075224618, 0.08457825969750131, 0.07479799440828838,
+    0.062314485627767015, 0.047579255841246296, 0.031126761969323853, 0.013576229705877019};
+
+// R and its first and second partial derivatives at a general parameter point.
+struct SurfPt {
+  double st, ct, sh, ch;               // sin t, cos t, sin theta, cos theta
+  double R, Rt, Rh, Rtt, Rth, Rhh;     // R, R_t, R_theta, R_tt, R_t theta, R_theta theta
+};
+
+template <int MM>
+__device__ __forceinline__ void surf_point(const Geom& g, double t, double th, SurfPt* p) {
+  sincos_bounded(t, &p->st, &p->ct);
+  sincos_bounded(th, &p->sh, &p->ch);
+  double cm[MM + 1], sm[MM + 1];
+  cm[0] = 1.0;
+  sm[0] = 0.0;
+#pragma unroll
+  for (int m = 1; m <= MM; ++m) {
+    cm[m] = fma(cm[m - 1], p->ch, -sm[m - 1] * p->sh);
+    sm[m] = fma(sm[m - 1], p->ch, cm[m - 1] * p->sh);
+  }
+  double R = 1.0, Rt = 0.0, Rh = 0.0, Rtt = 0.0, Rth = 0.0, Rhh = 0.0;
+  double sl = p->st, cl = p->ct, sp = 0.0, cp = 1.0;    // sin(l t), cos(l t) and l - 1
+  for (int l = 1; l <= g.lmax; ++l) {
+    // sum_m a cos(m theta), sum_m m a sin(m theta), sum_m m^2 a cos(m theta)
+    double ac = 0.0, as = 0.0, am2 = 0.0;
+#pragma unroll
+    for (int m = 0; m <= MM; ++m) {
+      const double a = (m <= g.mmax) ? g.a[l - 1][m] : 0.0;
+      ac = fma(a, cm[m], ac);
+      as = fma(a * m, sm[m], as);
+      am2 = fma(a * (m * m), cm[m], am2);
+    }
+    const double dl = l;
+    R = fma(sl, ac, R);
+    Rt = fma(dl * cl, ac, Rt);
+    Rh = fma(-sl, as, Rh);
+    Rtt = fma(-dl * dl * sl, ac, Rtt);
+    Rth = fma(-dl * cl, as, Rth);
+    Rhh = fma(-sl, am2, Rhh);
+    const double sn = 2.0 * p->ct * sl - sp, cn = 2.0 * p->ct * cl - cp;
+    sp = sl; sl = sn;
+    cp = cl; cl = cn;
+  }
+  p->R = R; p->Rt = Rt; p->Rh = Rh; p->Rtt = Rtt; p->Rth = Rth; p->Rhh = Rhh;
+}
+
+// Unit normal (r_t x r_theta)/|r_t x r_theta| of r = R omega: with omega, e_t =
+// omega_t and e_phi = omega_theta / sin t orthonormal, r_t x r_theta =
+// R [R sin t omega - R_t sin t e_t - R_theta e_phi].
+__device__ __forceinline__ void unit_normal(double R, double Rt, double Rh, double st, double ct,
+                                            double sh, double ch, double* nx, double* ny,
+                                            double* nz) {
+  const double a = R * st, bt = -Rt * st, c = -Rh;
+  const double inv = rsqrt_refined(fma(a, a, fma(bt, bt, c * c)));
+  *nx = (a * st * ch + bt * ct * ch - c * sh) * inv;
+  *ny = (a * st * sh + bt * ct * sh + c * ch) * inv;
+  *nz = (a * ct - bt * st) * inv;
+}
+
+// tau_0 = nu(v) . (r(v) - r(v + d)), v = (tv, hv), d = (dt, dh), by the line
+// integral of the Remark in Sec. 4; every lane returns the value.
+template <int MM>
+__device__ __forceinline__ double tau0_line(const Geom& g, double tv, double hv, double dt,
+                                            double dh, int lane) {
+  SurfPt v;
+  surf_point<MM>(g, tv, hv, &v);
+  double nx, ny, nz;
+  unit_normal(v.R, v.Rt, v.Rh, v.st, v.ct, v.sh, v.ch, &nx, &ny, &nz);
+  double acc = 0.0;
+  if (lane < 16) {
+    const double lam = kLamX[lane];
+    SurfPt p;
+    surf_point<MM>(g, fma(lam, dt, tv), fma(lam, dh, hv), &p);
+    // omega and its derivatives at the node
+    const double wx = p.st * p.ch, wy = p.st * p.sh, wz = p.ct;
+    const double tx = p.ct * p.ch, ty = p.ct * p.sh, tz = -p.st;          // omega_t
+    const double hx = -p.st * p.sh, hy = p.st * p.ch;                      // omega_theta
+    const double thx = -p.ct * p.sh, thy = p.ct * p.ch;                    // omega_t theta
+    const double hhx = -wx, hhy = -wy;                                     // omega_theta theta
+    // r_tt = R_tt w + 2 R_t w_t - R w; r_th = R_th w + R_t w_h + R_h w_t + R w_th;
+    // r_hh = R_hh w + 2 R_h w_h + R w_hh
+    const double a2 = dt * dt, ab = 2.0 * dt * dh, b2 = dh * dh;
+    const double qx = a2 * (p.Rtt * wx + 2.0 * p.Rt * tx - p.R * wx) +
+                      ab * (p.Rth * wx + p.Rt * hx + p.Rh * tx + p.R * thx) +
+                      b2 * (p.Rhh * wx + 2.0 * p.Rh * hx + p.R * hhx);
+    const double qy = a2 * (p.Rtt * wy + 2.0 * p.Rt * ty - p.R * wy) +
+                      ab * (p.Rth * wy + p.Rt * hy + p.Rh * ty + p.R * thy) +
+                      b2 * (p.Rhh * wy + 2.0 * p.Rh * hy + p.R * hhy);
+    const double qz = a2 * (p.Rtt * wz + 2.0 * p.Rt * tz - p.R * wz) +
+                      ab * (p.Rth * wz + p.Rh * tz) + b2 * (p.Rhh * wz);
+    acc = (lam - 1.0) * kLamW[lane] * fma(nx, qx, fma(ny, qy, nz * qz));
+  }
+  return wave_sum(acc);
+}
+
+// dc_m = sum_l a_lm l cos(l x): R_t = sum_m dc_m cos(m theta) on the curve t = x.
+template <int MM>
+__device__ __forceinline__ void pair_dcoef(const Geom& g, double x, double* dc) {
+  double sx, cx;
+  sincos_bounded(x, &sx, &cx);
+#pragma unroll
+  for (int m = 0; m <= MM; ++m) dc[m] = 0.0;
+  double cl = cx, cp = 1.0;
+  for (int l = 1; l <= g.lmax; ++l) {
+#pragma unroll
+    for (int m = 0; m <= MM; ++m) {
+      const double a = (m <= g.mmax) ? g.a[l - 1][m] : 0.0;
+      dc[m] = fma(a * l, cl, dc[m]);
+    }
+    const double cn = 2.0 * cx * cl - cp;
+    cp = cl; cl = cn;
+  }
+}
+
+// (sin x - x cos x) / x^3 for 0 <= x < 1 by its Taylor series,
+// sum_{j>=1} (-1)^{j+1} 2j x^{2j-2} / (2j+1)!, to j = 10.
+__device__ __forceinline__ double beta_series(double x) {
+  const double x2 = x * x;
+  double p = -3.9145882126782523e-19;
+  p = fma(p, x2, 1.4797143443923793e-16);
+  p = fma(p, x2, -4.498331606952833e-14);
+  p = fma(p, x2, 1.0706029224547743e-11);
+  p = fma(p, x2, -1.9270852604185937e-09);
+  p = fma(p, x2, 2.505210838544172e-07);
+  p = fma(p, x2, -2.2045855379188714e-05);
+  p = fma(p, x2, 0.0011904761904761906);
+  p = fma(p, x2, -0.03333333333333333);
+  return fma(p, x2, 0.3333333333333333);
+}
+
+// y_{s+1} = c_s y_s + e_s for s = 0..T-1 from y_0, by the 64 lanes: each lane
+// composes the affine maps of its segment of S consecutive steps, a lane scan
+// of the 2x2 matrices [[c, e], [0, 1]] gives the state entering each segment,
+// and each lane replays its segment, passing (s, y_{s+1}) to `store`.
+template <class Step, class Store>
+__device__ __forceinline__ void affine_scan_wave(int T, double y0, Step step, Store store, int lane) {
+  if (T <= 0) return;
+  const int S = (T + 63) / 64;
+  const int s0 = lane * S, s1 = min(T, s0 + S);
+  double e00 = 1.0, e01 = 0.0, e10 = 0.0, e11 = 1.0;
+  for (int s = s0; s < s1; ++s) {
+    double c, e;
+    step(s, &c, &e);
+    e01 = fma(c, e01, e);
+    e00 = c * e00;
+  }
+  mat_scan_lanes(e00, e01, e10, e11);
+  const double x00 = dpp_f64_fill<0x138, 0xf>(1.0, e00), x01 = dpp_f64_fill<0x138, 0xf>(0.0, e01);
+  double y = fma(x00, y0, x01);
+  for (int s = s0; s < s1; ++s) {
+    double c, e;
+    step(s, &c, &e);
+    y = fma(c, y, e);
+    store(s, y);
+  }
+}
+
+template <int MM, bool REFINE>
+__device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, double* wbase, int NF,
+                                         int64_t beg, int64_t end) {
+  const Prob& P = a.P;
+  const int M = P.M, mask = P.tab_n - 1, quarter = 2 * M;
+  const int lane0 = threadIdx.x & 63;
+  const bool adj = a.adjoint != 0;
+  cplx* z1a = reinterpret_cast<cplx*>(wbase);
+  cplx* z1b = z1a + NF;
+  double* Abuf = reinterpret_cast<double*>(z1b + NF);
+  const int capB = M + NF + 2;
+  double* Bbuf = Abuf + dl_cap_a(NF, M);
+  double* Btbuf = Bbuf + capB;
+  cplx* kc = reinterpret_cast<cplx*>(Btbuf + capB);    // <H s^{-3/2}>_n, n = 0..M
+  cplx* Pc = kc + (M + 1);                              // <P>_n, n = 0..M
+  cplx* kappa = static_cast<cplx*>(a.kappa);
+
+  const int tstride = (8 * M) / NF;
+  const int hstep = (4 * M) / NF;
+  const double nan = __builtin_nan("");
+  const double k = P.k, k3 = k * k * k;
+  const double invNF = 1.0 / NF;
+  const double inv_gstep = NF / (2.0 * M_PI);
+  PairGeo<MM> pg;
+
+  for (int64_t w = beg; w < end; ++w) {
+    int lane = lane0;
+    asm volatile("" : "+v"(lane));
+    const int64_t pi = a.list ? a.list[w] : w;
+    const double t = a.t_in[pi], ts = a.ts_in[pi];
+    const int j = a.az_in[pi] & (2 * M - 1);
+    const RootRec rr = a.roots[pi];
+    int st = a.status[pi] & ((1 << FFBIE_PAIR_P_SHIFT) - 1);
+    cplx* krow = kappa + pi * (int64_t)(2 * M);
+    if (st & FFBIE_PAIR_SINGULAR) {
+      for (int c = lane; c < 2 * M; c += 64) krow[c] = cplx{nan, nan};
+      continue;
+    }
+    const int J = 4 * j;
+    pair_geo<MM>(P.g, t, ts, tab, J, mask, quarter, &pg);
+    // d/dt coefficients of R on the curve that carries the normal
+    double dc[MM + 1];
+    pair_dcoef<MM>(P.g, adj ? t : ts, dc);
+    double nux = 0.0, nuy = 0.0, nuz = 0.0;            // K': unit normal at the target
+    if (adj) {
+      double Rt = 0.0, Rh = 0.0;
+#pragma unroll
+      for (int m = 0; m <= MM; ++m) {
+        Rt = fma(dc[m], tcos(tab, m * J, mask, quarter), Rt);
+        Rh = fma(-(double)m * pg.ga[m], tsin(tab, m * J, mask), Rh);
+      }
+      unit_normal(pg.R, Rt, Rh, pg.st, pg.ct, tsin(tab, J, mask), tcos(tab, J, mask, quarter), &nux,
+                  &nuy, &nuz);
+    }
+    const double u = rr.u, b = rr.b;
+    const double gstep = 2.0 * M_PI / NF;
+    const double qu_d = rint(u * inv_gstep);
+    const int qu = (int)qu_d;
+    const double ur = fma(-qu_d, gstep, u);
+    double sur, cur;
+    sincos_bounded(0.5 * ur, &sur, &cur);
+    double eb, omq;
+    if (b < 0.5) {
+      const double em = expm1(-b);
+      eb = 1.0 + em;
+      omq = -em;
+    } else {
+      eb = exp(-b);
+      omq = 1.0 - eb;
+    }
+    const int qj = j * (NF / (2 * M));
+
+    // ---- samples of H (real part) and P (imaginary part)
+    double maxH = 0.0, maxP = 0.0;
+    for (int q = lane; q < NF; q += 64) {
+      const int Kq = q * tstride;
+      double dx, dy, dz;
+      dr_grid<MM>(pg, tab, Kq, J, mask, quarter, &dx, &dy, &dz);
+      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+      const double ri = rsqrt_refined(r2);
+      const double rho = r2 * ri;
+      const double x = k * rho;
+      double skr, ckr;
+      sincos_bounded(x, &skr, &ckr);
+      const int hidx = (q - qj - qu) * hstep;
+      const double sh = fma(tsin(tab, hidx, mask), cur, -tcos(tab, hidx, mask, quarter) * sur);
+      const double s = fma(omq, omq, 4.0 * eb * sh * sh);
+      const double F = sqrt_pos(s) * ri;
+      double tau;
+      if (adj) {
+        tau = -fma(nux, dx, fma(nuy, dy, nuz * dz));
+      } else {
+        // unit normal at the source (t_s, theta_q)
+        const double cq = tcos(tab, Kq, mask, quarter), sq = tsin(tab, Kq, mask);
+        double Rs = 1.0, Rts = 0.0, Rhs = 0.0;
+#pragma unroll
+        for (int m = 0; m <= MM; ++m) {
+          const double cm = tcos(tab, m * Kq, mask, quarter), sm = tsin(tab, m * Kq, mask);
+          Rs = fma(pg.al[m], cm, Rs);
+          Rts = fma(dc[m], cm, Rts);
+          Rhs = fma(-(double)m * pg.al[m], sm, Rhs);
+        }
+        const double hxy = fma(cq, dx, sq * dy);
+        const double wd = fma(pg.sts, hxy, pg.cts * dz);      // omega . d
+        const double td = fma(pg.cts, hxy, -pg.sts * dz);     // e_t . d
+        const double pd = fma(-sq, dx, cq * dy);              // e_phi . d
+        const double A1 = Rs * pg.sts, A2 = -Rts * pg.sts, A3 = -Rhs;
+        tau = fma(A1, wd, fma(A2, td, A3 * pd)) * rsqrt_refined(fma(A1, A1, fma(A2, A2, A3 * A3)));
+      }
+      const double H = tau * fma(x, skr, ckr) * (F * F * F);
+      const double beta = (x < 1.0) ? k3 * beta_series(x) : (skr - x * ckr) * (ri * ri * ri);
+      const double Pv = beta * tau;
+      z1a[q] = cplx{H, Pv};
+      maxH = fmax(maxH, fabs(H));
+      maxP = fmax(maxP, fabs(Pv));
+    }
+    maxH = wave_max(maxH);
+    maxP = wave_max(maxP);
+    // P rides in the imaginary part scaled by a power of two to H's size, so
+    // that its size does not raise the rounding floor of H's coefficients
+    const int sexp = (maxH > 0.0 && maxP > 0.0) ? ilogb(maxH) - ilogb(maxP) : 0;
+    if (sexp != 0) {
+      const double sP = ldexp(1.0, sexp);
+      for (int q = lane; q < NF; q += 64) z1a[q].im *= sP;
+    }
+    wave_sync();
+    cplx *Z = z1a, *Fr = z1b, *Zd = z1a, *Fd = z1b;
+    fft_stockham_r4(Z, Fr, Zd, Fd, false, NF, M, tab, mask, quarter, (const cplx*)nullptr, lane);
+
+    const int ptr = trunc_index_real(Z, NF, invNF, P.eps0, maxH, lane);
+    if (ptr >= NF / 2 - 2) {
+      if (!REFINE && a.flag_list) {
+        if (lane == 0) {
+          const int32_t slot = atomicAdd(a.flag_count, 1);
+          a.flag_list[slot] = pi;
+          a.status[pi] = st | FFBIE_PAIR_REFINED;
+        }
+        continue;
+      }
+      st |= FFBIE_PAIR_UNRESOLVED;
+    }
+    // Coefficients convolved: for b < 0.2 all of them below N_F/2.  B_m grows
+    // like 1/b^2, and <H>_j below the truncation threshold still carry more than
+    // rounding (dropping them would cost about eps0 max|H| B_0 per coefficient);
+    // the translated swap weighs them by j^2 log(1/b).
+    const int p = b < kBackwardB ? NF / 2 - 1 : ptr;
+    const int Jq = J + qu * tstride;
+    cplx ph_lane, ph64;
+    {
+      double s1, c1;
+      sincos_bounded(lane * ur, &s1, &c1);
+      ph_lane = mk(tcos(tab, lane * Jq, mask, quarter), tsin(tab, lane * Jq, mask)) * mk(c1, s1);
+      const cplx h = mk(read_lane(ph_lane.re, 32), read_lane(ph_lane.im, 32));
+      ph64 = h * h;
+    }
+    // ---- G_j = <H>_j e^{ija} (mirrored, G[p + j]) and <P>_n, n = 0..M
+    cplx* G = Fr;
+    {
+      cplx ph = ph_lane;
+      for (int jj = lane; jj <= p; jj += 64, ph = ph * ph64) {
+        const cplx gv = real_part_coeff(Z, jj, NF, invNF) * ph;
+        G[p + jj] = gv;
+        G[p - jj] = conj(gv);
+      }
+      const double isP = ldexp(1.0, -sexp);
+      for (int n = lane; n <= M; n += 64) Pc[n] = isP * imag_part_coeff(Z, n, NF, invNF);
+    }
+    wave_sync();
+
+    // ---- A_m(b) and B_m(b).  e^b and cosh b are formed only where b < 0.2;
+    //      the backward recurrence takes 1/cosh b and e^b/cosh b from e^{-b},
+    //      which stay finite for any b
+    const double e_b = b < kBackwardB ? rcp_refined(eb) : 0.0;   // e^b
+    const double chb = 0.5 * (e_b + eb);                          // cosh b (b < 0.2)
+    const int mtopB = M + p;
+    const bool backward = b >= kBackwardB;
+    const int NB = backward ? max(mtopB, (int)ceil(37.0 / b)) + 8 : mtopB;
+    double* A = Abuf;
+    singular_factor_wave<double>(b, eb, omq, rr.A0, rr.D1, backward ? NB - 1 : mtopB, A, false, lane);
+    double* B = Bbuf + p;
+    bool translate = false;
+    if (!backward) {
+      // B_0 of eq. (4.9): E(e^{-2b}) = (pi/2)(omq A_0 - e^{-b} (A_1 - A_0)), 1 - e^{-2b} = omq (1 + e^{-b})
+      const double E = M_PI_2 * fma(omq, rr.A0, -eb * rr.D1);
+      const double omq2 = omq * (1.0 + eb);
+      const double B0 = 4.0 * E / (M_PI * omq2 * omq2) - rr.A0 / omq2;
+      if (lane == 0) B[0] = B0;
+      // Plain or translated swap, whichever amplifies the rounding of the
+      // samples of H less.  Rounding eps in each <H>_j reaches the plain sum as
+      // about eps B_0 sqrt(2p + 1) (B_m ~ B_0 for m b << 1) and the translated
+      // one as eps (log(1/b) + 3)/(2 pi) (sum_{j <= p} j^4)^{1/2}: through
+      // delta = g / sin^2(phi/2), the coefficients' second moment meets the
+      // log(1/b) term of <sin^2(phi/2) s^{-3/2}>.
+      {
+        const double pp = p;
+        const double s4 = pp * (pp + 1.0) * (2.0 * pp + 1.0) * (3.0 * pp * pp + 3.0 * pp - 1.0) / 30.0;
+        translate = B0 * sqrt(2.0 * pp + 1.0) > (0.5 * M_1_PI) * (3.0 - log(b)) * sqrt(s4);
+      }
+      // B_m = cosh(b) B_{m-1} - ((2m - 1)/2) e^b A_{m-1}, m = 1..mtopB
+      affine_scan_wave(
+          mtopB, B0,
+          [&](int s, double* c, double* e) {
+            *c = chb;
+            *e = -(s + 0.5) * e_b * A[s];
+          },
+          [&](int s, double y) { B[s + 1] = y; }, lane);
+    } else {
+      // B_{m-1} = (B_m + ((2m - 1)/2) e^b A_{m-1}) / cosh(b), m = NB..1, from B_NB = 0
+      const double den = rcp_refined(fma(eb, eb, 1.0));
+      const double ic = 2.0 * eb * den, eic = 2.0 * den;        // 1/cosh b, e^b/cosh b
+      affine_scan_wave(
+          NB, 0.0,
+          [&](int s, double* c, double* e) {
+            const int m = NB - s;
+            *c = ic;
+            *e = (m - 0.5) * eic * A[m - 1];
+          },
+          [&](int s, double y) {
+            const int m = NB - s - 1;
+            if (m <= mtopB) B[m] = y;
+          },
+          lane);
+    }
+    wave_sync();
+    for (int m = 1 + lane; m <= p; m += 64) B[-m] = B[m];
+    wave_sync();
+
+    if (!translate || !(b > 0)) {
+      swap_convolution<cplx>(G, p, B, M, ph_lane, ph64, 1.0, kc, nullptr, nullptr, lane);
+    } else {
+      // ---- translated swapping: H(a) with tau_0 by the line integral
+      double su, cu, shu, chu;
+      sincos_bounded(u, &su, &cu);
+      sincos_bounded(0.5 * u, &shu, &chu);
+      const double sj = tsin(tab, J, mask), cj = tcos(tab, J, mask, quarter);
+      const double th_j = M_PI * j / M;
+      double dx, dy, dz;
+      dr_values<MM>(pg, fma(cj, cu, -sj * su), fma(sj, cu, cj * su), shu, chu, fma(sj, chu, cj * shu),
+                    fma(cj, chu, -sj * shu), &dx, &dy, &dz);
+      const double rho_a = sqrt_pos(fma(dx, dx, fma(dy, dy, dz * dz)));
+      const double tau_a = adj ? tau0_line<MM>(P.g, t, th_j, ts - t, u, lane)
+                               : tau0_line<MM>(P.g, ts, th_j + u, t - ts, -u, lane);
+      const double xa = k * rho_a;
+      double sa, ca;
+      sincos_bounded(xa, &sa, &ca);
+      const double Fa = omq / rho_a, Fa3 = Fa * Fa * Fa;
+      const double cfa = fma(xa, sa, ca);
+      const double Ha = tau_a * cfa * Fa3;
+      // H'(a) from the derivatives at the root's real part, not from the
+      // interpolant's coefficients, whose rounding the factor n log(1/b) of
+      // <sin phi s^{-3/2}>_n would amplify: with (rho^2)' = 2 (r_s - r) . r_s,theta,
+      // F^3' = -(3/2) F^3 (rho^2)'/rho^2 (s' = 0 at phi = 0) and
+      // d/dphi (cos x + x sin x) = x cos x k (rho^2)'/(2 rho),
+      //   H' = F^3 [tau_0' c + tau_0 (x cos x k (rho^2)'/(2 rho) - (3/2) c (rho^2)'/rho^2)],
+      // tau_0' = nu_s' . (r_s - r) for K (nu_s . r_s,theta = 0), -nu_t . r_s,theta for K'.
+      double hp;
+      {
+        SurfPt sp;
+        surf_point<MM>(P.g, ts, th_j + u, &sp);
+        const double wx = sp.st * sp.ch, wy = sp.st * sp.sh, wz = sp.ct;
+        const double otx = sp.ct * sp.ch, oty = sp.ct * sp.sh, otz = -sp.st;   // omega_t
+        const double ohx = -sp.st * sp.sh, ohy = sp.st * sp.ch;                // omega_theta
+        const double rhx = fma(sp.Rh, wx, sp.R * ohx), rhy = fma(sp.Rh, wy, sp.R * ohy),
+                     rhz = sp.Rh * wz;                                         // r_theta
+        const double drho2 = 2.0 * fma(dx, rhx, fma(dy, rhy, dz * rhz));
+        double taup;
+        if (adj) {
+          taup = -fma(nux, rhx, fma(nuy, rhy, nuz * rhz));
+        } else {
+          const double othx = -sp.ct * sp.sh, othy = sp.ct * sp.ch;            // omega_t theta
+          const double rtx = fma(sp.Rt, wx, sp.R * otx), rty = fma(sp.Rt, wy, sp.R * oty),
+                       rtz = fma(sp.Rt, wz, sp.R * otz);                       // r_t
+          const double rthx = sp.Rth * wx + sp.Rt * ohx + sp.Rh * otx + sp.R * othx;
+          const double rthy = sp.Rth * wy + sp.Rt * ohy + sp.Rh * oty + sp.R * othy;
+          const double rthz = sp.Rth * wz + sp.Rh * otz;                       // r_t theta
+          const double rhhx = sp.Rhh * wx + 2.0 * sp.Rh * ohx - sp.R * wx;
+          const double rhhy = sp.Rhh * wy + 2.0 * sp.Rh * ohy - sp.R * wy;
+          const double rhhz = sp.Rhh * wz;                                     // r_theta theta
+          // n = r_t x r_theta, n' = r_t theta x r_theta + r_t x r_theta theta
+          const double nx = rty * rhz - rtz * rhy, ny = rtz * rhx - rtx * rhz, nz = rtx * rhy - rty * rhx;
+          const double npx = (rthy * rhz - rthz * rhy) + (rty * rhhz - rtz * rhhy);
+          const double npy = (rthz * rhx - rthx * rhz) + (rtz * rhhx - rtx * rhhz);
+          const double npz = (rthx * rhy - rthy * rhx) + (rtx * rhhy - rty * rhhx);
+          const double inn = rsqrt_refined(fma(nx, nx, fma(ny, ny, nz * nz)));
+          const double vx = nx * inn, vy = ny * inn, vz = nz * inn;
+          const double vn = fma(vx, npx, fma(vy, npy, vz * npz));
+          const double dvx = (npx - vx * vn) * inn, dvy = (npy - vy * vn) * inn, dvz = (npz - vz * vn) * inn;
+          taup = fma(dvx, dx, fma(dvy, dy, dvz * dz));
+        }
+        const double r2a = rho_a * rho_a;
+        hp = Fa3 * fma(taup, cfa,
+                       tau_a * (xa * ca * k * drho2 / (2.0 * rho_a) - 1.5 * cfa * drho2 / r2a));
+      }
+      wave_sync();
+      // g = H - H(a) - H'(a) sin(phi): G_0 -= H(a), G_{+-1} +-= i H'(a)/2
+      if (lane == 0) {
+        G[p].re -= Ha;
+        if (p >= 1) {
+          G[p + 1].im += 0.5 * hp;
+          G[p - 1].im -= 0.5 * hp;
+        }
+      }
+      wave_sync();
+      // delta_k = -4 sum_{j > k} (j - k) g_j, k = 0..p-1 (delta_0 real), mirrored
+      const int pd = max(p - 1, 0);
+      cplx* D = Z + pd;
+      for (int kk = lane; kk <= pd; kk += 64) {
+        double ar = 0.0, ai = 0.0;
+        for (int jj = kk + 1; jj <= p; ++jj) {
+          const double wgt = jj - kk;
+          ar = fma(wgt, G[p + jj].re, ar);
+          ai = fma(wgt, G[p + jj].im, ai);
+        }
+        const cplx d = cplx{-4.0 * ar, kk == 0 ? 0.0 : -4.0 * ai};
+        D[kk] = d;
+        D[-kk] = conj(d);
+      }
+      // Bt_m = (e^b / 4)(A_m - omq^2 B_m), mirrored
+      double* Bt = Btbuf + pd;
+      const double omq_sq = omq * omq;
+      for (int m = lane; m <= mtopB; m += 64) Bt[m] = 0.25 * e_b * fma(-omq_sq, B[m], A[m]);
+      wave_sync();
+      for (int m = 1 + lane; m <= pd; m += 64) Bt[-m] = Bt[m];
+      wave_sync();
+      swap_convolution<cplx>(Z, pd, Bt, M, ph_lane, ph64, 1.0, kc, nullptr, nullptr, lane);
+      wave_sync();
+      // + e^{-ina} [H(a) B_n - i H'(a) Delta_n / 2], Delta_n = B_{n-1} - B_{n+1}
+      const double em = expm1(b), emm = expm1(-b);
+      const double shb = 0.5 * (em - emm);
+      const double ich = rcp_refined(chb);
+      cplx ph = ph_lane;
+      for (int n = lane; n <= M; n += 64, ph = ph * ph64) {
+        double Dn = 0.0;
+        if (n >= 1)
+          Dn = -B[n] * shb * shb * ich +
+               0.5 * e_b * fma((2.0 * n - 1.0) * A[n - 1], ich, (2.0 * n + 1.0) * A[n]);
+        kc[n] = kc[n] + conj(ph) * mk(Ha * B[n], -0.5 * hp * Dn);
+      }
+    }
+    wave_sync();
+    // ---- kK_n = -<H s^{-3/2}>_n - i <P>_n, n = -M+1..M at column n + M - 1
+    for (int c = lane; c < 2 * M; c += 64) {
+      const int n = c - M + 1;
+      const cplx R = n >= 0 ? kc[n] : conj(kc[-n]);
+      const cplx Pn = n >= 0 ? Pc[n] : conj(Pc[-n]);
+      krow[c] = cplx{Pn.im - R.re, -R.im - Pn.re};
+    }
+    if (lane == 0) a.status[pi] = st | (min(ptr, 0xfff) << FFBIE_PAIR_P_SHIFT);
+    wave_sync();
+  }
+}
+
+template <int MM, bool REFINE>
+__global__ __launch_bounds__(256) void ffbie_dl_coeff_kernel_t(CoeffArgs a) {
+  extern __shared__ double smem[];
+  load_table(smem, a.tab_g, a.P.tab_n);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int waves_per_block = blockDim.x >> 6;
+  const int per_wave = dl_lds_per_wave(a.NF, a.P.M);
+  int64_t count = a.n;
+  if (a.list) count = *a.list_count;
+  const int64_t total_waves = (int64_t)gridDim.x * waves_per_block;
+  const int64_t gw = (int64_t)blockIdx.x * waves_per_block + wave;
+  const int64_t chunk = (count + total_waves - 1) / total_waves;
+  const int64_t beg = gw * chunk, end = min(count, beg + chunk);
+  dl_range<MM, REFINE>(a, smem, smem + a.P.tab_n + (size_t)wave * per_wave, a.NF, beg, end);
+}
+
 // ---------------------------------------------------------------------------
 // Launch helpers (one instantiation per bound on the surface's azimuthal order)
 // ---------------------------------------------------------------------------
@@ -1135,6 +1705,24 @@ hipError_t launch_batch(const BatchArgs& b, int mm, int64_t blocks, int threads,
 
 hipError_t launch_zero(int* p, int n, hipStream_t stream) {
   hipLaunchKernelGGL(ffbie_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_dl_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t lds,
+                           hipStream_t stream, bool refine) {
+  switch (mm_bucket(a.P.g.mmax)) {
+#define X(MMV)                                                                                   \
+  case MMV:                                                                                      \
+    if (refine)                                                                                  \
+      hipLaunchKernelGGL((ffbie_dl_coeff_kernel_t<MMV, true>), dim3((unsigned)blocks),          \
+                         dim3(64 * waves), lds, stream, a);                                      \
+    else                                                                                         \
+      hipLaunchKernelGGL((ffbie_dl_coeff_kernel_t<MMV, false>), dim3((unsigned)blocks),         \
+                         dim3(64 * waves), lds, stream, a);                                      \
+    break;
+    FFBIE_FOR_MM(X)
+#undef X
+  }
   return hipGetLastError();
 }
 

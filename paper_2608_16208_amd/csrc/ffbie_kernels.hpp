@@ -31,6 +31,8 @@ struct CoeffArgs {
   int radix;                 // main-pass FFT stages: 2 (radix-2 Stockham), 4 (radix-4, one radix-2
                              // stage if needed) or 0 (radix 4 for NF >= 256, else 2); refine
                              // passes use radix 2
+  int adjoint;               // double-layer kernel: 0 = K (normal at the source), 1 = K'
+                             // (normal at the target)
 };
 
 // Default pairs per wavefront and work item of the batched launch.
@@ -82,6 +84,15 @@ FFBIE_HD inline int coeff_lds_per_wave(int NF, int M, int L, int layout, bool si
   return single ? (reals + 1) / 2 : reals;
 }
 
+// Per-wavefront LDS of the double-layer coefficient kernel, in doubles: two
+// NF-complex FFT buffers, A_m up to the start of the backward recurrence for
+// B_m (m <= max(M + NF/2, 200) + 9), B_m and B~_m mirrored (M + NF + 2 each),
+// and the two half rows (M + 1 complex each) of the output.
+FFBIE_HD inline int dl_cap_a(int NF, int M) { return (M + NF / 2 > 200 ? M + NF / 2 : 200) + 10; }
+FFBIE_HD inline int dl_lds_per_wave(int NF, int M) {
+  return 2 * (2 * NF) + dl_cap_a(NF, M) + 2 * (M + NF + 2) + 2 * 2 * (M + 1);
+}
+
 hipError_t launch_root(const Prob& P, const double* tab, int64_t n, const double* t,
                        const int32_t* az, const double* ts, RootRec* out, int32_t* status,
                        double* root_out, hipStream_t stream);
@@ -91,6 +102,10 @@ hipError_t launch_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t ld
 hipError_t launch_batch(const BatchArgs& b, int mm, int64_t blocks, int threads, size_t lds,
                         hipStream_t stream, int phase, bool single);
 hipError_t launch_zero(int* p, int n, hipStream_t stream);
+// Double-layer coefficients (a.adjoint selects K or K'): main pass (refine =
+// false, NF = 2M, queueing unresolved pairs) or refine pass over the queue.
+hipError_t launch_dl_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t lds,
+                           hipStream_t stream, bool refine);
 __global__ void ffbie_singular_factor_kernel(int64_t n, const double* __restrict__ b_in, int mtop,
                                              double* __restrict__ out);
 
