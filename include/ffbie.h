@@ -186,8 +186,8 @@ ffbie_status ffbie_kernel_coeffs_mixed(ffbie_ctx *ctx, int64_t n_pairs,
  * rounding less (small b, chosen per pair):
  *   kK_n = < tau_0 (ik rho - 1) e^{ik rho} / rho^3 >_n,  n = -M+1..M,
  * with tau_0 = nu(r_s) . (r_s - r) for K (adjoint = 0, normal at the source,
- * eq. (2.10)) or nu(r) . (r - r_s) for K' (adjoint = 1, normal at the target,
- * eq. (2.8)); the kernels of K and K' are these divided by 2 pi.  Pairs,
+ * eq. (2.13)) or nu(r) . (r - r_s) for K' (adjoint = 1, normal at the target,
+ * eq. (2.10)); the kernels of K and K' are these divided by 2 pi.  Pairs,
  * inputs and the optional d_root and d_pair_status are as for
  * ffbie_kernel_coeffs; d_kappa [n_pairs][2M] complex128 receives kK_n at
  * column n + M - 1 (required).  FP64 throughout.  Errors as for
@@ -380,9 +380,12 @@ ffbie_status ffbie_collocation(ffbie_ctx *ctx, double *d_xyz, double *d_jac, dou
  *     p = (params[0], params[1], params[2]), the interior Dirichlet test of
  *     Sec. 5 (exact interior field G(.; p) when p is outside the surface);
  *   FFBIE_RHS_PLANE_WAVE: g = -e^{ik d.x} with d = params[0..2] (unit), the
- *     sound-soft exterior problem for the incident wave e^{ik d.x}.
+ *     sound-soft exterior problem for the incident wave e^{ik d.x};
+ *   FFBIE_RHS_PLANE_WAVE_DN: g = -d/d nu e^{ik d.x} = -ik (d . nu) e^{ik d.x}
+ *     (nu the outward unit normal), the sound-hard exterior problem, whose
+ *     second-kind equation (K' - I) phi = g is eq. (2.9) for (ENP).
  * params is a HOST pointer to 3 doubles. */
-enum { FFBIE_RHS_POINT_SOURCE = 0, FFBIE_RHS_PLANE_WAVE = 1 };
+enum { FFBIE_RHS_POINT_SOURCE = 0, FFBIE_RHS_PLANE_WAVE = 1, FFBIE_RHS_PLANE_WAVE_DN = 2 };
 ffbie_status ffbie_rhs(ffbie_ctx *ctx, int kind, const double *params, void *d_g);
 
 /* Assemble the N x N matrix S of the discretised single-layer equation
@@ -403,6 +406,37 @@ ffbie_status ffbie_rhs(ffbie_ctx *ctx, int kind, const double *params, void *d_g
  * unresolved, see ffbie_assembly_report. */
 ffbie_status ffbie_assemble(ffbie_ctx *ctx, void *d_S, int64_t ld);
 
+/* Operators of the boundary integral equations of Sec. 2 (eqs. (2.8), (2.10), (2.13)). */
+enum {
+  FFBIE_OP_S = 0,    /* single layer S = 2 int G phi dsigma (eq. (2.8))          */
+  FFBIE_OP_K = 1,    /* double layer K = 2 p.v. int dG/d nu(y) psi dsigma (eq. (2.13)) */
+  FFBIE_OP_KP = 2    /* adjoint K' = 2 p.v. int dG/d nu(x) phi dsigma (eq. (2.10)) */
+};
+
+/* What the unknowns of an assembled system are. */
+enum {
+  FFBIE_UNKNOWN_SCALED = 0,   /* density x Jacobian, phi~ = phi J (Sec. 3.4; ffbie_assemble) */
+  FFBIE_UNKNOWN_DENSITY = 1   /* the density values themselves: column c carries J_c       */
+};
+
+/* Assemble op + shift * I into d_S, with the layout, discretisation, near
+ * rule, workspace and return values of ffbie_assemble (op = FFBIE_OP_S,
+ * shift = 0, FFBIE_UNKNOWN_SCALED is ffbie_assemble).  For K and K' the far
+ * entries are (h/2) w_{l'} (1/2M) tau_0 (ik rho - 1) e^{ik rho} / rho^3 with
+ * tau_0 = nu_c . (x_c - x_r) (K) or nu_r . (x_r - x_c) (K'), and the near
+ * blocks take the coefficients of ffbie_kernel_coeffs_dl through the same
+ * rule.  With FFBIE_UNKNOWN_DENSITY every column c is multiplied by J_c and
+ * shift * I is added as it is; with FFBIE_UNKNOWN_SCALED it enters the
+ * diagonal as shift / J_r.  shift = +1 with K gives the exterior Dirichlet
+ * equation (K + I) psi = g, shift = -1 with K' the exterior Neumann equation
+ * (K' - I) phi = g (eqs. (2.12) and (2.9)); for these second-kind systems
+ * density unknowns keep the spectrum clustered at the shift, while scaled
+ * unknowns spread it by the range of 1/J (large near the poles), which
+ * iterative solvers feel.  FFBIE_EINVAL for an unknown op or unknowns value
+ * or a non-finite shift. */
+ffbie_status ffbie_assemble_op(ffbie_ctx *ctx, int op, double shift, int unknowns, void *d_S,
+                               int64_t ld);
+
 /* Near pairs of the last ffbie_assemble on this context: their number, how
  * many the coefficient path flagged FFBIE_PAIR_UNRESOLVED (the smooth factor
  * not resolved even by 4M azimuthal samples: the wavenumber is too large for
@@ -420,6 +454,16 @@ ffbie_status ffbie_assembly_report(ffbie_ctx *ctx, int64_t *n_near_pairs, int64_
  * d_pts [n_pts][3] float64, d_phi [N] complex128, d_u [n_pts] complex128. */
 ffbie_status ffbie_eval_field(ffbie_ctx *ctx, int64_t n_pts, const double *d_pts,
                               const void *d_phi, void *d_u);
+
+/* Field of a layer representation by the same product rule, for densities
+ * given as the unknowns of ffbie_assemble_op (FFBIE_UNKNOWN_*): op =
+ * FFBIE_OP_S with scaled unknowns is ffbie_eval_field; op = FFBIE_OP_K the
+ * double-layer representation u(x) = 2 int dG(x, y)/d nu(y) psi(y) dsigma
+ * (eq. (2.11)), u(x) = sum_c wq_c tau_0 (ik rho - 1) e^{ik rho} / rho^3 psi~_c
+ * with tau_0 = nu_c . (x_c - x), rho = |x - x_c| (psi~_c = J_c psi_c for
+ * density unknowns).  FFBIE_EINVAL for another op or unknowns value. */
+ffbie_status ffbie_eval_field_op(ffbie_ctx *ctx, int op, int unknowns, int64_t n_pts,
+                                 const double *d_pts, const void *d_phi, void *d_u);
 
 /* Dense solve of S phi~ = g for the matrix of ffbie_assemble (row-major
  * complex128, leading dimension ld >= N).  The paper leaves the solver open;

@@ -185,7 +185,7 @@ def matrix(amp, k, M, n_panels, tab, processes=None, kind="S"):
 
 
 def field_double_layer(amp, n_panels, M, k, psi, pts):
-    """Field of the double-layer representation of eq. (2.9),
+    """Field of the double-layer representation of eq. (2.11),
     u(x) = 2 int dG(x, y)/d nu(y) psi(y) d sigma, by the product rule:
     u(x) = sum_c W_c tau_0 (ik rho - 1) e^{ik rho} / rho^3 psi~_c with
     tau_0 = nu_c . (x_c - x)."""
@@ -211,6 +211,15 @@ def rhs_point_source(amp, n_panels, M, k, p):
 def rhs_plane_wave(amp, n_panels, M, k, d):
     x, _, _ = collocation(amp, n_panels, M)
     return -np.exp(1j * k * (x @ np.asarray(d)))
+
+
+def rhs_plane_wave_dn(amp, n_panels, M, k, d):
+    """-d/d nu e^{ik d.x} = -ik (d . nu) e^{ik d.x} on the collocation points
+    (the sound-hard exterior problem)."""
+    x, _, _ = collocation(amp, n_panels, M)
+    L = layout(n_panels, M)
+    nu = geo.normal(amp, L["t"], L["th"])
+    return -1j * k * (nu @ np.asarray(d)) * np.exp(1j * k * (x @ np.asarray(d)))
 
 
 def field(amp, n_panels, M, k, phi, pts):

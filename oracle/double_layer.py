@@ -1,8 +1,8 @@
 """Double-layer operator K and its adjoint K' (Sec. 4), from their definitions.
 TEST INFRASTRUCTURE ONLY.
 
-K[psi](r)  = 2 int dG(r; r_s)/d nu(r_s) psi(r_s) d sigma(r_s)   (eq. (2.10)),
-K'[phi](r) = 2 int dG(r; r_s)/d nu(r)   phi(r_s) d sigma(r_s)   (eq. (2.8)),
+K[psi](r)  = 2 int dG(r; r_s)/d nu(r_s) psi(r_s) d sigma(r_s)   (eq. (2.13)),
+K'[phi](r) = 2 int dG(r; r_s)/d nu(r)   phi(r_s) d sigma(r_s)   (eq. (2.10)),
 with G(r; r_s) = e^{ik rho} / (4 pi rho), rho = |r - r_s|.  Since
 dG/drho = (ik rho - 1) e^{ik rho} / (4 pi rho^2),
 

@@ -4,7 +4,9 @@ INFRASTRUCTURE ONLY.
 * ``lu_solve``: LAPACK LU with partial pivoting (scipy), FP64.
 * ``mie_scattered``: field scattered by the sound-soft unit sphere for the
   incident plane wave e^{ik d.x} (separation of variables),
-      u_s(x) = -sum_n (2n+1) i^n [j_n(k)/h_n(k)] h_n(k|x|) P_n(d.x/|x|).
+      u_s(x) = -sum_n (2n+1) i^n [j_n(k)/h_n(k)] h_n(k|x|) P_n(d.x/|x|);
+  ``mie_scattered_hard`` the same for the sound-hard sphere (zero normal
+  derivative of the total field), with j_n'(k)/h_n'(k) in place of j_n/h_n.
 * ``sphere_single_layer_eigenvalue``: on the unit sphere the operator of
   eq. (2.8), S[phi] = 2 int G phi dsigma, maps the spherical harmonic Y_n^m to
   2ik j_n(k) h_n(k) Y_n^m; ``sphere_double_layer_eigenvalue`` the same for K
@@ -32,6 +34,18 @@ def mie_scattered(k, pts, d, nmax=40):
     for n in range(nmax + 1):
         a = (2 * n + 1) * (1j ** n) * special.spherical_jn(n, k) / hankel1(n, k)
         u -= a * hankel1(n, k * r) * special.eval_legendre(n, cosg)
+    return u
+
+
+def mie_scattered_hard(k, pts, d, nmax=40):
+    pts = np.atleast_2d(pts)
+    r = np.linalg.norm(pts, axis=1)
+    cosg = pts @ np.asarray(d) / r
+    u = np.zeros(len(pts), dtype=complex)
+    for n in range(nmax + 1):
+        dj = special.spherical_jn(n, k, derivative=True)
+        dh = dj + 1j * special.spherical_yn(n, k, derivative=True)
+        u -= (2 * n + 1) * (1j ** n) * (dj / dh) * hankel1(n, k * r) * special.eval_legendre(n, cosg)
     return u
 
 

@@ -30,12 +30,15 @@ EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_probl
            "ffbie_batch_plan_create", "ffbie_batch_plan_execute", "ffbie_batch_plan_get_tuning",
            "ffbie_batch_plan_destroy", "ffbie_batch_plan_classes", "ffbie_gemm_sub",
            "ffbie_assembly_report", "ffbie_mlp_train", "ffbie_mlp_save", "ffbie_mlp_load",
-           "ffbie_kernel_coeffs_noalloc", "ffbie_kernel_coeffs_dl")
+           "ffbie_kernel_coeffs_noalloc", "ffbie_kernel_coeffs_dl", "ffbie_assemble_op",
+           "ffbie_eval_field_op")
 SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES, SOLVE_FGMRES_MLP, SOLVE_GMRES_BLOCKJACOBI = 0, 1, 2, 3, 4
 SOLVE_GMRES_LU32, SOLVE_FGMRES_BJ_MLP = 5, 6
 MLP_IN, MLP_HIDDEN, MLP_OUT = 514, 256, 512
 WNOTCONV, WUNRESOLVED = 2, 3
-RHS_POINT_SOURCE, RHS_PLANE_WAVE = 0, 1
+RHS_POINT_SOURCE, RHS_PLANE_WAVE, RHS_PLANE_WAVE_DN = 0, 1, 2
+OP_S, OP_K, OP_KP = 0, 1, 2
+UNKNOWN_SCALED, UNKNOWN_DENSITY = 0, 1
 P_SHIFT = 8
 
 
@@ -121,6 +124,8 @@ def load_library(path=LIB_PATH):
     lib.ffbie_rhs.argtypes = [vp, i32, dp, vp]
     lib.ffbie_assemble.argtypes = [vp, vp, i64]
     lib.ffbie_eval_field.argtypes = [vp, i64, vp, vp, vp]
+    lib.ffbie_assemble_op.argtypes = [vp, i32, ctypes.c_double, i32, vp, i64]
+    lib.ffbie_eval_field_op.argtypes = [vp, i32, i32, i64, vp, vp, vp]
     lib.ffbie_solve.argtypes = [vp, i32, vp, i64, vp, vp, ctypes.c_double, i32, ctypes.POINTER(_SolveInfo)]
     lib.ffbie_residual.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.ffbie_kernel_coeffs_batched.argtypes = [vp, i32, ctypes.POINTER(_BatchItem)]
@@ -408,24 +413,41 @@ class Context:
         self._check(self.lib.ffbie_rhs(self.h, int(kind), p, _ptr(g)), self.h)
         return g
 
-    def assemble(self, S=None):
-        """Row-major N x N complex128 single-layer matrix (allocated if S is None)."""
+    def assemble(self, S=None, op=OP_S, shift=0.0, unknowns=UNKNOWN_SCALED):
+        """Row-major N x N complex128 matrix of op + shift I (allocated if S is
+        None): op = OP_S the single layer, OP_K the double layer, OP_KP its
+        adjoint; shift = +1 with OP_K is the exterior Dirichlet equation
+        (K + I) psi = g, shift = -1 with OP_KP the exterior Neumann one.
+        unknowns: UNKNOWN_SCALED (density x Jacobian) or UNKNOWN_DENSITY."""
         torch = self._torch
         N, _ = self.query()
         if S is None:
             S = torch.empty((N, N), dtype=torch.complex128, device=self.device)
         if S.dim() != 2 or S.shape[0] != N or S.stride(1) != 1 or S.stride(0) < N or S.dtype != torch.complex128:
             raise FfbieError("S must be a row-major complex128 [N, >=N] device tensor")
-        rc = self._check(self.lib.ffbie_assemble(self.h, _ptr(S), S.stride(0)), self.h)
+        if op == OP_S and shift == 0.0 and unknowns == UNKNOWN_SCALED:
+            rc = self.lib.ffbie_assemble(self.h, _ptr(S), S.stride(0))
+        else:
+            rc = self.lib.ffbie_assemble_op(self.h, int(op), float(shift), int(unknowns), _ptr(S),
+                                            S.stride(0))
+        self._check(rc, self.h)
         self.last_assembly = dict(self.assembly_report(), status=rc)
         return S
 
-    def eval_field(self, pts, phi):
+    def eval_field(self, pts, phi, op=OP_S, unknowns=UNKNOWN_SCALED):
+        """Field of the single-layer (op = OP_S) or double-layer (OP_K)
+        representation with density phi (given as the system's unknowns) at
+        points pts [n, 3]."""
         torch = self._torch
         pts = pts.to(self.device, torch.float64).contiguous()
         phi = phi.to(self.device, torch.complex128).contiguous()
         u = torch.empty(pts.shape[0], dtype=torch.complex128, device=self.device)
-        self._check(self.lib.ffbie_eval_field(self.h, pts.shape[0], _ptr(pts), _ptr(phi), _ptr(u)), self.h)
+        if op == OP_S and unknowns == UNKNOWN_SCALED:
+            rc = self.lib.ffbie_eval_field(self.h, pts.shape[0], _ptr(pts), _ptr(phi), _ptr(u))
+        else:
+            rc = self.lib.ffbie_eval_field_op(self.h, int(op), int(unknowns), pts.shape[0], _ptr(pts),
+                                              _ptr(phi), _ptr(u))
+        self._check(rc, self.h)
         return u
 
     def solve(self, S, g, method=SOLVE_LU64, tol=1e-12, max_iter=50, phi=None):

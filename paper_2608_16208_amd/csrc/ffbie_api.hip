@@ -270,7 +270,7 @@ SysDims sys_dims(const ffbie_ctx* c) {
 Colloc colloc_view(const ffbie_ctx* c) {
   const int64_t N = c->colloc_n;
   double* b = c->d_colloc;
-  return Colloc{b, b + N, b + 2 * N, b + 3 * N, b + 4 * N};
+  return Colloc{b, b + N, b + 2 * N, b + 3 * N, b + 4 * N, b + 5 * N, b + 6 * N, b + 7 * N};
 }
 
 // Validated problem constants from the C-ABI description.
@@ -581,7 +581,7 @@ ffbie_status prepare_system(ffbie_ctx* c) {
     if (c->d_colloc) hipFree(c->d_colloc);
     c->d_colloc = nullptr;
     c->colloc_n = 0;
-    if (hipMalloc(&c->d_colloc, 5 * d.N * sizeof(double)) != hipSuccess)
+    if (hipMalloc(&c->d_colloc, kCollocArrays * d.N * sizeof(double)) != hipSuccess)
       return fail(c, FFBIE_ENOMEM, "ffbie: collocation workspace allocation failed");
     c->colloc_n = d.N;
   }
@@ -1053,7 +1053,7 @@ ffbie_status ffbie_query(ffbie_ctx* c, int64_t* n_unknowns_out, int64_t* n_near_
     const int64_t cap_pairs = kNearKappaBytes / (int64_t)(2 * d.M * sizeof(cplx));
     const int64_t chunk = std::min<int64_t>(near, cap_pairs + (int64_t)3 * kNodes * 2 * d.M * kNodes);
     const int64_t asm_ws = chunk * (20 + 2 * d.M * (int64_t)sizeof(cplx) + (int64_t)sizeof(RootRec) + 12) +
-                           (int64_t)kNodes * 3 * kNodes * (kNodes + 1) * 8 + 5 * N * 8;
+                           (int64_t)kNodes * 3 * kNodes * (kNodes + 1) * 8 + kCollocArrays * N * 8;
     // the largest solve: vectors and pivots, plus the complex64 copy of S
     // (LU32_IR64, GMRES_LU32) or the Krylov and flexible bases (GMRES forms),
     // or the mode blocks (block-Jacobi)
@@ -1093,7 +1093,7 @@ ffbie_status ffbie_rhs(ffbie_ctx* c, int kind, const double* params, void* d_g) 
   if (!c) return FFBIE_EINVAL;
   if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_rhs: no problem set");
   if (!params || !d_g) return fail(c, FFBIE_EINVAL, "ffbie_rhs: NULL pointer");
-  if (kind != FFBIE_RHS_POINT_SOURCE && kind != FFBIE_RHS_PLANE_WAVE)
+  if (kind != FFBIE_RHS_POINT_SOURCE && kind != FFBIE_RHS_PLANE_WAVE && kind != FFBIE_RHS_PLANE_WAVE_DN)
     return fail(c, FFBIE_EINVAL, "ffbie_rhs: unknown kind");
   for (int i = 0; i < 3; ++i)
     if (!std::isfinite(params[i])) return fail(c, FFBIE_EINVAL, "ffbie_rhs: non-finite parameter");
@@ -1105,14 +1105,29 @@ ffbie_status ffbie_rhs(ffbie_ctx* c, int kind, const double* params, void* d_g) 
 }
 
 ffbie_status ffbie_assemble(ffbie_ctx* c, void* d_S, int64_t ld) {
+  return ffbie_assemble_op(c, FFBIE_OP_S, 0.0, FFBIE_UNKNOWN_SCALED, d_S, ld);
+}
+
+ffbie_status ffbie_assemble_op(ffbie_ctx* c, int op, double shift, int unknowns, void* d_S,
+                               int64_t ld) {
   if (!c) return FFBIE_EINVAL;
   if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_assemble: no problem set");
   const SysDims d = sys_dims(c);
   if (!d_S || ld < d.N) return fail(c, FFBIE_EINVAL, "ffbie_assemble: NULL matrix or ld < N");
+  if (op != FFBIE_OP_S && op != FFBIE_OP_K && op != FFBIE_OP_KP)
+    return fail(c, FFBIE_EINVAL, "ffbie_assemble_op: op must be FFBIE_OP_S, FFBIE_OP_K or FFBIE_OP_KP");
+  if (!std::isfinite(shift)) return fail(c, FFBIE_EINVAL, "ffbie_assemble_op: non-finite shift");
+  if (unknowns != FFBIE_UNKNOWN_SCALED && unknowns != FFBIE_UNKNOWN_DENSITY)
+    return fail(c, FFBIE_EINVAL, "ffbie_assemble_op: unknowns must be FFBIE_UNKNOWN_SCALED or FFBIE_UNKNOWN_DENSITY");
+  const int density = unknowns == FFBIE_UNKNOWN_DENSITY ? 1 : 0;
   ffbie_status s = prepare_system(c);
   if (s != FFBIE_OK) return s;
   cplx* S = static_cast<cplx*>(d_S);
-  FFBIE_HIP(c, launch_far_assembly(d, c->prob.k, colloc_view(c), S, ld, c->stream));
+  if (op == FFBIE_OP_S)
+    FFBIE_HIP(c, launch_far_assembly(d, c->prob.k, colloc_view(c), S, ld, c->stream, density));
+  else
+    FFBIE_HIP(c, launch_far_assembly_dl(d, c->prob.k, colloc_view(c), op == FFBIE_OP_KP ? 1 : 0, S, ld,
+                                        c->stream, density));
   // near blocks, a chunk of target panels at a time
   const int64_t per_rel = (int64_t)kNodes * 2 * d.M * kNodes;      // pairs of one relation
   const int64_t cap_pairs = kNearKappaBytes / (int64_t)(2 * d.M * sizeof(cplx));
@@ -1145,14 +1160,20 @@ ffbie_status ffbie_assemble(ffbie_ctx* c, void* d_S, int64_t ld) {
     ch.n_pairs = near_pairs_before(p1, d) - ch.pair_base;
     FFBIE_HIP(c, launch_near_pairs(d, ch, c->gl_x, c->d_rule_y, c->d_near_t, c->d_near_az,
                                    c->d_near_ts, c->stream));
-    s = run_coeffs(c, ch.n_pairs, c->d_near_t, c->d_near_az, c->d_near_ts, c->d_near_kappa, nullptr,
-                   nullptr, nullptr);
+    if (op == FFBIE_OP_S)
+      s = run_coeffs(c, ch.n_pairs, c->d_near_t, c->d_near_az, c->d_near_ts, c->d_near_kappa, nullptr,
+                     nullptr, nullptr);
+    else
+      s = run_dl_coeffs(c, ch.n_pairs, c->d_near_t, c->d_near_az, c->d_near_ts, op == FFBIE_OP_KP ? 1 : 0,
+                        c->d_near_kappa, nullptr, nullptr);
     if (s != FFBIE_OK) return s;
     // the pairs' flags are in the context's status workspace
     FFBIE_HIP(c, launch_count_status(c->d_status, ch.n_pairs, c->d_asm_counts, c->stream));
-    FFBIE_HIP(c, launch_near_assembly(d, ch, c->d_near_kappa, c->d_wl, c->d_tab, S, ld, c->stream));
+    FFBIE_HIP(c, launch_near_assembly(d, ch, c->d_near_kappa, c->d_wl, c->d_tab, S, ld, c->stream,
+                                      density ? colloc_view(c).jac : nullptr));
     p0 = p1;
   }
+  if (shift != 0.0) FFBIE_HIP(c, launch_diag_shift(d, shift, colloc_view(c), S, ld, c->stream, density));
   unsigned long long cnt[2] = {0, 0};
   FFBIE_HIP(c, hipMemcpyAsync(cnt, c->d_asm_counts, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
   FFBIE_HIP(c, hipStreamSynchronize(c->stream));
@@ -1182,7 +1203,17 @@ ffbie_status ffbie_assembly_report(ffbie_ctx* c, int64_t* n_near_pairs, int64_t*
 
 ffbie_status ffbie_eval_field(ffbie_ctx* c, int64_t n_pts, const double* d_pts, const void* d_phi,
                               void* d_u) {
+  return ffbie_eval_field_op(c, FFBIE_OP_S, FFBIE_UNKNOWN_SCALED, n_pts, d_pts, d_phi, d_u);
+}
+
+ffbie_status ffbie_eval_field_op(ffbie_ctx* c, int op, int unknowns, int64_t n_pts, const double* d_pts,
+                                 const void* d_phi, void* d_u) {
   if (!c) return FFBIE_EINVAL;
+  if (op != FFBIE_OP_S && op != FFBIE_OP_K)
+    return fail(c, FFBIE_EINVAL, "ffbie_eval_field_op: op must be FFBIE_OP_S or FFBIE_OP_K");
+  if (unknowns != FFBIE_UNKNOWN_SCALED && unknowns != FFBIE_UNKNOWN_DENSITY)
+    return fail(c, FFBIE_EINVAL, "ffbie_eval_field_op: unknowns must be FFBIE_UNKNOWN_SCALED or FFBIE_UNKNOWN_DENSITY");
+  const int density = unknowns == FFBIE_UNKNOWN_DENSITY ? 1 : 0;
   if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_eval_field: no problem set");
   if (n_pts < 0 || n_pts > 65535) return fail(c, FFBIE_EINVAL, "ffbie_eval_field: need 0 <= n_pts <= 65535");
   if (n_pts == 0) return FFBIE_OK;
@@ -1203,9 +1234,14 @@ ffbie_status ffbie_eval_field(ffbie_ctx* c, int64_t n_pts, const double* d_pts, 
       return fail(c, FFBIE_ENOMEM, "ffbie_eval_field: workspace allocation failed");
     c->partial_cap = need;
   }
-  FFBIE_HIP(c, launch_field(d, c->prob.k, colloc_view(c), n_pts, d_pts,
-                            static_cast<const cplx*>(d_phi), c->d_partial, n_chunks,
-                            static_cast<cplx*>(d_u), c->stream));
+  if (op == FFBIE_OP_S)
+    FFBIE_HIP(c, launch_field(d, c->prob.k, colloc_view(c), n_pts, d_pts,
+                              static_cast<const cplx*>(d_phi), c->d_partial, n_chunks,
+                              static_cast<cplx*>(d_u), c->stream, density));
+  else
+    FFBIE_HIP(c, launch_field_dl(d, c->prob.k, colloc_view(c), n_pts, d_pts,
+                                 static_cast<const cplx*>(d_phi), c->d_partial, n_chunks,
+                                 static_cast<cplx*>(d_u), c->stream, density));
   return FFBIE_OK;
 }
 

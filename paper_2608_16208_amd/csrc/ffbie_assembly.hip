@@ -1,5 +1,6 @@
-// Assembly of the discrete single-layer system, right-hand sides and field
-// evaluation (paper Sec. 3.1 and 3.4) for gfx950.
+// Assembly of the discrete single-layer system and of the double-layer
+// operators K and K' (Sec. 4), right-hand sides and field evaluation (paper
+// Sec. 3.1 and 3.4) for gfx950.
 //
 // Layout: unknowns and collocation points share the index r = (i*16 + l)*2M + j
 // (panel i, Gauss-Legendre node l, azimuth j).  S is row-major: a row is one
@@ -32,7 +33,7 @@ struct GL16 {
 
 // Point of the star surface and the Jacobian |r_t x r_theta| (eq. (2.1)).
 __device__ void surface_point(const Geom& g, double t, double th, double* px, double* py,
-                              double* pz, double* jac) {
+                              double* pz, double* jac, double* nrm) {
   double st, ct, sth, cth;
   sincos_bounded(t, &st, &ct);
   sincos_bounded(th, &sth, &cth);
@@ -61,7 +62,11 @@ __device__ void surface_point(const Geom& g, double t, double th, double* px, do
   *px = R * ox;
   *py = R * oy;
   *pz = R * oz;
-  *jac = sqrt(cx * cx + cy * cy + cz * cz);
+  const double J = sqrt(cx * cx + cy * cy + cz * cz);
+  *jac = J;
+  nrm[0] = cx / J;
+  nrm[1] = cy / J;
+  nrm[2] = cz / J;
 }
 
 __global__ __launch_bounds__(256) void collocation_kernel(Geom g, SysDims d, GL16 gl, Colloc c,
@@ -75,14 +80,17 @@ __global__ __launch_bounds__(256) void collocation_kernel(Geom g, SysDims d, GL1
   const int i = (int)(r / (nj * kNodes));
   const double t = i * d.h + 0.5 * d.h * (gl.x[l] + 1.0);
   const double th = M_PI * j / d.M;
-  double x, y, z, J;
-  surface_point(g, t, th, &x, &y, &z, &J);
+  double x, y, z, J, nrm[3];
+  surface_point(g, t, th, &x, &y, &z, &J, nrm);
   const double wq = 0.5 * d.h * gl.w[l] / nj;
   c.x[r] = x;
   c.y[r] = y;
   c.z[r] = z;
   c.wq[r] = wq;
   c.jac[r] = J;
+  c.nx[r] = nrm[0];
+  c.ny[r] = nrm[1];
+  c.nz[r] = nrm[2];
   if (xyz) {
     xyz[3 * r] = x;
     xyz[3 * r + 1] = y;
@@ -123,12 +131,13 @@ constexpr int kFarRows = 8;
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 __global__ __launch_bounds__(256) void far_kernel(SysDims d, double k, Colloc c,
-                                                  cplx* __restrict__ S, int64_t ld) {
+                                                  cplx* __restrict__ S, int64_t ld, int density) {
   const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (col >= d.N) return;
   const int64_t per_panel = (int64_t)kNodes * 2 * d.M;
   const int pc = (int)(col / per_panel);
-  const double xc = c.x[col], yc = c.y[col], zc = c.z[col], wc = c.wq[col];
+  const double xc = c.x[col], yc = c.y[col], zc = c.z[col];
+  const double wc = density ? c.wq[col] * c.jac[col] : c.wq[col];
   const int64_t r0 = blockIdx.y * (int64_t)kFarRows;
   for (int rr = 0; rr < kFarRows; ++rr) {
     const int64_t r = r0 + rr;
@@ -146,6 +155,49 @@ __global__ __launch_bounds__(256) void far_kernel(SysDims d, double k, Colloc c,
     const dbl2 v = {f * co, f * s};
     __builtin_nontemporal_store(v, reinterpret_cast<dbl2*>(S + r * ld + col));
   }
+}
+
+// Far blocks of K (ADJ = false: tau_0 = nu_c . (x_c - x_r)) or K' (ADJ = true:
+// tau_0 = nu_r . (x_r - x_c)), the integrand of Sec. 4 times the product weight;
+// the same row walk and streaming stores as far_kernel.
+template <bool ADJ>
+__global__ __launch_bounds__(256) void far_kernel_dl(SysDims d, double k, Colloc c,
+                                                     cplx* __restrict__ S, int64_t ld, int density) {
+  const int64_t col = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (col >= d.N) return;
+  const int64_t per_panel = (int64_t)kNodes * 2 * d.M;
+  const int pc = (int)(col / per_panel);
+  const double xc = c.x[col], yc = c.y[col], zc = c.z[col];
+  const double wc = density ? c.wq[col] * c.jac[col] : c.wq[col];
+  double ncx = 0.0, ncy = 0.0, ncz = 0.0;
+  if (!ADJ) { ncx = c.nx[col]; ncy = c.ny[col]; ncz = c.nz[col]; }
+  const int64_t r0 = blockIdx.y * (int64_t)kFarRows;
+  for (int rr = 0; rr < kFarRows; ++rr) {
+    const int64_t r = r0 + rr;
+    if (r >= d.N) break;
+    const int pr = (int)(r / per_panel);
+    if (abs(pr - pc) <= 1) continue;
+    const double dx = xc - c.x[r], dy = yc - c.y[r], dz = zc - c.z[r];
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double ri = rsqrt_refined(r2);
+    const double rho = r2 * ri;
+    const double tau = ADJ ? -fma(c.nx[r], dx, fma(c.ny[r], dy, c.nz[r] * dz))
+                           : fma(ncx, dx, fma(ncy, dy, ncz * dz));
+    const double f = wc * tau * ri * ri * ri;
+    const double x = k * rho;
+    double s, co;
+    sincos_bounded(x, &s, &co);
+    // (ik rho - 1) e^{ik rho} = -(cos x + x sin x) + i (x cos x - sin x)
+    const dbl2 v = {-f * fma(x, s, co), f * fma(x, co, -s)};
+    __builtin_nontemporal_store(v, reinterpret_cast<dbl2*>(S + r * ld + col));
+  }
+}
+
+__global__ __launch_bounds__(256) void diag_shift_kernel(SysDims d, double shift, Colloc c,
+                                                         cplx* __restrict__ S, int64_t ld, int density) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= d.N) return;
+  S[r * ld + r].re += density ? shift : shift / c.jac[r];
 }
 
 // Inverse DFT size NF = 2M of G sequences held in LDS (positive exponent,
@@ -178,6 +230,7 @@ __global__ __launch_bounds__(256) void near_kernel(SysDims d, NearChunk ch,
                                                    const cplx* __restrict__ kappa,
                                                    const double* __restrict__ wl,
                                                    const double* __restrict__ tab_g,
+                                                   const double* __restrict__ colscale,
                                                    cplx* __restrict__ S, int64_t ld, int G) {
   extern __shared__ double lds[];
   const int M = d.M, NF = 2 * M;
@@ -204,6 +257,7 @@ __global__ __launch_bounds__(256) void near_kernel(SysDims d, NearChunk ch,
 
   const int64_t row = ((int64_t)i * kNodes + l) * NF + j;
   cplx* srow = S + row * ld + (int64_t)(i + rel) * kNodes * NF;
+  const double* cs = colscale ? colscale + (int64_t)(i + rel) * kNodes * NF : nullptr;
   for (int g0 = 0; g0 < kNodes; g0 += G) {
     // contract over the rule nodes, store in natural frequency order
     for (int x = threadIdx.x; x < G * NF; x += blockDim.x) {
@@ -227,7 +281,8 @@ __global__ __launch_bounds__(256) void near_kernel(SysDims d, NearChunk ch,
     for (int x = threadIdx.x; x < G * NF; x += blockDim.x) {
       const int s = x / NF;
       const int jp = x - s * NF;
-      srow[(int64_t)(g0 + s) * NF + jp] = src[s * NF + jp];
+      const int64_t cc = (int64_t)(g0 + s) * NF + jp;
+      srow[cc] = cs ? cs[cc] * src[s * NF + jp] : src[s * NF + jp];
     }
     __syncthreads();
   }
@@ -243,6 +298,7 @@ __global__ __launch_bounds__(256) void near_kernel128(SysDims d, NearChunk ch,
                                                       const cplx* __restrict__ kappa,
                                                       const double* __restrict__ wl,
                                                       const double* __restrict__ tab_g,
+                                                      const double* __restrict__ colscale,
                                                       cplx* __restrict__ S, int64_t ld) {
   constexpr int NF = 128;
   __shared__ double w_s[kNodes * kNodes];
@@ -294,11 +350,13 @@ __global__ __launch_bounds__(256) void near_kernel128(SysDims d, NearChunk ch,
   const int o = fft128_out_index(lane);
   const int64_t row = ((int64_t)i * kNodes + l) * NF + j;
   cplx* srow = S + row * ld + (int64_t)(i + rel) * kNodes * NF;
+  const double* cs = colscale ? colscale + (int64_t)(i + rel) * kNodes * NF : nullptr;
   for (int s = wave; s < kNodes; s += 4) {
     cplx x0 = conj(buf[s * NF + q0]), x1 = conj(buf[s * NF + q0 + 1]);
     fft128_regs(x0, x1, tw, lane);
-    srow[(int64_t)s * NF + o] = conj(x0);
-    srow[(int64_t)s * NF + o + 64] = conj(x1);
+    const int64_t c0 = (int64_t)s * NF + o;
+    srow[c0] = cs ? cs[c0] * conj(x0) : conj(x0);
+    srow[c0 + 64] = cs ? cs[c0 + 64] * conj(x1) : conj(x1);
   }
 }
 
@@ -313,18 +371,25 @@ __global__ __launch_bounds__(256) void rhs_kernel(SysDims d, double k, int kind,
     sincos_bounded(k * rho, &s, &co);
     const double f = 1.0 / (4.0 * M_PI * rho);
     g[r] = mk(f * co, f * s);
-  } else {
+  } else if (kind == FFBIE_RHS_PLANE_WAVE) {
     const double ph = k * (p0 * c.x[r] + p1 * c.y[r] + p2 * c.z[r]);
     double s, co;
     sincos_bounded(ph, &s, &co);
     g[r] = mk(-co, -s);
+  } else {
+    // -d/d nu e^{ik d.x} = -ik (d . nu) e^{ik d.x}
+    const double ph = k * (p0 * c.x[r] + p1 * c.y[r] + p2 * c.z[r]);
+    const double dn = k * (p0 * c.nx[r] + p1 * c.ny[r] + p2 * c.nz[r]);
+    double s, co;
+    sincos_bounded(ph, &s, &co);
+    g[r] = mk(dn * s, -dn * co);
   }
 }
 
 __global__ __launch_bounds__(256) void field_partial_kernel(SysDims d, double k, Colloc c,
                                                             const double* __restrict__ pts,
                                                             const cplx* __restrict__ phi,
-                                                            cplx* partial, int n_chunks) {
+                                                            cplx* partial, int n_chunks, int density) {
   __shared__ double red[2][256];
   const int64_t p = blockIdx.y;
   const int chunk = blockIdx.x;
@@ -338,8 +403,48 @@ __global__ __launch_bounds__(256) void field_partial_kernel(SysDims d, double k,
     const double rho = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
     double sn, cs;
     sincos_bounded(k * rho, &sn, &cs);
-    const double f = c.wq[s] / rho;
+    const double f = (density ? c.wq[s] * c.jac[s] : c.wq[s]) / rho;
     const cplx v = mk(f * cs, f * sn) * phi[s];
+    ar += v.re;
+    ai += v.im;
+  }
+  red[0][threadIdx.x] = ar;
+  red[1][threadIdx.x] = ai;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[p * n_chunks + chunk] = mk(red[0][0], red[1][0]);
+}
+
+// Partial sums of the double-layer field, sum_s wq tau_0 (ik rho - 1) e^{ik rho} / rho^3 psi_s,
+// tau_0 = nu_s . (x_s - p), with field_partial_kernel's fixed-order reduction.
+__global__ __launch_bounds__(256) void field_partial_dl_kernel(SysDims d, double k, Colloc c,
+                                                               const double* __restrict__ pts,
+                                                               const cplx* __restrict__ psi,
+                                                               cplx* partial, int n_chunks, int density) {
+  __shared__ double red[2][256];
+  const int64_t p = blockIdx.y;
+  const int chunk = blockIdx.x;
+  const int64_t per = (d.N + n_chunks - 1) / n_chunks;
+  const int64_t c0 = chunk * per;
+  const int64_t c1 = min(d.N, c0 + per);
+  const double px = pts[3 * p], py = pts[3 * p + 1], pz = pts[3 * p + 2];
+  double ar = 0.0, ai = 0.0;
+  for (int64_t s = c0 + threadIdx.x; s < c1; s += blockDim.x) {
+    const double dx = c.x[s] - px, dy = c.y[s] - py, dz = c.z[s] - pz;
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double rho = sqrt(r2);
+    const double tau = fma(c.nx[s], dx, fma(c.ny[s], dy, c.nz[s] * dz));
+    const double x = k * rho;
+    double sn, cs;
+    sincos_bounded(x, &sn, &cs);
+    const double f = (density ? c.wq[s] * c.jac[s] : c.wq[s]) * tau / (r2 * rho);
+    const cplx v = mk(-f * fma(x, sn, cs), f * fma(x, cs, -sn)) * psi[s];
     ar += v.re;
     ai += v.im;
   }
@@ -422,9 +527,9 @@ hipError_t launch_near_pairs(const SysDims& d, const NearChunk& ch, const double
 }
 
 hipError_t launch_far_assembly(const SysDims& d, double k, Colloc c, cplx* S, int64_t ld,
-                               hipStream_t s) {
+                               hipStream_t s, int density) {
   const dim3 grid((unsigned)((d.N + 255) / 256), (unsigned)((d.N + kFarRows - 1) / kFarRows));
-  hipLaunchKernelGGL(far_kernel, grid, dim3(256), 0, s, d, k, c, S, ld);
+  hipLaunchKernelGGL(far_kernel, grid, dim3(256), 0, s, d, k, c, S, ld, density);
   return hipGetLastError();
 }
 
@@ -438,18 +543,18 @@ int near_group(int M) {
 
 hipError_t launch_near_assembly(const SysDims& d, const NearChunk& ch, const cplx* kappa,
                                 const double* wl, const double* tab, cplx* S, int64_t ld,
-                                hipStream_t s) {
+                                hipStream_t s, const double* colscale) {
   const int G = near_group(d.M);
   const int NF = 2 * d.M;
   const size_t lds = sizeof(double) * (8 * d.M + kNodes * kNodes) + sizeof(cplx) * 2 * G * NF;
   const int64_t blocks = (int64_t)(ch.p1 - ch.p0) * kNodes * NF * 3;
   if (NF == 128) {
     hipLaunchKernelGGL(near_kernel128, dim3((unsigned)blocks), dim3(256), 0, s, d, ch, kappa, wl, tab,
-                       S, ld);
+                       colscale, S, ld);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(near_kernel, dim3((unsigned)blocks), dim3(256), lds, s, d, ch, kappa, wl, tab,
-                     S, ld, G);
+                     colscale, S, ld, G);
   return hipGetLastError();
 }
 
@@ -462,9 +567,39 @@ hipError_t launch_rhs(const SysDims& d, double k, int kind, const double* p, Col
 }
 
 hipError_t launch_field(const SysDims& d, double k, Colloc c, int64_t n_pts, const double* pts,
-                        const cplx* phi, cplx* partial, int n_chunks, cplx* u, hipStream_t s) {
+                        const cplx* phi, cplx* partial, int n_chunks, cplx* u, hipStream_t s,
+                        int density) {
   hipLaunchKernelGGL(field_partial_kernel, dim3(n_chunks, (unsigned)n_pts), dim3(256), 0, s, d, k,
-                     c, pts, phi, partial, n_chunks);
+                     c, pts, phi, partial, n_chunks, density);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(field_sum_kernel, dim3((unsigned)((n_pts + 255) / 256)), dim3(256), 0, s,
+                     n_pts, n_chunks, partial, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_far_assembly_dl(const SysDims& d, double k, Colloc c, int adjoint, cplx* S,
+                                  int64_t ld, hipStream_t s, int density) {
+  const dim3 grid((unsigned)((d.N + 255) / 256), (unsigned)((d.N + kFarRows - 1) / kFarRows));
+  if (adjoint)
+    hipLaunchKernelGGL(far_kernel_dl<true>, grid, dim3(256), 0, s, d, k, c, S, ld, density);
+  else
+    hipLaunchKernelGGL(far_kernel_dl<false>, grid, dim3(256), 0, s, d, k, c, S, ld, density);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_shift(const SysDims& d, double shift, Colloc c, cplx* S, int64_t ld,
+                             hipStream_t s, int density) {
+  hipLaunchKernelGGL(diag_shift_kernel, dim3((unsigned)((d.N + 255) / 256)), dim3(256), 0, s, d,
+                     shift, c, S, ld, density);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_dl(const SysDims& d, double k, Colloc c, int64_t n_pts, const double* pts,
+                           const cplx* psi, cplx* partial, int n_chunks, cplx* u, hipStream_t s,
+                           int density) {
+  hipLaunchKernelGGL(field_partial_dl_kernel, dim3(n_chunks, (unsigned)n_pts), dim3(256), 0, s, d, k,
+                     c, pts, psi, partial, n_chunks, density);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(field_sum_kernel, dim3((unsigned)((n_pts + 255) / 256)), dim3(256), 0, s,

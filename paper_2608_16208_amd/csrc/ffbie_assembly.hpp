@@ -15,14 +15,19 @@ struct SysDims {
   double h;                          // panel length pi / n_panels
 };
 
-// Collocation data in structure-of-arrays form: x, y, z, wq = (h/2) w_l / (2M), jac.
+// Collocation data in structure-of-arrays form: x, y, z, wq = (h/2) w_l / (2M), jac,
+// and the unit normal (r_t x r_theta)/jac.
 struct Colloc {
   double* x;
   double* y;
   double* z;
   double* wq;
   double* jac;
+  double* nx;
+  double* ny;
+  double* nz;
 };
+constexpr int kCollocArrays = 8;
 
 // Near pairs of a range of target panels [p0, p1).
 struct NearChunk {
@@ -55,15 +60,33 @@ hipError_t launch_collocation(const Geom& g, const SysDims& d, const double* gl_
 hipError_t launch_near_pairs(const SysDims& d, const NearChunk& ch, const double* gl_x,
                              const double* rule_y /* [16 l][3 rel][16 q] */, double* t,
                              int32_t* az, double* ts, hipStream_t s);
+// density = 1: the unknowns are density values (columns carry the Jacobian);
+// 0: density x Jacobian (the single-layer system's unknowns).
 hipError_t launch_far_assembly(const SysDims& d, double k, Colloc c, cplx* S, int64_t ld,
-                               hipStream_t s);
+                               hipStream_t s, int density = 0);
+// colscale: per-column factor of the written entries (the Jacobians for
+// density unknowns) or null.
 hipError_t launch_near_assembly(const SysDims& d, const NearChunk& ch, const cplx* kappa,
                                 const double* wl /* [16 l][3 rel][16 q][16 l'] */,
-                                const double* tab, cplx* S, int64_t ld, hipStream_t s);
+                                const double* tab, cplx* S, int64_t ld, hipStream_t s,
+                                const double* colscale = nullptr);
+// Far blocks of the double-layer operator K (adjoint = 0) or K' (adjoint = 1):
+// (h/2) w_l' (1/2M) tau_0 (ik rho - 1) e^{ik rho} / rho^3.
+hipError_t launch_far_assembly_dl(const SysDims& d, double k, Colloc c, int adjoint, cplx* S,
+                                  int64_t ld, hipStream_t s, int density);
+// S[r, r] += shift (density unknowns) or shift / jac[r] (density x Jacobian):
+// shift times the identity.
+hipError_t launch_diag_shift(const SysDims& d, double shift, Colloc c, cplx* S, int64_t ld,
+                             hipStream_t s, int density);
+// Field of the double-layer representation u = 2 int dG/d nu_s psi dsigma.
+hipError_t launch_field_dl(const SysDims& d, double k, Colloc c, int64_t n_pts, const double* pts,
+                           const cplx* psi, cplx* partial, int n_chunks, cplx* u, hipStream_t s,
+                           int density);
 hipError_t launch_rhs(const SysDims& d, double k, int kind, const double* p, Colloc c, cplx* g,
                       hipStream_t s);
 hipError_t launch_field(const SysDims& d, double k, Colloc c, int64_t n_pts, const double* pts,
-                        const cplx* phi, cplx* partial, int n_chunks, cplx* u, hipStream_t s);
+                        const cplx* phi, cplx* partial, int n_chunks, cplx* u, hipStream_t s,
+                        int density = 0);
 
 // counts[0] += pairs flagged FFBIE_PAIR_UNRESOLVED, counts[1] += pairs flagged
 // FFBIE_PAIR_ROOT_FALLBACK among st[0..n); launch_zero_counts clears n counters

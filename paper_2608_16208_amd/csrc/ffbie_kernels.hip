@@ -1328,8 +1328,11 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
     }
     const int qj = j * (NF / (2 * M));
 
-    // ---- samples of H (real part) and P (imaginary part)
-    double maxH = 0.0, maxP = 0.0;
+    // ---- samples of H (real part) and P (imaginary part).  maxN bounds the
+    //      rounding of the samples: tau_0 is a dot product with |r_s - r| = rho,
+    //      and cos x + x sin x carries rounding ~u x, so H_q is good to about
+    //      u rho (1 + x) F^3 -- the level below which its coefficients are noise
+    double maxH = 0.0, maxP = 0.0, maxN = 0.0;
     for (int q = lane; q < NF; q += 64) {
       const int Kq = q * tstride;
       double dx, dy, dz;
@@ -1365,7 +1368,9 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
         const double A1 = Rs * pg.sts, A2 = -Rts * pg.sts, A3 = -Rhs;
         tau = fma(A1, wd, fma(A2, td, A3 * pd)) * rsqrt_refined(fma(A1, A1, fma(A2, A2, A3 * A3)));
       }
-      const double H = tau * fma(x, skr, ckr) * (F * F * F);
+      const double F3 = F * F * F;
+      const double H = tau * fma(x, skr, ckr) * F3;
+      maxN = fmax(maxN, rho * (1.0 + x) * F3);
       const double beta = (x < 1.0) ? k3 * beta_series(x) : (skr - x * ckr) * (ri * ri * ri);
       const double Pv = beta * tau;
       z1a[q] = cplx{H, Pv};
@@ -1374,6 +1379,7 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
     }
     maxH = wave_max(maxH);
     maxP = wave_max(maxP);
+    maxN = wave_max(maxN);
     // P rides in the imaginary part scaled by a power of two to H's size, so
     // that its size does not raise the rounding floor of H's coefficients
     const int sexp = (maxH > 0.0 && maxP > 0.0) ? ilogb(maxH) - ilogb(maxP) : 0;
@@ -1385,7 +1391,11 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
     cplx *Z = z1a, *Fr = z1b, *Zd = z1a, *Fd = z1b;
     fft_stockham_r4(Z, Fr, Zd, Fd, false, NF, M, tab, mask, quarter, (const cplx*)nullptr, lane);
 
-    const int ptr = trunc_index_real(Z, NF, invNF, P.eps0, maxH, lane);
+    // truncation index (the rule of eq. (3.24)) against the larger of H's
+    // largest coefficient and its rounding scale: where tau_0 is a small
+    // difference of O(rho) terms (targets far from a source curve near a
+    // pole) the coefficients reach that floor, not eps0 max |H|
+    const int ptr = trunc_index_real(Z, NF, invNF, P.eps0, fmax(maxH, maxN), lane);
     if (ptr >= NF / 2 - 2) {
       if (!REFINE && a.flag_list) {
         if (lane == 0) {

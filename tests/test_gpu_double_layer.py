@@ -57,7 +57,8 @@ def fp64_bound(amp, k, M, t, j, ts, ref_row, adjoint=False, eps0=1e-15):
         translated: eps (log(1/b) + 3)/(2 pi) (sum_{j <= p} j^4)^{1/2},
     p = N_F/2 - 1, relative to the row's rms, times 2.  (a, b) is the
     quadratic-model root of rho^2 (Sec. 3.3); N_F = 4M where the 2M-sample
-    coefficients of H are not below eps0 max|H| at N_F/2 (the refine rule)."""
+    coefficients of H are not below eps0 max(max|H|, max rho (1 + x) F^3) at
+    N_F/2 (the refine rule)."""
     th = math.pi * j / M
     u0, r2, d2 = ocoeffs.minimiser(amp, t, th, ts)
     b0 = math.sqrt(2.0 * r2 / d2)
@@ -71,14 +72,15 @@ def fp64_bound(amp, k, M, t, j, ts, ref_row, adjoint=False, eps0=1e-15):
         tau = odl.tau0(amp, t, th, ts, thq - th, adjoint=adjoint)
         s = (-math.expm1(-b0)) ** 2 + 4.0 * math.exp(-b0) * np.sin(0.5 * (thq - a0)) ** 2
         x = k * rho
-        return tau * (np.cos(x) + x * np.sin(x)) * (np.sqrt(s) / rho) ** 3, x
+        F3 = (np.sqrt(s) / rho) ** 3
+        return tau * (np.cos(x) + x * np.sin(x)) * F3, x, np.max(rho * (1.0 + x) * F3)
 
     nf = 2 * M
-    H, x = samples(nf)
+    H, x, noise = samples(nf)
     c = np.abs(np.fft.fft(H)) / nf
-    if np.max(c[nf // 2 - 2:nf // 2 + 1]) > eps0 * np.max(np.abs(H)):
+    if np.max(c[nf // 2 - 2:nf // 2 + 1]) > eps0 * max(np.max(np.abs(H)), noise):
         nf = 4 * M
-        H, x = samples(nf)
+        H, x, _ = samples(nf)
     eps = 2.0 ** -53 * math.sqrt(np.mean(((1.0 + x) * H) ** 2)) / math.sqrt(nf)
     p = nf // 2 - 1
     m = math.exp(-2.0 * b0)
