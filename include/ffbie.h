@@ -315,6 +315,18 @@ ffbie_status ffbie_batch_plan_get_tuning(const ffbie_batch_plan *plan, int m_cla
                                          ffbie_tuning *tuning, double *tuned_ms, int *M);
 ffbie_status ffbie_batch_plan_destroy(ffbie_batch_plan *plan);
 
+/* On-disk cache of the autotuner's choices.  With a cache file set (path, a
+ * HOST string copied by the call; NULL or "" clears it), FFBIE_PLAN_AUTOTUNE
+ * first looks each M class up by (device architecture and compute-unit count,
+ * M, FP64 or mixed precision): a hit is used without timing (its recorded
+ * main-pass time is what ffbie_batch_plan_get_tuning reports), a miss is
+ * tuned as usual and added to the file, which is then rewritten (JSON: one
+ * flat entry per key, see the entries ffbie writes; written to path.tmp and
+ * renamed).  An unreadable or foreign file counts as empty.  Plan creation
+ * returns FFBIE_EDEVICE if the file cannot be written.  Entries are checked
+ * against the launch limits before use. */
+ffbie_status ffbie_set_tuning_cache(ffbie_ctx *ctx, const char *path);
+
 /* ------------------------------------------------------------------------
  * The discrete single-layer system (Sec. 3.1 and 3.4)
  * ------------------------------------------------------------------------

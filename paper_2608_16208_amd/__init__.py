@@ -31,7 +31,7 @@ EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_probl
            "ffbie_batch_plan_destroy", "ffbie_batch_plan_classes", "ffbie_gemm_sub",
            "ffbie_assembly_report", "ffbie_mlp_train", "ffbie_mlp_save", "ffbie_mlp_load",
            "ffbie_kernel_coeffs_noalloc", "ffbie_kernel_coeffs_dl", "ffbie_assemble_op",
-           "ffbie_eval_field_op")
+           "ffbie_eval_field_op", "ffbie_set_tuning_cache")
 SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES, SOLVE_FGMRES_MLP, SOLVE_GMRES_BLOCKJACOBI = 0, 1, 2, 3, 4
 SOLVE_GMRES_LU32, SOLVE_FGMRES_BJ_MLP = 5, 6
 MLP_IN, MLP_HIDDEN, MLP_OUT = 514, 256, 512
@@ -124,6 +124,7 @@ def load_library(path=LIB_PATH):
     lib.ffbie_rhs.argtypes = [vp, i32, dp, vp]
     lib.ffbie_assemble.argtypes = [vp, vp, i64]
     lib.ffbie_eval_field.argtypes = [vp, i64, vp, vp, vp]
+    lib.ffbie_set_tuning_cache.argtypes = [vp, ctypes.c_char_p]
     lib.ffbie_assemble_op.argtypes = [vp, i32, ctypes.c_double, i32, vp, i64]
     lib.ffbie_eval_field_op.argtypes = [vp, i32, i32, i64, vp, vp, vp]
     lib.ffbie_solve.argtypes = [vp, i32, vp, i64, vp, vp, ctypes.c_double, i32, ctypes.POINTER(_SolveInfo)]
@@ -346,6 +347,12 @@ class Context:
         self._check(self.lib.ffbie_get_tuning(self.h, ctypes.byref(t)), self.h)
         return {"fft_radix": t.fft_radix, "pairs_per_item": t.pairs_per_item,
                 "waves_per_block": t.waves_per_block, "persistent": t.persistent}
+
+    def set_tuning_cache(self, path):
+        """File of the batch autotuner's choices (None clears it); autotuned
+        plans read their M classes from it and add what they tune."""
+        self._check(self.lib.ffbie_set_tuning_cache(self.h, None if path is None else str(path).encode()),
+                    self.h)
 
     def enable_timing(self, on=True):
         self._check(self.lib.ffbie_enable_timing(self.h, int(bool(on))), self.h)

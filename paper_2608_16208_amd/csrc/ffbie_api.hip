@@ -19,6 +19,7 @@
 #include "ffbie_kernels.hpp"
 #include "ffbie_mlp.hpp"
 #include "ffbie_solve.hpp"
+#include "ffbie_tuning_cache.hpp"
 
 using namespace ffbie;
 
@@ -120,6 +121,7 @@ struct ffbie_ctx {
   // FFT radix (0: by N_F), pairs per batch work item, waves per workgroup,
   // persistent batch launches
   ffbie_tuning tune{0, kBatchTile, 4, 0};
+  std::string tune_cache;            // autotuner cache file ("" = none)
   ffbie_batch_plan* oneshot = nullptr;    // plan of the last ffbie_kernel_coeffs_batched call
   // learned preconditioner
   Mlp mlp;
@@ -888,7 +890,31 @@ ffbie_status plan_autotune(ffbie_ctx* c, ffbie_batch_plan* pl) {
     e = launch_batch(plan_args(pl), pl->mm, pl->n_root, 256, 8 * pl->Mmax * sizeof(double), c->stream, 0,
                      pl->single);
   if (e != hipSuccess) st = hip_fail(c, e, "autotune root pass");
+  // device key of the tuning cache: architecture and compute-unit count
+  std::vector<TuneEntry> cache;
+  std::string dev_key;
+  bool cache_dirty = false;
+  if (!c->tune_cache.empty()) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+      dev_key = std::string(prop.gcnArchName) + " x" + std::to_string(prop.multiProcessorCount);
+      cache = tune_cache_read(c->tune_cache);
+    }
+  }
+  const std::string prec = pl->single ? "f32" : "f64";
   for (int k = 0; k < (int)pl->cls.size() && st == FFBIE_OK; ++k) {
+    if (!dev_key.empty()) {
+      const TuneEntry* hit = tune_cache_find(cache, dev_key, pl->cls[k].M, prec);
+      std::string why;
+      if (hit && valid_tuning(hit->t, &why)) {
+        st = plan_shape(c, pl, k, hit->t);
+        if (st == FFBIE_OK && pl->cls[k].waves == hit->t.waves_per_block) {
+          pl->cls[k].tuned_ms = hit->main_ms;
+          continue;
+        }
+        if (st != FFBIE_OK) break;
+      }
+    }
     ffbie_tuning best = pl->cls[k].tune;
     float best_ms = -1.0f;
     for (int radix : {2, 4})
@@ -916,10 +942,28 @@ ffbie_status plan_autotune(ffbie_ctx* c, ffbie_batch_plan* pl) {
     if (st == FFBIE_OK) {
       st = plan_shape(c, pl, k, best);
       pl->cls[k].tuned_ms = best_ms;
+      if (!dev_key.empty()) {
+        TuneEntry te;
+        te.device = dev_key;
+        te.M = pl->cls[k].M;
+        te.precision = prec;
+        te.t = best;
+        te.main_ms = best_ms;
+        bool replaced = false;
+        for (TuneEntry& e : cache)
+          if (e.device == te.device && e.M == te.M && e.precision == te.precision) {
+            e = te;
+            replaced = true;
+          }
+        if (!replaced) cache.push_back(te);
+        cache_dirty = true;
+      }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (st == FFBIE_OK && cache_dirty && !tune_cache_write(c->tune_cache, cache))
+    return fail(c, FFBIE_EDEVICE, "ffbie_batch_plan_create: cannot write the tuning cache " + c->tune_cache);
   return st;
 }
 
@@ -1281,6 +1325,12 @@ ffbie_status ffbie_singular_factor(ffbie_ctx* c, int64_t n, const double* d_b, i
   hipLaunchKernelGGL(ffbie_singular_factor_kernel, dim3((unsigned)blocks), dim3(64 * w), lds,
                      c->stream, n, d_b, m_max, d_A);
   FFBIE_HIP(c, hipGetLastError());
+  return FFBIE_OK;
+}
+
+ffbie_status ffbie_set_tuning_cache(ffbie_ctx* c, const char* path) {
+  if (!c) return FFBIE_EINVAL;
+  c->tune_cache = path ? path : "";
   return FFBIE_OK;
 }
 

@@ -13,6 +13,7 @@ does not reach the tolerance.
 Command lines:
     python -m paper_2608_16208_amd.learned train --out weights.ffbiemlp [--systems 200]
     python -m paper_2608_16208_amd.learned study [--train 200 --test 50] [--save/--load ckpt]
+                                                 [--system first|second]
 """
 import argparse
 import time
@@ -21,8 +22,23 @@ import numpy as np
 
 import workloads
 
-from . import (Context, RHS_PLANE_WAVE, RHS_POINT_SOURCE, SOLVE_FGMRES_MLP, SOLVE_GMRES,
-               SOLVE_LU64)
+from . import (Context, OP_K, OP_S, RHS_PLANE_WAVE, RHS_POINT_SOURCE, SOLVE_FGMRES_MLP, SOLVE_GMRES,
+               SOLVE_LU64, UNKNOWN_DENSITY, UNKNOWN_SCALED)
+
+# The exterior Dirichlet problem as a system: the first-kind single-layer
+# equation S phi = g (eq. (2.7)) on density x Jacobian, or the second-kind
+# double-layer equation (K + I) psi = g (eq. (2.12)) on density values.
+SYSTEMS = {"first": dict(op=OP_S, shift=0.0, unknowns=UNKNOWN_SCALED),
+           "second": dict(op=OP_K, shift=1.0, unknowns=UNKNOWN_DENSITY)}
+
+
+def _assemble(ctx, system):
+    return ctx.assemble(**SYSTEMS[system])
+
+
+def _field(ctx, pts, x, system):
+    sy = SYSTEMS[system]
+    return ctx.eval_field(pts, x, op=sy["op"], unknowns=sy["unknowns"])
 
 
 def _inputs(ctx, S, rng, n_rhs):
@@ -75,19 +91,21 @@ def make_dataset(ctx, surfaces, M=64, n_rhs=8, seed=0, min_scale=1e-6, log=None)
     return torch.cat(X), torch.cat(T)
 
 
-def make_dataset_correction(ctx, surfaces, M=64, n_rhs=4, seed=0, min_scale=1e-6, log=None):
+def make_dataset_correction(ctx, surfaces, M=64, n_rhs=4, seed=0, min_scale=1e-6, log=None,
+                            system="first"):
     """Training pairs for the preconditioner P(v) = BJ(v) + NN(v): inputs are
     the mode features of Krylov-type vectors v of each system, targets the
     modes of the part of S^{-1} v that mode-block-Jacobi misses,
     S^{-1} v - BJ(v), scaled like the features.  S^{-1} v comes from an LU64
-    factorisation of each system (a copy of S).  Returns (X, T) float32 device
+    factorisation of each system (a copy of S).  `system` selects the first-
+    or second-kind equation (SYSTEMS).  Returns (X, T) float32 device
     tensors."""
     import torch
     rng = np.random.default_rng(seed)
     X, T = [], []
     for i, sf in enumerate(surfaces):
         ctx.set_problem(sf["amp"], 16, M, sf["k"])
-        S = ctx.assemble()
+        S = _assemble(ctx, system)
         ctx.blockjacobi_setup(S)
         vs = _inputs(ctx, S, rng, n_rhs)
         W = S.clone()
@@ -109,7 +127,7 @@ def make_dataset_correction(ctx, surfaces, M=64, n_rhs=4, seed=0, min_scale=1e-6
 
 
 def study(ctx, n_train=200, n_test=50, M=64, n_rhs=4, steps=3000, batch=2048, lr=1e-3, tol=1e-9,
-          max_iter=400, load=None, save_path=None, log=None):
+          max_iter=400, load=None, save_path=None, log=None, system="first"):
     """The learned-preconditioner study at its stated scale: a network trained
     on n_train method-generated systems (star surfaces with 20 amplitudes
     U(-0.1, 0.1), k ~ U[5, 30], 16 panels, M) to correct the mode-block-Jacobi
@@ -120,10 +138,12 @@ def study(ctx, n_train=200, n_test=50, M=64, n_rhs=4, steps=3000, batch=2048, lr
     the residual tolerance `tol` (at most max_iter iterations) and reports its
     iterations, time and field error, and whether it is within 1e-8 of the
     reference (time-to-1e-8 = assembly + solve + field when it is).  With
-    `load` the network is read from a checkpoint instead of trained."""
+    `load` the network is read from a checkpoint instead of trained.
+    `system`: "first" (S phi = g) or "second" ((K + I) psi = g), SYSTEMS."""
     import torch
     from . import SOLVE_GMRES_BLOCKJACOBI, SOLVE_FGMRES_BJ_MLP
-    out = {"n_train": n_train, "n_test": n_test, "M": M, "tol": tol, "max_iter": max_iter}
+    out = {"n_train": n_train, "n_test": n_test, "M": M, "tol": tol, "max_iter": max_iter,
+           "system": system}
     if load:
         ctx.mlp_load(load)
         out["network"] = "loaded from checkpoint"
@@ -131,7 +151,7 @@ def study(ctx, n_train=200, n_test=50, M=64, n_rhs=4, steps=3000, batch=2048, lr
         ctx.mlp_init(1234)
         t0 = time.perf_counter()
         X, T = make_dataset_correction(ctx, [workloads.learned_surface(i) for i in range(n_train)], M=M,
-                                       n_rhs=n_rhs, log=log)
+                                       n_rhs=n_rhs, log=log, system=system)
         out["dataset"] = {"samples": int(X.shape[0]), "s": time.perf_counter() - t0}
         t0 = time.perf_counter()
         out["training"] = dict(train(ctx, X, T, steps=steps, batch=batch, lr=lr, log=log),
@@ -149,7 +169,7 @@ def study(ctx, n_train=200, n_test=50, M=64, n_rhs=4, steps=3000, batch=2048, lr
         ctx.set_problem(sf["amp"], 16, M, sf["k"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        S = ctx.assemble()
+        S = _assemble(ctx, system)
         torch.cuda.synchronize()
         t_asm = time.perf_counter() - t0
         d = np.array([0.3, -0.5, 0.81])
@@ -158,7 +178,7 @@ def study(ctx, n_train=200, n_test=50, M=64, n_rhs=4, steps=3000, batch=2048, lr
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         phi_ref, _ = ctx.solve(W, g, method=SOLVE_LU64)
-        u_ref = ctx.eval_field(pts, phi_ref)
+        u_ref = _field(ctx, pts, phi_ref, system)
         torch.cuda.synchronize()
         t_lu = time.perf_counter() - t0
         del W
@@ -169,7 +189,7 @@ def study(ctx, n_train=200, n_test=50, M=64, n_rhs=4, steps=3000, batch=2048, lr
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             phi, info = ctx.solve(S, g, method=method, tol=tol, max_iter=max_iter)
-            u = ctx.eval_field(pts, phi)
+            u = _field(ctx, pts, phi, system)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             e = float(((u - u_ref).abs().norm() / u_ref.abs().norm()).item())
@@ -273,13 +293,16 @@ def main():
     a2.add_argument("--save", default=None, help="write the trained network here")
     a2.add_argument("--load", default=None, help="evaluate a saved network instead of training")
     a2.add_argument("--json", default=None, help="write the study's record here")
+    a2.add_argument("--system", default="first", choices=sorted(SYSTEMS),
+                    help="first-kind S phi = g or second-kind (K + I) psi = g")
     args = ap.parse_args()
     log = lambda s: print(s, flush=True)
     ctx = Context(0)
     if args.cmd == "study":
         import json
         res = study(ctx, n_train=args.train, n_test=args.test, M=args.M, n_rhs=args.rhs, steps=args.steps,
-                    batch=args.batch, lr=args.lr, load=args.load, save_path=args.save, log=log)
+                    batch=args.batch, lr=args.lr, load=args.load, save_path=args.save, log=log,
+                    system=args.system)
         log(json.dumps(res["summary"]))
         if args.json:
             with open(args.json, "w") as fh:

@@ -2,6 +2,9 @@
 // kernels include), driven from tests/test_host_device_code.py.
 //   sincos <x...>            : prints sin, cos of each x with sincos_bounded
 //   roots  (stdin problem)   : prints u, b, status of find_root for each pair
+//   tunecache <path>         : writes two autotuner cache entries to path, reads
+//                              them back and prints them; then reads path as it
+//                              is after a test has altered it
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -9,6 +12,7 @@
 #include <vector>
 
 #include "ffbie_root.hpp"
+#include "ffbie_tuning_cache.hpp"
 
 using namespace ffbie;
 
@@ -24,7 +28,32 @@ static double table_sin(int i, int M) {
   return sign * (double)v;
 }
 
+static void print_entries(const std::vector<TuneEntry>& v) {
+  printf("%zu\n", v.size());
+  for (const TuneEntry& e : v)
+    printf("%s|%d|%s|%d|%d|%d|%d|%.6g\n", e.device.c_str(), e.M, e.precision.c_str(), e.t.fft_radix,
+           e.t.pairs_per_item, e.t.waves_per_block, e.t.persistent, e.main_ms);
+}
+
 int main(int argc, char** argv) {
+  if (argc > 2 && !strcmp(argv[1], "tunecache")) {
+    if (argc > 3 && !strcmp(argv[3], "read")) {
+      print_entries(tune_cache_read(argv[2]));
+      return 0;
+    }
+    std::vector<TuneEntry> v(2);
+    v[0].device = "gfx950 x256"; v[0].M = 64; v[0].precision = "f64";
+    v[0].t = ffbie_tuning{2, 16, 4, 0}; v[0].main_ms = 12.5;
+    v[1].device = "gfx950 x256"; v[1].M = 128; v[1].precision = "f32";
+    v[1].t = ffbie_tuning{4, 8, 2, 1}; v[1].main_ms = 0.25;
+    if (!tune_cache_write(argv[2], v)) return 2;
+    const std::vector<TuneEntry> r = tune_cache_read(argv[2]);
+    print_entries(r);
+    const TuneEntry* h = tune_cache_find(r, "gfx950 x256", 128, "f32");
+    const TuneEntry* miss = tune_cache_find(r, "gfx950 x256", 128, "f64");
+    printf("%d %d\n", h ? h->t.fft_radix : -1, miss ? 1 : 0);
+    return 0;
+  }
   if (argc > 1 && !strcmp(argv[1], "sincos")) {
     double x;
     while (scanf("%lf", &x) == 1) {

@@ -1,6 +1,7 @@
 """Device math of the coefficient path, compiled for the host and checked on
 the CPU: the bounded-argument sin/cos and the root finder (the exact code the
-root kernel runs), against 30-50 digit arithmetic."""
+root kernel runs), against 30-50 digit arithmetic; and the autotuner's
+on-disk cache (write, read back, damaged files)."""
 import math
 import os
 import shutil
@@ -76,3 +77,29 @@ def test_root_finder_on_host(harness, cfgi):
         assert abs(f(z) / mp.diff(f, z)) <= 1e-13 * b, (i, b)
         checked += 1
     assert checked >= 40
+
+
+def test_tuning_cache_round_trip_and_damaged_files(harness, tmp_path):
+    path = str(tmp_path / "tune.json")
+    out = subprocess.run([harness, "tunecache", path], capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr
+    lines = out.stdout.split("\n")
+    assert lines[0] == "2"
+    assert lines[1] == "gfx950 x256|64|f64|2|16|4|0|12.5"
+    assert lines[2] == "gfx950 x256|128|f32|4|8|2|1|0.25"
+    assert lines[3] == "4 0"                      # hit on (M, precision), miss on the other precision
+    import json
+    doc = json.load(open(path))                   # the file is plain JSON
+    assert doc["format"] == "ffbie-tuning-cache" and len(doc["entries"]) == 2
+
+    def read(text):
+        with open(path, "w") as fh:
+            fh.write(text)
+        r = subprocess.run([harness, "tunecache", path, "read"], capture_output=True, text=True)
+        return r.stdout.split("\n")[0]
+
+    assert read(json.dumps(doc)) == "2"           # re-serialised by another writer: still read
+    assert read('{"format": "something-else", "entries": []}') == "0"
+    assert read(json.dumps(doc)[:-20]) == "0"     # truncated
+    doc["entries"][0]["extra"] = 1
+    assert read(json.dumps(doc)) == "0"           # unknown key: the whole file is ignored
