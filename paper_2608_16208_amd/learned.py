@@ -183,7 +183,8 @@ def study(ctx, n_train=200, n_test=50, M=64, n_rhs=4, steps=3000, batch=2048, lr
         t_lu = time.perf_counter() - t0
         del W
         torch.cuda.empty_cache()
-        row = {"k": sf["k"], "assembly_s": t_asm, "lu64": {"s": t_asm + t_lu}}
+        row = {"k": sf["k"], "assembly_s": t_asm, "lu64": {"s": t_asm + t_lu},
+               "unresolved_near_pairs": ctx.last_assembly["unresolved"]}
         for name, method in (("gmres", SOLVE_GMRES), ("gmres_blockjacobi", SOLVE_GMRES_BLOCKJACOBI),
                              ("fgmres_bj_nn", SOLVE_FGMRES_BJ_MLP)):
             torch.cuda.synchronize()
