@@ -23,4 +23,6 @@ geometry  star-family surfaces r(t, theta) and the cancellation-free
           difference r(v) - r(u) of Remark 4.2 (line integral in parameter space)
 coeffs    direct-quadrature <rho^-1>_l and <e^{ik rho}/rho>_n (Sec. 3.2)
 special   A_m(b) from its defining integral, eq. (3.26)
+banded    the O(M) route of Sec. 3.2.1: <rho^2>_n, the m0 rule of eq. (3.13)
+          and the banded system of eqs. (3.14)-(3.18), solved densely
 """
