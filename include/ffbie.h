@@ -53,8 +53,12 @@ enum {
   FFBIE_PAIR_REFINED = 4,         /* smooth factor not resolved by 2M samples; recomputed
                                      with 4M samples                                        */
   FFBIE_PAIR_UNRESOLVED = 8,      /* smooth factor not resolved even by 4M samples          */
-  FFBIE_PAIR_FAR = 16             /* b0 >= 3: the quadratic-model estimate (a0, b0), not a
+  FFBIE_PAIR_FAR = 16,            /* b0 >= 3: the quadratic-model estimate (a0, b0), not a
                                      Newton-refined root, parametrises the swap             */
+  FFBIE_PAIR_NOT_PD = 32          /* ffbie_rhoinv_banded: a pivot of the banded system's
+                                     L D L^H factorisation was not positive (the system is
+                                     Hermitian but not positive definite for this pair; the
+                                     sufficient condition of Lemma 3.4 does not hold)       */
 };
 /* Bits 8..19 of a pair's status word hold the truncation index p (eq. (3.24))
  * of the smooth factor used for its kernel coefficients: (status >> 8) & 0xfff. */
@@ -196,6 +200,41 @@ ffbie_status ffbie_kernel_coeffs_dl(ffbie_ctx *ctx, int64_t n_pairs,
                                     const double *d_tgt_t, const int32_t *d_tgt_az,
                                     const double *d_src_t, int adjoint,
                                     void *d_kappa, double *d_root, int32_t *d_pair_status);
+
+/* <rho^-1>_l, l = 0..L (L = M + M0), by the O(M) banded route of Sec. 3.2.1:
+ * an alternative to the singularity swap of ffbie_kernel_coeffs for the same
+ * coefficients.  For each pair, with m0 the truncation index of eq. (3.13):
+ *   - <rho^2>_n, n = 0..m0, from 64 equispaced samples of rho^2 (exact: rho^2
+ *     is a trigonometric polynomial in theta_s);
+ *   - the known values of eq. (3.16), <rho^-1>_l for l < m0 and l > L - m0, by
+ *     composite 16-point Gauss-Legendre quadrature graded towards the complex
+ *     root of rho^2 (Lemma 3.6) and fine enough for e^{-i L theta_s};
+ *   - the other L - 2 m0 + 1 coefficients from the Hermitian banded system of
+ *     eqs. (3.14)-(3.18), a_j(i) = (m0 + 2i + j) <rho^2>_{m0-j}, by an
+ *     unpivoted L D L^H factorisation (A is positive definite where eq. (3.19)
+ *     holds, Lemma 3.4).
+ * Pairs and inputs as for ffbie_kernel_coeffs.
+ *   m0           1..8, or 0 for eq. (3.13) over this call's pairs with the
+ *                discretisation's eps0 (the largest n <= deg with
+ *                max_pairs |<rho^2>_n| / <rho^2>_0 > eps0, at least 1), where
+ *                deg = max(2 m, m + 1) for the highest azimuthal order m of the
+ *                surface is the degree of rho^2 (1 for the sphere, Remark 3.5).
+ *                The automatic rule waits for the device (one stream
+ *                synchronisation).
+ *   d_rhoinv     [n_pairs][L+1] complex128, <rho^-1>_l at column l (required).
+ *   d_pair_status[n_pairs] int32 or NULL: the root kernel's FFBIE_PAIR_* bits
+ *                and FFBIE_PAIR_NOT_PD.
+ *   m0_used      host int or NULL: receives the m0 used.
+ * The call allocates device workspaces on first use and when n_pairs grows: 144
+ * bytes per pair and the factor records of a chunk of pairs (at most 2 GiB).
+ * A pair with t == t_s gets a NaN row and FFBIE_PAIR_SINGULAR.  Returns
+ * FFBIE_EINVAL for n_pairs < 0, m0 outside 0..8, m0 = 0 on a surface whose
+ * rho^2 has degree above 8, M + M0 < 4 m0, or NULL pointers; n_pairs == 0 is a
+ * no-op.  FP64 throughout. */
+ffbie_status ffbie_rhoinv_banded(ffbie_ctx *ctx, int64_t n_pairs,
+                                 const double *d_tgt_t, const int32_t *d_tgt_az,
+                                 const double *d_src_t, int m0, void *d_rhoinv,
+                                 int32_t *d_pair_status, int *m0_used);
 
 /* Device-side timing of the kernels ffbie_kernel_coeffs launches.  With
  * timing enabled, HIP events are recorded on the context's stream around the

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libffbie.so")
 
 FFBIE_OK = 0
 PAIR_SINGULAR, PAIR_ROOT_FALLBACK, PAIR_REFINED, PAIR_UNRESOLVED, PAIR_FAR = 1, 2, 4, 8, 16
+PAIR_NOT_PD = 32
 KAPPA_SWAP, KAPPA_PAPER_CONV = 0, 1
 
 EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_problem",
@@ -31,7 +32,7 @@ EXPORTS = ("ffbie_create", "ffbie_destroy", "ffbie_last_error", "ffbie_set_probl
            "ffbie_batch_plan_destroy", "ffbie_batch_plan_classes", "ffbie_gemm_sub",
            "ffbie_assembly_report", "ffbie_mlp_train", "ffbie_mlp_save", "ffbie_mlp_load",
            "ffbie_kernel_coeffs_noalloc", "ffbie_kernel_coeffs_dl", "ffbie_assemble_op",
-           "ffbie_eval_field_op", "ffbie_set_tuning_cache")
+           "ffbie_eval_field_op", "ffbie_set_tuning_cache", "ffbie_rhoinv_banded")
 SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES, SOLVE_FGMRES_MLP, SOLVE_GMRES_BLOCKJACOBI = 0, 1, 2, 3, 4
 SOLVE_GMRES_LU32, SOLVE_FGMRES_BJ_MLP = 5, 6
 MLP_IN, MLP_HIDDEN, MLP_OUT = 514, 256, 512
@@ -107,6 +108,7 @@ def load_library(path=LIB_PATH):
     lib.ffbie_kernel_coeffs_mixed.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     lib.ffbie_kernel_coeffs_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     lib.ffbie_kernel_coeffs_dl.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, vp]
+    lib.ffbie_rhoinv_banded.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, ctypes.POINTER(i32)]
     lib.ffbie_singular_factor.argtypes = [vp, i64, vp, i32, vp]
     lib.ffbie_enable_timing.argtypes = [vp, i32]
     dp = ctypes.POINTER(ctypes.c_double)
@@ -286,6 +288,32 @@ class Context:
         rc = self.lib.ffbie_kernel_coeffs_dl(self.h, n, _ptr(t), _ptr(az), _ptr(ts), int(adjoint),
                                              _ptr(out["kappa"]), _ptr(out["root"]), _ptr(out["status"]))
         self._check(rc, self.h)
+        return out
+
+    def rhoinv_banded(self, t, az, ts, m0=0, status=True, rhoinv=None):
+        """<rho^-1>_l, l = 0..M+M0, by the banded route of Sec. 3.2.1, as
+        rhoinv [n, M+M0+1] complex128; m0 = 0 applies the rule of eq. (3.13).
+        Returns dict(rhoinv, status, m0)."""
+        torch = self._torch
+        dev = self.device
+        t = t.to(dev, torch.float64).contiguous()
+        ts = ts.to(dev, torch.float64).contiguous()
+        az = az.to(dev, torch.int32).contiguous()
+        n = t.numel()
+        if az.numel() != n or ts.numel() != n:
+            raise FfbieError("t, az and ts must have the same length")
+        shape = (n, self.M + self.M0 + 1)
+        if rhoinv is not None and (rhoinv.dtype != torch.complex128 or tuple(rhoinv.shape) != shape
+                                   or not rhoinv.is_contiguous()):
+            raise FfbieError("rhoinv must be a contiguous [n, M+M0+1] complex128 tensor")
+        out = {"rhoinv": rhoinv if rhoinv is not None else
+               torch.empty(shape, dtype=torch.complex128, device=dev)}
+        out["status"] = torch.empty((n,), dtype=torch.int32, device=dev) if status else None
+        used = ctypes.c_int(-1)
+        rc = self.lib.ffbie_rhoinv_banded(self.h, n, _ptr(t), _ptr(az), _ptr(ts), int(m0),
+                                          _ptr(out["rhoinv"]), _ptr(out["status"]), ctypes.byref(used))
+        self._check(rc, self.h)
+        out["m0"] = used.value
         return out
 
     def _batch_items(self, problems, mixed=False):

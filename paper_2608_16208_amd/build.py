@@ -9,7 +9,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["csrc/ffbie_api.hip", "csrc/ffbie_kernels.hip", "csrc/ffbie_assembly.hip",
-           "csrc/ffbie_solve.hip", "csrc/ffbie_gemm.hip", "csrc/ffbie_mlp.hip", "csrc/ffbie_blockjacobi.hip"]
+           "csrc/ffbie_solve.hip", "csrc/ffbie_gemm.hip", "csrc/ffbie_mlp.hip", "csrc/ffbie_blockjacobi.hip",
+           "csrc/ffbie_banded.hip"]
 LIB = os.path.join(HERE, "libffbie.so")
 
 FLAGS = [

@@ -16,6 +16,7 @@
 #include "ffbie_assembly.hpp"
 #include "ffbie_blockjacobi.hpp"
 #include "ffbie_gemm.hpp"
+#include "ffbie_banded.hpp"
 #include "ffbie_kernels.hpp"
 #include "ffbie_mlp.hpp"
 #include "ffbie_solve.hpp"
@@ -129,6 +130,12 @@ struct ffbie_ctx {
   int64_t factored_n = 0;            // size of the LU64 factorisation held (ffbie_lu_factor)
   cplx* d_zbasis = nullptr;
   int64_t zbasis_n = 0;
+  // banded route (Sec. 3.2.1): <rho^2>_n per pair, the m0-rule maxima, factor records
+  cplx* d_band_c2 = nullptr;
+  int64_t band_c2_cap = 0;
+  unsigned long long* d_band_ratio = nullptr;
+  cplx* d_band_fac = nullptr;
+  int64_t band_fac_cap = 0;          // complex entries
   // flags of the near pairs of the last assembly
   unsigned long long* d_asm_counts = nullptr;
   int64_t asm_pairs = -1, asm_unresolved = -1, asm_fallback = -1;
@@ -385,6 +392,9 @@ ffbie_status ffbie_destroy(ffbie_ctx* c) {
                   (void*)c->d_tabs[3]})
     if (p) hipFree(p);
   if (c->d_zbasis) (void)hipFree(c->d_zbasis);
+  if (c->d_band_c2) (void)hipFree(c->d_band_c2);
+  if (c->d_band_ratio) (void)hipFree(c->d_band_ratio);
+  if (c->d_band_fac) (void)hipFree(c->d_band_fac);
   if (c->d_asm_counts) (void)hipFree(c->d_asm_counts);
   if (c->d_train_idx) (void)hipFree(c->d_train_idx);
   c->mlp.release();
@@ -1052,6 +1062,102 @@ ffbie_status ffbie_kernel_coeffs_dl(ffbie_ctx* c, int64_t n, const double* d_t, 
   if (n > (int64_t)1 << 31) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_dl: n_pairs > 2^31");
   FFBIE_HIP(c, hipSetDevice(c->device));
   return run_dl_coeffs(c, n, d_t, d_az, d_ts, adjoint, d_kappa, d_root, d_pair_status);
+}
+
+ffbie_status ffbie_rhoinv_banded(ffbie_ctx* c, int64_t n, const double* d_t, const int32_t* d_az,
+                                 const double* d_ts, int m0, void* d_rhoinv, int32_t* d_pair_status,
+                                 int* m0_used) {
+  static const char* fn = "ffbie_rhoinv_banded: ";
+  if (!c) return FFBIE_EINVAL;
+  if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, std::string(fn) + "no problem set");
+  if (n < 0) return fail(c, FFBIE_EINVAL, std::string(fn) + "n_pairs < 0");
+  if (m0 < 0 || m0 > kBandMaxM0) return fail(c, FFBIE_EINVAL, std::string(fn) + "need 0 <= m0 <= 8");
+  const Prob& P = c->prob;
+  const int deg = rho2_degree(P.g);
+  if (m0 == 0 && deg > kBandMaxM0)
+    return fail(c, FFBIE_EINVAL, std::string(fn) + "rho^2 has degree " + std::to_string(deg) +
+                                     " > 8 in the azimuth: pass m0 explicitly");
+  const int m0_cap = m0 ? m0 : deg;
+  if (P.L < 4 * m0_cap)
+    return fail(c, FFBIE_EINVAL, std::string(fn) + "M + M0 must be at least 4 m0");
+  if (m0_used) *m0_used = m0;
+  if (n == 0) return FFBIE_OK;
+  if (!d_t || !d_az || !d_ts || !d_rhoinv)
+    return fail(c, FFBIE_EINVAL, std::string(fn) + "NULL input or output pointer");
+  if (n > (int64_t)1 << 31) return fail(c, FFBIE_EINVAL, std::string(fn) + "n_pairs > 2^31");
+  FFBIE_HIP(c, hipSetDevice(c->device));
+  ffbie_status s = ensure_ws(c, n);
+  if (s != FFBIE_OK) return s;
+  if (n > c->band_c2_cap) {
+    if (c->d_band_c2) hipFree(c->d_band_c2);
+    c->d_band_c2 = nullptr;
+    c->band_c2_cap = 0;
+    if (hipMalloc(&c->d_band_c2, n * kBandC2 * sizeof(cplx)) != hipSuccess)
+      return fail(c, FFBIE_ENOMEM, std::string(fn) + "workspace allocation failed");
+    c->band_c2_cap = n;
+  }
+  if (!c->d_band_ratio &&
+      hipMalloc(&c->d_band_ratio, kBandC2 * sizeof(unsigned long long)) != hipSuccess) {
+    c->d_band_ratio = nullptr;
+    return fail(c, FFBIE_ENOMEM, std::string(fn) + "workspace allocation failed");
+  }
+  int32_t* status = d_pair_status ? d_pair_status : c->d_status;
+  FFBIE_HIP(c, launch_root(P, c->d_tab, n, d_t, d_az, d_ts, c->d_roots, status, nullptr, c->stream));
+  BandArgs a{};
+  a.P = P;
+  a.tab_g = c->d_tab;
+  a.n = n;
+  a.t_in = d_t;
+  a.az_in = d_az;
+  a.ts_in = d_ts;
+  a.roots = c->d_roots;
+  a.status = status;
+  a.c2 = c->d_band_c2;
+  a.ratio = c->d_band_ratio;
+  a.rhoinv = static_cast<cplx*>(d_rhoinv);
+  for (int q = 0; q < kNodes; ++q) { a.gl_x[q] = c->gl_x[q]; a.gl_w[q] = c->gl_w[q]; }
+  FFBIE_HIP(c, launch_zero(reinterpret_cast<int*>(c->d_band_ratio), 2 * kBandC2, c->stream));
+  FFBIE_HIP(c, launch_band_rho2(a, c->stream));
+  if (m0 == 0) {
+    // eq. (3.13) over this call's pairs, capped at the degree of rho^2 (the
+    // coefficients above it vanish; only the transform's rounding shows there)
+    unsigned long long bits[kBandC2];
+    FFBIE_HIP(c, hipMemcpyAsync(bits, c->d_band_ratio, sizeof(bits), hipMemcpyDeviceToHost,
+                                c->stream));
+    FFBIE_HIP(c, hipStreamSynchronize(c->stream));
+    m0 = 1;
+    for (int q = 1; q <= deg; ++q) {
+      double r;
+      std::memcpy(&r, &bits[q], sizeof(r));
+      if (r > P.eps0) m0 = q;
+    }
+    if (m0_used) *m0_used = m0;
+  }
+  a.m0 = m0;
+  FFBIE_HIP(c, launch_band_moments(a, c->stream));
+  // factor records: (M1 + 1) rows of m0 + 1 complex values per pair, pairs in
+  // chunks of at most 2 GiB of records
+  const int64_t rows = P.L - 2 * m0 + 1;
+  const int64_t per_pair = rows * (m0 + 1);
+  int64_t chunk = ((int64_t)1 << 31) / (int64_t)(per_pair * sizeof(cplx));
+  chunk = std::max<int64_t>(64, chunk / 64 * 64);
+  chunk = std::min<int64_t>(chunk, (n + 63) / 64 * 64);
+  if (chunk * per_pair > c->band_fac_cap) {
+    if (c->d_band_fac) hipFree(c->d_band_fac);
+    c->d_band_fac = nullptr;
+    c->band_fac_cap = 0;
+    if (hipMalloc(&c->d_band_fac, chunk * per_pair * sizeof(cplx)) != hipSuccess)
+      return fail(c, FFBIE_ENOMEM, std::string(fn) + "factor workspace allocation failed");
+    c->band_fac_cap = chunk * per_pair;
+  }
+  a.fac = c->d_band_fac;
+  a.stride = chunk;
+  for (int64_t c0 = 0; c0 < n; c0 += chunk) {
+    a.chunk0 = c0;
+    a.chunk_n = std::min<int64_t>(chunk, n - c0);
+    FFBIE_HIP(c, launch_band_solve(a, c->stream));
+  }
+  return FFBIE_OK;
 }
 
 ffbie_status ffbie_builtin_near_rule(ffbie_near_rule* out) {
