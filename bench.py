@@ -313,6 +313,63 @@ def double_layer_block(ctx, cfg, torch, np, ffbie, tt, jj, tss, kappa, steps=3, 
     return out
 
 
+def banded_block(ctx, cfg, torch, np, ffbie, tt, jj, tss, kappa, steps=3, sample=1 << 18):
+    """The O(M) banded route to <rho^-1>_l of Sec. 3.2.1 (ffbie_rhoinv_banded)
+    next to the swap path emitting the same table (ffbie_kernel_coeffs with
+    <rho^-1>): the config-2 all-pairs launch (M = M0 = 64, m0 by the rule of
+    eq. (3.13)), its largest row difference from the swap path, and the
+    crossover study the paper leaves out: ms per call of both routes on a
+    seeded sample of config-2 pairs (30 % near pairs) at M = 16 .. 128."""
+    import workloads
+    n = tt.numel()
+    M = cfg["M"]
+    dev = tt.device
+    ctx.set_problem(cfg["amp"], cfg["n_panels"], M, cfg["k"])
+    band = torch.empty((n, 2 * M + 1), dtype=torch.complex128, device=dev)
+    out = ctx.rhoinv_banded(tt, jj, tss, rhoinv=band)
+    m0 = out["m0"]
+    _, dt = _timed(torch, lambda: [ctx.rhoinv_banded(tt, jj, tss, rhoinv=band) for _ in range(steps)])
+    st = out["status"].cpu().numpy()
+    ref = torch.empty_like(band)
+    ctx.kernel_coeffs(tt, jj, tss, kappa=kappa, rhoinv_out=ref, status=False)
+    _, dt_s = _timed(torch, lambda: [ctx.kernel_coeffs(tt, jj, tss, kappa=kappa, rhoinv_out=ref, status=False)
+                                     for _ in range(steps)])
+    worst = 0.0
+    for a in range(0, n, 1 << 20):
+        d = (torch.amax(torch.abs(band[a:a + (1 << 20)] - ref[a:a + (1 << 20)]), dim=1)
+             / torch.amax(torch.abs(ref[a:a + (1 << 20)]), dim=1))
+        worst = max(worst, float(d.max().item()))
+    del band, ref
+    torch.cuda.empty_cache()
+    res = {"workload": "config 2, all %d pairs, M = M0 = %d, L = %d" % (n, M, 2 * M), "m0": m0,
+           "ms_per_call": 1e3 * dt / steps, "rhoinv_coeffs_per_s": n * (2 * M + 1) * steps / dt,
+           "swap_with_rhoinv_ms_per_call": 1e3 * dt_s / steps, "ratio_banded_to_swap": dt / dt_s,
+           "max_row_rel_diff_vs_swap": worst,
+           "not_positive_definite_pairs": int(((st & ffbie.PAIR_NOT_PD) > 0).sum())}
+    cross = []
+    for Mx in (16, 32, 64, 128):
+        t, j, ts = workloads.sample_pairs(cfg["n_panels"], Mx, sample, seed=1)
+        a_t, a_j, a_ts = (torch.tensor(v, device=dev) for v in (t, j, ts))
+        ctx.set_problem(cfg["amp"], cfg["n_panels"], Mx, cfg["k"])
+        rb = torch.empty((sample, 2 * Mx + 1), dtype=torch.complex128, device=dev)
+        rs = torch.empty_like(rb)
+        kx = torch.empty((sample, 2 * Mx), dtype=torch.complex128, device=dev)
+        ctx.rhoinv_banded(a_t, a_j, a_ts, rhoinv=rb)
+        _, tb = _timed(torch, lambda: [ctx.rhoinv_banded(a_t, a_j, a_ts, rhoinv=rb) for _ in range(5)])
+        so = ctx.kernel_coeffs(a_t, a_j, a_ts, kappa=kx, rhoinv_out=rs)
+        _, tsw = _timed(torch, lambda: [ctx.kernel_coeffs(a_t, a_j, a_ts, kappa=kx, rhoinv_out=rs,
+                                                          status=False) for _ in range(5)])
+        sst = so["status"].cpu().numpy()
+        cross.append({"M": Mx, "pairs": sample, "banded_ms": 1e3 * tb / 5, "swap_with_rhoinv_ms": 1e3 * tsw / 5,
+                      "ratio_banded_to_swap": tb / tsw,
+                      "swap_refined": int(((sst & ffbie.PAIR_REFINED) > 0).sum()),
+                      "swap_unresolved": int(((sst & ffbie.PAIR_UNRESOLVED) > 0).sum())})
+        del rb, rs, kx
+    res["crossover"] = cross
+    ctx.set_problem(cfg["amp"], cfg["n_panels"], M, cfg["k"])
+    return res
+
+
 def config3_block(ctx, torch, np, ffbie, solve=True):
     """Config 3: the star surface with 20 seeded amplitudes U(-0.1, 0.1), k = 20,
     32 panels, M = 128.
@@ -576,6 +633,8 @@ def main():
                     help="skip the config-3 block (near-set coefficients at M = 128, FP64 and mixed, "
                          "and the N = 65536 solves)")
     ap.add_argument("--no-ceilings", action="store_true", help="skip the plain-kernel HBM ceilings")
+    ap.add_argument("--no-banded", action="store_true",
+                    help="skip the O(M) banded <rho^-1> route and its crossover study")
     ap.add_argument("--no-double-layer", action="store_true",
                     help="skip the double-layer block (K and K' coefficients, second-kind solve)")
     ap.add_argument("--no-batch", action="store_true",
@@ -763,6 +822,9 @@ def main():
         result["double_layer"] = double_layer_block(ctx, cfg, torch, np, ffbie, tt, jj, tss, kappa,
                                                     solve=not args.no_solve)
         log("double-layer block done")
+    if not args.no_banded:
+        result["banded_rhoinv"] = banded_block(ctx, cfg, torch, np, ffbie, tt, jj, tss, kappa)
+        log("banded block done")
     del kappa, tt, jj, tss, status
     torch.cuda.empty_cache()
     if not args.no_solve:

@@ -226,7 +226,7 @@ ffbie_status ffbie_kernel_coeffs_dl(ffbie_ctx *ctx, int64_t n_pairs,
  *                and FFBIE_PAIR_NOT_PD.
  *   m0_used      host int or NULL: receives the m0 used.
  * The call allocates device workspaces on first use and when n_pairs grows: 144
- * bytes per pair and the factor records of a chunk of pairs (at most 2 GiB).
+ * bytes per pair and the factor records of a chunk of pairs (at most 4 GiB).
  * A pair with t == t_s gets a NaN row and FFBIE_PAIR_SINGULAR.  Returns
  * FFBIE_EINVAL for n_pairs < 0, m0 outside 0..8, m0 = 0 on a surface whose
  * rho^2 has degree above 8, M + M0 < 4 m0, or NULL pointers; n_pairs == 0 is a

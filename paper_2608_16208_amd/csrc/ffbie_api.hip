@@ -133,7 +133,7 @@ struct ffbie_ctx {
   // banded route (Sec. 3.2.1): <rho^2>_n per pair, the m0-rule maxima, factor records
   cplx* d_band_c2 = nullptr;
   int64_t band_c2_cap = 0;
-  unsigned long long* d_band_ratio = nullptr;
+  double* d_band_ratio = nullptr;     // [16384 + 1][9]: per-block maxima, then the maxima
   cplx* d_band_fac = nullptr;
   int64_t band_fac_cap = 0;          // complex entries
   // flags of the near pairs of the last assembly
@@ -1097,7 +1097,7 @@ ffbie_status ffbie_rhoinv_banded(ffbie_ctx* c, int64_t n, const double* d_t, con
     c->band_c2_cap = n;
   }
   if (!c->d_band_ratio &&
-      hipMalloc(&c->d_band_ratio, kBandC2 * sizeof(unsigned long long)) != hipSuccess) {
+      hipMalloc(&c->d_band_ratio, (16384 + 1) * kBandC2 * sizeof(double)) != hipSuccess) {
     c->d_band_ratio = nullptr;
     return fail(c, FFBIE_ENOMEM, std::string(fn) + "workspace allocation failed");
   }
@@ -1113,33 +1113,30 @@ ffbie_status ffbie_rhoinv_banded(ffbie_ctx* c, int64_t n, const double* d_t, con
   a.roots = c->d_roots;
   a.status = status;
   a.c2 = c->d_band_c2;
+  a.ratio_part = m0 == 0 ? c->d_band_ratio + kBandC2 : nullptr;
   a.ratio = c->d_band_ratio;
   a.rhoinv = static_cast<cplx*>(d_rhoinv);
   for (int q = 0; q < kNodes; ++q) { a.gl_x[q] = c->gl_x[q]; a.gl_w[q] = c->gl_w[q]; }
-  FFBIE_HIP(c, launch_zero(reinterpret_cast<int*>(c->d_band_ratio), 2 * kBandC2, c->stream));
   FFBIE_HIP(c, launch_band_rho2(a, c->stream));
   if (m0 == 0) {
     // eq. (3.13) over this call's pairs, capped at the degree of rho^2 (the
     // coefficients above it vanish; only the transform's rounding shows there)
-    unsigned long long bits[kBandC2];
-    FFBIE_HIP(c, hipMemcpyAsync(bits, c->d_band_ratio, sizeof(bits), hipMemcpyDeviceToHost,
+    double ratio[kBandC2];
+    FFBIE_HIP(c, hipMemcpyAsync(ratio, c->d_band_ratio, sizeof(ratio), hipMemcpyDeviceToHost,
                                 c->stream));
     FFBIE_HIP(c, hipStreamSynchronize(c->stream));
     m0 = 1;
-    for (int q = 1; q <= deg; ++q) {
-      double r;
-      std::memcpy(&r, &bits[q], sizeof(r));
-      if (r > P.eps0) m0 = q;
-    }
+    for (int q = 1; q <= deg; ++q)
+      if (ratio[q] > P.eps0) m0 = q;
     if (m0_used) *m0_used = m0;
   }
   a.m0 = m0;
   FFBIE_HIP(c, launch_band_moments(a, c->stream));
   // factor records: (M1 + 1) rows of m0 + 1 complex values per pair, pairs in
-  // chunks of at most 2 GiB of records
+  // chunks of at most 4 GiB of records
   const int64_t rows = P.L - 2 * m0 + 1;
   const int64_t per_pair = rows * (m0 + 1);
-  int64_t chunk = ((int64_t)1 << 31) / (int64_t)(per_pair * sizeof(cplx));
+  int64_t chunk = ((int64_t)1 << 32) / (int64_t)(per_pair * sizeof(cplx));
   chunk = std::max<int64_t>(64, chunk / 64 * 64);
   chunk = std::min<int64_t>(chunk, (n + 63) / 64 * 64);
   if (chunk * per_pair > c->band_fac_cap) {

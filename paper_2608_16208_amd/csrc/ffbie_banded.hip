@@ -9,16 +9,17 @@
 // banded system A x = b of eqs. (3.17)-(3.18),
 //   A_{rc} = (2 m0 + r + c) <rho^2>_{r-c},  |r - c| <= m0.
 // Three kernels:
-//  1. <rho^2>_n, n = 0..8, one pair per wavefront: rho^2 at 64 equispaced
-//     source azimuths (one per lane, exact for a polynomial of degree < 32),
-//     the transform by wavefront sums; the largest |<rho^2>_n| / <rho^2>_0
-//     over the call's pairs feeds the m0 rule of eq. (3.13).
+//  1. <rho^2>_n, n = 0..8: rho^2 at 16 equispaced source azimuths (exact
+//     while its degree is at most 7; 64 otherwise), one per lane, the
+//     transform by sums over the lanes of each pair; the largest
+//     |<rho^2>_n| / <rho^2>_0 over the call's pairs feeds the m0 rule of
+//     eq. (3.13).
 //  2. the 2 m0 known coefficients by composite 16-point Gauss-Legendre
 //     quadrature (the paper uses adaptive Gauss-Legendre), one pair per
 //     wavefront, 4 panels x 16 nodes per pass over the lanes.  The panels are
 //     graded geometrically (ratio 4) towards the real part a of the complex
 //     root of rho^2, from a first panel of length b (its imaginary part), and
-//     are at most 12 / L long elsewhere, so that e^{-i L theta} is integrated
+//     are at most 14 / L long elsewhere, so that e^{-i L theta} is integrated
 //     to rounding.
 //  3. the banded system, one pair per lane: a right-looking L D L^H
 //     factorisation with the (m0+1) x (m0+1) active window in registers, the
@@ -45,7 +46,7 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwoPi = 6.28318530717958647693;
-constexpr double kBandKappa = 6.0;   // panel half-length times the highest order
+constexpr double kBandKappa = 7.0;   // panel half-length times the highest order
 
 __device__ __forceinline__ void stage_table(double* tab, const double* __restrict__ tab_g, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) tab[i] = tab_g[i];
@@ -55,21 +56,41 @@ __device__ __forceinline__ void stage_table(double* tab, const double* __restric
 // ---------------------------------------------------------------------------
 // 1. <rho^2>_n
 // ---------------------------------------------------------------------------
-template <int MM>
+// Sum over each segment of NS lanes (16 or 64), returned to every lane of it.
+template <int NS>
+__device__ __forceinline__ double segment_sum(double v) {
+  if constexpr (NS == 64) {
+    return wave_sum(v);
+  } else {
+    v += dpp_zero<0x111>(v);   // row_shr:1
+    v += dpp_zero<0x112>(v);   // row_shr:2
+    v += dpp_zero<0x114>(v);   // row_shr:4
+    v += dpp_zero<0x118>(v);   // row_shr:8
+    return __shfl(v, (int)((threadIdx.x & 48) | 15), 64);
+  }
+}
+
+// NS samples per pair (16 while rho^2 has degree <= 7, else 64), 64 / NS pairs
+// per wavefront
+template <int MM, int NS>
 __global__ __launch_bounds__(256) void band_rho2_kernel(BandArgs a) {
   extern __shared__ double tab[];
   stage_table(tab, a.tab_g, a.P.tab_n);
+  constexpr int kPerWave = 64 / NS;
   const int lane = threadIdx.x & 63;
+  const int q = lane % NS, seg = lane / NS;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int mask = a.P.tab_n - 1, quarter = 2 * a.P.M;
-  const int Kq = lane * (a.P.M / 8);          // table index of 2 pi lane / 64
+  const int Kq = q * (8 * a.P.M / NS);        // table index of 2 pi q / NS
   const double nan = __builtin_nan("");
-  double worst = 0.0;                          // lane n: largest ratio at order n
-  for (int64_t i = wave; i < a.n; i += n_waves) {
+  double worst = 0.0;                          // lane n of a segment: largest ratio at order n
+  for (int64_t i0 = wave * kPerWave; i0 < a.n; i0 += n_waves * kPerWave) {
+    const int64_t i = i0 + seg;
+    if (i >= a.n) continue;                    // a whole segment: no lane of another is touched
     cplx* out = a.c2 + i * kBandC2;
     if (a.status[i] & FFBIE_PAIR_SINGULAR) {
-      if (lane < kBandC2) out[lane] = mk(nan, nan);
+      if (q < kBandC2) out[q] = mk(nan, nan);
       continue;
     }
     const int J = 4 * (a.az_in[i] & (2 * a.P.M - 1));
@@ -77,24 +98,51 @@ __global__ __launch_bounds__(256) void band_rho2_kernel(BandArgs a) {
     pair_geo<MM>(a.P.g, a.t_in[i], a.ts_in[i], tab, J, mask, quarter, &p);
     double dx, dy, dz;
     dr_grid<MM>(p, tab, Kq, J, mask, quarter, &dx, &dy, &dz);
-    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz)) * (1.0 / 64.0);
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz)) * (1.0 / NS);
     cplx mine = mk(0.0, 0.0);
     double c0 = 0.0;
 #pragma unroll
     for (int n = 0; n < kBandC2; ++n) {
       const int idx = n * Kq;
-      const double re = wave_sum(r2 * tab[(idx + quarter) & mask]);
-      const double im = -wave_sum(r2 * tab[idx & mask]);
+      const double re = segment_sum<NS>(r2 * tab[(idx + quarter) & mask]);
+      const double im = -segment_sum<NS>(r2 * tab[idx & mask]);
       if (n == 0) c0 = re;
-      if (lane == n) mine = mk(re, im);
+      if (q == n) mine = mk(re, im);
     }
-    if (lane < kBandC2) {
-      out[lane] = mine;
+    if (q < kBandC2) {
+      out[q] = mine;
       worst = fmax(worst, sqrt(abs2(mine)) / c0);
     }
   }
-  if (lane < kBandC2 && worst > 0.0)
-    atomicMax(a.ratio + lane, (unsigned long long)__double_as_longlong(worst));
+  if (!a.ratio_part) return;
+  // per-block maxima, no atomics: a reduction kernel combines the blocks
+  __shared__ double red[256 / NS][kBandC2];
+  const int segs = blockDim.x / NS, sb = threadIdx.x / NS;
+  if (q < kBandC2) red[sb][q] = worst;
+  __syncthreads();
+  if (threadIdx.x < kBandC2) {
+    double m = 0.0;
+    for (int w = 0; w < segs; ++w) m = fmax(m, red[w][threadIdx.x]);
+    a.ratio_part[(int64_t)blockIdx.x * kBandC2 + threadIdx.x] = m;
+  }
+}
+
+// ratio[n] = max over the blocks of ratio_part[b][n]
+__global__ __launch_bounds__(256) void band_ratio_reduce_kernel(const double* __restrict__ part,
+                                                                 int blocks, double* __restrict__ out) {
+  __shared__ double red[256];
+  for (int n = 0; n < kBandC2; ++n) {
+    double m = 0.0;
+    for (int b = threadIdx.x; b < blocks; b += blockDim.x) m = fmax(m, part[(int64_t)b * kBandC2 + n]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = red[0];
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -265,27 +313,23 @@ __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs a) {
       u = u + ((double)(M0T + 2 * rr + j) * C2(M0T - j)) * tail[r + j - 2 * M0T];
     bl[r] = mk(-u.re, -u.im);
   }
-  auto rhs = [&](int r) {
-    cplx v = mk(0.0, 0.0);
-#pragma unroll
-    for (int q = 0; q < M0T; ++q) {
-      if (r == q) v = v + bf[q];
-      if (r == N - M0T + q) v = v + bl[q];
-    }
-    return v;
-  };
   // active window: W[d][e] = current A_{i+d, i+e}, 0 <= e <= d <= m0, and the
-  // right-hand sides of rows i..i+m0
+  // right-hand sides of rows i..i+m0 (the first m0 rows all start in it)
   cplx W[M0T + 1][M0T + 1], bw[M0T + 1];
 #pragma unroll
   for (int d = 0; d <= M0T; ++d) {
 #pragma unroll
     for (int e = 0; e <= d; ++e)
-      W[d][e] = d < N ? (double)(2 * M0T + d + e) * C2(d - e) : mk(0.0, 0.0);
-    bw[d] = d < N ? rhs(d) : mk(0.0, 0.0);
+      W[d][e] = (double)(2 * M0T + d + e) * C2(d - e);
+    bw[d] = d < M0T ? bf[d] : mk(0.0, 0.0);
   }
   const int64_t S = a.stride;
   cplx* fac = a.fac + k;
+  // the last m0 rows enter the window during the sweep: their right-hand
+  // sides wait in the z slot of their own record, written only when the row
+  // becomes the pivot
+#pragma unroll
+  for (int q = 0; q < M0T; ++q) fac[(int64_t)(N - M0T + q) * (M0T + 1) * S] = bl[q];
   bool not_pd = false;
   for (int r = 0; r < N; ++r) {
     const double D = W[0][0].re;
@@ -316,7 +360,8 @@ __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs a) {
 #pragma unroll
     for (int e = 0; e <= M0T; ++e)
       W[M0T][e] = in ? (double)(M0T + 2 * rn + e) * C2(M0T - e) : mk(0.0, 0.0);
-    bw[M0T] = in ? rhs(rn) : mk(0.0, 0.0);
+    bw[M0T] = mk(0.0, 0.0);
+    if (in && rn >= N - M0T) bw[M0T] = fac[(int64_t)rn * (M0T + 1) * S];
   }
   // backward substitution L^H x = z: x_r = z_r - sum_d conj(l_d(r)) x_{r+d}
   cplx xw[M0T + 1];
@@ -347,17 +392,34 @@ int64_t wave_blocks(int64_t n) {
 
 #define FFBIE_BAND_MM(X) X(0) X(1) X(2) X(4) X(8)
 
+namespace {
+bool rho2_narrow(const BandArgs& a) { return rho2_degree(a.P.g) <= 7 && a.P.M >= 16; }
+}  // namespace
+
+int band_rho2_blocks(const BandArgs& a) {
+  return (int)wave_blocks(rho2_narrow(a) ? (a.n + 3) / 4 : a.n);
+}
+
 hipError_t launch_band_rho2(const BandArgs& a, hipStream_t s) {
   const size_t lds = a.P.tab_n * sizeof(double);
+  // 16 samples resolve a trigonometric polynomial of degree <= 7 exactly
+  const bool narrow = rho2_narrow(a);
+  const int blocks = band_rho2_blocks(a);
+  const dim3 grid((unsigned)blocks);
   switch (mm_of(a.P.g.mmax)) {
 #define X(MMV)                                                                                   \
   case MMV:                                                                                      \
-    hipLaunchKernelGGL(band_rho2_kernel<MMV>, dim3((unsigned)wave_blocks(a.n)), dim3(256), lds, s, \
-                       a);                                                                       \
+    if (narrow)                                                                                  \
+      hipLaunchKernelGGL((band_rho2_kernel<MMV, 16>), grid, dim3(256), lds, s, a);               \
+    else                                                                                         \
+      hipLaunchKernelGGL((band_rho2_kernel<MMV, 64>), grid, dim3(256), lds, s, a);               \
     break;
     FFBIE_BAND_MM(X)
 #undef X
   }
+  if (a.ratio_part)
+    hipLaunchKernelGGL(band_ratio_reduce_kernel, dim3(1), dim3(256), 0, s, a.ratio_part, blocks,
+                       a.ratio);
   return hipGetLastError();
 }
 
