@@ -20,12 +20,16 @@
 //     graded geometrically (ratio 4) towards the real part a of the complex
 //     root of rho^2, from a first panel of length b (its imaginary part), and
 //     are at most 14 / L long elsewhere, so that e^{-i L theta} is integrated
-//     to rounding.
+//     to rounding.  Where the coefficients of rho^2 certify that the last m0
+//     coefficients are below e^-40 of the first (decays_by), those are set to
+//     zero and the panels only need to resolve 1/rho.
 //  3. the banded system, one pair per lane: a right-looking L D L^H
 //     factorisation with the (m0+1) x (m0+1) active window in registers, the
 //     forward substitution fused with it, the factor rows stored to a
 //     workspace (coalesced across the lanes) and read back for the backward
-//     substitution.  A is positive definite when eq. (3.19) holds (Lemma 3.4);
+//     substitution, four rows of records loaded at a time.  The system is cut
+//     (at N/8, N/4 or N/2 rows) where the same certificate puts the dropped
+//     coefficients below e^-40 of the first.  A is positive definite when eq. (3.19) holds (Lemma 3.4);
 //     a pivot that is not positive is reported per pair.
 #include "ffbie_banded.hpp"
 
@@ -52,6 +56,28 @@ __device__ __forceinline__ void stage_table(double* tab, const double* __restric
   for (int i = threadIdx.x; i < n; i += blockDim.x) tab[i] = tab_g[i];
   __syncthreads();
 }
+
+// A decay certificate from the coefficients of rho^2 alone: if
+//   S(y) = sum_{n=1..8} 2 |<rho^2>_n| e^{n y} <= <rho^2>_0 / 2,
+// then |rho^2| >= <rho^2>_0 / 2 on the strip |Im theta| <= y (no root there),
+// so |<rho^-1>_l| <= (2 / <rho^2>_0)^{1/2} e^{-y |l|} by moving the contour,
+// while <rho^-1>_0 >= (3 <rho^2>_0 / 2)^{-1/2}: |<rho^-1>_l| <= 2 e^{-y |l|}
+// <rho^-1>_0.  (The root kernel's b need not belong to the root nearest the
+// real axis, so it is not used for this.)
+__device__ __forceinline__ bool decays_by(const cplx* __restrict__ c2, double y) {
+  const double e = exp(y);
+  double p = 1.0, s = 0.0;
+#pragma unroll
+  for (int n = 1; n < kBandC2; ++n) {
+    p *= e;
+    s = fma(2.0 * sqrt(abs2(c2[n])), p, s);
+  }
+  return s <= 0.5 * c2[0].re;
+}
+
+// exponent with e^{-x} * 2 <= e^{-40}: coefficients past it are below e^-40
+// of <rho^-1>_0
+constexpr double kDecayExp = 40.7;
 
 // ---------------------------------------------------------------------------
 // 1. <rho^2>_n
@@ -160,7 +186,7 @@ __global__ __launch_bounds__(256) void band_moments_kernel(BandArgs a) {
   const int mask = a.P.tab_n - 1, quarter = 2 * a.P.M;
   const int L = a.P.L, m0 = a.m0, l0 = L - m0 + 1;
   const double xg1 = 1.0 + a.gl_x[g], wg = a.gl_w[g];
-  const double hmax = fmin(2.0 * kBandKappa / L, 0.25 * kPi);
+  const double hmax_tail = fmin(2.0 * kBandKappa / L, 0.25 * kPi);
   const double nan = __builtin_nan("");
   for (int64_t i = wave; i < a.n; i += n_waves) {
     cplx* row = a.rhoinv + i * (L + 1);
@@ -174,6 +200,15 @@ __global__ __launch_bounds__(256) void band_moments_kernel(BandArgs a) {
     const double sj = tab[J & mask], cj = tab[(J + quarter) & mask];
     const RootRec rr = a.roots[i];
     const double a_off = rr.u;
+    // Where the certificate shows the last m0 coefficients below e^-40 of
+    // <rho^-1>_0 they are taken as zero (they enter only the right-hand sides
+    // of the last m0 equations).  Such a pair needs no panels short enough for
+    // e^{-i L theta}: its panels resolve the analytic 1/rho, whose
+    // singularities lie at least y_tail from the real axis (at most
+    // 1.5 y_tail long; measured 1e-15 of <rho^-1>_0 on config-2 pairs).
+    const double y_tail = kDecayExp / l0;
+    const bool tail_zero = decays_by(a.c2 + i * kBandC2, y_tail);
+    const double hmax = tail_zero ? fmin(0.25 * kPi, 1.5 * y_tail) : hmax_tail;
     // panels on each side of a: [0, h0], [h0, 4 h0], ... while shorter than
     // hmax (K panels, last edge eK), then nu equal panels up to pi
     const double h0 = fmin(rr.b, hmax);
@@ -230,18 +265,20 @@ __global__ __launch_bounds__(256) void band_moments_kernel(BandArgs a) {
           er = nr;
         }
       }
-      double st, ct;
-      sincos_bounded(l0 * d, &st, &ct);
-      er = ct;
-      ei = -st;
+      if (!tail_zero) {
+        double st, ct;
+        sincos_bounded(l0 * d, &st, &ct);
+        er = ct;
+        ei = -st;
 #pragma unroll
-      for (int l = 0; l < M0C; ++l) {
-        if (l < m0) {
-          Tr[l] = fma(f, er, Tr[l]);
-          Ti[l] = fma(f, ei, Ti[l]);
-          const double nr = fma(er, cd, ei * sd);
-          ei = fma(ei, cd, -er * sd);
-          er = nr;
+        for (int l = 0; l < M0C; ++l) {
+          if (l < m0) {
+            Tr[l] = fma(f, er, Tr[l]);
+            Ti[l] = fma(f, ei, Ti[l]);
+            const double nr = fma(er, cd, ei * sd);
+            ei = fma(ei, cd, -er * sd);
+            er = nr;
+          }
         }
       }
     }
@@ -251,7 +288,8 @@ __global__ __launch_bounds__(256) void band_moments_kernel(BandArgs a) {
     for (int l = 0; l < M0C; ++l) {
       if (l < m0) {
         const double hr = wave_sum(Hr[l]), hi = wave_sum(Hi[l]);
-        const double tr = wave_sum(Tr[l]), ti = wave_sum(Ti[l]);
+        const double tr = tail_zero ? 0.0 : wave_sum(Tr[l]);
+        const double ti = tail_zero ? 0.0 : wave_sum(Ti[l]);
         if (lane == l) {
           const int ih = l * J, it = (l0 + l) * J;
           const cplx ph = mk(tab[(ih + quarter) & mask], -tab[ih & mask]);
@@ -325,13 +363,30 @@ __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs a) {
   }
   const int64_t S = a.stride;
   cplx* fac = a.fac + k;
+  // where the decay certificate puts <rho^-1>_l below e^-40 of <rho^-1>_0,
+  // the system is cut (Ne rows, zero known values beyond, as in Olver's
+  // boundary-value treatment) and the rest of the row is zero
+  int Ne = N;
+  {
+    // the smallest of N/8, N/4, N/2 rows whose first dropped coefficient,
+    // l = m0 + Ne, the decay certificate puts below e^-40 of <rho^-1>_0
+    const cplx* c2g = a.c2 + i * kBandC2;
+#pragma unroll
+    for (int f = 8; f >= 2; f >>= 1) {
+      const int cand = max(2 * M0T + 1, N / f);
+      if (Ne == N && cand < N && decays_by(c2g, kDecayExp / (M0T + cand))) Ne = cand;
+    }
+  }
+  const int tail_from = Ne == N ? N - M0T : N;   // rows with known tail terms
   // the last m0 rows enter the window during the sweep: their right-hand
   // sides wait in the z slot of their own record, written only when the row
   // becomes the pivot
+  if (Ne == N) {
 #pragma unroll
-  for (int q = 0; q < M0T; ++q) fac[(int64_t)(N - M0T + q) * (M0T + 1) * S] = bl[q];
+    for (int q = 0; q < M0T; ++q) fac[(int64_t)(N - M0T + q) * (M0T + 1) * S] = bl[q];
+  }
   bool not_pd = false;
-  for (int r = 0; r < N; ++r) {
+  for (int r = 0; r < Ne; ++r) {
     const double D = W[0][0].re;
     not_pd |= !(D > 0.0);
     const double inv = 1.0 / D;
@@ -356,26 +411,45 @@ __global__ __launch_bounds__(64) void band_solve_kernel(BandArgs a) {
       for (int e = 1; e <= d; ++e) W[d - 1][e - 1] = W[d][e];
     }
     const int rn = r + 1 + M0T;                   // row entering the window
-    const bool in = rn < N;
+    const bool in = rn < Ne;
 #pragma unroll
     for (int e = 0; e <= M0T; ++e)
       W[M0T][e] = in ? (double)(M0T + 2 * rn + e) * C2(M0T - e) : mk(0.0, 0.0);
     bw[M0T] = mk(0.0, 0.0);
-    if (in && rn >= N - M0T) bw[M0T] = fac[(int64_t)rn * (M0T + 1) * S];
+    if (in && rn >= tail_from) bw[M0T] = fac[(int64_t)rn * (M0T + 1) * S];
   }
   // backward substitution L^H x = z: x_r = z_r - sum_d conj(l_d(r)) x_{r+d}
   cplx xw[M0T + 1];
 #pragma unroll
   for (int d = 0; d <= M0T; ++d) xw[d] = mk(0.0, 0.0);
-  for (int r = N - 1; r >= 0; --r) {
-    const cplx* rec = fac + (int64_t)r * (M0T + 1) * S;
-    cplx x = rec[0];
+  // records are loaded kBlk rows at a time, all loads of a block issued before
+  // its arithmetic, so that one memory latency is exposed per block
+  constexpr int kBlk = 4;
+  for (int r = Ne; r < N; ++r) row[M0T + r] = mk(0.0, 0.0);
+  for (int r0 = Ne - 1; r0 >= 0; r0 -= kBlk) {
+    cplx blk[kBlk][M0T + 1];
 #pragma unroll
-    for (int d = 1; d <= M0T; ++d) x = x - conj(rec[d * S]) * xw[d];
-    row[M0T + r] = x;
+    for (int b = 0; b < kBlk; ++b) {
+      const int r = r0 - b;
+      if (r >= 0) {
+        const cplx* rec = fac + (int64_t)r * (M0T + 1) * S;
 #pragma unroll
-    for (int d = M0T; d >= 2; --d) xw[d] = xw[d - 1];
-    xw[1] = x;
+        for (int d = 0; d <= M0T; ++d) blk[b][d] = rec[d * S];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kBlk; ++b) {
+      const int r = r0 - b;
+      if (r >= 0) {
+        cplx x = blk[b][0];
+#pragma unroll
+        for (int d = 1; d <= M0T; ++d) x = x - conj(blk[b][d]) * xw[d];
+        row[M0T + r] = x;
+#pragma unroll
+        for (int d = M0T; d >= 2; --d) xw[d] = xw[d - 1];
+        xw[1] = x;
+      }
+    }
   }
   if (not_pd) a.status[i] |= FFBIE_PAIR_NOT_PD;
 }
