@@ -434,9 +434,12 @@ ffbie_status ffbie_collocation(ffbie_ctx *ctx, double *d_xyz, double *d_jac, dou
  *     sound-soft exterior problem for the incident wave e^{ik d.x};
  *   FFBIE_RHS_PLANE_WAVE_DN: g = -d/d nu e^{ik d.x} = -ik (d . nu) e^{ik d.x}
  *     (nu the outward unit normal), the sound-hard exterior problem, whose
- *     second-kind equation (K' - I) phi = g is eq. (2.9) for (ENP).
+ *     second-kind equation (K' - I) phi = g is eq. (2.9) for (ENP);
+ *   FFBIE_RHS_POINT_SOURCE_DN: g = d/d nu G(x; p), the interior Neumann test
+ *     of Sec. 5 (exact interior field G(.; p) when p is outside the surface).
  * params is a HOST pointer to 3 doubles. */
-enum { FFBIE_RHS_POINT_SOURCE = 0, FFBIE_RHS_PLANE_WAVE = 1, FFBIE_RHS_PLANE_WAVE_DN = 2 };
+enum { FFBIE_RHS_POINT_SOURCE = 0, FFBIE_RHS_PLANE_WAVE = 1, FFBIE_RHS_PLANE_WAVE_DN = 2,
+       FFBIE_RHS_POINT_SOURCE_DN = 3 };
 ffbie_status ffbie_rhs(ffbie_ctx *ctx, int kind, const double *params, void *d_g);
 
 /* Assemble the N x N matrix S of the discretised single-layer equation

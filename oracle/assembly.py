@@ -222,6 +222,19 @@ def rhs_plane_wave_dn(amp, n_panels, M, k, d):
     return -1j * k * (nu @ np.asarray(d)) * np.exp(1j * k * (x @ np.asarray(d)))
 
 
+def rhs_point_source_dn(amp, n_panels, M, k, p):
+    """d/d nu G(x; p) on the collocation points, G = e^{ik rho} / (4 pi rho):
+    dG/drho (x - p) . nu / rho with dG/drho = e^{ik rho} (ik rho - 1) / (4 pi rho^2)
+    (the interior Neumann test of Sec. 5)."""
+    x, _, _ = collocation(amp, n_panels, M)
+    L = layout(n_panels, M)
+    nu = geo.normal(amp, L["t"], L["th"])
+    d = x - np.asarray(p)
+    rho = np.linalg.norm(d, axis=1)
+    dGdr = np.exp(1j * k * rho) * (1j * k * rho - 1.0) / (4 * np.pi * rho ** 2)
+    return dGdr * np.einsum("nc,nc->n", d, nu) / rho
+
+
 def field(amp, n_panels, M, k, phi, pts):
     x, _, wq = collocation(amp, n_panels, M)
     pts = np.atleast_2d(pts)

@@ -37,7 +37,7 @@ SOLVE_LU64, SOLVE_LU32_IR64, SOLVE_GMRES, SOLVE_FGMRES_MLP, SOLVE_GMRES_BLOCKJAC
 SOLVE_GMRES_LU32, SOLVE_FGMRES_BJ_MLP = 5, 6
 MLP_IN, MLP_HIDDEN, MLP_OUT = 514, 256, 512
 WNOTCONV, WUNRESOLVED = 2, 3
-RHS_POINT_SOURCE, RHS_PLANE_WAVE, RHS_PLANE_WAVE_DN = 0, 1, 2
+RHS_POINT_SOURCE, RHS_PLANE_WAVE, RHS_PLANE_WAVE_DN, RHS_POINT_SOURCE_DN = 0, 1, 2, 3
 OP_S, OP_K, OP_KP = 0, 1, 2
 UNKNOWN_SCALED, UNKNOWN_DENSITY = 0, 1
 P_SHIFT = 8

@@ -1240,7 +1240,8 @@ ffbie_status ffbie_rhs(ffbie_ctx* c, int kind, const double* params, void* d_g) 
   if (!c) return FFBIE_EINVAL;
   if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_rhs: no problem set");
   if (!params || !d_g) return fail(c, FFBIE_EINVAL, "ffbie_rhs: NULL pointer");
-  if (kind != FFBIE_RHS_POINT_SOURCE && kind != FFBIE_RHS_PLANE_WAVE && kind != FFBIE_RHS_PLANE_WAVE_DN)
+  if (kind != FFBIE_RHS_POINT_SOURCE && kind != FFBIE_RHS_PLANE_WAVE && kind != FFBIE_RHS_PLANE_WAVE_DN &&
+      kind != FFBIE_RHS_POINT_SOURCE_DN)
     return fail(c, FFBIE_EINVAL, "ffbie_rhs: unknown kind");
   for (int i = 0; i < 3; ++i)
     if (!std::isfinite(params[i])) return fail(c, FFBIE_EINVAL, "ffbie_rhs: non-finite parameter");

@@ -376,6 +376,16 @@ __global__ __launch_bounds__(256) void rhs_kernel(SysDims d, double k, int kind,
     double s, co;
     sincos_bounded(ph, &s, &co);
     g[r] = mk(-co, -s);
+  } else if (kind == FFBIE_RHS_POINT_SOURCE_DN) {
+    // d/d nu G(x; p) = e^{ik rho} (ik rho - 1) / (4 pi rho^2) * ((x - p) . nu) / rho
+    const double dx = c.x[r] - p0, dy = c.y[r] - p1, dz = c.z[r] - p2;
+    const double rho = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
+    double s, co;
+    sincos_bounded(k * rho, &s, &co);
+    const double dn = fma(dx, c.nx[r], fma(dy, c.ny[r], dz * c.nz[r])) / rho;
+    const double f = dn / (4.0 * M_PI * rho * rho);
+    const double kr = k * rho;
+    g[r] = mk(f * (-co - kr * s), f * fma(kr, co, -s));
   } else {
     // -d/d nu e^{ik d.x} = -ik (d . nu) e^{ik d.x}
     const double ph = k * (p0 * c.x[r] + p1 * c.y[r] + p2 * c.z[r]);

@@ -99,6 +99,10 @@ def test_sound_hard_rhs_and_dl_field_match_oracle(ctx):
     g = ctx.rhs(ffbie.RHS_PLANE_WAVE_DN, cfg["d"]).cpu().numpy()
     ref = oasm.rhs_plane_wave_dn(cfg["amp"], cfg["n_panels"], cfg["M"], cfg["k"], cfg["d"])
     assert np.max(np.abs(g - ref)) / np.max(np.abs(ref)) <= 1e-12     # normals: 1e-13 level
+    p_out = [3.0, 4.0, 10.5]
+    g = ctx.rhs(ffbie.RHS_POINT_SOURCE_DN, p_out).cpu().numpy()
+    ref = oasm.rhs_point_source_dn(cfg["amp"], cfg["n_panels"], cfg["M"], cfg["k"], p_out)
+    assert np.max(np.abs(g - ref)) / np.max(np.abs(ref)) <= 1e-12
     rng = np.random.default_rng(8)
     psi = rng.standard_normal(N) + 1j * rng.standard_normal(N)
     pts = _far_points(32, 9)

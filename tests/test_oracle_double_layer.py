@@ -197,3 +197,23 @@ def test_sound_hard_rhs_is_minus_normal_derivative():
     fd = (np.exp(1j * k * ((x + h * nu) @ dvec)) - np.exp(1j * k * ((x - h * nu) @ dvec))) / (2 * h)
     g = oasm.rhs_plane_wave_dn(amp, npan, M, k, dvec)
     assert np.max(np.abs(g + fd)) <= 1e-8
+
+
+def test_point_source_dn_rhs_is_normal_derivative():
+    """rhs_point_source_dn against a central difference of G(x; p) along the
+    normal at the collocation points (the interior Neumann test of Sec. 5)."""
+    amp = SMOOTH_AMP
+    npan, M, k = 2, 8, 2.5
+    p = np.array([3.0, 4.0, 10.5])
+    L = oasm.layout(npan, M)
+    x = geo.point(amp, L["t"], L["th"])
+    nu = geo.normal(amp, L["t"], L["th"])
+
+    def G(y):
+        r = np.linalg.norm(y - p, axis=1)
+        return np.exp(1j * k * r) / (4 * np.pi * r)
+
+    h = 1e-5
+    fd = (G(x + h * nu) - G(x - h * nu)) / (2 * h)
+    g = oasm.rhs_point_source_dn(amp, npan, M, k, p)
+    assert np.max(np.abs(g - fd)) <= 1e-9 * np.max(np.abs(g))
