@@ -370,6 +370,42 @@ def banded_block(ctx, cfg, torch, np, ffbie, tt, jj, tss, kappa, steps=3, sample
     return res
 
 
+def interior_protocol(ctx, torch, np, ffbie):
+    """The interior point-source protocol of Sec. 5 on the analytic star
+    surface of workloads.INTERIOR_AMP: (IDP) by S and by K - I, (INP) by
+    K' + I, LU64, E_j = ||u_num - u_exa||_2 / #(points) over 200 points of the
+    test ball, for the (k, N_p, 2M) rows of workloads.INTERIOR_ROWS.  The
+    paper's own surfaces (ellipsoid, bean, tori) are not star surfaces."""
+    import workloads
+    P = workloads.interior_test_points()
+    src = workloads.INTERIOR_SOURCE
+    pts = torch.tensor(P)
+    rows = []
+    ctx.set_near_rule(None)
+    for k, npan, M in workloads.INTERIOR_ROWS:
+        ctx.set_problem(workloads.INTERIOR_AMP, npan, M, k)
+        r = np.linalg.norm(P - src, axis=1)
+        exact = np.exp(1j * k * r) / (4 * np.pi * r)
+        gD = ctx.rhs(ffbie.RHS_POINT_SOURCE, list(src))
+        gN = ctx.rhs(ffbie.RHS_POINT_SOURCE_DN, list(src))
+        rec = {"k": k, "N_p": npan, "2M": 2 * M, "N": 32 * M * npan}
+        t0 = time.perf_counter()
+        for name, op, shift, unk, g, fop in (("S", ffbie.OP_S, 0.0, ffbie.UNKNOWN_SCALED, gD, ffbie.OP_S),
+                                             ("K", ffbie.OP_K, -1.0, ffbie.UNKNOWN_DENSITY, gD, ffbie.OP_K),
+                                             ("K'", ffbie.OP_KP, 1.0, ffbie.UNKNOWN_DENSITY, gN, ffbie.OP_S)):
+            A = ctx.assemble(op=op, shift=shift, unknowns=unk)
+            x, _ = ctx.solve(A, g, method=ffbie.SOLVE_LU64)
+            u = ctx.eval_field(pts, x, op=fop, unknowns=unk).cpu().numpy()
+            rec["E_" + name] = float(np.linalg.norm(u - exact) / len(exact))
+            del A
+            torch.cuda.empty_cache()
+        torch.cuda.synchronize()
+        rec["wall_s"] = time.perf_counter() - t0
+        rows.append(rec)
+    return {"surface": "R = 1 + 0.2 sin t cos(theta) + 0.1 sin 2t cos(theta), r* = (3, 4, 10.5), "
+                       "Omega_T = ball((0, -0.2, 0.1), 0.2), 200 points", "rows": rows}
+
+
 def config3_block(ctx, torch, np, ffbie, solve=True):
     """Config 3: the star surface with 20 seeded amplitudes U(-0.1, 0.1), k = 20,
     32 panels, M = 128.
@@ -831,6 +867,8 @@ def main():
         result["time_to_1e-8_field_error"] = time_to_field_error(ctx, cfg, torch, np, ffbie)
         result["near_set"] = near_set_rate(ctx, cfg, torch)
         log("config-2 solves done")
+        result["interior_protocol"] = interior_protocol(ctx, torch, np, ffbie)
+        log("interior protocol done")
     if not args.no_config3:
         result["config3"] = config3_block(ctx, torch, np, ffbie, solve=not args.no_solve)
         log("config-3 block done")

@@ -106,6 +106,25 @@ def learned_surface(i, held_out=False):
                 seed=(2000 if held_out else 1000) + i)
 
 
+# The interior point-source protocol of Sec. 5 on an analytic star surface
+# (azimuthal order 1 keeps the poles smooth): R = 1 + 0.2 sin t cos(theta) +
+# 0.1 sin(2t) cos(theta).  Source r* = (3, 4, 10.5) outside; the test region
+# is the ball |r - (0, -0.2, 0.1)| < 0.2 of the paper's Example 1, sampled at
+# seeded points; (k, n_panels, M) follow the paper's (k, N_p, 2M) rows with the
+# nearest supported M.
+INTERIOR_AMP = np.array([[0.0, 0.2], [0.0, 0.1]])
+INTERIOR_SOURCE = np.array([3.0, 4.0, 10.5])
+INTERIOR_ROWS = ((1.0, 4, 16), (2.0, 4, 16), (4.0, 4, 16), (8.0, 8, 32), (16.0, 16, 64))
+
+
+def interior_test_points(n=200, seed=5, center=(0.0, -0.2, 0.1), radius=0.2):
+    """Seeded points uniform in the test ball Omega_T."""
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    return np.asarray(center) + radius * d * rng.uniform(0.0, 1.0, n)[:, None] ** (1.0 / 3.0)
+
+
 def all_pairs(n_panels, M, length=math.pi):
     """Every (target node, target azimuth, source curve node) with t_s != t.
 
