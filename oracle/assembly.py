@@ -119,7 +119,7 @@ def near_kappa(amp, k, M, n_panels, rows, tab, processes=None, kind="S"):
     coefficients at azimuth j are those at azimuth 0 times e^{-i n theta_j}
     (rotation invariance, the axisymmetric relation of Remark 3.5)."""
     L = layout(n_panels, M)
-    axisym = amp is None or not np.any(amp)
+    axisym = geo.is_axisymmetric(amp)
     keys, T, J, TS = [], [], [], []
     for r in rows:
         i, l, j = int(L["i"][r]), int(L["l"][r]), int(L["j"][r])

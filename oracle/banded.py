@@ -44,11 +44,14 @@ def rho2_coeffs(amp, t, th, ts, n_max, n_fft=64):
 def degree_bound(amp):
     """Degree in theta_s of rho^2 for the star family: R(t_s, .) has degree
     mmax, rho^2 = R^2 + R_s^2 - 2 R R_s (sin t sin t_s cos(theta_s - theta)
-    + cos t cos t_s)."""
+    + cos t cos t_s).  Stretched by D = diag(d) with d_x != d_y, the term
+    R_s^2 (d_x^2 cos^2 theta_s + d_y^2 sin^2 theta_s) sin^2 t_s keeps its
+    cos(2 theta_s) part: degree 2 mmax + 2."""
     a = geo.as_amp(amp)
-    if a.size == 0 or not np.any(a):
-        return 1
-    mmax = max(m for m in range(a.shape[1]) if np.any(a[:, m] != 0.0))
+    d = geo.axes_of(amp)
+    mmax = max([m for m in range(a.shape[1]) if np.any(a[:, m] != 0.0)], default=0) if a.size else 0
+    if d[0] != d[1]:
+        return 2 * mmax + 2
     return max(2 * mmax, mmax + 1)
 
 

@@ -1,4 +1,5 @@
-"""Star-family surfaces and the cancellation-free point difference (oracle).
+"""Star-family surfaces (optionally stretched along the axes) and the
+cancellation-free point difference (oracle).
 
 Surface (Sec. 2, eq. (2.1)): the paper's parametrisation r(t, theta) with
 t in [0, L] along a generating curve and theta the 2*pi-periodic azimuth.  The
@@ -28,8 +29,35 @@ def _gl01(n):
     return _LAM_CACHE[n]
 
 
+class Scaled:
+    """A star surface stretched along the coordinate axes (the ellipsoid of
+    Sec. 5, Example 1, is the unit sphere with axes (1, 2, 3)):
+        r(t, theta) = D R(t, theta) omega(t, theta),  D = diag(axes).
+    Every function of this module takes either a plain amplitude table or a
+    Scaled surface."""
+
+    def __init__(self, amp, axes):
+        self.amp = as_amp(amp)
+        self.axes = np.asarray(axes, dtype=np.float64).reshape(3)
+        if not np.all(self.axes > 0):
+            raise ValueError("axes must be positive")
+
+
+def axes_of(surface):
+    """The stretch D of a surface (ones for a plain amplitude table)."""
+    return surface.axes if isinstance(surface, Scaled) else np.ones(3)
+
+
+def is_axisymmetric(surface):
+    """Rotation-invariant about the z axis: no amplitudes and equal x, y axes."""
+    a, d = as_amp(surface), axes_of(surface)
+    return not np.any(a) and d[0] == d[1]
+
+
 def as_amp(amp):
     """Amplitude table as a float64 array of shape (lmax, mmax+1)."""
+    if isinstance(amp, Scaled):
+        return amp.amp
     if amp is None:
         return np.zeros((0, 1))
     a = np.asarray(amp, dtype=np.float64)
@@ -68,17 +96,18 @@ def _omega(t, th, dt=0, dth=0):
 
 def point(amp, t, th):
     """r(t, theta), shape (..., 3)."""
-    return radius(amp, t, th)[..., None] * _omega(t, th)
+    return axes_of(amp) * (radius(amp, t, th)[..., None] * _omega(t, th))
 
 
 def derivs(amp, t, th):
     """(r_t, r_theta) at (t, theta), each shape (..., 3)."""
+    D = axes_of(amp)
     R = radius(amp, t, th)[..., None]
     Rt = radius(amp, t, th, dt=1)[..., None]
     Rth = radius(amp, t, th, dth=1)[..., None]
     rt = Rt * _omega(t, th) + R * _omega(t, th, dt=1)
     rth = Rth * _omega(t, th) + R * _omega(t, th, dth=1)
-    return rt, rth
+    return D * rt, D * rth
 
 
 def second_theta(amp, t, th):
@@ -86,8 +115,8 @@ def second_theta(amp, t, th):
     R = radius(amp, t, th)[..., None]
     Rth = radius(amp, t, th, dth=1)[..., None]
     Rthth = radius(amp, t, th, dth=2)[..., None]
-    return (Rthth * _omega(t, th) + 2.0 * Rth * _omega(t, th, dth=1)
-            + R * _omega(t, th, dth=2))
+    return axes_of(amp) * (Rthth * _omega(t, th) + 2.0 * Rth * _omega(t, th, dth=1)
+                           + R * _omega(t, th, dth=2))
 
 
 def second_derivs(amp, t, th):
@@ -102,7 +131,8 @@ def second_derivs(amp, t, th):
     rtt = Rtt * w + 2.0 * Rt * wt + R * _omega(t, th, dt=2)
     rtth = Rtth * w + Rt * wth + Rth * wt + R * _omega(t, th, dt=1, dth=1)
     rthth = Rthth * w + 2.0 * Rth * wth + R * _omega(t, th, dth=2)
-    return rtt, rtth, rthth
+    D = axes_of(amp)
+    return D * rtt, D * rtth, D * rthth
 
 
 def jacobian(amp, t, th):
