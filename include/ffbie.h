@@ -78,15 +78,25 @@ typedef struct ffbie_ctx ffbie_ctx;
 
 /* Surface of the star family, a radial perturbation of the unit sphere in the
  * parametrisation of Sec. 2, eq. (2.1), with t in [0, pi] (polar angle) and
- * theta the azimuth:
- *   r(t, theta) = R(t, theta) (sin t cos theta, sin t sin theta, cos t),
- *   R(t, theta) = 1 + sum_{l=1..lmax} sum_{m=0..mmax} a[(l-1)(mmax+1) + m] sin(l t) cos(m theta).
- * lmax = 0 gives the unit sphere.  `a` is a HOST pointer, row-major
- * [lmax][mmax+1], copied by ffbie_set_problem.  Limits: lmax <= 8, mmax <= 8. */
+ * theta the azimuth, optionally stretched along the coordinate axes:
+ *   r(t, theta) = D R(t, theta) (sin t cos theta, sin t sin theta, cos t),
+ *   R(t, theta) = 1 + sum_{l=1..lmax} sum_{m=0..mmax} a[(l-1)(mmax+1) + m] sin(l t) cos(m theta),
+ *   D = diag(axes[0], axes[1], axes[2]).
+ * lmax = 0 gives the unit sphere; lmax = 0 with axes (1, 2, 3) the ellipsoid
+ * x^2 + y^2/4 + z^2/9 = 1 of Sec. 5, Example 1.  `a` and `axes` are HOST
+ * pointers copied by ffbie_set_problem; `a` is row-major [lmax][mmax+1];
+ * axes NULL means (1, 1, 1), otherwise three positive finite values.  Limits:
+ * lmax <= 8, mmax <= 8.  Stretched surfaces run the FP64 single-problem path
+ * (ffbie_kernel_coeffs, _noalloc, the S operator of the assembly, the
+ * solvers and the fields); the double-layer coefficients (ffbie_kernel_coeffs_dl
+ * and the K, K' operators of ffbie_assemble_op), the mixed-precision path, the
+ * batch plans and ffbie_rhoinv_banded take unstretched surfaces only
+ * (FFBIE_EINVAL otherwise). */
 typedef struct {
   int lmax;
   int mmax;
   const double *a;
+  const double *axes;
 } ffbie_geometry;
 
 /* Discretisation (Sec. 3.1-3.2): n_panels Gauss-Legendre panels of 16 nodes

@@ -48,7 +48,17 @@ class FfbieError(RuntimeError):
 
 
 class _Geometry(ctypes.Structure):
-    _fields_ = [("lmax", ctypes.c_int), ("mmax", ctypes.c_int), ("a", ctypes.POINTER(ctypes.c_double))]
+    _fields_ = [("lmax", ctypes.c_int), ("mmax", ctypes.c_int), ("a", ctypes.POINTER(ctypes.c_double)),
+                ("axes", ctypes.POINTER(ctypes.c_double))]
+
+
+def _axes_ptr(axes, owner):
+    """Pointer to three float64 axes (kept alive on owner), or NULL."""
+    if axes is None:
+        owner._axes = None
+        return None
+    owner._axes = np.ascontiguousarray(axes, dtype=np.float64).reshape(3)
+    return owner._axes.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
 class _Disc(ctypes.Structure):
@@ -218,10 +228,13 @@ class Context:
         except Exception:
             pass
 
-    def set_problem(self, amp, n_panels, M, k, M0=None, eps0=0.0, variant=KAPPA_SWAP):
+    def set_problem(self, amp, n_panels, M, k, M0=None, eps0=0.0, variant=KAPPA_SWAP, axes=None):
+        """Surface (amplitude table, optional axes of the stretch D), panels,
+        M, wavenumber k, M0, truncation threshold eps0, kappa variant."""
         a = np.ascontiguousarray(np.zeros((0, 1)) if amp is None else amp, dtype=np.float64)
         self._amp = a
-        geo = _Geometry(a.shape[0], a.shape[1] - 1, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        geo = _Geometry(a.shape[0], a.shape[1] - 1, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                        _axes_ptr(axes, self))
         disc = _Disc(int(n_panels), int(M), int(M if M0 is None else M0), float(eps0), int(variant))
         self._check(self.lib.ffbie_set_problem(self.h, ctypes.byref(geo), ctypes.byref(disc), float(k)), self.h)
         self.M, self.M0 = int(M), int(M if M0 is None else M0)
@@ -341,7 +354,11 @@ class Context:
                 st = torch.empty((n,), dtype=torch.int32, device=dev)
             keep += [a, t, ts, az, kap, st]
             it = arr[i]
-            it.g = _Geometry(a.shape[0], a.shape[1] - 1, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+            ax = None if pr.get("axes") is None else np.ascontiguousarray(pr["axes"], dtype=np.float64)
+            if ax is not None:
+                keep.append(ax)
+            it.g = _Geometry(a.shape[0], a.shape[1] - 1, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             None if ax is None else ax.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
             it.d = _Disc(1, M, int(pr.get("M0", M)), float(pr.get("eps0", 0.0)), KAPPA_SWAP)
             it.k = float(pr["k"])
             it.n_pairs = n

@@ -308,6 +308,16 @@ bool make_prob(const ffbie_geometry* g, const ffbie_discretization* d, double k,
       if (!std::isfinite(v)) { *why = "non-finite amplitude"; return false; }
       P.g.a[l][m] = v;
     }
+  P.g.ax[0] = P.g.ax[1] = P.g.ax[2] = 1.0;
+  P.g.scaled = 0;
+  if (g->axes) {
+    for (int c = 0; c < 3; ++c) {
+      const double v = g->axes[c];
+      if (!(v > 0) || !std::isfinite(v)) { *why = "axes must be positive and finite"; return false; }
+      P.g.ax[c] = v;
+      if (v != 1.0) P.g.scaled = 1;
+    }
+  }
   P.k = k;
   P.eps0 = d->eps0 > 0 ? d->eps0 : 1e-15;
   P.M = d->M;
@@ -803,6 +813,9 @@ ffbie_status plan_build(ffbie_ctx* c, ffbie_batch_plan* pl, int n_items, const f
       return fail(c, FFBIE_EINVAL, "ffbie batch: item " + std::to_string(i) + ": " + why);
     if (it.d.kappa_variant != FFBIE_KAPPA_SWAP)
       return fail(c, FFBIE_EINVAL, "ffbie batch: only FFBIE_KAPPA_SWAP is batched");
+    if (probs[i].g.scaled)
+      return fail(c, FFBIE_EINVAL, "ffbie batch: item " + std::to_string(i) +
+                                       ": stretched surfaces (axes != 1) are not batched");
     if (it.n_pairs < 0 || it.n_pairs > ((int64_t)1 << 31))
       return fail(c, FFBIE_EINVAL, "ffbie batch: n_pairs out of range");
     if (it.n_pairs == 0) continue;
@@ -1040,6 +1053,8 @@ ffbie_status ffbie_kernel_coeffs_mixed(ffbie_ctx* c, int64_t n, const double* d_
   if (!c) return FFBIE_EINVAL;
   if (!c->has_problem) return fail(c, FFBIE_ENOPROBLEM, "ffbie_kernel_coeffs_mixed: no problem set");
   if (n < 0) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_mixed: n_pairs < 0");
+  if (c->prob.g.scaled)
+    return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_mixed: stretched surfaces (axes != 1) take the FP64 path");
   if (n == 0) return FFBIE_OK;
   if (!d_t || !d_az || !d_ts || !d_kappa)
     return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_mixed: NULL input or kappa pointer");
@@ -1056,6 +1071,8 @@ ffbie_status ffbie_kernel_coeffs_dl(ffbie_ctx* c, int64_t n, const double* d_t, 
   if (n < 0) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_dl: n_pairs < 0");
   if (adjoint != 0 && adjoint != 1)
     return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_dl: adjoint must be 0 (K) or 1 (K')");
+  if (c->prob.g.scaled)
+    return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_dl: stretched surfaces (axes != 1) are not supported");
   if (n == 0) return FFBIE_OK;
   if (!d_t || !d_az || !d_ts || !d_kappa)
     return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_dl: NULL input or kappa pointer");
@@ -1073,6 +1090,8 @@ ffbie_status ffbie_rhoinv_banded(ffbie_ctx* c, int64_t n, const double* d_t, con
   if (n < 0) return fail(c, FFBIE_EINVAL, std::string(fn) + "n_pairs < 0");
   if (m0 < 0 || m0 > kBandMaxM0) return fail(c, FFBIE_EINVAL, std::string(fn) + "need 0 <= m0 <= 8");
   const Prob& P = c->prob;
+  if (P.g.scaled)
+    return fail(c, FFBIE_EINVAL, std::string(fn) + "stretched surfaces (axes != 1) are not supported");
   const int deg = rho2_degree(P.g);
   if (m0 == 0 && deg > kBandMaxM0)
     return fail(c, FFBIE_EINVAL, std::string(fn) + "rho^2 has degree " + std::to_string(deg) +
@@ -1267,6 +1286,8 @@ ffbie_status ffbie_assemble_op(ffbie_ctx* c, int op, double shift, int unknowns,
   if (!std::isfinite(shift)) return fail(c, FFBIE_EINVAL, "ffbie_assemble_op: non-finite shift");
   if (unknowns != FFBIE_UNKNOWN_SCALED && unknowns != FFBIE_UNKNOWN_DENSITY)
     return fail(c, FFBIE_EINVAL, "ffbie_assemble_op: unknowns must be FFBIE_UNKNOWN_SCALED or FFBIE_UNKNOWN_DENSITY");
+  if (op != FFBIE_OP_S && c->prob.g.scaled)
+    return fail(c, FFBIE_EINVAL, "ffbie_assemble_op: K and K' take unstretched surfaces only (axes = 1)");
   const int density = unknowns == FFBIE_UNKNOWN_DENSITY ? 1 : 0;
   ffbie_status s = prepare_system(c);
   if (s != FFBIE_OK) return s;

@@ -54,14 +54,16 @@ __device__ void surface_point(const Geom& g, double t, double th, double* px, do
   const double ox = st * cth, oy = st * sth, oz = ct;          // omega
   const double tx = ct * cth, ty = ct * sth, tz = -st;         // d omega / dt
   const double hx = -st * sth, hy = st * cth, hz = 0.0;        // d omega / dtheta
-  const double rtx = Rt * ox + R * tx, rty = Rt * oy + R * ty, rtz = Rt * oz + R * tz;
-  const double rhx = Rth * ox + R * hx, rhy = Rth * oy + R * hy, rhz = Rth * oz + R * hz;
+  // r = D R omega: D scales r, r_t and r_theta (unit D: the star itself)
+  const double gx = g.ax[0], gy = g.ax[1], gz = g.ax[2];
+  const double rtx = gx * (Rt * ox + R * tx), rty = gy * (Rt * oy + R * ty), rtz = gz * (Rt * oz + R * tz);
+  const double rhx = gx * (Rth * ox + R * hx), rhy = gy * (Rth * oy + R * hy), rhz = gz * (Rth * oz + R * hz);
   const double cx = rty * rhz - rtz * rhy;
   const double cy = rtz * rhx - rtx * rhz;
   const double cz = rtx * rhy - rty * rhx;
-  *px = R * ox;
-  *py = R * oy;
-  *pz = R * oz;
+  *px = gx * (R * ox);
+  *py = gy * (R * oy);
+  *pz = gz * (R * oz);
   const double J = sqrt(cx * cx + cy * cy + cz * cz);
   *jac = J;
   nrm[0] = cx / J;

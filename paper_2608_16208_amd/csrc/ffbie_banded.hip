@@ -36,13 +36,15 @@
 namespace ffbie {
 
 int rho2_degree(const Geom& g) {
-  int mtop = -1;
+  int mtop = 0;
   for (int l = 0; l < g.lmax; ++l)
     for (int m = 0; m <= g.mmax; ++m)
       if (g.a[l][m] != 0.0 && m > mtop) mtop = m;
   // R(t_s, .) has degree mtop; rho^2 = R^2 + R_s^2 - 2 R R_s (sin t sin t_s
-  // cos(theta_s - theta) + cos t cos t_s) has degree max(2 mtop, mtop + 1)
-  if (mtop <= 0) return 1;
+  // cos(theta_s - theta) + cos t cos t_s) has degree max(2 mtop, mtop + 1).
+  // Stretched with unequal x and y axes, R_s^2 (d_x^2 cos^2 + d_y^2 sin^2)
+  // keeps a cos(2 theta_s) part: 2 mtop + 2.
+  if (g.ax[0] != g.ax[1]) return 2 * mtop + 2;
   return 2 * mtop > mtop + 1 ? 2 * mtop : mtop + 1;
 }
 

@@ -29,6 +29,8 @@ constexpr int kWave = 64;
 struct Geom {
   int lmax, mmax;
   double a[kMaxL][kMaxM + 1];
+  double ax[3];    // stretch D = diag(ax) of the coordinates (1, 1, 1: the star itself)
+  int scaled;      // ax differs from (1, 1, 1)
 };
 
 // Problem-wide constants for the coefficient kernels.
@@ -192,6 +194,7 @@ struct PairGeo {
   double S1, C1;              // sin t_s - sin t, cos t_s - cos t (product forms)
   double R;                   // R(t, theta_j)
   double al[MM + 1], be[MM + 1], ga[MM + 1];
+  double sx, sy, sz;          // the stretch D (read only by the stretched instantiations)
 };
 
 // R(t, theta_j) = 1 + sum_m ga_m cos(m theta_j), theta_j at table index J.
@@ -213,6 +216,7 @@ FFBIE_HD __forceinline__ void pair_geo(const Geom& g, double t, double ts, const
   sincos_bounded(0.5 * (ts - t), &shd, &chd);
   sincos_bounded(0.5 * (ts + t), &shs, &chs);
   p->st = st; p->ct = ct; p->sts = sts; p->cts = cts;
+  p->sx = g.ax[0]; p->sy = g.ax[1]; p->sz = g.ax[2];
   p->S1 = 2.0 * chs * shd;
   p->C1 = -2.0 * shs * shd;
 #pragma unroll
@@ -240,7 +244,9 @@ FFBIE_HD __forceinline__ void pair_geo(const Geom& g, double t, double ts, const
 // Delta r = r(t_s, theta_q) - r(t, theta_j) from the trigonometric values of
 // the grid angles: cq, sq = cos, sin theta_q; dh, cD = sin, cos of
 // (theta_q - theta_j)/2; sS, cS = sin, cos of (theta_q + theta_j)/2.
-template <int MM>
+// ST: the surface is stretched by D (the differences are scaled by it); the
+// unstretched instantiation carries no trace of D.
+template <int MM, bool ST = false>
 FFBIE_HD __forceinline__ void dr_values(const PairGeo<MM>& p, double cq, double sq, double dh, double cD,
                                         double sS, double cS, double* dx, double* dy, double* dz) {
   const double dcos = -2.0 * sS * dh;   // cos theta_q - cos theta_j
@@ -273,16 +279,21 @@ FFBIE_HD __forceinline__ void dr_values(const PairGeo<MM>& p, double cq, double 
   *dx = fma(dR, wx, p.R * ox);
   *dy = fma(dR, wy, p.R * oy);
   *dz = fma(dR, wz, p.R * oz);
+  if constexpr (ST) {
+    *dx *= p.sx;
+    *dy *= p.sy;
+    *dz *= p.sz;
+  }
 }
 
 // Delta r for a source azimuth on the table grid: Kq = table index of theta_q,
 // J = table index of theta_j (both even).
-template <int MM>
+template <int MM, bool ST = false>
 FFBIE_HD __forceinline__ void dr_grid(const PairGeo<MM>& p, const double* tab, int Kq, int J,
                                       int mask, int quarter, double* dx, double* dy, double* dz) {
   const int hd = (Kq - J) >> 1;      // (theta_q - theta_j)/2
   const int hs = (Kq + J) >> 1;      // (theta_q + theta_j)/2
-  dr_values<MM>(p, tcos(tab, Kq, mask, quarter), tsin(tab, Kq, mask), tsin(tab, hd, mask),
+  dr_values<MM, ST>(p, tcos(tab, Kq, mask, quarter), tsin(tab, Kq, mask), tsin(tab, hd, mask),
                 MM >= 2 ? tcos(tab, hd, mask, quarter) : 0.0, tsin(tab, hs, mask),
                 tcos(tab, hs, mask, quarter), dx, dy, dz);
 }
@@ -294,7 +305,7 @@ struct Rho2 {
   cplx f, f1, f2;
 };
 
-template <int MM>
+template <int MM, bool ST = false>
 FFBIE_HD __forceinline__ Rho2 rho2_complex(const PairGeo<MM>& p, double sj, double cj,
                                              const double* smj, const double* cmj, cplx d,
                                              bool want2) {
@@ -332,17 +343,23 @@ FFBIE_HD __forceinline__ Rho2 rho2_complex(const PairGeo<MM>& p, double sj, doub
   }
   const cplx wx = p.sts * cq, wy = p.sts * sq, wz = mk(p.cts, 0);
   const cplx ox = p.S1 * cq + p.st * dcos, oy = p.S1 * sq + p.st * dsin, oz = mk(p.C1, 0);
-  const cplx Dx = dR * wx + p.R * ox, Dy = dR * wy + p.R * oy, Dz = dR * wz + p.R * oz;
-  // r_theta(t_s, theta') = R_theta w + Rs w_theta,  w_theta = (-sts sin, sts cos, 0)
-  const cplx tx = Rth * wx - Rs * (p.sts * sq), ty = Rth * wy + Rs * (p.sts * cq), tz = Rth * wz;
+  // D (1 unless ST) scales the difference and its azimuthal derivatives
+  const double gx = ST ? p.sx : 1.0, gy = ST ? p.sy : 1.0, gz = ST ? p.sz : 1.0;
+  cplx Dx = dR * wx + p.R * ox, Dy = dR * wy + p.R * oy, Dz = dR * wz + p.R * oz;
+  // r_theta(t_s, theta') = D (R_theta w + Rs w_theta),  w_theta = (-sts sin, sts cos, 0)
+  cplx tx = Rth * wx - Rs * (p.sts * sq), ty = Rth * wy + Rs * (p.sts * cq), tz = Rth * wz;
+  if constexpr (ST) {
+    Dx = gx * Dx; Dy = gy * Dy; Dz = gz * Dz;
+    tx = gx * tx; ty = gy * ty; tz = gz * tz;
+  }
   Rho2 out;
   out.f = Dx * Dx + Dy * Dy + Dz * Dz;
   out.f1 = 2.0 * (Dx * tx + Dy * ty + Dz * tz);
   if (want2) {
-    // r_thth = R_thth w + 2 R_th w_th + Rs w_thth,  w_thth = (-sts cos, -sts sin, 0)
-    const cplx ux = Rthth * wx - 2.0 * (Rth * (p.sts * sq)) - Rs * (p.sts * cq);
-    const cplx uy = Rthth * wy + 2.0 * (Rth * (p.sts * cq)) - Rs * (p.sts * sq);
-    const cplx uz = Rthth * wz;
+    // r_thth = D (R_thth w + 2 R_th w_th + Rs w_thth),  w_thth = (-sts cos, -sts sin, 0)
+    const cplx ux = gx * (Rthth * wx - 2.0 * (Rth * (p.sts * sq)) - Rs * (p.sts * cq));
+    const cplx uy = gy * (Rthth * wy + 2.0 * (Rth * (p.sts * cq)) - Rs * (p.sts * sq));
+    const cplx uz = gz * (Rthth * wz);
     out.f2 = 2.0 * (tx * tx + ty * ty + tz * tz + Dx * ux + Dy * uy + Dz * uz);
   } else {
     out.f2 = mk(0, 0);

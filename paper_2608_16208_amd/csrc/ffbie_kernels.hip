@@ -45,7 +45,7 @@ __device__ __forceinline__ void load_table(double* tab, const double* __restrict
 // order-2 kernel then keeps 12 VGPRs in scratch and still runs 5 % faster than
 // at the three its 136 VGPRs would allow; higher orders are left to the
 // compiler.
-template <int MM>
+template <int MM, bool ST = false>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 4 : 1, MM <= 2 ? 4 : 8))) void ffbie_root_kernel_t(
     Prob P, const double* __restrict__ tab_g, int64_t n, const double* __restrict__ t_in,
@@ -65,7 +65,7 @@ __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 4 : 1, MM <= 2 ? 4 : 8))) void ffbi
     return;
   }
   int st;
-  const RootRec r = find_root<MM>(P, tab, t, j, ts, &st);
+  const RootRec r = find_root<MM, ST>(P, tab, t, j, ts, &st);
   out[i] = r;
   status[i] = st;
   if (root_out) { root_out[2 * i] = r.u; root_out[2 * i + 1] = r.b; }
@@ -569,7 +569,7 @@ __device__ __forceinline__ void swap_convolution(const C* G, int p, const declty
 // spectral stage (transforms, truncation, A_m storage, convolutions, outputs):
 // double, or float for the mixed-precision path; geometry, samples, the root
 // and the recurrences for A_m run in FP64 either way.
-template <int MM, bool REFINE, class R, int RADIX>
+template <int MM, bool REFINE, class R, int RADIX, bool ST = false>
 __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* tab,
                                             const typename Spec<R>::C* tw, double* wbase, int NF,
                                             int64_t beg, int64_t end) {
@@ -666,7 +666,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     double sumF = 0.0;
     auto sample = [&](int q, C& z1, C& z2) {
       double dx, dy, dz;
-      dr_grid<MM>(pg, tab, q * tstride, J, mask, quarter, &dx, &dy, &dz);
+      dr_grid<MM, ST>(pg, tab, q * tstride, J, mask, quarter, &dx, &dy, &dz);
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
       const double ri = rsqrt_refined(r2);      // 1/rho
       const double rho = r2 * ri;
@@ -884,7 +884,7 @@ constexpr int coeff_persist_waves_per_simd() {
   return MM <= 4 ? 3 : 2;
 }
 
-template <int MM, bool REFINE, class R, int RADIX>
+template <int MM, bool REFINE, class R, int RADIX, bool ST = false>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(coeff_waves_per_simd<MM, R>(), coeff_waves_per_simd<MM, R>()))) void ffbie_coeff_kernel_t(
     CoeffArgs a) {
@@ -911,8 +911,8 @@ __attribute__((amdgpu_waves_per_eu(coeff_waves_per_simd<MM, R>(), coeff_waves_pe
   const int64_t gw = (int64_t)blockIdx.x * waves_per_block + wave;
   const int64_t chunk = (count + total_waves - 1) / total_waves;
   const int64_t beg = gw * chunk, end = min(count, beg + chunk);
-  coeff_range<MM, REFINE, R, RADIX>(a, tab, tw, smem + a.P.tab_n + twd + (size_t)wave * per_wave, a.NF,
-                             beg, end);
+  coeff_range<MM, REFINE, R, RADIX, ST>(a, tab, tw, smem + a.P.tab_n + twd + (size_t)wave * per_wave,
+                                        a.NF, beg, end);
 }
 
 // ===========================================================================
@@ -1650,8 +1650,12 @@ hipError_t launch_root(const Prob& P, const double* tab, int64_t n, const double
   switch (mm_bucket(P.g.mmax)) {
 #define X(MMV)                                                                                   \
   case MMV:                                                                                      \
-    hipLaunchKernelGGL(ffbie_root_kernel_t<MMV>, dim3((unsigned)blocks), dim3(threads), lds,    \
-                       stream, P, tab, n, t, az, ts, out, status, root_out);                     \
+    if (P.g.scaled)                                                                              \
+      hipLaunchKernelGGL((ffbie_root_kernel_t<MMV, true>), dim3((unsigned)blocks), dim3(threads), \
+                         lds, stream, P, tab, n, t, az, ts, out, status, root_out);              \
+    else                                                                                         \
+      hipLaunchKernelGGL((ffbie_root_kernel_t<MMV, false>), dim3((unsigned)blocks), dim3(threads), \
+                         lds, stream, P, tab, n, t, az, ts, out, status, root_out);              \
     break;
     FFBIE_FOR_MM(X)
 #undef X
@@ -1663,15 +1667,20 @@ hipError_t launch_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t ld
                         hipStream_t stream, bool refine, bool single) {
   // refine passes always take radix-2 transforms
   const bool r4 = !refine && (a.radix == 4 || (a.radix == 0 && a.NF >= 256));
+  // stretched surfaces (FP64 only; the host rejects the mixed path for them)
+  const bool st = a.P.g.scaled != 0;
+  if (st && single) return hipErrorInvalidValue;
   switch (mm_bucket(a.P.g.mmax)) {
-#define K(MMV, RF, RT, RX)                                                                       \
-  hipLaunchKernelGGL((ffbie_coeff_kernel_t<MMV, RF, RT, RX>), dim3((unsigned)blocks),           \
+#define K(MMV, RF, RT, RX, ST)                                                                   \
+  hipLaunchKernelGGL((ffbie_coeff_kernel_t<MMV, RF, RT, RX, ST>), dim3((unsigned)blocks),       \
                      dim3(64 * waves), lds, stream, a)
-#define KR(MMV, RT)                                                                              \
-  if (refine) K(MMV, true, RT, 2); else if (r4) K(MMV, false, RT, 4); else K(MMV, false, RT, 2)
+#define KR(MMV, RT, ST)                                                                          \
+  if (refine) K(MMV, true, RT, 2, ST); else if (r4) K(MMV, false, RT, 4, ST); else K(MMV, false, RT, 2, ST)
 #define X(MMV)                                                                                   \
   case MMV:                                                                                      \
-    if (single) { KR(MMV, float); } else { KR(MMV, double); }                                    \
+    if (single) { KR(MMV, float, false); }                                                       \
+    else if (st) { KR(MMV, double, true); }                                                      \
+    else { KR(MMV, double, false); }                                                             \
     break;
     FFBIE_FOR_MM(X)
 #undef X

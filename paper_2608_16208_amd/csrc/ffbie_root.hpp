@@ -10,7 +10,7 @@ constexpr double kBFar = 3.0;        // b0 beyond which the quadratic-model root
 
 // t, ts: curve parameters; j: target azimuth index in [0, 2M); tab: angle table.
 // Returns the record and writes the FFBIE_PAIR_* bits to *status.
-template <int MM>
+template <int MM, bool ST = false>
 FFBIE_HD inline RootRec find_root(const Prob& P, const double* tab, double t, int j, double ts,
                                   int* status) {
   const int M = P.M, mask = P.tab_n - 1, quarter = 2 * M;
@@ -25,11 +25,24 @@ FFBIE_HD inline RootRec find_root(const Prob& P, const double* tab, double t, in
   //     (~1e-16 absolute) only matters between grid values that agree to that
   //     level, where either is a valid start for the Newton steps below.  The
   //     angle values of theta_q are the same for every pair.
+  //     On a surface stretched by D the same expansion reads
+  //     rho^2 = R_s^2 |D w|^2 - 2 R_s (D w) . (D r_t) + |D r_t|^2.
   const double sj = tsin(tab, J, mask), cj = tcos(tab, J, mask, quarter);
   const double Rt = pg.R;
-  const double wa = pg.sts * (Rt * pg.st * cj), wb = pg.sts * (Rt * pg.st * sj);
-  const double wc = pg.cts * (Rt * pg.ct);
-  const double Rs0 = 1.0 + pg.al[0], Rt2 = Rt * Rt;
+  constexpr bool scaled = ST;
+  const double s2x = pg.sx * pg.sx, s2y = pg.sy * pg.sy, s2z = pg.sz * pg.sz;
+  double wa = pg.sts * (Rt * pg.st * cj), wb = pg.sts * (Rt * pg.st * sj);
+  double wc = pg.cts * (Rt * pg.ct);
+  double Rt2 = Rt * Rt;
+  if (scaled) {
+    wa *= s2x;
+    wb *= s2y;
+    wc *= s2z;
+    const double px = Rt * pg.st * cj, py = Rt * pg.st * sj, pz = Rt * pg.ct;
+    Rt2 = fma(s2x * px, px, fma(s2y * py, py, s2z * pz * pz));
+  }
+  const double sts2 = pg.sts * pg.sts, cts2 = pg.cts * pg.cts;
+  const double Rs0 = 1.0 + pg.al[0];
   double best = 1e300;
   int qbest = j;
   for (int q = 0; q < 2 * M; ++q) {
@@ -48,7 +61,13 @@ FFBIE_HD inline RootRec find_root(const Prob& P, const double* tab, double t, in
       }
     }
     const double d = fma(wa, cq, fma(wb, sq, wc));
-    const double r2 = fma(Rs, fma(-2.0, d, Rs), Rt2);
+    double r2;
+    if (!scaled) {
+      r2 = fma(Rs, fma(-2.0, d, Rs), Rt2);
+    } else {
+      const double w2 = fma(sts2 * s2x, cq * cq, fma(sts2 * s2y, sq * sq, s2z * cts2));   // |D w|^2
+      r2 = fma(Rs, fma(-2.0, d, Rs * w2), Rt2);
+    }
     if (r2 < best) { best = r2; qbest = q; }
   }
   int dq = (qbest - j) & (2 * M - 1);
@@ -65,14 +84,14 @@ FFBIE_HD inline RootRec find_root(const Prob& P, const double* tab, double t, in
 
   // (2) real minimiser a0 by Newton on d rho^2 / d theta_s, kept within the grid cell
   const double lo = x - h, hi = x + h;
-  Rho2 r = rho2_complex<MM>(pg, sj, cj, smj, cmj, mk(x, 0), true);
+  Rho2 r = rho2_complex<MM, ST>(pg, sj, cj, smj, cmj, mk(x, 0), true);
   for (int it = 0; it < 12; ++it) {
     const double f0 = r.f.re, g1 = r.f1.re, g2 = r.f2.re;
     if (!(g2 > 0)) break;
     const double step = g1 / g2;
     const double bscale = sqrt(fmax(2.0 * f0 / g2, 0.0));
     x = fmin(fmax(x - step, lo), hi);
-    r = rho2_complex<MM>(pg, sj, cj, smj, cmj, mk(x, 0), true);
+    r = rho2_complex<MM, ST>(pg, sj, cj, smj, cmj, mk(x, 0), true);
     if (fabs(step) <= 1e-10 * bscale + 1e-300) break;
   }
   int st = 0;
@@ -94,7 +113,7 @@ FFBIE_HD inline RootRec find_root(const Prob& P, const double* tab, double t, in
     // the offset 0.2 b0 off the line: fewest Newton evaluations and fallbacks
     // among 0 .. 0.8 b0 on samples of config-2 pairs
     cplx z = mk(x + 0.2 * b0, b0);
-    Rho2 e = rho2_complex<MM>(pg, sj, cj, smj, cmj, z, false);
+    Rho2 e = rho2_complex<MM, ST>(pg, sj, cj, smj, cmj, z, false);
     bool conv = false;
     double sn_prev = 1e300;
     for (int it = 0; it < 40 && !conv; ++it) {
@@ -110,7 +129,7 @@ FFBIE_HD inline RootRec find_root(const Prob& P, const double* tab, double t, in
           break;
         }
         sn_prev = sn;
-        e = rho2_complex<MM>(pg, sj, cj, smj, cmj, z, false);
+        e = rho2_complex<MM, ST>(pg, sj, cj, smj, cmj, z, false);
         continue;
       }
       // far from the root: backtrack until Im z stays positive and |rho^2| decreases
@@ -121,7 +140,7 @@ FFBIE_HD inline RootRec find_root(const Prob& P, const double* tab, double t, in
       for (int bt = 0; bt < 12; ++bt) {
         zn = z - lam * step;
         if (zn.im > 0.05 * z.im) {
-          en = rho2_complex<MM>(pg, sj, cj, smj, cmj, zn, false);
+          en = rho2_complex<MM, ST>(pg, sj, cj, smj, cmj, zn, false);
           if (sqrt(abs2(en.f)) <= (1.0 - 0.25 * lam) * sqrt(abs2(e.f))) { ok = true; break; }
         }
         lam *= 0.5;

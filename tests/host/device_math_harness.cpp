@@ -69,6 +69,7 @@ int main(int argc, char** argv) {
   Prob P{};
   P.M = M; P.M0 = M; P.L = 2 * M; P.tab_n = 8 * M; P.k = k; P.eps0 = 1e-15;
   P.g.lmax = lmax; P.g.mmax = mmax;
+  P.g.ax[0] = P.g.ax[1] = P.g.ax[2] = 1.0;
   for (int l = 0; l < lmax; ++l)
     for (int m = 0; m <= mmax; ++m)
       if (scanf("%lf", &P.g.a[l][m]) != 1) return 1;

@@ -59,8 +59,9 @@ def test_no_coefficient_kernel_spills(report):
 @pytest.mark.parametrize("real, waves", [("d", 4), ("f", 5)])
 def test_config2_kernel_occupancy(report, real, waves):
     """The kernel of the config-2 launch (azimuthal order 2, radix 2, main
-    pass): four wavefronts per SIMD in FP64, five with the FP32 spectral stage."""
-    name = "_ZN5ffbie20ffbie_coeff_kernel_tILi2ELb0E%sLi2EEEvNS_9CoeffArgsE" % real
+    pass, unstretched surface): four wavefronts per SIMD in FP64, five with the
+    FP32 spectral stage."""
+    name = "_ZN5ffbie20ffbie_coeff_kernel_tILi2ELb0E%sLi2ELb0EEEvNS_9CoeffArgsE" % real
     f = report[name]
     assert int(f["Occupancy"]) == waves, f
     assert int(f["VGPRs"]) <= 512 // waves, f
