@@ -86,11 +86,10 @@ typedef struct ffbie_ctx ffbie_ctx;
  * x^2 + y^2/4 + z^2/9 = 1 of Sec. 5, Example 1.  `a` and `axes` are HOST
  * pointers copied by ffbie_set_problem; `a` is row-major [lmax][mmax+1];
  * axes NULL means (1, 1, 1), otherwise three positive finite values.  Limits:
- * lmax <= 8, mmax <= 8.  Stretched surfaces run the FP64 single-problem path
- * (ffbie_kernel_coeffs, _noalloc, the S operator of the assembly, the
- * solvers and the fields); the double-layer coefficients (ffbie_kernel_coeffs_dl
- * and the K, K' operators of ffbie_assemble_op), the mixed-precision path, the
- * batch plans and ffbie_rhoinv_banded take unstretched surfaces only
+ * lmax <= 8, mmax <= 8.  Stretched surfaces run the FP64 single-problem paths
+ * (ffbie_kernel_coeffs, _noalloc, ffbie_kernel_coeffs_dl, the S, K and K'
+ * operators of the assembly, the solvers and the fields); the mixed-precision
+ * path, the batch plans and ffbie_rhoinv_banded take unstretched surfaces only
  * (FFBIE_EINVAL otherwise). */
 typedef struct {
   int lmax;

@@ -1071,8 +1071,6 @@ ffbie_status ffbie_kernel_coeffs_dl(ffbie_ctx* c, int64_t n, const double* d_t, 
   if (n < 0) return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_dl: n_pairs < 0");
   if (adjoint != 0 && adjoint != 1)
     return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_dl: adjoint must be 0 (K) or 1 (K')");
-  if (c->prob.g.scaled)
-    return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_dl: stretched surfaces (axes != 1) are not supported");
   if (n == 0) return FFBIE_OK;
   if (!d_t || !d_az || !d_ts || !d_kappa)
     return fail(c, FFBIE_EINVAL, "ffbie_kernel_coeffs_dl: NULL input or kappa pointer");
@@ -1286,8 +1284,6 @@ ffbie_status ffbie_assemble_op(ffbie_ctx* c, int op, double shift, int unknowns,
   if (!std::isfinite(shift)) return fail(c, FFBIE_EINVAL, "ffbie_assemble_op: non-finite shift");
   if (unknowns != FFBIE_UNKNOWN_SCALED && unknowns != FFBIE_UNKNOWN_DENSITY)
     return fail(c, FFBIE_EINVAL, "ffbie_assemble_op: unknowns must be FFBIE_UNKNOWN_SCALED or FFBIE_UNKNOWN_DENSITY");
-  if (op != FFBIE_OP_S && c->prob.g.scaled)
-    return fail(c, FFBIE_EINVAL, "ffbie_assemble_op: K and K' take unstretched surfaces only (axes = 1)");
   const int density = unknowns == FFBIE_UNKNOWN_DENSITY ? 1 : 0;
   ffbie_status s = prepare_system(c);
   if (s != FFBIE_OK) return s;

@@ -1158,15 +1158,34 @@ __device__ __forceinline__ void unit_normal(double R, double Rt, double Rh, doub
   *nz = (a * ct - bt * st) * inv;
 }
 
+// Normal of the stretched surface D r from a normal n of r: D r_t x D r_theta
+// = cof(D) (r_t x r_theta), cof(D) = diag(d_y d_z, d_x d_z, d_x d_y);
+// renormalised to unit length.
+__device__ __forceinline__ void stretch_normal(const Geom& g, double* nx, double* ny, double* nz) {
+  const double cx = g.ax[1] * g.ax[2], cy = g.ax[0] * g.ax[2], cz = g.ax[0] * g.ax[1];
+  const double mx = cx * *nx, my = cy * *ny, mz = cz * *nz;
+  const double inv = rsqrt_refined(fma(mx, mx, fma(my, my, mz * mz)));
+  *nx = mx * inv;
+  *ny = my * inv;
+  *nz = mz * inv;
+}
+
 // tau_0 = nu(v) . (r(v) - r(v + d)), v = (tv, hv), d = (dt, dh), by the line
-// integral of the Remark in Sec. 4; every lane returns the value.
-template <int MM>
+// integral of the Remark in Sec. 4; every lane returns the value.  ST: the
+// surface is stretched by D (its second derivatives and normal with it).
+template <int MM, bool ST = false>
 __device__ __forceinline__ double tau0_line(const Geom& g, double tv, double hv, double dt,
                                             double dh, int lane) {
   SurfPt v;
   surf_point<MM>(g, tv, hv, &v);
   double nx, ny, nz;
   unit_normal(v.R, v.Rt, v.Rh, v.st, v.ct, v.sh, v.ch, &nx, &ny, &nz);
+  if constexpr (ST) {
+    stretch_normal(g, &nx, &ny, &nz);
+    nx *= g.ax[0];   // nu . (D q) = (D nu) . q
+    ny *= g.ax[1];
+    nz *= g.ax[2];
+  }
   double acc = 0.0;
   if (lane < 16) {
     const double lam = kLamX[lane];
@@ -1256,7 +1275,7 @@ __device__ __forceinline__ void affine_scan_wave(int T, double y0, Step step, St
   }
 }
 
-template <int MM, bool REFINE>
+template <int MM, bool REFINE, bool ST = false>
 __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, double* wbase, int NF,
                                          int64_t beg, int64_t end) {
   const Prob& P = a.P;
@@ -1309,6 +1328,7 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
       }
       unit_normal(pg.R, Rt, Rh, pg.st, pg.ct, tsin(tab, J, mask), tcos(tab, J, mask, quarter), &nux,
                   &nuy, &nuz);
+      if constexpr (ST) stretch_normal(P.g, &nux, &nuy, &nuz);
     }
     const double u = rr.u, b = rr.b;
     const double gstep = 2.0 * M_PI / NF;
@@ -1336,7 +1356,7 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
     for (int q = lane; q < NF; q += 64) {
       const int Kq = q * tstride;
       double dx, dy, dz;
-      dr_grid<MM>(pg, tab, Kq, J, mask, quarter, &dx, &dy, &dz);
+      dr_grid<MM, ST>(pg, tab, Kq, J, mask, quarter, &dx, &dy, &dz);
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
       const double ri = rsqrt_refined(r2);
       const double rho = r2 * ri;
@@ -1361,12 +1381,23 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
           Rts = fma(dc[m], cm, Rts);
           Rhs = fma(-(double)m * pg.al[m], sm, Rhs);
         }
-        const double hxy = fma(cq, dx, sq * dy);
-        const double wd = fma(pg.sts, hxy, pg.cts * dz);      // omega . d
-        const double td = fma(pg.cts, hxy, -pg.sts * dz);     // e_t . d
-        const double pd = fma(-sq, dx, cq * dy);              // e_phi . d
         const double A1 = Rs * pg.sts, A2 = -Rts * pg.sts, A3 = -Rhs;
-        tau = fma(A1, wd, fma(A2, td, A3 * pd)) * rsqrt_refined(fma(A1, A1, fma(A2, A2, A3 * A3)));
+        if constexpr (ST) {
+          // the normal A1 omega + A2 e_t + A3 e_phi of r, stretched: cof(D) n
+          const double ex = fma(A1, pg.sts, A2 * pg.cts);
+          double mx = fma(ex, cq, -A3 * sq), my = fma(ex, sq, A3 * cq);
+          double mz = fma(A1, pg.cts, -A2 * pg.sts);
+          mx *= P.g.ax[1] * P.g.ax[2];
+          my *= P.g.ax[0] * P.g.ax[2];
+          mz *= P.g.ax[0] * P.g.ax[1];
+          tau = fma(mx, dx, fma(my, dy, mz * dz)) * rsqrt_refined(fma(mx, mx, fma(my, my, mz * mz)));
+        } else {
+          const double hxy = fma(cq, dx, sq * dy);
+          const double wd = fma(pg.sts, hxy, pg.cts * dz);      // omega . d
+          const double td = fma(pg.cts, hxy, -pg.sts * dz);     // e_t . d
+          const double pd = fma(-sq, dx, cq * dy);              // e_phi . d
+          tau = fma(A1, wd, fma(A2, td, A3 * pd)) * rsqrt_refined(fma(A1, A1, fma(A2, A2, A3 * A3)));
+        }
       }
       const double F3 = F * F * F;
       const double H = tau * fma(x, skr, ckr) * F3;
@@ -1503,11 +1534,11 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
       const double sj = tsin(tab, J, mask), cj = tcos(tab, J, mask, quarter);
       const double th_j = M_PI * j / M;
       double dx, dy, dz;
-      dr_values<MM>(pg, fma(cj, cu, -sj * su), fma(sj, cu, cj * su), shu, chu, fma(sj, chu, cj * shu),
-                    fma(cj, chu, -sj * shu), &dx, &dy, &dz);
+      dr_values<MM, ST>(pg, fma(cj, cu, -sj * su), fma(sj, cu, cj * su), shu, chu,
+                        fma(sj, chu, cj * shu), fma(cj, chu, -sj * shu), &dx, &dy, &dz);
       const double rho_a = sqrt_pos(fma(dx, dx, fma(dy, dy, dz * dz)));
-      const double tau_a = adj ? tau0_line<MM>(P.g, t, th_j, ts - t, u, lane)
-                               : tau0_line<MM>(P.g, ts, th_j + u, t - ts, -u, lane);
+      const double tau_a = adj ? tau0_line<MM, ST>(P.g, t, th_j, ts - t, u, lane)
+                               : tau0_line<MM, ST>(P.g, ts, th_j + u, t - ts, -u, lane);
       const double xa = k * rho_a;
       double sa, ca;
       sincos_bounded(xa, &sa, &ca);
@@ -1528,22 +1559,24 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
         const double wx = sp.st * sp.ch, wy = sp.st * sp.sh, wz = sp.ct;
         const double otx = sp.ct * sp.ch, oty = sp.ct * sp.sh, otz = -sp.st;   // omega_t
         const double ohx = -sp.st * sp.sh, ohy = sp.st * sp.ch;                // omega_theta
-        const double rhx = fma(sp.Rh, wx, sp.R * ohx), rhy = fma(sp.Rh, wy, sp.R * ohy),
-                     rhz = sp.Rh * wz;                                         // r_theta
+        // D (1 unless ST) scales every derivative of r below
+        const double gx = ST ? P.g.ax[0] : 1.0, gy = ST ? P.g.ax[1] : 1.0, gz = ST ? P.g.ax[2] : 1.0;
+        const double rhx = gx * fma(sp.Rh, wx, sp.R * ohx), rhy = gy * fma(sp.Rh, wy, sp.R * ohy),
+                     rhz = gz * (sp.Rh * wz);                                  // r_theta
         const double drho2 = 2.0 * fma(dx, rhx, fma(dy, rhy, dz * rhz));
         double taup;
         if (adj) {
           taup = -fma(nux, rhx, fma(nuy, rhy, nuz * rhz));
         } else {
           const double othx = -sp.ct * sp.sh, othy = sp.ct * sp.ch;            // omega_t theta
-          const double rtx = fma(sp.Rt, wx, sp.R * otx), rty = fma(sp.Rt, wy, sp.R * oty),
-                       rtz = fma(sp.Rt, wz, sp.R * otz);                       // r_t
-          const double rthx = sp.Rth * wx + sp.Rt * ohx + sp.Rh * otx + sp.R * othx;
-          const double rthy = sp.Rth * wy + sp.Rt * ohy + sp.Rh * oty + sp.R * othy;
-          const double rthz = sp.Rth * wz + sp.Rh * otz;                       // r_t theta
-          const double rhhx = sp.Rhh * wx + 2.0 * sp.Rh * ohx - sp.R * wx;
-          const double rhhy = sp.Rhh * wy + 2.0 * sp.Rh * ohy - sp.R * wy;
-          const double rhhz = sp.Rhh * wz;                                     // r_theta theta
+          const double rtx = gx * fma(sp.Rt, wx, sp.R * otx), rty = gy * fma(sp.Rt, wy, sp.R * oty),
+                       rtz = gz * fma(sp.Rt, wz, sp.R * otz);                  // r_t
+          const double rthx = gx * (sp.Rth * wx + sp.Rt * ohx + sp.Rh * otx + sp.R * othx);
+          const double rthy = gy * (sp.Rth * wy + sp.Rt * ohy + sp.Rh * oty + sp.R * othy);
+          const double rthz = gz * (sp.Rth * wz + sp.Rh * otz);                // r_t theta
+          const double rhhx = gx * (sp.Rhh * wx + 2.0 * sp.Rh * ohx - sp.R * wx);
+          const double rhhy = gy * (sp.Rhh * wy + 2.0 * sp.Rh * ohy - sp.R * wy);
+          const double rhhz = gz * (sp.Rhh * wz);                              // r_theta theta
           // n = r_t x r_theta, n' = r_t theta x r_theta + r_t x r_theta theta
           const double nx = rty * rhz - rtz * rhy, ny = rtz * rhx - rtx * rhz, nz = rtx * rhy - rty * rhx;
           const double npx = (rthy * rhz - rthz * rhy) + (rty * rhhz - rtz * rhhy);
@@ -1618,7 +1651,7 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
   }
 }
 
-template <int MM, bool REFINE>
+template <int MM, bool REFINE, bool ST = false>
 __global__ __launch_bounds__(256) void ffbie_dl_coeff_kernel_t(CoeffArgs a) {
   extern __shared__ double smem[];
   load_table(smem, a.tab_g, a.P.tab_n);
@@ -1631,7 +1664,7 @@ __global__ __launch_bounds__(256) void ffbie_dl_coeff_kernel_t(CoeffArgs a) {
   const int64_t gw = (int64_t)blockIdx.x * waves_per_block + wave;
   const int64_t chunk = (count + total_waves - 1) / total_waves;
   const int64_t beg = gw * chunk, end = min(count, beg + chunk);
-  dl_range<MM, REFINE>(a, smem, smem + a.P.tab_n + (size_t)wave * per_wave, a.NF, beg, end);
+  dl_range<MM, REFINE, ST>(a, smem, smem + a.P.tab_n + (size_t)wave * per_wave, a.NF, beg, end);
 }
 
 // ---------------------------------------------------------------------------
@@ -1729,18 +1762,19 @@ hipError_t launch_zero(int* p, int n, hipStream_t stream) {
 
 hipError_t launch_dl_coeff(const CoeffArgs& a, int64_t blocks, int waves, size_t lds,
                            hipStream_t stream, bool refine) {
+  const bool st = a.P.g.scaled != 0;
   switch (mm_bucket(a.P.g.mmax)) {
+#define K(MMV, RF, ST)                                                                           \
+  hipLaunchKernelGGL((ffbie_dl_coeff_kernel_t<MMV, RF, ST>), dim3((unsigned)blocks),            \
+                     dim3(64 * waves), lds, stream, a)
 #define X(MMV)                                                                                   \
   case MMV:                                                                                      \
-    if (refine)                                                                                  \
-      hipLaunchKernelGGL((ffbie_dl_coeff_kernel_t<MMV, true>), dim3((unsigned)blocks),          \
-                         dim3(64 * waves), lds, stream, a);                                      \
-    else                                                                                         \
-      hipLaunchKernelGGL((ffbie_dl_coeff_kernel_t<MMV, false>), dim3((unsigned)blocks),         \
-                         dim3(64 * waves), lds, stream, a);                                      \
+    if (refine) { if (st) K(MMV, true, true); else K(MMV, true, false); }                        \
+    else { if (st) K(MMV, false, true); else K(MMV, false, false); }                             \
     break;
     FFBIE_FOR_MM(X)
 #undef X
+#undef K
   }
   return hipGetLastError();
 }

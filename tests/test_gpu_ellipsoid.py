@@ -8,10 +8,15 @@ stretched non-axisymmetric star.
 * collocation points, normals and Jacobians (1e-13) and sampled rows of the
   assembled S (1e-10 of the row's largest entry, the oracle's near rule
   loaded on both sides);
+* K and K' coefficients against the oracle (1e-10, or the FP64 bound of the
+  s^{-3/2} factor);
 * the interior Dirichlet test of Sec. 5 by S on the ellipsoid at the paper's
-  k = 1, 2, 4 with (N_p, 2M) = (4, 32) (the paper's Table 1 uses (4, 30)):
-  E_S below the 1e-9 bar the paper sets itself;
-* the entry points that take unstretched surfaces only reject this one.
+  k = 1, 2, 4 with (N_p, 2M) = (4, 32) (the paper's Table 1 uses (4, 30)), and
+  the interior Dirichlet and Neumann tests by K - I and K' + I with
+  (4, 64) (the paper: (4, 40)): every E_j below the 1e-9 bar the paper sets
+  itself;
+* the entry points that take unstretched surfaces only (mixed precision, the
+  banded route) reject this one.
 """
 import numpy as np
 import pytest
@@ -118,12 +123,63 @@ def test_stretched_surface_rejected_where_unsupported(ctx):
     one = torch.tensor([0.7], dtype=torch.float64, device=dev)
     az = torch.tensor([3], dtype=torch.int32, device=dev)
     with pytest.raises(ffbie.FfbieError):
-        ctx.kernel_coeffs_dl(one, az, one + 0.1)
-    with pytest.raises(ffbie.FfbieError):
         ctx.kernel_coeffs(one, az, one + 0.1, mixed=True)
     with pytest.raises(ffbie.FfbieError):
         ctx.rhoinv_banded(one, az, one + 0.1)
     with pytest.raises(ffbie.FfbieError):
-        ctx.assemble(op=ffbie.OP_K)
-    with pytest.raises(ffbie.FfbieError):
         ctx.set_problem(None, 4, 16, 1.0, axes=(1.0, 0.0, 2.0))
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+@pytest.mark.parametrize("name", list(SURFACES))
+def test_stretched_dl_coefficients_match_oracle(ctx, name, adjoint):
+    """K and K' coefficients on the stretched surfaces against the oracle's
+    direct quadrature: 1e-10, or the FP64 bound where the s^{-3/2} factor
+    amplifies rounding (as for the unstretched surfaces)."""
+    from oracle import double_layer as odl
+    from test_gpu_double_layer import fp64_bound
+    amp, axes = SURFACES[name]
+    surface = geo.Scaled(amp, axes)
+    M, npan, k = 32, 8, 3.0
+    t, j, ts = workloads.sample_pairs(npan, M, 48, seed=91)
+    ctx.set_problem(amp, npan, M, k, axes=axes)
+    dev = ctx.device
+    out = ctx.kernel_coeffs_dl(torch.tensor(t, device=dev), torch.tensor(j, device=dev),
+                               torch.tensor(ts, device=dev), adjoint=adjoint)
+    got = out["kappa"].cpu().numpy()
+    st = out["status"].cpu().numpy()
+    ref, _ = odl.pairs_kcoeffs(surface, k, M, t, j, ts, adjoint=adjoint, processes=8)
+    err = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    bound = np.array([max(1e-10, fp64_bound(surface, k, M, t[i], j[i], ts[i], ref[i], adjoint=adjoint))
+                      for i in range(len(t))])
+    print("%s %s: worst %.2e, worst error / bar %.2f" % (name, "K'" if adjoint else "K", err.max(),
+                                                       (err / bound).max()), flush=True)
+    assert not (st & 8).any()
+    assert np.all(err <= bound), (err / bound).max()
+
+
+@pytest.mark.parametrize("k", [1.0, 4.0])
+def test_ellipsoid_interior_problems_by_K_and_Kp(ctx, k):
+    """(IDP) by (K - I) psi = G(.; r*) with the double-layer field and (INP) by
+    (K' + I) phi = d/dnu G(.; r*) with the single-layer field on the ellipsoid,
+    (N_p, 2M) = (4, 64) (the paper's Table 1: (4, 40)); E_j below 1e-9."""
+    import paper_2608_16208_amd as ffbie
+    ctx.set_near_rule(None)
+    ctx.set_problem(None, 4, 32, k, axes=ELL_AXES)
+    P = workloads.interior_test_points()
+    exact = osolve.point_source(k, P, workloads.INTERIOR_SOURCE)
+    pts = torch.tensor(P)
+    src = list(workloads.INTERIOR_SOURCE)
+    E = {}
+    for name, op, shift, g, fop in (("K", ffbie.OP_K, -1.0, ctx.rhs(ffbie.RHS_POINT_SOURCE, src), ffbie.OP_K),
+                                    ("K'", ffbie.OP_KP, 1.0, ctx.rhs(ffbie.RHS_POINT_SOURCE_DN, src),
+                                     ffbie.OP_S)):
+        A = ctx.assemble(op=op, shift=shift, unknowns=ffbie.UNKNOWN_DENSITY)
+        x, _ = ctx.solve(A, g, method=ffbie.SOLVE_LU64)
+        u = ctx.eval_field(pts, x, op=fop, unknowns=ffbie.UNKNOWN_DENSITY).cpu().numpy()
+        E[name] = float(np.linalg.norm(u - exact) / len(exact))
+        del A
+    torch.cuda.empty_cache()
+    print("ellipsoid k = %g, (4, 64): %s" % (k, ", ".join("E_%s = %.1e" % kv for kv in E.items())),
+          flush=True)
+    assert all(v < 1e-9 for v in E.values()), E
