@@ -371,39 +371,53 @@ def banded_block(ctx, cfg, torch, np, ffbie, tt, jj, tss, kappa, steps=3, sample
 
 
 def interior_protocol(ctx, torch, np, ffbie):
-    """The interior point-source protocol of Sec. 5 on the analytic star
-    surface of workloads.INTERIOR_AMP: (IDP) by S and by K - I, (INP) by
-    K' + I, LU64, E_j = ||u_num - u_exa||_2 / #(points) over 200 points of the
-    test ball, for the (k, N_p, 2M) rows of workloads.INTERIOR_ROWS.  The
-    paper's own surfaces (ellipsoid, bean, tori) are not star surfaces."""
+    """The interior point-source protocol of Sec. 5: (IDP) by S and by K - I,
+    (INP) by K' + I, LU64, E_j = ||u_num - u_exa||_2 / #(points) over 200
+    points of the test ball, source r* = (3, 4, 10.5).
+    * the ellipsoid of Example 1 at the rows of the paper's Table 1 (same N_p,
+      the next supported 2M), the paper's E_j beside each;
+    * an analytic star surface (workloads.INTERIOR_AMP) at INTERIOR_ROWS."""
     import workloads
     P = workloads.interior_test_points()
     src = workloads.INTERIOR_SOURCE
     pts = torch.tensor(P)
-    rows = []
     ctx.set_near_rule(None)
-    for k, npan, M in workloads.INTERIOR_ROWS:
-        ctx.set_problem(workloads.INTERIOR_AMP, npan, M, k)
+    ops = {"S": (ffbie.OP_S, 0.0, ffbie.UNKNOWN_SCALED, ffbie.RHS_POINT_SOURCE, ffbie.OP_S),
+           "K": (ffbie.OP_K, -1.0, ffbie.UNKNOWN_DENSITY, ffbie.RHS_POINT_SOURCE, ffbie.OP_K),
+           "K'": (ffbie.OP_KP, 1.0, ffbie.UNKNOWN_DENSITY, ffbie.RHS_POINT_SOURCE_DN, ffbie.OP_S)}
+
+    def error(amp, axes, k, npan, M, name):
+        ctx.set_problem(amp, npan, M, k, axes=axes)
         r = np.linalg.norm(P - src, axis=1)
         exact = np.exp(1j * k * r) / (4 * np.pi * r)
-        gD = ctx.rhs(ffbie.RHS_POINT_SOURCE, list(src))
-        gN = ctx.rhs(ffbie.RHS_POINT_SOURCE_DN, list(src))
+        op, shift, unk, rhs, fop = ops[name]
+        g = ctx.rhs(rhs, list(src))
+        A = ctx.assemble(op=op, shift=shift, unknowns=unk)
+        x, _ = ctx.solve(A, g, method=ffbie.SOLVE_LU64)
+        u = ctx.eval_field(pts, x, op=fop, unknowns=unk).cpu().numpy()
+        del A
+        torch.cuda.empty_cache()
+        return float(np.linalg.norm(u - exact) / len(exact))
+
+    t0 = time.perf_counter()
+    ell = []
+    for k, dS, eS, dK, eK, dKp, eKp in workloads.PAPER_TABLE1:
+        rec = {"k": k}
+        for name, (npan, two_m), paper in (("S", dS, eS), ("K", dK, eK), ("K'", dKp, eKp)):
+            M = workloads.supported_M(two_m)
+            rec[name] = {"N_p": npan, "2M": 2 * M, "E": error(None, workloads.ELLIPSOID_AXES, k, npan, M, name),
+                         "paper_2M": two_m, "paper_E": paper}
+        ell.append(rec)
+    star = []
+    for k, npan, M in workloads.INTERIOR_ROWS:
         rec = {"k": k, "N_p": npan, "2M": 2 * M, "N": 32 * M * npan}
-        t0 = time.perf_counter()
-        for name, op, shift, unk, g, fop in (("S", ffbie.OP_S, 0.0, ffbie.UNKNOWN_SCALED, gD, ffbie.OP_S),
-                                             ("K", ffbie.OP_K, -1.0, ffbie.UNKNOWN_DENSITY, gD, ffbie.OP_K),
-                                             ("K'", ffbie.OP_KP, 1.0, ffbie.UNKNOWN_DENSITY, gN, ffbie.OP_S)):
-            A = ctx.assemble(op=op, shift=shift, unknowns=unk)
-            x, _ = ctx.solve(A, g, method=ffbie.SOLVE_LU64)
-            u = ctx.eval_field(pts, x, op=fop, unknowns=unk).cpu().numpy()
-            rec["E_" + name] = float(np.linalg.norm(u - exact) / len(exact))
-            del A
-            torch.cuda.empty_cache()
-        torch.cuda.synchronize()
-        rec["wall_s"] = time.perf_counter() - t0
-        rows.append(rec)
-    return {"surface": "R = 1 + 0.2 sin t cos(theta) + 0.1 sin 2t cos(theta), r* = (3, 4, 10.5), "
-                       "Omega_T = ball((0, -0.2, 0.1), 0.2), 200 points", "rows": rows}
+        for name in ("S", "K", "K'"):
+            rec["E_" + name] = error(workloads.INTERIOR_AMP, None, k, npan, M, name)
+        star.append(rec)
+    return {"points": "200 seeded points of the ball |r - (0, -0.2, 0.1)| < 0.2, r* = (3, 4, 10.5)",
+            "ellipsoid_table1": ell,
+            "star": {"surface": "R = 1 + 0.2 sin t cos(theta) + 0.1 sin 2t cos(theta)", "rows": star},
+            "wall_s": time.perf_counter() - t0}
 
 
 def config3_block(ctx, torch, np, ffbie, solve=True):

@@ -117,6 +117,28 @@ INTERIOR_SOURCE = np.array([3.0, 4.0, 10.5])
 INTERIOR_ROWS = ((1.0, 4, 16), (2.0, 4, 16), (4.0, 4, 16), (8.0, 8, 32), (16.0, 16, 64))
 
 
+# Sec. 5, Example 1: the ellipsoid x^2 + y^2/4 + z^2/9 = 1 (the unit sphere
+# stretched by these axes), and the rows of the paper's Table 1: k, then for
+# S, K and K' the (N_p, 2M) used and the error E_j it reports.  The rows run
+# here take the same N_p and the next supported 2M (a power of two).
+ELLIPSOID_AXES = (1.0, 2.0, 3.0)
+PAPER_TABLE1 = (
+    (1.0, (4, 30), 6.4e-11, (4, 40), 7.6e-12, (4, 40), 1.3e-11),
+    (2.0, (4, 30), 1.2e-10, (4, 40), 1.6e-11, (4, 40), 9.3e-12),
+    (4.0, (4, 30), 8.4e-10, (4, 40), 1.2e-10, (4, 40), 2.6e-10),
+    (8.0, (8, 60), 9.7e-11, (8, 60), 2.3e-11, (8, 60), 2.2e-10),
+    (16.0, (16, 100), 9.6e-10, (16, 100), 7.2e-11, (16, 100), 8.0e-12),
+)
+
+
+def supported_M(two_m):
+    """The smallest supported M (16, 32, 64, 128) with 2M >= two_m."""
+    for M in (16, 32, 64, 128):
+        if 2 * M >= two_m:
+            return M
+    raise ValueError(two_m)
+
+
 def interior_test_points(n=200, seed=5, center=(0.0, -0.2, 0.1), radius=0.2):
     """Seeded points uniform in the test ball Omega_T."""
     rng = np.random.default_rng(seed)
