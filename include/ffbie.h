@@ -159,10 +159,10 @@ ffbie_status ffbie_kernel_coeffs(ffbie_ctx *ctx, int64_t n_pairs,
 /* ffbie_kernel_coeffs for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same computation, arguments and outputs, but its scratch
- * (a 32-byte root record, a refine-list slot and a status word per pair, and
+ * (a 64-byte root record, a refine-list slot and a status word per pair, and
  * the refine-list counter) lives in a file-scope device array of the library,
  * one per GPU, allocated with the library's code and held until the process
- * ends: about 44 MiB, room for at most 1048576 pairs.  The call allocates
+ * ends: about 76 MiB, room for at most 1048576 pairs.  The call allocates
  * nothing (no hipMalloc, no library allocation) and needs only a problem set by
  * ffbie_set_problem.  n_pairs above 1048576 gives FFBIE_EINVAL.  Every call on
  * one GPU shares that GPU's array and leaves its contents behind (the counter
@@ -325,7 +325,7 @@ ffbie_status ffbie_get_tuning(const ffbie_ctx *ctx, ffbie_tuning *tuning);
  * refine pass as one persistent launch, after one root launch for all.  ffbie_batch_plan_create validates the items
  * (HOST array; the device buffers they name must stay valid for the plan's
  * life), orders them, uploads the descriptors and allocates the plan's own
- * workspace (root records, refine queue, counters: about 44 B per pair).
+ * workspace (root records, refine queue, counters: about 76 B per pair).
  * flags (or-ed):
  *   FFBIE_PLAN_AUTOTUNE  for each M class of the batch, time its main pass for
  *                        every candidate tuning (radix {2, 4} x pairs_per_item

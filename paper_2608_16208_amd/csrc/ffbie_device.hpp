@@ -122,11 +122,29 @@ FFBIE_HD __forceinline__ double poly_fma(double a, double b, double c) {
 #endif
 }
 
+// sin and cos of the reduced argument r (|r| <= pi/4) rotated by q quarter turns
+FFBIE_HD __forceinline__ void sincos_quadrant(double r, int q, double* s, double* c);
+
 FFBIE_HD __forceinline__ void sincos_bounded(double x, double* s, double* c) {
   const double qf = rint(x * 0.6366197723675814);           // x * 2/pi
   double r = fma(-qf, 1.5707963267341256, x);
   r = fma(-qf, 6.077100506303966e-11, r);
   r = fma(-qf, 2.0222662487959506e-21, r);
+  sincos_quadrant(r, static_cast<int>(static_cast<long long>(qf) & 3), s, c);
+}
+
+// The same with the quadrant from one 32-bit conversion instead of a 64-bit
+// one, for the arguments of the coefficient passes' inner steps (the sampled
+// phases k rho and the swap phases n ur), which stay far inside that bound.
+FFBIE_HD __forceinline__ void sincos_moderate(double x, double* s, double* c) {
+  const double qf = rint(x * 0.6366197723675814);           // x * 2/pi
+  double r = fma(-qf, 1.5707963267341256, x);
+  r = fma(-qf, 6.077100506303966e-11, r);
+  r = fma(-qf, 2.0222662487959506e-21, r);
+  sincos_quadrant(r, static_cast<int>(qf) & 3, s, c);
+}
+
+FFBIE_HD __forceinline__ void sincos_quadrant(double r, int q, double* s, double* c) {
   const double r2 = r * r;
   double ps = 2.8114572543455206e-15;                         // 1/17!
   ps = poly_fma(ps, r2, -7.647163731819816e-13);                  // -1/15!
@@ -146,7 +164,6 @@ FFBIE_HD __forceinline__ void sincos_bounded(double x, double* s, double* c) {
   pc = poly_fma(pc, r2, 0.041666666666666664);                    //  1/4!
   pc = poly_fma(pc, r2, -0.5);                                    // -1/2!
   const double cr = fma(pc, r2, 1.0);
-  const int q = static_cast<int>(static_cast<long long>(qf) & 3);
   const double ss = (q & 1) ? cr : sr;
   const double cc = (q & 1) ? sr : cr;
   *s = (q & 2) ? -ss : ss;

@@ -59,7 +59,7 @@ __attribute__((amdgpu_waves_per_eu(MM <= 2 ? 4 : 1, MM <= 2 ? 4 : 8))) void ffbi
   const int j = az_in[i] & (2 * P.M - 1);
   const double nan = __builtin_nan("");
   if (t == ts || !(t == t) || !(ts == ts)) {
-    out[i] = RootRec{nan, nan, nan, nan};
+    out[i] = RootRec{nan, nan, nan, nan, nan, nan, nan, nan};
     status[i] = FFBIE_PAIR_SINGULAR;
     if (root_out) { root_out[2 * i] = nan; root_out[2 * i + 1] = nan; }
     return;
@@ -607,7 +607,6 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
   const double s_down = ldexp(1.0, -kexp);
   const R s_up = (R)ldexp(1.0, kexp);
 
-  const double inv_gstep = NF / (2.0 * M_PI);   // 1 / (2 pi / NF)
   const double inv_NF = 1.0 / NF;
   double t_prev = nan, ts_prev = nan;
   PairGeo<MM> pg;
@@ -622,7 +621,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     const int64_t pi = a.list ? a.list[w] : w;
     const double t = a.t_in[pi], ts = a.ts_in[pi];
     const int j = a.az_in[pi] & (2 * M - 1);
-    const RootRec rr = a.roots[pi];
+    const RootRec rr = load_root(a.roots, pi);
     int st = a.status[pi] & ((1 << FFBIE_PAIR_P_SHIFT) - 1);
     C* krow = kappa + pi * (int64_t)(2 * M);
     C* crow = rhoinv ? rhoinv + pi * (int64_t)(L + 1) : nullptr;
@@ -639,26 +638,20 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     } else {
       pair_geo_R<MM>(tab, J, mask, quarter, &pg);
     }
-    const double u = rr.u, b = rr.b;
-    // a = theta_j + qu * (2 pi / NF) + ur,  |ur| <= pi / NF
-    const double gstep = 2.0 * M_PI / NF;   // any rounding of qu is exact in ur
-    const double qu_d = rint(u * inv_gstep);
-    const int qu = (int)qu_d;
-    const double ur = fma(-qu_d, gstep, u);
-    double sur, cur;
-    sincos_bounded(0.5 * ur, &sur, &cur);
-    // e^{-b} and 1 - e^{-b} from one transcendental, each to full relative
-    // accuracy: below b = 1/2 from expm1 (e^{-b} > 0.6), above from exp
-    // (1 - e^{-b} > 0.39); b is the same in every lane
-    double eb, omq;
-    if (b < 0.5) {
-      const double em = expm1(-b);
-      eb = 1.0 + em;
-      omq = -em;
+    const double b = rr.b;
+    // a = theta_j + qu * (2 pi / NF) + ur,  |ur| <= pi / NF; e^{-b}, 1 - e^{-b}
+    // and, on the 2M-point grid of the main pass, sin and cos of ur/2 come
+    // with the root record
+    int qu;
+    double ur, sur, cur;
+    root_grid_offset(rr.u, NF, &qu, &ur);
+    if constexpr (!REFINE) {
+      sur = rr.sh;
+      cur = rr.ch;
     } else {
-      eb = exp(-b);
-      omq = 1.0 - eb;
+      sincos_bounded(0.5 * ur, &sur, &cur);
     }
+    const double eb = rr.eb, omq = rr.omq;
     const int qj = j * (NF / (2 * M));
 
     // ---- samples on the NF-point grid: sample(q, z1, z2) gives the inputs of
@@ -671,7 +664,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
       const double ri = rsqrt_refined(r2);      // 1/rho
       const double rho = r2 * ri;
       double skr, ckr;
-      sincos_bounded(k * rho, &skr, &ckr);
+      sincos_moderate(k * rho, &skr, &ckr);
       const int hidx = (q - qj - qu) * hstep;   // (theta_q - a)/2 = hidx pi/(4M) - ur/2
       const double sh = fma(tsin(tab, hidx, mask), cur, -tcos(tab, hidx, mask, quarter) * sur);
       const double s = fma(omq, omq, 4.0 * eb * sh * sh);
@@ -777,7 +770,7 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     cplx ph_lane, ph64;
     {
       double s1, c1;
-      sincos_bounded(lane * ur, &s1, &c1);
+      sincos_moderate(lane * ur, &s1, &c1);
       ph_lane = mk(tcos(tab, lane * Jq, mask, quarter), tsin(tab, lane * Jq, mask)) * mk(c1, s1);
       const cplx h = mk(read_lane(ph_lane.re, 32), read_lane(ph_lane.im, 32));
       ph64 = h * h;
@@ -1021,7 +1014,7 @@ __global__ __launch_bounds__(256) void ffbie_root_batch_kernel_t(BatchArgs b) {
   const double nan = __builtin_nan("");
   RootRec* out = const_cast<RootRec*>(a.roots);
   if (t == ts || !(t == t) || !(ts == ts)) {
-    out[i] = RootRec{nan, nan, nan, nan};
+    out[i] = RootRec{nan, nan, nan, nan, nan, nan, nan, nan};
     a.status[i] = FFBIE_PAIR_SINGULAR;
     return;
   }
@@ -1297,7 +1290,6 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
   const double nan = __builtin_nan("");
   const double k = P.k, k3 = k * k * k;
   const double invNF = 1.0 / NF;
-  const double inv_gstep = NF / (2.0 * M_PI);
   PairGeo<MM> pg;
 
   for (int64_t w = beg; w < end; ++w) {
@@ -1306,7 +1298,7 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
     const int64_t pi = a.list ? a.list[w] : w;
     const double t = a.t_in[pi], ts = a.ts_in[pi];
     const int j = a.az_in[pi] & (2 * M - 1);
-    const RootRec rr = a.roots[pi];
+    const RootRec rr = load_root(a.roots, pi);
     int st = a.status[pi] & ((1 << FFBIE_PAIR_P_SHIFT) - 1);
     cplx* krow = kappa + pi * (int64_t)(2 * M);
     if (st & FFBIE_PAIR_SINGULAR) {
@@ -1331,21 +1323,16 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
       if constexpr (ST) stretch_normal(P.g, &nux, &nuy, &nuz);
     }
     const double u = rr.u, b = rr.b;
-    const double gstep = 2.0 * M_PI / NF;
-    const double qu_d = rint(u * inv_gstep);
-    const int qu = (int)qu_d;
-    const double ur = fma(-qu_d, gstep, u);
-    double sur, cur;
-    sincos_bounded(0.5 * ur, &sur, &cur);
-    double eb, omq;
-    if (b < 0.5) {
-      const double em = expm1(-b);
-      eb = 1.0 + em;
-      omq = -em;
+    int qu;
+    double ur, sur, cur;
+    root_grid_offset(u, NF, &qu, &ur);
+    if constexpr (!REFINE) {        // the main pass samples the 2M-point grid
+      sur = rr.sh;
+      cur = rr.ch;
     } else {
-      eb = exp(-b);
-      omq = 1.0 - eb;
+      sincos_bounded(0.5 * ur, &sur, &cur);
     }
+    const double eb = rr.eb, omq = rr.omq;
     const int qj = j * (NF / (2 * M));
 
     // ---- samples of H (real part) and P (imaginary part).  maxN bounds the
@@ -1362,7 +1349,7 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
       const double rho = r2 * ri;
       const double x = k * rho;
       double skr, ckr;
-      sincos_bounded(x, &skr, &ckr);
+      sincos_moderate(x, &skr, &ckr);
       const int hidx = (q - qj - qu) * hstep;
       const double sh = fma(tsin(tab, hidx, mask), cur, -tcos(tab, hidx, mask, quarter) * sur);
       const double s = fma(omq, omq, 4.0 * eb * sh * sh);
@@ -1447,7 +1434,7 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
     cplx ph_lane, ph64;
     {
       double s1, c1;
-      sincos_bounded(lane * ur, &s1, &c1);
+      sincos_moderate(lane * ur, &s1, &c1);
       ph_lane = mk(tcos(tab, lane * Jq, mask, quarter), tsin(tab, lane * Jq, mask)) * mk(c1, s1);
       const cplx h = mk(read_lane(ph_lane.re, 32), read_lane(ph_lane.im, 32));
       ph64 = h * h;

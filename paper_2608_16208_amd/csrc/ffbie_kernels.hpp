@@ -5,10 +5,59 @@
 namespace ffbie {
 
 // Per-pair output of the root kernel: offset u = a - theta_j of the complex
-// root theta_+ = a + ib of rho^2, its imaginary part b, A_0(b) and A_1 - A_0.
+// root theta_+ = a + ib of rho^2, its imaginary part b, A_0(b) and A_1 - A_0;
+// then values the coefficient passes take from the root alone and would
+// otherwise form in every lane of their wavefront: eb = e^{-b} and
+// omq = 1 - e^{-b} (each to full relative accuracy), and sh, ch = sin, cos of
+// ur/2, ur the offset of a from the nearest point of the 2M-point sample grid
+// (root_grid_offset with NF = 2M).
 struct RootRec {
   double u, b, A0, D1;
+  double eb, omq, sh, ch;
 };
+
+// The root record of pair `pi`, which must be the same in every lane of the
+// wavefront (the coefficient passes take one pair per wavefront).  The address
+// is made explicitly uniform and read through the constant address space (the
+// passes only read the records, written by the root kernel in an earlier
+// launch), so the record is fetched by scalar loads into SGPRs and takes no
+// VGPRs.
+__device__ __forceinline__ RootRec load_root(const RootRec* roots, int64_t pi) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  using CRec = const __attribute__((address_space(4))) RootRec;
+  const uint64_t p = reinterpret_cast<uint64_t>(roots + pi);
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)p);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(p >> 32));
+  return *(CRec*)((hi << 32) | lo);
+#else
+  return roots[pi];
+#endif
+}
+
+// e^{-b} and 1 - e^{-b} from one transcendental, each to full relative
+// accuracy: below b = 1/2 from expm1 (e^{-b} > 0.6), above from exp
+// (1 - e^{-b} > 0.39).
+FFBIE_HD __forceinline__ void root_exp_b(double b, double* eb, double* omq) {
+  if (b < 0.5) {
+    const double em = expm1(-b);
+    *eb = 1.0 + em;
+    *omq = -em;
+  } else {
+    *eb = exp(-b);
+    *omq = 1.0 - *eb;
+  }
+}
+
+// The root's real part a = theta_j + u on an NF-point grid of step
+// 2 pi / NF: a = theta_j + qu (2 pi / NF) + ur with |ur| <= pi / NF (any
+// rounding of qu is absorbed exactly by ur).
+FFBIE_HD __forceinline__ void root_grid_offset(double u, int NF, int* qu, double* ur) {
+  const double inv_gstep = NF / (2.0 * M_PI);
+  const double gstep = 2.0 * M_PI / NF;
+  const double qu_d = rint(u * inv_gstep);
+  *qu = (int)qu_d;
+  *ur = fma(-qu_d, gstep, u);
+}
 
 struct CoeffArgs {
   Prob P;

@@ -164,8 +164,14 @@ FFBIE_HD inline RootRec find_root(const Prob& P, const double* tab, double t, in
   ellip_KE(exp(-2.0 * b), sqrt(-expm1(-2.0 * b)), &K, &E);
   const double A0 = M_2_PI * K;
   const double D1 = M_2_PI * (expm1(b) * K - exp(b) * E);
+  // (5) the root-only values of the coefficient passes (see RootRec)
+  double eb, omq, sh, ch, ur;
+  int qu;
+  root_exp_b(b, &eb, &omq);
+  root_grid_offset(u, 2 * M, &qu, &ur);
+  sincos_bounded(0.5 * ur, &sh, &ch);
   *status = st;
-  return RootRec{u, b, A0, D1};
+  return RootRec{u, b, A0, D1, eb, omq, sh, ch};
 }
 
 }  // namespace ffbie
