@@ -1291,6 +1291,8 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
   const double k = P.k, k3 = k * k * k;
   const double invNF = 1.0 / NF;
   PairGeo<MM> pg;
+  double dc[MM + 1];
+  double t_prev = nan, ts_prev = nan;
 
   for (int64_t w = beg; w < end; ++w) {
     int lane = lane0;
@@ -1306,10 +1308,16 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
       continue;
     }
     const int J = 4 * j;
-    pair_geo<MM>(P.g, t, ts, tab, J, mask, quarter, &pg);
-    // d/dt coefficients of R on the curve that carries the normal
-    double dc[MM + 1];
-    pair_dcoef<MM>(P.g, adj ? t : ts, dc);
+    // consecutive pairs of one (target node, source node) differ only in the
+    // target azimuth: the t, t_s parts of the geometry are kept
+    if (!(t == t_prev && ts == ts_prev)) {
+      pair_geo<MM>(P.g, t, ts, tab, J, mask, quarter, &pg);
+      // d/dt coefficients of R on the curve that carries the normal
+      pair_dcoef<MM>(P.g, adj ? t : ts, dc);
+      t_prev = t; ts_prev = ts;
+    } else {
+      pair_geo_R<MM>(tab, J, mask, quarter, &pg);
+    }
     double nux = 0.0, nuy = 0.0, nuz = 0.0;            // K': unit normal at the target
     if (adj) {
       double Rt = 0.0, Rh = 0.0;
