@@ -143,7 +143,7 @@ __device__ __forceinline__ void mat_scan_lanes(double& e00, double& e01, double&
 // Returns the factor by which A still has to be multiplied: 1, except on the
 // FP64 Miller path with `defer` set, where the values stay as the recurrence
 // left them and the caller applies A_0 / y_0 (to a linear function of A) itself.
-template <class R>
+template <class R, int CACHE = 1>
 __device__ __forceinline__ double singular_factor_wave(double b, double eb, double omq, double A0,
                                                        double D1, int mtop, R* A, bool defer,
                                                        int lane) {
@@ -157,6 +157,12 @@ __device__ __forceinline__ double singular_factor_wave(double b, double eb, doub
     wave_sync();
     return 1.0;
   }
+  // Each lane keeps the coefficients of the first CACHE steps of its segment
+  // from the product pass for the replay (with four, segments up to N = 256
+  // need no step formed twice, which covers M <= 64); later steps are formed
+  // again.  CACHE is what the calling kernel's register budget allows.
+  constexpr int kStepCache = CACHE;
+  double cal[kStepCache], cbe[kStepCache];
   if ((double)mtop * b <= kTauFwd) {
     // ---- forward: w_{m+1} = F_m w_m, w = (D, A),
     //      F_m = [[alpha, beta], [alpha, 1 + beta]], alpha = (2m-1)/(2m+1),
@@ -165,15 +171,34 @@ __device__ __forceinline__ double singular_factor_wave(double b, double eb, doub
     const int cnt = mtop - 1;
     const int S = cnt > 0 ? (cnt + 63) / 64 : 1;
     const int m_first = 1 + lane * S;
+    auto coef = [&](int m, double* al, double* be) {
+      const double r = rcp_refined(2.0 * m + 1.0);
+      *al = (2.0 * m - 1.0) * r;
+      *be = s2 * m * r;
+    };
     double e00 = 1, e01 = 0, e10 = 0, e11 = 1;
-    for (int s = 0; s < S; ++s) {
+    auto product_step = [&](double al, double be) {
+      // F_m E: the second row of F_m is its first plus (0, 1)
+      const double n00 = fma(al, e00, be * e10), n01 = fma(al, e01, be * e11);
+      e10 = n00 + e10;
+      e11 = n01 + e11;
+      e00 = n00;
+      e01 = n01;
+    };
+#pragma unroll
+    for (int s = 0; s < kStepCache; ++s) {
+      const int m = m_first + s;
+      if (s < S && m <= mtop - 1) {
+        coef(m, &cal[s], &cbe[s]);
+        product_step(cal[s], cbe[s]);
+      }
+    }
+    for (int s = kStepCache; s < S; ++s) {
       const int m = m_first + s;
       if (m > mtop - 1) break;
-      const double r = rcp_refined(2.0 * m + 1.0);
-      const double al = (2.0 * m - 1.0) * r, be = s2 * m * r;
-      double n00, n01, n10, n11;
-      mat_mul(al, be, al, 1.0 + be, e00, e01, e10, e11, &n00, &n01, &n10, &n11);
-      e00 = n00; e01 = n01; e10 = n10; e11 = n11;
+      double al, be;
+      coef(m, &al, &be);
+      product_step(al, be);
     }
     // inclusive prefix scan: E_l = Phi_l ... Phi_0
     mat_scan_lanes(e00, e01, e10, e11);
@@ -182,15 +207,23 @@ __device__ __forceinline__ double singular_factor_wave(double b, double eb, doub
     const double x10 = dpp_f64_fill<0x138, 0xf>(0.0, e10), x11 = dpp_f64_fill<0x138, 0xf>(1.0, e11);
     const double w1D = D1, w1A = A0 + D1;
     double wD = fma(x00, w1D, x01 * w1A), wA = fma(x10, w1D, x11 * w1A);
-    for (int s = 0; s < S; ++s) {
-      const int m = m_first + s;
-      if (m > mtop - 1) break;
-      const double r = rcp_refined(2.0 * m + 1.0);
-      const double al = (2.0 * m - 1.0) * r, be = s2 * m * r;
+    auto replay_step = [&](int m, double al, double be) {
       const double nD = fma(al, wD, be * wA);
       wA = wA + nD;
       wD = nD;
       A[m + 1] = (R)wA;
+    };
+#pragma unroll
+    for (int s = 0; s < kStepCache; ++s) {
+      const int m = m_first + s;
+      if (s < S && m <= mtop - 1) replay_step(m, cal[s], cbe[s]);
+    }
+    for (int s = kStepCache; s < S; ++s) {
+      const int m = m_first + s;
+      if (m > mtop - 1) break;
+      double al, be;
+      coef(m, &al, &be);
+      replay_step(m, al, be);
     }
     if (lane == 0) { A[0] = (R)A0; A[1] = (R)(A0 + D1); }
     wave_sync();
@@ -213,33 +246,71 @@ __device__ __forceinline__ double singular_factor_wave(double b, double eb, doub
   const double ch4 = 2.0 * (rcp_refined(eb) + eb);
   const int S = (N + 63) / 64;
   // segment g = 63 - lane (the highest indices in lane 0), so that the suffix
-  // products over segments are prefix products in lane order
+  // products over segments are prefix products in lane order; step s of the
+  // segment is the transition m = top - s
   const int seg = 63 - lane;
   const int top = seg * S + S;      // segment: transitions m = top .. seg*S + 1
-  double p00 = 1, p01 = 0, p10 = 0, p11 = 1;
-  for (int m = top; m > seg * S; --m) {
-    if (m > N) continue;
+  auto coef = [&](int m, double* al, double* be) {
     const double r = rcp_refined(2.0 * m - 1.0);
-    const double al = ch4 * m * r, be = -(2.0 * m + 1.0) * r;
-    double n00, n01, n10, n11;
-    mat_mul(al, be, 1.0, 0.0, p00, p01, p10, p11, &n00, &n01, &n10, &n11);
-    p00 = n00; p01 = n01; p10 = n10; p11 = n11;
+    *al = ch4 * m * r;
+    *be = -(2.0 * m + 1.0) * r;
+  };
+  double p00 = 1, p01 = 0, p10 = 0, p11 = 1;
+  auto product_step = [&](double al, double be) {
+    // T_m P with T_m = [[al, be], [1, 0]]: the second row of the product is
+    // the first row of P
+    const double n00 = fma(al, p00, be * p10), n01 = fma(al, p01, be * p11);
+    p10 = p00;
+    p11 = p01;
+    p00 = n00;
+    p01 = n01;
+  };
+#pragma unroll
+  for (int s = 0; s < kStepCache; ++s) {
+    const int m = top - s;
+    if (s < S && m <= N) {
+      coef(m, &cal[s], &cbe[s]);
+      product_step(cal[s], cbe[s]);
+    }
+  }
+  for (int s = kStepCache; s < S; ++s) {
+    const int m = top - s;
+    if (m > N) continue;
+    double al, be;
+    coef(m, &al, &be);
+    product_step(al, be);
   }
   // inclusive suffix scan over segments: Q_g = P_g P_{g+1} ... P_63
   mat_scan_lanes(p00, p01, p10, p11);
   const double q00 = dpp_f64_fill<0x138, 0xf>(1.0, p00), q10 = dpp_f64_fill<0x138, 0xf>(0.0, p10);
   // state entering the segment: Q_{g+1} (y_s, 0)
   double y0 = q00 * kMillerStart, y1 = q10 * kMillerStart;   // (y_top, y_top+1)
+  // y_{m-1} = al y_m + be y_{m+1}; store(m - 1, y_{m-1})
+  auto replay = [&](auto store) {
+#pragma unroll
+    for (int s = 0; s < kStepCache; ++s) {
+      const int m = top - s;
+      if (s < S && m <= N) {
+        const double yn = fma(cal[s], y0, cbe[s] * y1);
+        y1 = y0;
+        y0 = yn;
+        store(m - 1, yn);
+      }
+    }
+    for (int s = kStepCache; s < S; ++s) {
+      const int m = top - s;
+      if (m > N) continue;
+      double al, be;
+      coef(m, &al, &be);
+      const double yn = fma(al, y0, be * y1);
+      y1 = y0;
+      y0 = yn;
+      store(m - 1, yn);
+    }
+  };
   if constexpr (sizeof(R) == sizeof(double)) {
     // store the unnormalised values, then scale by A_0 / y_0 with y_0 as replayed
-    for (int m = top; m > seg * S; --m) {
-      if (m > N) continue;
-      const double r = rcp_refined(2.0 * m - 1.0);
-      const double yn = (ch4 * m * y0 - (2.0 * m + 1.0) * y1) * r;
-      y1 = y0;
-      y0 = yn;                       // y_{m-1}
-      if (m - 1 <= mtop) A[m - 1] = yn;
-    }
+    replay([&](int m, double y) { if (m <= mtop) A[m] = y; });
     wave_sync();
     const double scale = A0 * rcp_refined(A[0]);
     if (defer && meff == mtop) return scale;
@@ -249,14 +320,7 @@ __device__ __forceinline__ double singular_factor_wave(double b, double eb, doub
     // the unnormalised values leave the float range: lane 63 holds the whole
     // product Q_0, so y_0 = Q_0[0][0] y_N fixes the normalisation first
     const double scale = A0 / (lane63(p00) * kMillerStart);
-    for (int m = top; m > seg * S; --m) {
-      if (m > N) continue;
-      const double r = rcp_refined(2.0 * m - 1.0);
-      const double yn = (ch4 * m * y0 - (2.0 * m + 1.0) * y1) * r;
-      y1 = y0;
-      y0 = yn;                       // y_{m-1}
-      if (m - 1 <= mtop) A[m - 1] = (R)((m - 1 <= meff) ? yn * scale : 0.0);
-    }
+    replay([&](int m, double y) { if (m <= mtop) A[m] = (R)((m <= meff) ? y * scale : 0.0); });
     for (int m = N + lane; m <= mtop; m += 64) A[m] = (R)0.0;
   }
   wave_sync();
@@ -803,7 +867,9 @@ __device__ __forceinline__ void coeff_range(const CoeffArgs& a, const double* ta
     const int mtop = paper ? L + pF : (want_c ? max(L + pF, M + pH) : M + pH);
     // on the FP64 path A may come back unnormalised: its factor rides on the
     // phases of the convolutions, which are linear in A
-    const double asc = singular_factor_wave(b, eb, omq, rr.A0, rr.D1, mtop, A, true, lane);
+    // four cached recurrence steps fit the FP64 kernels of low azimuthal order
+    constexpr int kCache = (sizeof(R) == sizeof(double) && MM <= 2) ? 4 : 1;
+    const double asc = singular_factor_wave<R, kCache>(b, eb, omq, rr.A0, rr.D1, mtop, A, true, lane);
     for (int m = 1 + lane; m <= max(pF, pH); m += 64) A[-m] = A[m];
     wave_sync();
 
@@ -1043,7 +1109,7 @@ __global__ __launch_bounds__(256) void ffbie_singular_factor_kernel(int64_t n,
     A0 = M_2_PI * K;
     D1 = M_2_PI * (expm1(b) * K - exp(b) * E);
   }
-  singular_factor_wave(b, exp(-b), -expm1(-b), A0, D1, mtop, A, false, lane);
+  singular_factor_wave<double, 4>(b, exp(-b), -expm1(-b), A0, D1, mtop, A, false, lane);
   for (int m = lane; m <= mtop; m += 64) out[idx * (mtop + 1) + m] = A[m];
 }
 
@@ -1470,7 +1536,7 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
     const bool backward = b >= kBackwardB;
     const int NB = backward ? max(mtopB, (int)ceil(37.0 / b)) + 8 : mtopB;
     double* A = Abuf;
-    singular_factor_wave<double>(b, eb, omq, rr.A0, rr.D1, backward ? NB - 1 : mtopB, A, false, lane);
+    singular_factor_wave<double, 4>(b, eb, omq, rr.A0, rr.D1, backward ? NB - 1 : mtopB, A, false, lane);
     double* B = Bbuf + p;
     bool translate = false;
     if (!backward) {
