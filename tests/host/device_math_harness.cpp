@@ -1,7 +1,10 @@
 // Host build of the device math of the coefficient path (the same headers the
 // kernels include), driven from tests/test_host_device_code.py.
 //   sincos <x...>            : prints sin, cos of each x with sincos_bounded
-//   roots  (stdin problem)   : prints u, b, status of find_root for each pair
+//   sincosm <x...>           : the same with sincos_moderate
+//   roots  (stdin problem)   : prints u, b, status of find_root for each pair, then
+//                              the root record's e^{-b}, 1 - e^{-b} and the sine
+//                              and cosine of half the offset from the 2M grid
 //   tunecache <path>         : writes two autotuner cache entries to path, reads
 //                              them back and prints them; then reads path as it
 //                              is after a test has altered it
@@ -54,11 +57,13 @@ int main(int argc, char** argv) {
     printf("%d %d\n", h ? h->t.fft_radix : -1, miss ? 1 : 0);
     return 0;
   }
-  if (argc > 1 && !strcmp(argv[1], "sincos")) {
+  if (argc > 1 && (!strcmp(argv[1], "sincos") || !strcmp(argv[1], "sincosm"))) {
+    const bool moderate = !strcmp(argv[1], "sincosm");
     double x;
     while (scanf("%lf", &x) == 1) {
       double s, c;
-      sincos_bounded(x, &s, &c);
+      if (moderate) sincos_moderate(x, &s, &c);
+      else sincos_bounded(x, &s, &c);
       printf("%.17g %.17g\n", s, c);
     }
     return 0;
@@ -87,7 +92,7 @@ int main(int argc, char** argv) {
     else if (mmax <= 2) r = find_root<2>(P, tab.data(), t, j, ts, &st);
     else if (mmax <= 4) r = find_root<4>(P, tab.data(), t, j, ts, &st);
     else r = find_root<8>(P, tab.data(), t, j, ts, &st);
-    printf("%.17g %.17g %d\n", r.u, r.b, st);
+    printf("%.17g %.17g %d %.17g %.17g %.17g %.17g\n", r.u, r.b, st, r.eb, r.omq, r.sh, r.ch);
   }
   return 0;
 }

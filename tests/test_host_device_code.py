@@ -31,12 +31,15 @@ def harness(tmp_path_factory):
     return exe
 
 
-def test_sincos_bounded_accuracy(harness):
+@pytest.mark.parametrize("mode", ["sincos", "sincosm"])
+def test_sincos_bounded_accuracy(harness, mode):
+    """sincos_bounded and sincos_moderate (the quadrant from a 32-bit
+    conversion) against 50-digit sin and cos, negative arguments included."""
     rng = np.random.default_rng(0)
     xs = np.concatenate([rng.uniform(-100, 100, 400), rng.uniform(-1e-3, 1e-3, 50),
                          np.array([0.0, math.pi / 4, math.pi / 2, math.pi, 3 * math.pi / 2,
-                                   1e-300, -2.5, 1000.0, 12345.678])])
-    out = subprocess.run([harness, "sincos"], input="\n".join(repr(float(x)) for x in xs),
+                                   1e-300, -2.5, -3 * math.pi / 4, 1000.0, 12345.678])])
+    out = subprocess.run([harness, mode], input="\n".join(repr(float(x)) for x in xs),
                          capture_output=True, text=True).stdout.split()
     got = np.array(out, dtype=float).reshape(-1, 2)
     mp.mp.dps = 50
@@ -56,7 +59,7 @@ def test_root_finder_on_host(harness, cfgi):
            + " ".join(repr(float(v)) for v in a.ravel()) + f"\n{len(t)}\n"
            + "\n".join(f"{float(t[i])!r} {int(j[i])} {float(ts[i])!r}" for i in range(len(t))))
     out = subprocess.run([harness], input=inp, capture_output=True, text=True).stdout.split()
-    res = np.array(out, dtype=float).reshape(-1, 3)
+    res = np.array(out, dtype=float).reshape(-1, 7)
     mp.mp.dps = 30
 
     def r_mp(tt, th):
@@ -66,7 +69,18 @@ def test_root_finder_on_host(harness, cfgi):
 
     checked = 0
     for i in range(len(t)):
-        u, b, st = res[i]
+        u, b, st, eb, omq, sh, ch = res[i]
+        # the root-only values the record carries for the coefficient passes:
+        # e^{-b} and 1 - e^{-b} to a few ulp, relative; the half offset of the
+        # root from the nearest point of the 2M-point grid, step pi/M
+        bm = mp.mpf(float(b))
+        assert abs(eb - float(mp.exp(-bm))) <= 4e-16 * float(mp.exp(-bm)), (i, b)
+        assert abs(omq - float(-mp.expm1(-bm))) <= 4e-16 * float(-mp.expm1(-bm)), (i, b)
+        um = mp.mpf(float(u))
+        qu = int(round(float(u) * M / math.pi))
+        half = (um - qu * mp.pi / M) / 2
+        assert abs(half) <= mp.pi / (4 * M) * (1 + 1e-12)
+        assert abs(sh - float(mp.sin(half))) <= 1e-15 and abs(ch - float(mp.cos(half))) <= 1e-15, i
         if int(st) & (2 | 16):
             continue
         th = mp.pi * int(j[i]) / M
