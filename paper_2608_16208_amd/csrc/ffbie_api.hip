@@ -46,6 +46,7 @@ constexpr size_t kNoAllocBytes = kNoAllocCountOff + 256;
 static_assert(kNoAllocListOff % 256 == 0 && kNoAllocStatusOff % 256 == 0 && kNoAllocCountOff % 256 == 0,
               "scratch parts must stay 256-byte aligned");
 constexpr int kMaxDevices = 64;
+constexpr size_t kLdsPerCU = 160 * 1024;   // LDS of one gfx950 compute unit
 }  // namespace
 
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
@@ -73,6 +74,7 @@ hipError_t noalloc_scratch(int device, void** out) {
 
 struct ffbie_ctx {
   int device = 0;
+  int n_cu = 256;            // compute units of the device (grid sizing)
   hipStream_t stream = nullptr;
   std::string err;
   bool has_problem = false;
@@ -368,6 +370,10 @@ ffbie_status ffbie_create(ffbie_ctx** out, int device, void* hip_stream) {
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
   if (hipSetDevice(device) != hipSuccess) { delete c; return FFBIE_EDEVICE; }
+  int n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      n_cu > 0)
+    c->n_cu = n_cu;
   if (hipMalloc(&c->d_count, 4 * sizeof(int32_t)) != hipSuccess) { delete c; return FFBIE_ENOMEM; }
   void* sp = nullptr;
   if (noalloc_scratch(device, &sp) != hipSuccess) {
@@ -532,20 +538,31 @@ ffbie_status run_dl_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int
   a.status = status;
   a.kappa = d_kappa;
   a.adjoint = adjoint;
-  auto waves = [&](int NF, size_t* lds) {
+  // wavefronts per workgroup (1..4, at most 64 KiB of LDS per workgroup) that
+  // put the most wavefronts on a CU's 160 KiB of LDS (the table is per
+  // workgroup, so fewer, larger workgroups share it; a leftover that fits no
+  // further workgroup is lost); *per_cu receives that count
+  auto waves = [&](int NF, size_t* lds, int* per_cu) {
     const size_t per_wave = sizeof(double) * dl_lds_per_wave(NF, P.M);
     const size_t tab = sizeof(double) * P.tab_n;
-    int w = 4;
-    while (w > 1 && tab + w * per_wave > 65536) --w;
-    *lds = tab + w * per_wave;
-    return w;
+    int best_w = 1, best = 0;
+    for (int w = 1; w <= 4; ++w) {
+      const size_t wg = tab + w * per_wave;
+      if (wg > 65536) break;
+      const int on_cu = (int)(kLdsPerCU / wg) * w;
+      if (on_cu >= best) { best = on_cu; best_w = w; }
+    }
+    *lds = tab + best_w * per_wave;
+    *per_cu = best;
+    return best_w;
   };
   {
     a.NF = 2 * P.M;
     a.flag_list = c->d_list;
     a.flag_count = c->d_count;
     size_t lds;
-    const int w = waves(a.NF, &lds);
+    int per_cu;
+    const int w = waves(a.NF, &lds, &per_cu);
     const int64_t pairs_per_wave = 8;
     int64_t blocks = (n + w * pairs_per_wave - 1) / (w * pairs_per_wave);
     if (blocks < 1) blocks = 1;
@@ -558,8 +575,12 @@ ffbie_status run_dl_coeffs(ffbie_ctx* c, int64_t n, const double* d_t, const int
     a.flag_list = nullptr;
     a.flag_count = nullptr;
     size_t lds;
-    const int w = waves(a.NF, &lds);
-    FFBIE_HIP(c, launch_dl_coeff(a, 512, w, lds, c->stream, true));
+    int per_cu;
+    const int w = waves(a.NF, &lds, &per_cu);
+    // enough workgroups for every CU's share of wavefronts (the queue is
+    // split evenly over all wavefronts of the grid)
+    const int64_t blocks = std::max<int64_t>(1, (int64_t)c->n_cu * per_cu / w);
+    FFBIE_HIP(c, launch_dl_coeff(a, blocks, w, lds, c->stream, true));
   }
   return FFBIE_OK;
 }

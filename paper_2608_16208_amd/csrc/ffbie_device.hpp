@@ -214,6 +214,37 @@ struct PairGeo {
   double sx, sy, sz;          // the stretch D (read only by the stretched instantiations)
 };
 
+// A value that is the same in every lane of the wavefront, moved to SGPRs:
+// VALU instructions read it from there as their scalar operand, so it holds
+// no VGPR while it stays live.
+FFBIE_HD __forceinline__ double to_uniform(double v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)u);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(u >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+#else
+  return v;
+#endif
+}
+
+// The per-pair geometry of one wavefront's pair (the same in every lane) in
+// SGPRs.
+template <int MM>
+FFBIE_HD __forceinline__ void pair_geo_uniform(PairGeo<MM>* p) {
+  p->st = to_uniform(p->st); p->ct = to_uniform(p->ct);
+  p->sts = to_uniform(p->sts); p->cts = to_uniform(p->cts);
+  p->S1 = to_uniform(p->S1); p->C1 = to_uniform(p->C1);
+  p->R = to_uniform(p->R);
+#pragma unroll
+  for (int m = 0; m <= MM; ++m) {
+    p->al[m] = to_uniform(p->al[m]);
+    p->be[m] = to_uniform(p->be[m]);
+    p->ga[m] = to_uniform(p->ga[m]);
+  }
+  p->sx = to_uniform(p->sx); p->sy = to_uniform(p->sy); p->sz = to_uniform(p->sz);
+}
+
 // R(t, theta_j) = 1 + sum_m ga_m cos(m theta_j), theta_j at table index J.
 template <int MM>
 FFBIE_HD __forceinline__ void pair_geo_R(const double* tab, int J, int mask, int quarter,

@@ -1380,10 +1380,13 @@ __device__ __forceinline__ void dl_range(const CoeffArgs& a, const double* tab, 
       pair_geo<MM>(P.g, t, ts, tab, J, mask, quarter, &pg);
       // d/dt coefficients of R on the curve that carries the normal
       pair_dcoef<MM>(P.g, adj ? t : ts, dc);
+#pragma unroll
+      for (int m = 0; m <= MM; ++m) dc[m] = to_uniform(dc[m]);
       t_prev = t; ts_prev = ts;
     } else {
       pair_geo_R<MM>(tab, J, mask, quarter, &pg);
     }
+    pair_geo_uniform<MM>(&pg);
     double nux = 0.0, nuy = 0.0, nuz = 0.0;            // K': unit normal at the target
     if (adj) {
       double Rt = 0.0, Rh = 0.0;
