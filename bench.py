@@ -370,13 +370,11 @@ def banded_block(ctx, cfg, torch, np, ffbie, tt, jj, tss, kappa, steps=3, sample
     return res
 
 
-def interior_protocol(ctx, torch, np, ffbie):
-    """The interior point-source protocol of Sec. 5: (IDP) by S and by K - I,
-    (INP) by K' + I, LU64, E_j = ||u_num - u_exa||_2 / #(points) over 200
-    points of the test ball, source r* = (3, 4, 10.5).
-    * the ellipsoid of Example 1 at the rows of the paper's Table 1 (same N_p,
-      the next supported 2M), the paper's E_j beside each;
-    * an analytic star surface (workloads.INTERIOR_AMP) at INTERIOR_ROWS."""
+def _interior_errors(ctx, torch, np, ffbie):
+    """E_j of the interior point-source protocol of Sec. 5 for one discretisation:
+    (IDP) by S and by K - I, (INP) by K' + I, LU64, E_j = ||u_num - u_exa||_2 /
+    #(points) over 200 seeded points of the test ball, source r* = (3, 4, 10.5).
+    Returns error(amp, axes, k, n_panels, M, name) for name in S, K, K'."""
     import workloads
     P = workloads.interior_test_points()
     src = workloads.INTERIOR_SOURCE
@@ -398,7 +396,16 @@ def interior_protocol(ctx, torch, np, ffbie):
         del A
         torch.cuda.empty_cache()
         return float(np.linalg.norm(u - exact) / len(exact))
+    return error
 
+
+def interior_protocol(ctx, torch, np, ffbie):
+    """The interior point-source protocol of Sec. 5 (see _interior_errors):
+    * the ellipsoid of Example 1 at the rows of the paper's Table 1 (same N_p,
+      the next supported 2M), the paper's E_j beside each;
+    * an analytic star surface (workloads.INTERIOR_AMP) at INTERIOR_ROWS."""
+    import workloads
+    error = _interior_errors(ctx, torch, np, ffbie)
     t0 = time.perf_counter()
     ell = []
     for k, dS, eS, dK, eK, dKp, eKp in workloads.PAPER_TABLE1:
@@ -418,6 +425,31 @@ def interior_protocol(ctx, torch, np, ffbie):
             "ellipsoid_table1": ell,
             "star": {"surface": "R = 1 + 0.2 sin t cos(theta) + 0.1 sin 2t cos(theta)", "rows": star},
             "wall_s": time.perf_counter() - t0}
+
+
+def ellipsoid_convergence(ctx, torch, np, ffbie):
+    """The convergence study of Sec. 5, Example 1 at k = 16: E_S, E_K and E_K'
+    of the interior protocol on the ellipsoid with N_p = 16 panels and 2M =
+    32 .. 256, and with 2M = 128 and N_p = 4 .. 32 (the paper's study sweeps
+    2M at N_p = 16 and N_p at 2M = 100)."""
+    import workloads
+    error = _interior_errors(ctx, torch, np, ffbie)
+    t0 = time.perf_counter()
+    k = 16.0
+    runs = {"vs_2M (N_p = 16)": [(16, M) for M in (16, 32, 64, 128)],
+            "vs_N_p (2M = 128)": [(npan, 64) for npan in (4, 8, 16, 32)]}
+    out = {"k": k, "surface": "ellipsoid x^2 + y^2/4 + z^2/9 = 1"}
+    for label, rows in runs.items():
+        recs = []
+        for npan, M in rows:
+            rec = {"N_p": npan, "2M": 2 * M, "N": 32 * M * npan}
+            for name in ("S", "K", "K'"):
+                rec["E_" + name] = error(None, workloads.ELLIPSOID_AXES, k, npan, M, name)
+            recs.append(rec)
+            log("convergence %s: %s" % (label, json.dumps(rec)))
+        out[label] = recs
+    out["wall_s"] = time.perf_counter() - t0
+    return out
 
 
 def config3_block(ctx, torch, np, ffbie, solve=True):
@@ -691,6 +723,8 @@ def main():
                     help="skip the batched many-surface measurement")
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the assembly + solve + field measurement")
+    ap.add_argument("--convergence", action="store_true",
+                    help="add the k = 16 ellipsoid convergence study (about two minutes of solves)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 2 GiB device copy (reference dispatch for HBM counters)")
     args = ap.parse_args()
@@ -883,6 +917,9 @@ def main():
         log("config-2 solves done")
         result["interior_protocol"] = interior_protocol(ctx, torch, np, ffbie)
         log("interior protocol done")
+        if args.convergence:
+            result["ellipsoid_convergence"] = ellipsoid_convergence(ctx, torch, np, ffbie)
+            log("convergence study done")
     if not args.no_config3:
         result["config3"] = config3_block(ctx, torch, np, ffbie, solve=not args.no_solve)
         log("config-3 block done")

@@ -183,3 +183,35 @@ def test_ellipsoid_interior_problems_by_K_and_Kp(ctx, k):
     print("ellipsoid k = %g, (4, 64): %s" % (k, ", ".join("E_%s = %.1e" % kv for kv in E.items())),
           flush=True)
     assert all(v < 1e-9 for v in E.values()), E
+
+
+def test_ellipsoid_errors_decay_with_2M_and_panels(ctx):
+    """The convergence study of Sec. 5, Example 1 (k = 16): the interior
+    protocol's E_j for S, K - I and K' + I drop by more than two orders of
+    magnitude from 2M = 32 to 64 at N_p = 16 and from N_p = 8 to 16 at 2M = 64."""
+    import paper_2608_16208_amd as ffbie
+    ctx.set_near_rule(None)
+    P = workloads.interior_test_points()
+    k = 16.0
+    exact = osolve.point_source(k, P, workloads.INTERIOR_SOURCE)
+    pts = torch.tensor(P)
+    src = list(workloads.INTERIOR_SOURCE)
+    ops = {"S": (ffbie.OP_S, 0.0, ffbie.UNKNOWN_SCALED, ffbie.RHS_POINT_SOURCE, ffbie.OP_S),
+           "K": (ffbie.OP_K, -1.0, ffbie.UNKNOWN_DENSITY, ffbie.RHS_POINT_SOURCE, ffbie.OP_K),
+           "K'": (ffbie.OP_KP, 1.0, ffbie.UNKNOWN_DENSITY, ffbie.RHS_POINT_SOURCE_DN, ffbie.OP_S)}
+
+    def err(npan, M, name):
+        op, shift, unk, rhs, fop = ops[name]
+        ctx.set_problem(None, npan, M, k, axes=ELL_AXES)
+        g = ctx.rhs(rhs, src)
+        A = ctx.assemble(op=op, shift=shift, unknowns=unk)
+        x, _ = ctx.solve(A, g, method=ffbie.SOLVE_LU64)
+        u = ctx.eval_field(pts, x, op=fop, unknowns=unk).cpu().numpy()
+        del A
+        torch.cuda.empty_cache()
+        return float(np.linalg.norm(u - exact) / len(exact))
+
+    for name in ops:
+        fine, coarse_m, coarse_p = err(16, 32, name), err(16, 16, name), err(8, 32, name)
+        print("%s: (16, 64) %.1e, (16, 32) %.1e, (8, 64) %.1e" % (name, fine, coarse_m, coarse_p), flush=True)
+        assert coarse_m > 100 * fine and coarse_p > 100 * fine, (name, fine, coarse_m, coarse_p)
